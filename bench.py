@@ -1,0 +1,216 @@
+"""Benchmark: fwd+bwd iterations/s of the PMF-STGR motion path on one MI355X.
+
+Workload (synthetic, seeded): 32 random views of the 660-view scan, a
+200,000-Gaussian reference volume at 256x256x128 (1.5x1.5x2 mm), MBC levels of
+1k/4k/16k Gaussians on 64^3/128^3/256x256x128 grids with 3 bases x 3
+components, a 512x384 detector at 0.776 mm, SAD/SDD 1000/1500 mm, 0.75 mm
+ray step, float32.  One step = voxelize (reference + 3 MBC levels), combine +
+warp + project all 32 views, L2 loss against synthetic target projections,
+and the full adjoint down to every Gaussian parameter and coefficient.
+
+``value`` is the batched schedule (fused motion path, all views per launch);
+the plain schedule (one view at a time) is timed beside it.  Per-kernel GPU
+times come from HIP events the library records on its launch stream during
+the timed region; the FP64 oracle is timed on a bounded sample on the host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector (published)
+FLOP_PER_SAMPLE = 22           # trilinear sample: 7 lerps x 3 flops + 1 accumulate
+
+
+def ray_samples(grid, cone, angles) -> np.ndarray:
+    """Samples per ray of the midpoint rule (float64 geometry), [V][nv][nu]."""
+    n = np.asarray(grid.n, np.float64)
+    h = np.asarray(grid.h, np.float64)
+    c0 = np.asarray(grid.center, np.float64) - 0.5 * (n - 1) * h
+    lo, hi = c0 - 0.5 * h, c0 + (n - 0.5) * h
+    step = cone.step if cone.step > 0 else 0.5 * h.min()
+    a = (np.arange(cone.nu) - 0.5 * (cone.nu - 1) + cone.off_u) * cone.du
+    b = (np.arange(cone.nv) - 0.5 * (cone.nv - 1) + cone.off_v) * cone.dv
+    A, Bv = np.meshgrid(a, b)
+    out = []
+    for th in np.asarray(angles, np.float64):
+        ct, st = math.cos(th), math.sin(th)
+        o = np.array([cone.sad * ct, cone.sad * st, 0.0])
+        p = np.stack([-(cone.sdd - cone.sad) * ct - A * st, -(cone.sdd - cone.sad) * st + A * ct, Bv], -1)
+        d = p - o
+        d /= np.linalg.norm(d, axis=-1, keepdims=True)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            ta = (lo - o) / d
+            tb = (hi - o) / d
+        t0 = np.nanmax(np.minimum(ta, tb), axis=-1)
+        t1 = np.nanmin(np.maximum(ta, tb), axis=-1)
+        L = np.maximum(t1 - np.maximum(t0, 0.0), 0.0)
+        out.append(np.where(L > 0, np.maximum(1, np.ceil(L / step)), 0))
+    return np.stack(out)
+
+
+def kernel_model(name, w, V, samples):
+    """Algorithmic work of one launch of a kernel in the batched step:
+    (bound, achieved-unit quantity, hbm bytes)."""
+    N = w.grid.size
+    npix = w.cone.nu * w.cone.nv
+    if name in ("project", "project_bwd"):
+        flops = FLOP_PER_SAMPLE * float(samples.sum())
+        byts = 4.0 * (V * N + V * npix)
+        return "alu", flops, byts
+    return None
+
+
+def cpu_baseline(w, target, views: int = 2):
+    """FP64 oracle on a bounded sample: the volumes, `views` views' fwd+bwd and
+    the voxelization adjoints; extrapolated linearly to all views."""
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    import oracle
+    oracle.build()
+    cores = oracle.get_threads()
+    t0 = time.perf_counter()
+    ref, bases = oracle.forward_volumes(w)
+    t_vol = time.perf_counter() - t0
+    N = w.grid.size
+    g_ref = np.zeros(N)
+    g_bases = [np.zeros_like(b) for b in bases]
+    t1 = time.perf_counter()
+    for v in range(views):
+        cv = w.coeff[v:v + 1]
+        dvf = oracle.combine(bases, w.levels, cv, w.grid)
+        wv = oracle.warp(ref, w.grid, dvf)
+        p = oracle.project(wv, w.grid, w.cone, w.angles[v:v + 1])
+        _, gp = oracle.l2_loss(p, target[v:v + 1])
+        gp *= 1.0 / len(w.angles)
+        gw = oracle.project_bwd(gp, w.grid, w.cone, w.angles[v:v + 1])
+        gr, gd = oracle.warp_bwd(ref, w.grid, dvf, gw)
+        g_ref += gr.reshape(-1)
+        gb, _ = oracle.combine_bwd(bases, w.levels, cv, w.grid, gd)
+        for a, b in zip(g_bases, gb):
+            a += b
+    t_view = (time.perf_counter() - t1) / views
+    t2 = time.perf_counter()
+    oracle.voxelize_bwd(w.ref, w.grid, w.trunc_k, g_ref.reshape(1, -1))
+    for s, g, gb in zip(w.mbc, w.levels, g_bases):
+        oracle.voxelize_bwd(s, g, w.trunc_k, gb)
+    t_vb = time.perf_counter() - t2
+    t_iter = t_vol + len(w.angles) * t_view + t_vb
+    return {"value": 1.0 / t_iter, "unit": "iterations/s", "cores": cores, "kind": "oracle",
+            "sample": (f"FP64 oracle: volumes ({t_vol:.2f} s) + {views} of {len(w.angles)} views "
+                       f"fwd+bwd ({t_view:.2f} s/view) + voxelization adjoints ({t_vb:.2f} s), "
+                       f"extrapolated linearly to {len(w.angles)} views = {t_iter:.1f} s/iteration")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--plain-steps", type=int, default=3)
+    ap.add_argument("--views", type=int, default=32)
+    ap.add_argument("--bases", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(views would shard across GPUs with one all-reduce of the parameter "
+              "gradients; not implemented). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2503_22139_amd import ops, synth
+    from paper_2503_22139_amd.model import MotionModel
+
+    torch.cuda.init()
+    w = synth.headline(nviews=args.views, nbases=args.bases)
+    m = MotionModel(w)
+    truth = MotionModel(synth.perturbed_truth(w))
+    target_np = synth.add_target_noise(truth.forward_batched().cpu().numpy())
+    del truth
+    target = torch.from_numpy(target_np).cuda()
+    V = len(w.angles)
+
+    print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        m.step_batched(target)
+    torch.cuda.synchronize()
+    for name in ops.pmf_profile_names():
+        ops.pmf_profile_read(name)
+    ops.pmf_profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        loss, grads = m.step_batched(target)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ops.pmf_profile(False)
+    ms = (t1 - t0) / args.steps * 1e3
+    kern = {}
+    for name in ops.pmf_profile_names():
+        tot, cnt = ops.pmf_profile_read(name)
+        kern[name] = {"ms_per_step": tot / args.steps, "launches_per_step": cnt / args.steps,
+                      "avg_ms": tot / max(cnt, 1)}
+    print(f"[bench] batched {ms:.2f} ms/step", file=sys.stderr, flush=True)
+
+    # plain schedule (one view at a time)
+    m.step_plain(target)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.plain_steps):
+        m.step_plain(target)
+    torch.cuda.synchronize()
+    ms_plain = (time.perf_counter() - t0) / args.plain_steps * 1e3
+    print(f"[bench] plain {ms_plain:.2f} ms/step", file=sys.stderr, flush=True)
+
+    samples = ray_samples(w.grid, w.cone, w.angles)
+    dom = max((k for k in kern if kernel_model(k, w, V, samples)), key=lambda k: kern[k]["ms_per_step"])
+    bound, flops, byts = kernel_model(dom, w, V, samples)
+    avg_s = kern[dom]["avg_ms"] * 1e-3
+    achieved = flops / avg_s / 1e12
+    roof = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+            "avg_launch_ms": kern[dom]["avg_ms"], "algorithmic_flop": flops,
+            "hbm": {"achieved": byts / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": byts / avg_s / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes": byts}}
+
+    out = {
+        "metric": "fwd+bwd iterations/s (32 views, 256²×128) batched vs plain; % HBM roofline",
+        "value": 1e3 / ms,
+        "unit": "iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": (f"motion path fwd+bwd, {V} random views of 660, reference 200k Gaussians "
+                                f"@256x256x128 (1.5x1.5x2 mm), MBC 1k/4k/16k @64^3/128^3/256x256x128, "
+                                f"B={args.bases}, detector 512x384 @0.776 mm, SAD/SDD 1000/1500, step 0.75 mm"),
+                   "views": V, "grid": list(w.grid.n), "detector": [w.cone.nu, w.cone.nv],
+                   "schedule": "batched"},
+        "plain": {"value": 1e3 / ms_plain, "ms_per_step": ms_plain, "steps": args.plain_steps},
+        "speedup_vs_plain": ms_plain / ms,
+        "loss": float(loss),
+        "kernels": kern,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w, target_np)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

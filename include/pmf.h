@@ -1,0 +1,240 @@
+/*
+ * pmf.h -- C ABI of libpmf.so, the MI355X (gfx950) implementation of the
+ * differentiable forward model of PMF-STGR (arXiv 2503.22139, Sec. 2.3):
+ *
+ *   reference Gaussians --voxelize (Eq. 4-5)--> I_ref
+ *   MBC Gaussians       --voxelize, signed (Sec. 2.3.1)--> basis volumes E_l
+ *   E_l, w(p)           --combine (Eq. 3)--> DVF d(x, p)
+ *   I_ref, d            --warp (Eq. 2)--> I(x, p)
+ *   I(x, p)             --cone-beam line integrals (Eq. 6)--> DRR
+ *
+ * and the adjoint (gradient) of every step.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Every float pointer is a DEVICE pointer to contiguous float32 data owned
+ *    by the caller, unless the comment says "host".  The library never
+ *    allocates, frees or retains memory: scratch space is a caller-provided
+ *    device buffer whose size the matching *_workspace() query returns.
+ *  - Every call enqueues work on `stream` (a hipStream_t; NULL = the legacy
+ *    default stream) and returns without waiting.  Host-side argument checks
+ *    run first; on failure nothing is enqueued.
+ *  - Forward outputs and gradient outputs are OVERWRITTEN (not accumulated).
+ *  - Return value: PMF_OK (0) or a negative pmf_status; pmf_last_error()
+ *    gives a message (thread-local, valid until the next call on the thread).
+ *  - Volumes: grid (n, h, center); voxel (i,j,k) has its centre at
+ *    center + ((i,j,k) - (n-1)/2) * h (mm); memory order [n0][n1][n2], axis 2
+ *    (the rotation axis z) fastest.  Multi-channel volumes are [C][n0][n1][n2].
+ *    Every n_a >= 2, every h_a > 0, and n0*n1*n2 < 2^31.
+ *  - Interpolation (warp, DVF upsampling, ray samples) is trilinear over the
+ *    voxel centres; a point beyond the box of the voxels (more than half a
+ *    voxel past the outer centres) reads 0, and a point on that half-voxel rim
+ *    reads the edge voxel.
+ *  - Projections are [V][nv][nu], u fastest.
+ *
+ * Concurrency: calls are reentrant; two calls that write the same buffer, or
+ * share one workspace, must be ordered on one stream.
+ */
+#ifndef PMF_H
+#define PMF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PMF_VERSION 100 /* 1.0.0 */
+
+typedef enum {
+    PMF_OK = 0,
+    PMF_EINVAL = -1,       /* invalid argument (null pointer, bad size or geometry) */
+    PMF_EHIP = -2,         /* a HIP runtime call or kernel launch failed */
+    PMF_EWORKSPACE = -3,   /* workspace missing or smaller than the query returned */
+    PMF_EUNSUPPORTED = -4  /* valid but outside what this build supports (e.g. C > 16) */
+} pmf_status;
+
+/* Voxel grid.  n: voxels per axis; h: spacing (mm); center: world position of
+ * the grid centre (mm). */
+typedef struct {
+    int32_t n[3];
+    float h[3];
+    float center[3];
+} pmf_grid_t;
+
+/* Circular cone-beam geometry with a flat detector (Sec. 2.3.3, Table I).
+ * The gantry rotates about z; at angle t the source sits at
+ * SAD (cos t, sin t, 0) and the detector centre at -(SDD - SAD)(cos t, sin t, 0);
+ * detector axes e_u = (-sin t, cos t, 0), e_v = (0, 0, 1).  Pixel (iu, iv) is
+ * centred at (iu - (nu-1)/2 + off_u) du along e_u and (iv - (nv-1)/2 + off_v) dv
+ * along e_v; one ray joins the source to each pixel centre.  The line integral
+ * (Eq. 6) over the ray's chord [t_n, t_f] through the volume box is taken with
+ * the midpoint rule on N = max(1, ceil((t_f - t_n)/step)) equal sub-intervals.
+ * step <= 0 selects half the smallest voxel spacing.  Requires 0 < SAD < SDD
+ * and the volume box to lie strictly inside the source circle. */
+typedef struct {
+    float sad, sdd;
+    int32_t nu, nv;
+    float du, dv;
+    float off_u, off_v;
+    float step;
+} pmf_cone_t;
+
+/* A set of m anisotropic Gaussians, Eq. 4, with Sigma = R(q) diag(scale^2) R(q)^T.
+ * mean [m][3] mm; scale [m][3] mm (standard deviations, > 0); quat [m][4]
+ * (w, x, y, z), any non-zero norm (normalised inside); value [m][c]: the
+ * density rho (c = 1) or signed motion-basis values (c channels, Sec. 2.3.1).
+ * m = 0 is allowed. */
+typedef struct {
+    const float *mean;
+    const float *scale;
+    const float *quat;
+    const float *value;
+    int64_t m;
+    int32_t c;
+} pmf_gauss_t;
+
+/* Gradients with respect to a pmf_gauss_t's arrays (same shapes). */
+typedef struct {
+    float *mean;
+    float *scale;
+    float *quat;
+    float *value;
+} pmf_gauss_grad_t;
+
+/* ------------------------------------------------------------------ info */
+int pmf_version(void);
+const char *pmf_last_error(void);
+
+/* ------------------------------------------------------------ voxelize
+ * Eq. 5 on the voxel centres (point samples):
+ *   vol[c][j] = sum_i value[i][c] exp(-m_ij / 2),   m_ij = d^T Sigma_i^-1 d,
+ *   d = x_j - mean_i, over the Gaussians with m_ij <= trunc_k^2
+ *   (trunc_k = INFINITY: every Gaussian everywhere).
+ * Values may be negative (the negative-permitting voxelizer of Sec. 2.3.1).
+ * vol: [c][N] output.  Needs the workspace from pmf_voxelize_workspace().
+ * Supports c <= 16. */
+size_t pmf_voxelize_workspace(int64_t m, int32_t c, const pmf_grid_t *grid);
+int pmf_voxelize(const pmf_gauss_t *g, const pmf_grid_t *grid, float trunc_k, float *vol,
+                 void *ws, size_t ws_bytes, void *stream);
+
+/* Gradient of a scalar loss through pmf_voxelize given g_vol = dL/dvol [c][N],
+ * with the truncation mask held fixed: writes dL/dmean, dL/dscale, dL/dquat
+ * (through the normalisation of q) and dL/dvalue.  No workspace. */
+int pmf_voxelize_bwd(const pmf_gauss_t *g, const pmf_grid_t *grid, float trunc_k,
+                     const float *g_vol, const pmf_gauss_grad_t *grad, void *stream);
+
+/* ------------------------------------------------------- combine DVF (Eq. 3)
+ * Low-rank motion model with L levels of B bases per Cartesian component
+ * (the paper uses L = 3 levels, one basis per level and component):
+ *   dvf[v][k][j] = sum_l sum_b coeff[v][l][b][k] * S(bases[l][b*3 + k], x_j)
+ * where S samples level l's volume (grid lvl[l], [3B][N_l]) trilinearly at the
+ * output voxel centre x_j (upsampling; identity when lvl[l] equals out).
+ * bases: HOST array of L device pointers; lvl: HOST array of L grids;
+ * coeff: device [V][L][B][3]; dvf: device [V][3][N] (mm).
+ * Supports L <= 4, B <= 4. */
+int pmf_combine_dvf(int L, int B, const float *const *bases, const pmf_grid_t *lvl,
+                    const float *coeff, int V, const pmf_grid_t *out, float *dvf, void *stream);
+
+/* Adjoint of pmf_combine_dvf given g_dvf [V][3][N]:
+ *   g_coeff[v][l][b][k] = sum_j g_dvf[v][k][j] S(bases[l][b*3+k], x_j)
+ *   g_bases[l][b*3+k]   = sum_v coeff[v][l][b][k] S_l^T g_dvf[v][k]
+ * g_bases: HOST array of L device pointers ([3B][N_l] each).
+ * Needs the workspace from pmf_combine_dvf_bwd_workspace(). */
+size_t pmf_combine_dvf_bwd_workspace(int L, int B, const pmf_grid_t *lvl, int V,
+                                     const pmf_grid_t *out);
+int pmf_combine_dvf_bwd(int L, int B, const float *const *bases, const pmf_grid_t *lvl,
+                        const float *coeff, int V, const pmf_grid_t *out, const float *g_dvf,
+                        float *const *g_bases, float *g_coeff, void *ws, size_t ws_bytes,
+                        void *stream);
+
+/* ------------------------------------------------------------ warp (Eq. 2)
+ * Pull-back warp of the reference volume by each view's DVF:
+ *   out[v][j] = S(ref, x_j + dvf[v][:, j]).
+ * ref [N]; dvf [V][3][N] (mm); out [V][N]. */
+int pmf_warp(const float *ref, const pmf_grid_t *grid, const float *dvf, int V, float *out,
+             void *stream);
+
+/* Adjoint of pmf_warp given g_out [V][N]:
+ *   g_ref = sum_v S_v^T g_out[v]   (trilinear weights at x_j + dvf),  [N]
+ *   g_dvf[v][a][j] = g_out[v][j] dS/dy_a(ref, x_j + dvf[v][:, j]),    [V][3][N]
+ * dS/dy_a is the derivative of the trilinear interpolant inside the
+ * voxel-centre hull and 0 on the half-voxel rim and outside. */
+int pmf_warp_bwd(const float *ref, const pmf_grid_t *grid, const float *dvf, int V,
+                 const float *g_out, float *g_ref, float *g_dvf, void *stream);
+
+/* --------------------------------------------------- projection (Eq. 6)
+ * DRRs of V views: proj[v][iv][iu] = delta * sum_s S(vol_v, o + t_s d),
+ * t_s = t_n + (s + 1/2) delta (geometry in pmf_cone_t).
+ * vol_v = vol + v * vol_stride (floats); vol_stride = 0 projects one volume
+ * in every view.  angles: device [V] (rad).  proj: [V][nv][nu]. */
+int pmf_project(const float *vol, int64_t vol_stride, const pmf_grid_t *grid,
+                const pmf_cone_t *cone, const float *angles, int V, float *proj, void *stream);
+
+/* Exact adjoint (back-projection) of pmf_project given g_proj [V][nv][nu]:
+ * g_vol_v = P_v^T g_proj[v].  vol_stride = N writes one volume per view
+ * ([V][N]); vol_stride = 0 writes their sum ([N]).
+ * Needs the workspace from pmf_project_bwd_workspace(). */
+size_t pmf_project_bwd_workspace(const pmf_cone_t *cone, int V);
+int pmf_project_bwd(const float *g_proj, const pmf_grid_t *grid, const pmf_cone_t *cone,
+                    const float *angles, int V, float *g_vol, int64_t vol_stride, void *ws,
+                    size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------ L2 loss
+ * Projection-domain loss of a batch of V views (the batch mean of Eq. 12 with
+ * an L2 data term, Eq. 1):
+ *   loss = (1/V) sum (proj - target)^2,   g_proj = 2 (proj - target) / V.
+ * npix = nu * nv.  loss: device scalar.  g_proj may be NULL.
+ * Needs the workspace from pmf_l2_loss_workspace(). */
+size_t pmf_l2_loss_workspace(int64_t npix, int V);
+int pmf_l2_loss(const float *proj, const float *target, int64_t npix, int V, float *loss,
+                float *g_proj, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------ utility
+ * dst[i] += src[i] for i < n: accumulation of per-view gradients by callers
+ * that run the steps one view at a time. */
+int pmf_accumulate(float *dst, const float *src, int64_t n, void *stream);
+
+/* ---------------------------------------------------------- profiling
+ * Per-kernel GPU time for measurement.  While enabled, every kernel launch
+ * of the library is bracketed by two HIP events recorded on the stream it
+ * is launched on.  pmf_profile returns the previous state.  pmf_profile_read
+ * waits for, sums and discards the records of one kernel name (total_ms over
+ * count launches).  pmf_profile_names writes the comma-separated names that
+ * hold records into buf (host, len bytes, NUL-terminated) and returns the
+ * full length.  Not for use while a stream is being captured into a graph. */
+int pmf_profile(int enable);
+int pmf_profile_read(const char *kernel, double *total_ms, int64_t *count);
+size_t pmf_profile_names(char *buf, size_t len);
+
+/* ----------------------------------------- batched motion path (fused)
+ * All V views of the motion path in one pass over the bases:
+ *   proj[v] = P_v( warp(ref, combine(bases, coeff[v])) )
+ * The DVFs are never written to memory; the warped volumes of all views live
+ * in the workspace.  Arguments as in the calls above.
+ * Needs the workspace from pmf_warp_project_workspace(). */
+size_t pmf_warp_project_workspace(int L, int B, const pmf_grid_t *lvl, int V,
+                                    const pmf_grid_t *grid, const pmf_cone_t *cone);
+int pmf_warp_project(const float *ref, const pmf_grid_t *grid, int L, int B,
+                       const float *const *bases, const pmf_grid_t *lvl, const float *coeff,
+                       int V, const pmf_cone_t *cone, const float *angles, float *proj,
+                       void *ws, size_t ws_bytes, void *stream);
+
+/* Adjoint of pmf_warp_project given g_proj [V][nv][nu]: writes g_ref [N],
+ * g_bases (HOST array of L device pointers, [3B][N_l] each) and g_coeff
+ * [V][L][B][3].  Recomputes every view's DVF instead of storing it.
+ * Needs the workspace from pmf_warp_project_bwd_workspace(). */
+size_t pmf_warp_project_bwd_workspace(int L, int B, const pmf_grid_t *lvl, int V,
+                                        const pmf_grid_t *grid, const pmf_cone_t *cone);
+int pmf_warp_project_bwd(const float *ref, const pmf_grid_t *grid, int L, int B,
+                           const float *const *bases, const pmf_grid_t *lvl, const float *coeff,
+                           int V, const pmf_cone_t *cone, const float *angles,
+                           const float *g_proj, float *g_ref, float *const *g_bases,
+                           float *g_coeff, void *ws, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PMF_H */

@@ -1,0 +1,379 @@
+// api.cpp -- the extern "C" entry points of libpmf.so (declared in pmf.h).
+//
+// Every entry point validates its arguments on the host before touching the
+// HIP runtime, so a rejected call enqueues nothing.  Errors are reported as a
+// pmf_status with a thread-local message.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <string>
+
+#include "pmf_internal.h"
+
+using namespace pmf;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int ok() {
+    g_err.clear();
+    return PMF_OK;
+}
+
+int hip_status(hipError_t e, const char *what) {
+    if (e == hipSuccess) return ok();
+    return fail(PMF_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool finite_pos(float x) { return isfinite(x) && x > 0.0f; }
+
+int check_grid(const pmf_grid_t *g, const char *name) {
+    if (!g) return fail(PMF_EINVAL, "%s: null grid", name);
+    int64_t N = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (g->n[a] < 2) return fail(PMF_EINVAL, "%s: n[%d] = %d < 2", name, a, g->n[a]);
+        if (!finite_pos(g->h[a])) return fail(PMF_EINVAL, "%s: h[%d] must be > 0", name, a);
+        if (!isfinite(g->center[a])) return fail(PMF_EINVAL, "%s: center not finite", name);
+        N *= g->n[a];
+    }
+    if (N >= ((int64_t)1 << 31)) return fail(PMF_EINVAL, "%s: more than 2^31 voxels", name);
+    return PMF_OK;
+}
+
+int check_cone(const pmf_cone_t *c, const pmf_grid_t *g) {
+    if (!c) return fail(PMF_EINVAL, "cone: null");
+    if (!(isfinite(c->sad) && isfinite(c->sdd) && c->sad > 0.0f && c->sdd > c->sad))
+        return fail(PMF_EINVAL, "cone: need 0 < SAD < SDD");
+    if (c->nu < 1 || c->nv < 1) return fail(PMF_EINVAL, "cone: nu, nv must be >= 1");
+    if ((int64_t)c->nu * c->nv >= ((int64_t)1 << 31))
+        return fail(PMF_EINVAL, "cone: too many pixels");
+    if (!finite_pos(c->du) || !finite_pos(c->dv)) return fail(PMF_EINVAL, "cone: du, dv must be > 0");
+    if (!isfinite(c->off_u) || !isfinite(c->off_v) || !isfinite(c->step))
+        return fail(PMF_EINVAL, "cone: offsets and step must be finite");
+    // the volume box must lie strictly inside the source circle
+    double rmax = 0.0;
+    for (int q = 0; q < 4; ++q) {
+        double x = g->center[0] + ((q & 1) ? 0.5 : -0.5) * g->n[0] * (double)g->h[0];
+        double y = g->center[1] + ((q & 2) ? 0.5 : -0.5) * g->n[1] * (double)g->h[1];
+        rmax = fmax(rmax, sqrt(x * x + y * y));
+    }
+    if (!(rmax < c->sad)) return fail(PMF_EINVAL, "cone: volume box reaches the source circle");
+    return PMF_OK;
+}
+
+int check_gauss(const pmf_gauss_t *gs) {
+    if (!gs) return fail(PMF_EINVAL, "gaussians: null");
+    if (gs->m < 0) return fail(PMF_EINVAL, "gaussians: m < 0");
+    if (gs->c < 1) return fail(PMF_EINVAL, "gaussians: c must be >= 1");
+    if (gs->c > 16) return fail(PMF_EUNSUPPORTED, "gaussians: c = %d > 16", gs->c);
+    if (gs->m > ((int64_t)1 << 26)) return fail(PMF_EUNSUPPORTED, "gaussians: m > 2^26");
+    if (gs->m > 0 && (!gs->mean || !gs->scale || !gs->quat || !gs->value))
+        return fail(PMF_EINVAL, "gaussians: null array");
+    return PMF_OK;
+}
+
+int check_k(float k) {
+    if (!(k > 0.0f)) return fail(PMF_EINVAL, "trunc_k must be > 0 (or INFINITY)");
+    return PMF_OK;
+}
+
+int check_ws(void *ws, size_t have, size_t need) {
+    if (need == 0) return PMF_OK;
+    if (!ws) return fail(PMF_EWORKSPACE, "workspace: null (need %zu bytes)", need);
+    if (have < need) return fail(PMF_EWORKSPACE, "workspace: %zu bytes < %zu needed", have, need);
+    return PMF_OK;
+}
+
+int check_levels(int L, int B, const float *const *bases, const pmf_grid_t *lvl, const char *what) {
+    if (L < 1 || B < 1) return fail(PMF_EINVAL, "%s: L and B must be >= 1", what);
+    if (L > MAXL || B > MAXB) return fail(PMF_EUNSUPPORTED, "%s: L <= 4 and B <= 4", what);
+    if (!bases || !lvl) return fail(PMF_EINVAL, "%s: null level arrays", what);
+    for (int l = 0; l < L; ++l) {
+        if (!bases[l]) return fail(PMF_EINVAL, "%s: null basis pointer %d", what, l);
+        int r = check_grid(&lvl[l], "level grid");
+        if (r) return r;
+    }
+    return PMF_OK;
+}
+
+LevelsK make_levels(int L, int B, const float *const *bases, const pmf_grid_t *lvl,
+                    const GridK &out, GridK *lg) {
+    LevelsK lv;
+    lv.L = L;
+    lv.B = B;
+    for (int l = 0; l < MAXL; ++l) {
+        lv.E[l] = l < L ? bases[l] : nullptr;
+        if (l < L) {
+            lg[l] = make_grid(lvl[l]);
+            lv.map[l] = make_axis_map(out, lg[l]);
+        }
+    }
+    return lv;
+}
+
+hipStream_t as_stream(void *s) { return (hipStream_t)s; }
+
+}  // namespace
+
+#define PMF_CHECK(expr)         \
+    do {                        \
+        int r_ = (expr);        \
+        if (r_ != PMF_OK) return r_; \
+    } while (0)
+
+extern "C" {
+
+int pmf_version(void) { return PMF_VERSION; }
+
+const char *pmf_last_error(void) { return g_err.c_str(); }
+
+// ---------------------------------------------------------------- voxelize
+size_t pmf_voxelize_workspace(int64_t m, int32_t c, const pmf_grid_t *grid) {
+    if (!grid || m < 0 || c < 1) return 0;
+    if (check_grid(grid, "grid") != PMF_OK) return 0;
+    GridK g = make_grid(*grid);
+    return vox_workspace(vox_plan(m, c, g), m);
+}
+
+int pmf_voxelize(const pmf_gauss_t *gs, const pmf_grid_t *grid, float trunc_k, float *vol, void *ws,
+                 size_t ws_bytes, void *stream) {
+    PMF_CHECK(check_gauss(gs));
+    PMF_CHECK(check_grid(grid, "grid"));
+    PMF_CHECK(check_k(trunc_k));
+    if (!vol) return fail(PMF_EINVAL, "voxelize: null output");
+    GridK g = make_grid(*grid);
+    VoxPlan p = vox_plan(gs->m, gs->c, g);
+    PMF_CHECK(check_ws(ws, ws_bytes, vox_workspace(p, gs->m)));
+    return hip_status(launch_voxelize(*gs, g, trunc_k, vol, p, ws, as_stream(stream)), "voxelize");
+}
+
+int pmf_voxelize_bwd(const pmf_gauss_t *gs, const pmf_grid_t *grid, float trunc_k,
+                     const float *g_vol, const pmf_gauss_grad_t *grad, void *stream) {
+    PMF_CHECK(check_gauss(gs));
+    PMF_CHECK(check_grid(grid, "grid"));
+    PMF_CHECK(check_k(trunc_k));
+    if (!grad) return fail(PMF_EINVAL, "voxelize_bwd: null gradient struct");
+    if (gs->m > 0 && (!g_vol || !grad->mean || !grad->scale || !grad->quat || !grad->value))
+        return fail(PMF_EINVAL, "voxelize_bwd: null array");
+    GridK g = make_grid(*grid);
+    return hip_status(launch_voxelize_bwd(*gs, g, trunc_k, g_vol, *grad, as_stream(stream)),
+                      "voxelize_bwd");
+}
+
+// ----------------------------------------------------------------- combine
+int pmf_combine_dvf(int L, int B, const float *const *bases, const pmf_grid_t *lvl,
+                    const float *coeff, int V, const pmf_grid_t *out, float *dvf, void *stream) {
+    PMF_CHECK(check_levels(L, B, bases, lvl, "combine"));
+    PMF_CHECK(check_grid(out, "output grid"));
+    if (V < 1) return fail(PMF_EINVAL, "combine: V must be >= 1");
+    if (!coeff || !dvf) return fail(PMF_EINVAL, "combine: null pointer");
+    GridK go = make_grid(*out);
+    GridK lg[MAXL];
+    LevelsK lv = make_levels(L, B, bases, lvl, go, lg);
+    return hip_status(launch_combine(lv, coeff, V, go, dvf, as_stream(stream)), "combine");
+}
+
+size_t pmf_combine_dvf_bwd_workspace(int L, int B, const pmf_grid_t *lvl, int V,
+                                     const pmf_grid_t *out) {
+    if (L < 1 || L > MAXL || B < 1 || B > MAXB || !lvl || !out || V < 1) return 0;
+    if (check_grid(out, "output grid") != PMF_OK) return 0;
+    for (int l = 0; l < L; ++l)
+        if (check_grid(&lvl[l], "level grid") != PMF_OK) return 0;
+    GridK go = make_grid(*out);
+    GridK lg[MAXL];
+    const float *dummy[MAXL] = {nullptr, nullptr, nullptr, nullptr};
+    LevelsK lv = make_levels(L, B, dummy, lvl, go, lg);
+    return combine_bwd_workspace(lv, lg, V, go);
+}
+
+int pmf_combine_dvf_bwd(int L, int B, const float *const *bases, const pmf_grid_t *lvl,
+                        const float *coeff, int V, const pmf_grid_t *out, const float *g_dvf,
+                        float *const *g_bases, float *g_coeff, void *ws, size_t ws_bytes,
+                        void *stream) {
+    PMF_CHECK(check_levels(L, B, bases, lvl, "combine_bwd"));
+    PMF_CHECK(check_grid(out, "output grid"));
+    if (V < 1) return fail(PMF_EINVAL, "combine_bwd: V must be >= 1");
+    if (!coeff || !g_dvf || !g_bases || !g_coeff) return fail(PMF_EINVAL, "combine_bwd: null pointer");
+    for (int l = 0; l < L; ++l)
+        if (!g_bases[l]) return fail(PMF_EINVAL, "combine_bwd: null g_bases[%d]", l);
+    GridK go = make_grid(*out);
+    GridK lg[MAXL];
+    LevelsK lv = make_levels(L, B, bases, lvl, go, lg);
+    PMF_CHECK(check_ws(ws, ws_bytes, combine_bwd_workspace(lv, lg, V, go)));
+    return hip_status(
+        launch_combine_bwd(lv, lg, coeff, V, go, g_dvf, g_bases, g_coeff, ws, as_stream(stream)),
+        "combine_bwd");
+}
+
+// -------------------------------------------------------------------- warp
+int pmf_warp(const float *ref, const pmf_grid_t *grid, const float *dvf, int V, float *out,
+             void *stream) {
+    PMF_CHECK(check_grid(grid, "grid"));
+    if (V < 1) return fail(PMF_EINVAL, "warp: V must be >= 1");
+    if (!ref || !dvf || !out) return fail(PMF_EINVAL, "warp: null pointer");
+    GridK g = make_grid(*grid);
+    return hip_status(launch_warp(ref, g, dvf, V, out, as_stream(stream)), "warp");
+}
+
+int pmf_warp_bwd(const float *ref, const pmf_grid_t *grid, const float *dvf, int V,
+                 const float *g_out, float *g_ref, float *g_dvf, void *stream) {
+    PMF_CHECK(check_grid(grid, "grid"));
+    if (V < 1) return fail(PMF_EINVAL, "warp_bwd: V must be >= 1");
+    if (!ref || !dvf || !g_out || !g_ref || !g_dvf) return fail(PMF_EINVAL, "warp_bwd: null pointer");
+    GridK g = make_grid(*grid);
+    return hip_status(launch_warp_bwd(ref, g, dvf, V, g_out, g_ref, g_dvf, as_stream(stream)),
+                      "warp_bwd");
+}
+
+// -------------------------------------------------------------- projection
+int pmf_project(const float *vol, int64_t vol_stride, const pmf_grid_t *grid,
+                const pmf_cone_t *cone, const float *angles, int V, float *proj, void *stream) {
+    PMF_CHECK(check_grid(grid, "grid"));
+    PMF_CHECK(check_cone(cone, grid));
+    if (V < 1) return fail(PMF_EINVAL, "project: V must be >= 1");
+    if (!vol || !angles || !proj) return fail(PMF_EINVAL, "project: null pointer");
+    if (vol_stride < 0) return fail(PMF_EINVAL, "project: vol_stride < 0");
+    GridK g = make_grid(*grid);
+    if (vol_stride != 0 && vol_stride < grid_size(g))
+        return fail(PMF_EINVAL, "project: vol_stride must be 0 or >= N");
+    ConeK c = make_cone(*cone, g);
+    return hip_status(launch_project(vol, vol_stride, g, c, angles, V, proj, as_stream(stream)),
+                      "project");
+}
+
+size_t pmf_project_bwd_workspace(const pmf_cone_t *cone, int V) {
+    if (!cone || V < 1 || cone->nu < 1 || cone->nv < 1) return 0;
+    return project_bwd_workspace(*cone, V);
+}
+
+int pmf_project_bwd(const float *g_proj, const pmf_grid_t *grid, const pmf_cone_t *cone,
+                    const float *angles, int V, float *g_vol, int64_t vol_stride, void *ws,
+                    size_t ws_bytes, void *stream) {
+    PMF_CHECK(check_grid(grid, "grid"));
+    PMF_CHECK(check_cone(cone, grid));
+    if (V < 1) return fail(PMF_EINVAL, "project_bwd: V must be >= 1");
+    if (!g_proj || !angles || !g_vol) return fail(PMF_EINVAL, "project_bwd: null pointer");
+    GridK g = make_grid(*grid);
+    if (vol_stride != 0 && vol_stride < grid_size(g))
+        return fail(PMF_EINVAL, "project_bwd: vol_stride must be 0 or >= N");
+    PMF_CHECK(check_ws(ws, ws_bytes, project_bwd_workspace(*cone, V)));
+    ConeK c = make_cone(*cone, g);
+    return hip_status(
+        launch_project_bwd(g_proj, g, c, angles, V, g_vol, vol_stride, ws, as_stream(stream)),
+        "project_bwd");
+}
+
+// -------------------------------------------------------------------- loss
+size_t pmf_l2_loss_workspace(int64_t npix, int V) {
+    if (npix < 1 || V < 1) return 0;
+    return l2_workspace(npix, V);
+}
+
+int pmf_l2_loss(const float *proj, const float *target, int64_t npix, int V, float *loss,
+                float *g_proj, void *ws, size_t ws_bytes, void *stream) {
+    if (npix < 1 || V < 1) return fail(PMF_EINVAL, "l2_loss: npix and V must be >= 1");
+    if (!proj || !target || !loss) return fail(PMF_EINVAL, "l2_loss: null pointer");
+    PMF_CHECK(check_ws(ws, ws_bytes, l2_workspace(npix, V)));
+    return hip_status(launch_l2(proj, target, npix, V, loss, g_proj, ws, as_stream(stream)),
+                      "l2_loss");
+}
+
+// ----------------------------------------------------------------- utility
+int pmf_accumulate(float *dst, const float *src, int64_t n, void *stream) {
+    if (n < 0) return fail(PMF_EINVAL, "accumulate: n < 0");
+    if (n > 0 && (!dst || !src)) return fail(PMF_EINVAL, "accumulate: null pointer");
+    return hip_status(launch_accumulate(dst, src, n, as_stream(stream)), "accumulate");
+}
+
+// --------------------------------------------------------------- profiling
+int pmf_profile(int enable) { return profile_enable(enable); }
+
+int pmf_profile_read(const char *kernel, double *total_ms, int64_t *count) {
+    if (!kernel || !total_ms || !count) return fail(PMF_EINVAL, "profile_read: null pointer");
+    if (profile_read(kernel, total_ms, count) != 0) return fail(PMF_EHIP, "profile_read: event error");
+    return ok();
+}
+
+size_t pmf_profile_names(char *buf, size_t len) { return profile_names(buf, len); }
+
+// ------------------------------------------------------ fused motion path
+size_t pmf_warp_project_workspace(int L, int B, const pmf_grid_t *lvl, int V,
+                                  const pmf_grid_t *grid, const pmf_cone_t *cone) {
+    (void)lvl;
+    if (L < 1 || L > MAXL || B < 1 || B > MAXB || V < 1 || !grid || !cone) return 0;
+    if (check_grid(grid, "grid") != PMF_OK) return 0;
+    GridK g = make_grid(*grid);
+    LevelsK lv{};
+    lv.L = L;
+    lv.B = B;
+    return warp_project_workspace(lv, V, g, *cone);
+}
+
+int pmf_warp_project(const float *ref, const pmf_grid_t *grid, int L, int B,
+                     const float *const *bases, const pmf_grid_t *lvl, const float *coeff, int V,
+                     const pmf_cone_t *cone, const float *angles, float *proj, void *ws,
+                     size_t ws_bytes, void *stream) {
+    PMF_CHECK(check_grid(grid, "grid"));
+    PMF_CHECK(check_levels(L, B, bases, lvl, "warp_project"));
+    PMF_CHECK(check_cone(cone, grid));
+    if (V < 1) return fail(PMF_EINVAL, "warp_project: V must be >= 1");
+    if (!ref || !coeff || !angles || !proj) return fail(PMF_EINVAL, "warp_project: null pointer");
+    GridK g = make_grid(*grid);
+    GridK lg[MAXL];
+    LevelsK lv = make_levels(L, B, bases, lvl, g, lg);
+    PMF_CHECK(check_ws(ws, ws_bytes, warp_project_workspace(lv, V, g, *cone)));
+    ConeK c = make_cone(*cone, g);
+    return hip_status(
+        launch_warp_project(ref, g, lv, coeff, V, c, angles, proj, ws, as_stream(stream)),
+        "warp_project");
+}
+
+size_t pmf_warp_project_bwd_workspace(int L, int B, const pmf_grid_t *lvl, int V,
+                                      const pmf_grid_t *grid, const pmf_cone_t *cone) {
+    if (L < 1 || L > MAXL || B < 1 || B > MAXB || V < 1 || !grid || !cone || !lvl) return 0;
+    if (check_grid(grid, "grid") != PMF_OK) return 0;
+    for (int l = 0; l < L; ++l)
+        if (check_grid(&lvl[l], "level grid") != PMF_OK) return 0;
+    GridK g = make_grid(*grid);
+    GridK lg[MAXL];
+    const float *dummy[MAXL] = {nullptr, nullptr, nullptr, nullptr};
+    LevelsK lv = make_levels(L, B, dummy, lvl, g, lg);
+    return warp_project_bwd_workspace(lv, lg, V, g, *cone);
+}
+
+int pmf_warp_project_bwd(const float *ref, const pmf_grid_t *grid, int L, int B,
+                         const float *const *bases, const pmf_grid_t *lvl, const float *coeff,
+                         int V, const pmf_cone_t *cone, const float *angles, const float *g_proj,
+                         float *g_ref, float *const *g_bases, float *g_coeff, void *ws,
+                         size_t ws_bytes, void *stream) {
+    PMF_CHECK(check_grid(grid, "grid"));
+    PMF_CHECK(check_levels(L, B, bases, lvl, "warp_project_bwd"));
+    PMF_CHECK(check_cone(cone, grid));
+    if (V < 1) return fail(PMF_EINVAL, "warp_project_bwd: V must be >= 1");
+    if (!ref || !coeff || !angles || !g_proj || !g_ref || !g_bases || !g_coeff)
+        return fail(PMF_EINVAL, "warp_project_bwd: null pointer");
+    for (int l = 0; l < L; ++l)
+        if (!g_bases[l]) return fail(PMF_EINVAL, "warp_project_bwd: null g_bases[%d]", l);
+    GridK g = make_grid(*grid);
+    GridK lg[MAXL];
+    LevelsK lv = make_levels(L, B, bases, lvl, g, lg);
+    PMF_CHECK(check_ws(ws, ws_bytes, warp_project_bwd_workspace(lv, lg, V, g, *cone)));
+    ConeK c = make_cone(*cone, g);
+    return hip_status(launch_warp_project_bwd(ref, g, lv, lg, coeff, V, c, angles, g_proj, g_ref,
+                                              g_bases, g_coeff, ws, as_stream(stream)),
+                      "warp_project_bwd");
+}
+
+}  // extern "C"

@@ -1,0 +1,345 @@
+// fused.hip -- the motion path of all views in one pass (batched form).
+//
+// Forward: one thread per voxel samples the L*B*3 basis values once, then for
+// every view forms the DVF in registers (Eq. 3) and warps the reference
+// volume (Eq. 2); only the warped volumes reach memory, and one launch
+// projects all of them.
+//
+// Adjoint: the back-projection of every view's residual (brick owner, LDS),
+// then one pass over the voxels that, for every view, recomputes the DVF,
+// takes the warp adjoint and the Eq. 3 adjoint in registers:
+//   - g_ref: added into an LDS copy of the brick plus a halo, flushed once
+//     for all views (global atomics only for the halo and for the rare
+//     displacement that leaves the halo);
+//   - dL/dE: sum over views of coeff * g_dvf, per voxel in registers; stored
+//     directly for a level on the output grid, otherwise handed to the
+//     separable upsampling transpose;
+//   - dL/dcoeff: per-view wave sums into LDS, then per-workgroup partials
+//     summed in block order.
+#include <math.h>
+
+#include "pmf_internal.h"
+
+namespace pmf {
+
+template <int L, int B>
+__global__ __launch_bounds__(256) void k_combine_warp(const float *__restrict__ ref, GridK g,
+                                                      LevelsK lv, const float *__restrict__ coeff,
+                                                      int V, float *__restrict__ warped) {
+    const int64_t N = grid_size(g);
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    const int iz = (int)(j % g.n[2]);
+    const int iy = (int)((j / g.n[2]) % g.n[1]);
+    const int ix = (int)(j / ((int64_t)g.n[2] * g.n[1]));
+    float sv[L][B][3];
+    basis_samples<L, B>(lv, ix, iy, iz, sv);
+    for (int v = 0; v < V; ++v) {
+        const float *cv = coeff + (int64_t)v * L * B * 3;
+        float d[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            float t = 0.0f;
+#pragma unroll
+            for (int l = 0; l < L; ++l)
+#pragma unroll
+                for (int b = 0; b < B; ++b) t = fmaf(cv[(l * B + b) * 3 + k], sv[l][b][k], t);
+            d[k] = t;
+        }
+        warped[(int64_t)v * N + j] =
+            sample_u(ref, g.n, fmaf(d[0], g.inv_h[0], (float)ix), fmaf(d[1], g.inv_h[1], (float)iy),
+                     fmaf(d[2], g.inv_h[2], (float)iz));
+    }
+}
+
+// Brick of the adjoint pass: 8x8x8 voxels, two per thread; LDS box with a
+// halo of HALO voxels on every side for the g_ref scatter.  Views are taken
+// in chunks of at most VCH per launch.
+constexpr int FB = 8;
+constexpr int HALO = 3;
+constexpr int HB = FB + 2 * HALO + 1;
+constexpr int VCH = 64;
+
+struct GOut {
+    float *dst[MAXL];   // per level: [3B][N] destination (g_bases or staging buffer)
+};
+
+template <int L, int B>
+__global__ __launch_bounds__(256) void k_warp_combine_bwd(
+    const float *__restrict__ ref, GridK g, LevelsK lv, const float *__restrict__ coeff, int V,
+    const float *__restrict__ g_I, float *__restrict__ g_ref, GOut gout, int accumulate, int nb1,
+    int nb2, float *__restrict__ partial) {
+    constexpr int NC = L * B * 3;
+    extern __shared__ float smem[];
+    float *box = smem;                  // HB^3
+    float *cacc = smem + HB * HB * HB;  // V * NC
+    for (int i = threadIdx.x; i < HB * HB * HB; i += blockDim.x) box[i] = 0.0f;
+    for (int i = threadIdx.x; i < V * NC; i += blockDim.x) cacc[i] = 0.0f;
+    const int bid = blockIdx.x;
+    const int b2 = bid % nb2, b1 = (bid / nb2) % nb1, b0 = bid / (nb2 * nb1);
+    const int B0 = b0 * FB, B1 = b1 * FB, B2 = b2 * FB;
+    const int64_t N = grid_size(g);
+    const int s1 = g.n[2], s0 = g.n[1] * g.n[2];
+
+    int vx[2], vy[2], vz[2];
+    bool ok[2];
+    int64_t jj[2];
+    float sv[2][L][B][3];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int t = threadIdx.x + q * 256;
+        vx[q] = B0 + t / (FB * FB);
+        vy[q] = B1 + (t / FB) % FB;
+        vz[q] = B2 + t % FB;
+        ok[q] = vx[q] < g.n[0] && vy[q] < g.n[1] && vz[q] < g.n[2];
+        jj[q] = ok[q] ? ((int64_t)vx[q] * g.n[1] + vy[q]) * g.n[2] + vz[q] : 0;
+        basis_samples<L, B>(lv, ok[q] ? vx[q] : 0, ok[q] ? vy[q] : 0, ok[q] ? vz[q] : 0, sv[q]);
+    }
+    float G[2][L][B][3];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int l = 0; l < L; ++l)
+#pragma unroll
+            for (int b = 0; b < B; ++b)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) G[q][l][b][k] = 0.0f;
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    for (int v = 0; v < V; ++v) {
+        const float *cv = coeff + (int64_t)v * L * B * 3;
+        float gD[2][3];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            gD[q][0] = gD[q][1] = gD[q][2] = 0.0f;
+            if (!ok[q]) continue;
+            float d[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                float t = 0.0f;
+#pragma unroll
+                for (int l = 0; l < L; ++l)
+#pragma unroll
+                    for (int b = 0; b < B; ++b) t = fmaf(cv[(l * B + b) * 3 + k], sv[q][l][b][k], t);
+                d[k] = t;
+            }
+            const float u0 = fmaf(d[0], g.inv_h[0], (float)vx[q]);
+            const float u1 = fmaf(d[1], g.inv_h[1], (float)vy[q]);
+            const float u2 = fmaf(d[2], g.inv_h[2], (float)vz[q]);
+            int i0, i1, i2;
+            float f0, f1, f2;
+            if (!axis_cell(u0, g.n[0], i0, f0) || !axis_cell(u1, g.n[1], i1, f1) ||
+                !axis_cell(u2, g.n[2], i2, f2))
+                continue;
+            const float go = g_I[(int64_t)v * N + jj[q]];
+            if (go == 0.0f) continue;
+            const int64_t base = ((int64_t)i0 * g.n[1] + i1) * g.n[2] + i2;
+            const float *p = ref + base;
+            const float c000 = p[0], c001 = p[1], c010 = p[s1], c011 = p[s1 + 1];
+            const float c100 = p[s0], c101 = p[s0 + 1], c110 = p[s0 + s1], c111 = p[s0 + s1 + 1];
+            const float a00 = lerp1(c000, c001, f2), a01 = lerp1(c010, c011, f2);
+            const float a10 = lerp1(c100, c101, f2), a11 = lerp1(c110, c111, f2);
+            const float ddx = lerp1(a10, a11, f1) - lerp1(a00, a01, f1);
+            const float ddy = lerp1(a01, a11, f0) - lerp1(a00, a10, f0);
+            const float e00 = lerp1(c000, c010, f1), e01 = lerp1(c001, c011, f1);
+            const float e10 = lerp1(c100, c110, f1), e11 = lerp1(c101, c111, f1);
+            const float ddz = lerp1(e01, e11, f0) - lerp1(e00, e10, f0);
+            gD[q][0] = go * ddx * g.inv_h[0] * axis_free(u0, g.n[0]);
+            gD[q][1] = go * ddy * g.inv_h[1] * axis_free(u1, g.n[1]);
+            gD[q][2] = go * ddz * g.inv_h[2] * axis_free(u2, g.n[2]);
+            const float w0[2] = {1.0f - f0, f0}, w1[2] = {1.0f - f1, f1}, w2[2] = {1.0f - f2, f2};
+            const int l0 = i0 - (B0 - HALO), l1 = i1 - (B1 - HALO), l2 = i2 - (B2 - HALO);
+            const bool inbox = l0 >= 0 && l0 + 1 < HB && l1 >= 0 && l1 + 1 < HB && l2 >= 0 &&
+                               l2 + 1 < HB;
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        const float w = go * w0[a] * w1[b] * w2[c];
+                        if (inbox)
+                            atomicAdd(&box[((l0 + a) * HB + (l1 + b)) * HB + (l2 + c)], w);
+                        else
+                            unsafeAtomicAdd(&g_ref[base + a * s0 + b * s1 + c], w);
+                    }
+        }
+#pragma unroll
+        for (int l = 0; l < L; ++l)
+#pragma unroll
+            for (int b = 0; b < B; ++b)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const float c = cv[(l * B + b) * 3 + k];
+                    G[0][l][b][k] = fmaf(c, gD[0][k], G[0][l][b][k]);
+                    G[1][l][b][k] = fmaf(c, gD[1][k], G[1][l][b][k]);
+                    const float t =
+                        warp_sum(fmaf(gD[0][k], sv[0][l][b][k], gD[1][k] * sv[1][l][b][k]));
+                    if (lane == 0) atomicAdd(&cacc[v * NC + (l * B + b) * 3 + k], t);
+                }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < HB * HB * HB; i += blockDim.x) {
+        const float val = box[i];
+        if (val == 0.0f) continue;
+        const int z = B2 - HALO + i % HB, y = B1 - HALO + (i / HB) % HB,
+                  x = B0 - HALO + i / (HB * HB);
+        if (x < 0 || y < 0 || z < 0 || x >= g.n[0] || y >= g.n[1] || z >= g.n[2]) continue;
+        unsafeAtomicAdd(&g_ref[((int64_t)x * g.n[1] + y) * g.n[2] + z], val);
+    }
+    for (int i = threadIdx.x; i < V * NC; i += blockDim.x)
+        partial[(int64_t)blockIdx.x * V * NC + i] = cacc[i];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        if (!ok[q]) continue;
+#pragma unroll
+        for (int l = 0; l < L; ++l)
+#pragma unroll
+            for (int b = 0; b < B; ++b)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    float *dst = gout.dst[l] + (int64_t)(b * 3 + k) * N + jj[q];
+                    *dst = accumulate ? *dst + G[q][l][b][k] : G[q][l][b][k];
+                }
+    }
+}
+
+// g_coeff[v0 + v][...] = sum over bricks of the per-brick partials, in brick order.
+__global__ void k_reduce_coeff_blocks(const float *__restrict__ partial, int nblk, int V, int NC,
+                                      float *__restrict__ g_coeff) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= V * NC) return;
+    float s = 0.0f;
+    for (int i = 0; i < nblk; ++i) s += partial[(int64_t)i * V * NC + t];
+    g_coeff[t] = s;
+}
+
+size_t warp_project_workspace(const LevelsK &lv, int V, const GridK &g, const pmf_cone_t &c) {
+    (void)lv;
+    (void)c;
+    return align256(sizeof(float) * (size_t)grid_size(g) * (size_t)V);
+}
+
+hipError_t launch_warp_project(const float *ref, const GridK &g, const LevelsK &lv,
+                               const float *coeff, int V, const ConeK &c, const float *angles,
+                               float *proj, void *ws, hipStream_t s) {
+    const int64_t N = grid_size(g);
+    float *warped = (float *)ws;
+    hipError_t e = dispatch_lb(lv.L, lv.B, [&](auto Lc, auto Bc) {
+        constexpr int L = decltype(Lc)::value, B = decltype(Bc)::value;
+        {
+            ProfScope prof_("combine_warp", s);
+            k_combine_warp<L, B><<<(unsigned)((N + 255) / 256), 256, 0, s>>>(ref, g, lv, coeff, V,
+                                                                              warped);
+        }
+        return hipGetLastError();
+    });
+    if (e != hipSuccess) return e;
+    return launch_project(warped, N, g, c, angles, V, proj, s);
+}
+
+struct BwdLayout {
+    size_t gI, rays, gbuf, partial, adj, total;
+    int nbrick, nb[3];
+};
+
+static BwdLayout bwd_layout(const LevelsK &lv, const GridK *lvl_grids, int V, const GridK &g,
+                            int nu, int nv) {
+    BwdLayout b;
+    const int64_t N = grid_size(g);
+    for (int a = 0; a < 3; ++a) b.nb[a] = (g.n[a] + FB - 1) / FB;
+    b.nbrick = b.nb[0] * b.nb[1] * b.nb[2];
+    size_t adj = 0;
+    int ncoarse = 0;
+    for (int l = 0; l < lv.L; ++l) {
+        const AxisMap &m = lv.map[l];
+        if (m.ident[0] && m.ident[1] && m.ident[2]) continue;
+        ++ncoarse;
+        size_t w = upsample_adjoint_workspace(3 * lv.B, lvl_grids[l], g, m);
+        if (w > adj) adj = w;
+    }
+    pmf_cone_t pc{};
+    pc.nu = nu;
+    pc.nv = nv;
+    const int vc = V < VCH ? V : VCH;
+    b.gI = align256(sizeof(float) * (size_t)N * V);
+    b.rays = project_bwd_workspace(pc, V);
+    b.gbuf = align256(sizeof(float) * (size_t)N * 3 * lv.B * (size_t)ncoarse);
+    b.partial = align256(sizeof(float) * (size_t)b.nbrick * vc * lv.L * lv.B * 3);
+    b.adj = adj;
+    b.total = b.gI + b.rays + b.gbuf + b.partial + b.adj;
+    return b;
+}
+
+size_t warp_project_bwd_workspace(const LevelsK &lv, const GridK *lvl_grids, int V, const GridK &g,
+                                  const pmf_cone_t &c) {
+    return bwd_layout(lv, lvl_grids, V, g, c.nu, c.nv).total;
+}
+
+hipError_t launch_warp_project_bwd(const float *ref, const GridK &g, const LevelsK &lv,
+                                   const GridK *lvl_grids, const float *coeff, int V,
+                                   const ConeK &c, const float *angles, const float *g_proj,
+                                   float *g_ref, float *const *g_bases, float *g_coeff, void *ws,
+                                   hipStream_t s) {
+    const BwdLayout lay = bwd_layout(lv, lvl_grids, V, g, c.nu, c.nv);
+    char *w = (char *)ws;
+    float *gI = (float *)w;
+    w += lay.gI;
+    void *rays = w;
+    w += lay.rays;
+    float *gbuf = (float *)w;
+    w += lay.gbuf;
+    float *partial = (float *)w;
+    w += lay.partial;
+    void *adjws = w;
+    const int64_t N = grid_size(g);
+    const int NC = lv.L * lv.B * 3;
+
+    hipError_t e = launch_project_bwd(g_proj, g, c, angles, V, gI, N, rays, s);
+    if (e != hipSuccess) return e;
+    if ((e = launch_fill(g_ref, N, 0.0f, s)) != hipSuccess) return e;
+    GOut gout;
+    const float *staged[MAXL] = {nullptr, nullptr, nullptr, nullptr};
+    int nst = 0;
+    for (int l = 0; l < MAXL; ++l) gout.dst[l] = nullptr;
+    for (int l = 0; l < lv.L; ++l) {
+        const AxisMap &m = lv.map[l];
+        if (m.ident[0] && m.ident[1] && m.ident[2]) {
+            gout.dst[l] = g_bases[l];
+        } else {
+            gout.dst[l] = gbuf + (int64_t)(nst++) * N * 3 * lv.B;
+            staged[l] = gout.dst[l];
+        }
+    }
+    for (int v0 = 0; v0 < V; v0 += VCH) {
+        const int vc = V - v0 < VCH ? V - v0 : VCH;
+        const size_t lds = sizeof(float) * ((size_t)HB * HB * HB + (size_t)vc * NC);
+        e = dispatch_lb(lv.L, lv.B, [&](auto Lc, auto Bc) {
+            constexpr int L = decltype(Lc)::value, B = decltype(Bc)::value;
+            {
+                ProfScope prof_("warp_combine_bwd", s);
+                k_warp_combine_bwd<L, B><<<(unsigned)lay.nbrick, 256, lds, s>>>(
+                    ref, g, lv, coeff + (int64_t)v0 * NC, vc, gI + (int64_t)v0 * N, g_ref, gout,
+                    v0 > 0, lay.nb[1], lay.nb[2], partial);
+            }
+            return hipGetLastError();
+        });
+        if (e != hipSuccess) return e;
+        {
+            ProfScope prof_("coeff_reduce", s);
+            k_reduce_coeff_blocks<<<(unsigned)((vc * NC + 255) / 256), 256, 0, s>>>(
+                partial, lay.nbrick, vc, NC, g_coeff + (int64_t)v0 * NC);
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    for (int l = 0; l < lv.L; ++l) {
+        if (!staged[l]) continue;
+        e = launch_upsample_adjoint(lv, l, lvl_grids[l], coeff, 1, g, nullptr, staged[l],
+                                    g_bases[l], adjws, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace pmf

@@ -1,0 +1,263 @@
+// pmf_internal.h -- shared definitions of the gfx950 kernels and the C-ABI layer.
+//
+// Kernel-side descriptions of grids and cone-beam geometry, the trilinear
+// stencil used by every step (warp, DVF upsampling, ray samples), the
+// per-ray set-up of the midpoint-rule line integral, and the declarations of
+// the host-side launchers implemented in the .hip files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pmf.h"
+
+namespace pmf {
+
+// ----------------------------------------------------------------- grids
+struct GridK {
+    int n[3];
+    float h[3];
+    float inv_h[3];
+    float c0[3];     // centre of voxel (0,0,0), float
+    double c0d[3];   // same, double (ray set-up)
+    double hd[3];
+};
+
+GridK make_grid(const pmf_grid_t &g);
+__host__ __device__ inline int64_t grid_size(const GridK &g) { return (int64_t)g.n[0] * g.n[1] * g.n[2]; }
+
+// Mapping of an output grid's voxel index onto a level grid's voxel units,
+// u_a = off_a + i_a * scale_a (float fma), identity when the grids coincide.
+struct AxisMap {
+    float scale[3];
+    float off[3];
+    int n[3];       // level grid size
+    int ident[3];   // 1 if the axis map is exactly the identity
+};
+AxisMap make_axis_map(const GridK &out, const GridK &lvl);
+
+// ------------------------------------------------------------- geometry
+struct ConeK {
+    double sad, sdd, du, dv, off_u, off_v;
+    double step;    // resolved step (mm)
+    int nu, nv;
+    double lo[3], hi[3];   // volume box
+};
+ConeK make_cone(const pmf_cone_t &c, const GridK &g);
+
+// Per-ray constants of the midpoint rule, in voxel units of the grid:
+// sample s sits at u = fma(s, su, bu) on each axis; n samples; step delta (mm).
+struct alignas(16) RayK {
+    float bu[3];
+    float delta;
+    float su[3];
+    int n;
+};
+
+// --------------------------------------------------------- device helpers
+#ifdef __HIPCC__
+// Trilinear coordinate on one axis: false if u is beyond the half-voxel rim
+// (or NaN); otherwise the clamped cell index i in [0, n-2] and fraction f.
+__device__ __forceinline__ bool axis_cell(float u, int n, int &i, float &f) {
+    if (!(u >= -0.5f && u <= (float)n - 0.5f)) return false;
+    float uc = fminf(fmaxf(u, 0.0f), (float)(n - 1));
+    int ii = (int)floorf(uc);
+    ii = ii < n - 2 ? ii : n - 2;
+    i = ii;
+    f = uc - (float)ii;
+    return true;
+}
+
+// Derivative switch: the interpolant moves with u only strictly inside the
+// voxel-centre hull.
+__device__ __forceinline__ float axis_free(float u, int n) {
+    return (u > 0.0f && u < (float)(n - 1)) ? 1.0f : 0.0f;
+}
+
+__device__ __forceinline__ float lerp1(float a, float b, float t) { return fmaf(t, b - a, a); }
+
+// Trilinear read at voxel-unit coordinate (u0,u1,u2); 0 outside the box.
+__device__ __forceinline__ float sample_u(const float *__restrict__ vol, const int n[3], float u0,
+                                          float u1, float u2) {
+    int i0, i1, i2;
+    float f0, f1, f2;
+    if (!axis_cell(u0, n[0], i0, f0) || !axis_cell(u1, n[1], i1, f1) ||
+        !axis_cell(u2, n[2], i2, f2))
+        return 0.0f;
+    const int s1 = n[2], s0 = n[1] * n[2];
+    const float *p = vol + ((i0 * n[1] + i1) * n[2] + i2);
+    float c00 = lerp1(p[0], p[1], f2);
+    float c01 = lerp1(p[s1], p[s1 + 1], f2);
+    float c10 = lerp1(p[s0], p[s0 + 1], f2);
+    float c11 = lerp1(p[s0 + s1], p[s0 + s1 + 1], f2);
+    return lerp1(lerp1(c00, c01, f1), lerp1(c10, c11, f1), f0);
+}
+
+__device__ __forceinline__ float warp_sum(float v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+#endif
+
+// ------------------------------------------------- basis upsampling helpers
+constexpr int MAXL = 4, MAXB = 4;
+struct LevelsK {
+    const float *E[MAXL];
+    AxisMap map[MAXL];
+    int L, B;
+};
+
+#ifdef __HIPCC__
+struct LevelStencil {
+    int base;
+    float f0, f1, f2;
+    int s0, s1;  // strides of axes 0 and 1 in the level grid
+    bool in;
+};
+
+__device__ __forceinline__ float level_coord(const AxisMap &m, int a, int i) {
+    return m.ident[a] ? (float)i : fmaf((float)i, m.scale[a], m.off[a]);
+}
+
+__device__ __forceinline__ LevelStencil level_stencil(const AxisMap &m, int ix, int iy, int iz) {
+    LevelStencil st;
+    int i0, i1, i2;
+    st.in = axis_cell(level_coord(m, 0, ix), m.n[0], i0, st.f0) &&
+            axis_cell(level_coord(m, 1, iy), m.n[1], i1, st.f1) &&
+            axis_cell(level_coord(m, 2, iz), m.n[2], i2, st.f2);
+    st.s1 = m.n[2];
+    st.s0 = m.n[1] * m.n[2];
+    st.base = st.in ? (i0 * m.n[1] + i1) * m.n[2] + i2 : 0;
+    return st;
+}
+
+__device__ __forceinline__ float stencil_read(const float *__restrict__ E, const LevelStencil &st) {
+    const float *p = E + st.base;
+    const int s0 = st.s0, s1 = st.s1;
+    float c00 = lerp1(p[0], p[1], st.f2);
+    float c01 = lerp1(p[s1], p[s1 + 1], st.f2);
+    float c10 = lerp1(p[s0], p[s0 + 1], st.f2);
+    float c11 = lerp1(p[s0 + s1], p[s0 + s1 + 1], st.f2);
+    return lerp1(lerp1(c00, c01, st.f1), lerp1(c10, c11, st.f1), st.f0);
+}
+
+// sv[l][b][k] = S(E_l[b*3+k], x_j) for the voxel (ix,iy,iz) of the output grid.
+template <int L, int B>
+__device__ __forceinline__ void basis_samples(const LevelsK &lv, int ix, int iy, int iz,
+                                              float sv[L][B][3]) {
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        const LevelStencil st = level_stencil(lv.map[l], ix, iy, iz);
+        const int64_t Nl = (int64_t)lv.map[l].n[0] * lv.map[l].n[1] * lv.map[l].n[2];
+#pragma unroll
+        for (int b = 0; b < B; ++b)
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                sv[l][b][k] = st.in ? stencil_read(lv.E[l] + (b * 3 + k) * Nl, st) : 0.0f;
+    }
+}
+#endif
+
+// Calls f(IC<L>{}, IC<B>{}) with compile-time level and basis counts.
+template <int V>
+struct IC {
+    static constexpr int value = V;
+};
+template <typename F>
+hipError_t dispatch_lb(int L, int B, F &&f) {
+#define PMF_LB(l, b) \
+    if (L == l && B == b) return f(IC<l>{}, IC<b>{});
+    PMF_LB(1, 1) PMF_LB(1, 2) PMF_LB(1, 3) PMF_LB(1, 4)
+    PMF_LB(2, 1) PMF_LB(2, 2) PMF_LB(2, 3) PMF_LB(2, 4)
+    PMF_LB(3, 1) PMF_LB(3, 2) PMF_LB(3, 3) PMF_LB(3, 4)
+    PMF_LB(4, 1) PMF_LB(4, 2) PMF_LB(4, 3) PMF_LB(4, 4)
+#undef PMF_LB
+    return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------- profiling
+// When enabled (pmf_profile), each kernel launch is bracketed by two HIP
+// events recorded on its stream; pmf_profile_read sums their elapsed times.
+struct ProfScope {
+    ProfScope(const char *name, hipStream_t s);
+    ~ProfScope();
+    const char *name;
+    hipStream_t stream;
+    hipEvent_t start, stop;
+    bool on;
+};
+
+int profile_enable(int on);
+int profile_read(const char *name, double *total_ms, int64_t *count);
+size_t profile_names(char *buf, size_t len);
+
+// ------------------------------------------------------------- launchers
+// Each returns hipSuccess or the launch error.  Arguments were validated.
+hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_accumulate(float *dst, const float *src, int64_t n, hipStream_t s);
+
+// voxelize
+struct VoxPlan {
+    int T[3];          // tile dims (voxels)
+    int nt[3];         // tiles per axis
+    int64_t ntiles;
+    int64_t cap;       // capacity of the (tile, gaussian) list
+    int maxtiles;      // Gaussians overlapping more tiles go to the large list
+};
+VoxPlan vox_plan(int64_t m, int c, const GridK &g);
+size_t vox_workspace(const VoxPlan &p, int64_t m);
+hipError_t launch_voxelize(const pmf_gauss_t &gs, const GridK &g, float k, float *vol,
+                           const VoxPlan &p, void *ws, hipStream_t s);
+hipError_t launch_voxelize_bwd(const pmf_gauss_t &gs, const GridK &g, float k, const float *g_vol,
+                               const pmf_gauss_grad_t &gr, hipStream_t s);
+
+// combine
+hipError_t launch_combine(const LevelsK &lv, const float *coeff, int V, const GridK &out, float *dvf,
+                          hipStream_t s);
+size_t combine_bwd_workspace(const LevelsK &lv, const GridK *lvl_grids, int V, const GridK &out);
+hipError_t launch_combine_bwd(const LevelsK &lv, const GridK *lvl_grids, const float *coeff, int V,
+                              const GridK &out, const float *g_dvf, float *const *g_bases,
+                              float *g_coeff, void *ws, hipStream_t s);
+// separable transpose of the upsampling of one level, from a full-grid
+// per-channel source G [C][N] (or from g_dvf/coeff when G is null)
+hipError_t launch_upsample_adjoint(const LevelsK &lv, int l, const GridK &lvl_grid,
+                                   const float *coeff, int V, const GridK &out, const float *g_dvf,
+                                   const float *G, float *g_base, void *ws, hipStream_t s);
+size_t upsample_adjoint_workspace(int C, const GridK &lvl_grid, const GridK &out, const AxisMap &m);
+
+// warp
+hipError_t launch_warp(const float *ref, const GridK &g, const float *dvf, int V, float *out,
+                       hipStream_t s);
+hipError_t launch_warp_bwd(const float *ref, const GridK &g, const float *dvf, int V,
+                           const float *g_out, float *g_ref, float *g_dvf, hipStream_t s);
+
+// projection
+hipError_t launch_project(const float *vol, int64_t stride, const GridK &g, const ConeK &c,
+                          const float *angles, int V, float *proj, hipStream_t s);
+size_t project_bwd_workspace(const pmf_cone_t &c, int V);
+hipError_t launch_project_bwd(const float *g_proj, const GridK &g, const ConeK &c,
+                              const float *angles, int V, float *g_vol, int64_t stride, void *ws,
+                              hipStream_t s);
+
+// loss
+size_t l2_workspace(int64_t npix, int V);
+hipError_t launch_l2(const float *proj, const float *target, int64_t npix, int V, float *loss,
+                     float *g, void *ws, hipStream_t s);
+
+// fused motion path
+size_t warp_project_workspace(const LevelsK &lv, int V, const GridK &g, const pmf_cone_t &c);
+hipError_t launch_warp_project(const float *ref, const GridK &g, const LevelsK &lv,
+                               const float *coeff, int V, const ConeK &c, const float *angles,
+                               float *proj, void *ws, hipStream_t s);
+size_t warp_project_bwd_workspace(const LevelsK &lv, const GridK *lvl_grids, int V, const GridK &g,
+                                  const pmf_cone_t &c);
+hipError_t launch_warp_project_bwd(const float *ref, const GridK &g, const LevelsK &lv,
+                                   const GridK *lvl_grids, const float *coeff, int V,
+                                   const ConeK &c, const float *angles, const float *g_proj,
+                                   float *g_ref, float *const *g_bases, float *g_coeff, void *ws,
+                                   hipStream_t s);
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace pmf

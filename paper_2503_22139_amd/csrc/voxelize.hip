@@ -1,0 +1,500 @@
+// voxelize.hip -- Eq. 5 (Gaussian voxelization) and its gradient.
+//
+// Forward: tile-binned splatting into LDS.  Each Gaussian's truncation
+// ellipsoid is bounded by a box of voxels; Gaussians are binned into the
+// tiles their box overlaps (count, scan, fill).  One workgroup owns a tile:
+// its waves take the tile's Gaussians one at a time (parameters wave-uniform,
+// held in scalar registers), evaluate them over box-and-tile in 4x4x4 voxel
+// chunks and add into an LDS copy of the tile; the tile is then stored once
+// with plain coalesced writes -- no global atomics.  Gaussians whose box
+// spans more tiles than the bin capacity (e.g. untruncated ones) go to a
+// separate list that is splatted with global atomics after the tiles.
+//
+// Backward: Gaussian owner.  One wave per Gaussian walks the same voxel box,
+// accumulates the per-Gaussian sums in registers and reduces them across the
+// wave; lane 0 applies the chain rule through Sigma = R diag(s^2) R^T and the
+// quaternion normalisation.
+#include <math.h>
+
+#include "pmf_internal.h"
+
+namespace pmf {
+
+struct alignas(16) GaussK {
+    float mu[3];
+    float a00;
+    float a01, a02, a11, a12;
+    float a22;
+    int lo0, lo1, lo2;
+    int hi0, hi1, hi2;
+    int pad0, pad1;
+};
+
+struct GaussFull {
+    float mu[3], s[3], qh[4], qn;
+    float R[3][3];
+    float A[3][3];
+    int lo[3], hi[3];
+};
+
+// Sigma^-1 = R diag(s^-2) R^T and the voxel box that holds the ellipsoid
+// m <= k^2 (half-extent k sqrt(Sigma_aa) per axis, widened by one voxel).
+__device__ __forceinline__ void gauss_full(const float *__restrict__ mean,
+                                           const float *__restrict__ scale,
+                                           const float *__restrict__ quat, int64_t i, float k,
+                                           const GridK &g, GaussFull &G) {
+    for (int a = 0; a < 3; ++a) {
+        G.mu[a] = mean[3 * i + a];
+        G.s[a] = scale[3 * i + a];
+    }
+    float q[4];
+    for (int c = 0; c < 4; ++c) q[c] = quat[4 * i + c];
+    const float qn = sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    G.qn = qn;
+    for (int c = 0; c < 4; ++c) G.qh[c] = q[c] / qn;
+    const float w = G.qh[0], x = G.qh[1], y = G.qh[2], z = G.qh[3];
+    G.R[0][0] = 1.0f - 2.0f * (y * y + z * z);
+    G.R[0][1] = 2.0f * (x * y - w * z);
+    G.R[0][2] = 2.0f * (x * z + w * y);
+    G.R[1][0] = 2.0f * (x * y + w * z);
+    G.R[1][1] = 1.0f - 2.0f * (x * x + z * z);
+    G.R[1][2] = 2.0f * (y * z - w * x);
+    G.R[2][0] = 2.0f * (x * z - w * y);
+    G.R[2][1] = 2.0f * (y * z + w * x);
+    G.R[2][2] = 1.0f - 2.0f * (x * x + y * y);
+    float is2[3], s2[3];
+    for (int c = 0; c < 3; ++c) {
+        s2[c] = G.s[c] * G.s[c];
+        is2[c] = 1.0f / s2[c];
+    }
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            G.A[a][b] = G.R[a][0] * G.R[b][0] * is2[0] + G.R[a][1] * G.R[b][1] * is2[1] +
+                        G.R[a][2] * G.R[b][2] * is2[2];
+    for (int a = 0; a < 3; ++a) {
+        if (isinf(k)) {
+            G.lo[a] = 0;
+            G.hi[a] = g.n[a] - 1;
+            continue;
+        }
+        const float var = G.R[a][0] * G.R[a][0] * s2[0] + G.R[a][1] * G.R[a][1] * s2[1] +
+                          G.R[a][2] * G.R[a][2] * s2[2];
+        const float ext = k * sqrtf(var);
+        float l = floorf((G.mu[a] - ext - g.c0[a]) * g.inv_h[a]) - 1.0f;
+        float u = ceilf((G.mu[a] + ext - g.c0[a]) * g.inv_h[a]) + 1.0f;
+        l = fmaxf(l, 0.0f);
+        u = fminf(u, (float)(g.n[a] - 1));
+        if (!(l <= u)) {  // outside the grid (or NaN): empty box
+            G.lo[a] = 1;
+            G.hi[a] = 0;
+        } else {
+            G.lo[a] = (int)l;
+            G.hi[a] = (int)u;
+        }
+    }
+}
+
+__device__ __forceinline__ float quad(const GaussK &p, float d0, float d1, float d2) {
+    const float t0 = fmaf(p.a00, d0, fmaf(p.a01, d1, p.a02 * d2));
+    const float t1 = fmaf(p.a01, d0, fmaf(p.a11, d1, p.a12 * d2));
+    const float t2 = fmaf(p.a02, d0, fmaf(p.a12, d1, p.a22 * d2));
+    return fmaf(d0, t0, fmaf(d1, t1, d2 * t2));
+}
+
+// ---------------------------------------------------------------- binning
+__global__ __launch_bounds__(256) void k_vox_prep(pmf_gauss_t gs, GridK g, float k, int T0,
+                                                  int T1, int T2, int nt1, int nt2, int maxtiles,
+                                                  GaussK *__restrict__ rec,
+                                                  int32_t *__restrict__ tile_count,
+                                                  int32_t *__restrict__ large,
+                                                  int32_t *__restrict__ nlarge) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= gs.m) return;
+    GaussFull G;
+    gauss_full(gs.mean, gs.scale, gs.quat, i, k, g, G);
+    GaussK r;
+    for (int a = 0; a < 3; ++a) r.mu[a] = G.mu[a];
+    r.a00 = G.A[0][0];
+    r.a01 = G.A[0][1];
+    r.a02 = G.A[0][2];
+    r.a11 = G.A[1][1];
+    r.a12 = G.A[1][2];
+    r.a22 = G.A[2][2];
+    r.lo0 = G.lo[0];
+    r.lo1 = G.lo[1];
+    r.lo2 = G.lo[2];
+    r.hi0 = G.hi[0];
+    r.hi1 = G.hi[1];
+    r.hi2 = G.hi[2];
+    r.pad0 = r.pad1 = 0;
+    rec[i] = r;
+    if (G.lo[0] > G.hi[0] || G.lo[1] > G.hi[1] || G.lo[2] > G.hi[2]) return;
+    const int t0a = G.lo[0] / T0, t0b = G.hi[0] / T0;
+    const int t1a = G.lo[1] / T1, t1b = G.hi[1] / T1;
+    const int t2a = G.lo[2] / T2, t2b = G.hi[2] / T2;
+    const int64_t cnt = (int64_t)(t0b - t0a + 1) * (t1b - t1a + 1) * (t2b - t2a + 1);
+    if (cnt > maxtiles) {
+        large[atomicAdd(nlarge, 1)] = (int32_t)i;
+        return;
+    }
+    for (int a = t0a; a <= t0b; ++a)
+        for (int b = t1a; b <= t1b; ++b)
+            for (int c = t2a; c <= t2b; ++c) atomicAdd(&tile_count[(a * nt1 + b) * nt2 + c], 1);
+}
+
+// Exclusive scan of n counts by one workgroup of 1024 threads: off[0..n],
+// and cursor[] = off[] for the fill pass.
+__global__ __launch_bounds__(1024) void k_scan(const int32_t *__restrict__ cnt, int64_t n,
+                                               int32_t *__restrict__ off,
+                                               int32_t *__restrict__ cursor) {
+    __shared__ int32_t part[1024];
+    const int64_t per = (n + 1023) / 1024;
+    const int64_t b = threadIdx.x * per;
+    const int64_t e = b + per < n ? b + per : n;
+    int32_t s = 0;
+    for (int64_t i = b; i < e; ++i) s += cnt[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        int32_t t = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0;
+        __syncthreads();
+        part[threadIdx.x] += t;
+        __syncthreads();
+    }
+    int32_t run = part[threadIdx.x] - s;
+    for (int64_t i = b; i < e; ++i) {
+        off[i] = run;
+        cursor[i] = run;
+        run += cnt[i];
+    }
+    if (threadIdx.x == 1023) off[n] = part[1023];
+}
+
+__global__ __launch_bounds__(256) void k_vox_fill(int64_t m, const GaussK *__restrict__ rec,
+                                                  int T0, int T1, int T2, int nt1, int nt2,
+                                                  int maxtiles, int32_t *__restrict__ cursor,
+                                                  int32_t *__restrict__ list) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const GaussK r = rec[i];
+    if (r.lo0 > r.hi0 || r.lo1 > r.hi1 || r.lo2 > r.hi2) return;
+    const int t0a = r.lo0 / T0, t0b = r.hi0 / T0;
+    const int t1a = r.lo1 / T1, t1b = r.hi1 / T1;
+    const int t2a = r.lo2 / T2, t2b = r.hi2 / T2;
+    const int64_t cnt = (int64_t)(t0b - t0a + 1) * (t1b - t1a + 1) * (t2b - t2a + 1);
+    if (cnt > maxtiles) return;
+    for (int a = t0a; a <= t0b; ++a)
+        for (int b = t1a; b <= t1b; ++b)
+            for (int c = t2a; c <= t2b; ++c)
+                list[atomicAdd(&cursor[(a * nt1 + b) * nt2 + c], 1)] = (int32_t)i;
+}
+
+// ------------------------------------------------------------ tile splat
+// Evaluate Gaussian `gi` over the voxel box [lo, hi] (inclusive) in 4x4x4
+// chunks; call add(local index fn) for each in-mask voxel.
+template <typename Add>
+__device__ __forceinline__ void splat_box(const GaussK &p, const GridK &g, float k2, int lo0,
+                                          int lo1, int lo2, int hi0, int hi1, int hi2, Add add) {
+    const int lane = threadIdx.x & 63;
+    const int lx = lane >> 4, ly = (lane >> 2) & 3, lz = lane & 3;
+    for (int cx = lo0; cx <= hi0; cx += 4) {
+        const int ix = cx + lx;
+        const float d0 = fmaf((float)ix, g.h[0], g.c0[0]) - p.mu[0];
+        for (int cy = lo1; cy <= hi1; cy += 4) {
+            const int iy = cy + ly;
+            const float d1 = fmaf((float)iy, g.h[1], g.c0[1]) - p.mu[1];
+            for (int cz = lo2; cz <= hi2; cz += 4) {
+                const int iz = cz + lz;
+                if (ix > hi0 || iy > hi1 || iz > hi2) continue;
+                const float d2 = fmaf((float)iz, g.h[2], g.c0[2]) - p.mu[2];
+                const float mm = quad(p, d0, d1, d2);
+                if (!(mm <= k2)) continue;
+                add(ix, iy, iz, __expf(-0.5f * mm));
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_vox_tile(const GaussK *__restrict__ rec,
+                                                  const float *__restrict__ value, int C, GridK g,
+                                                  float k2, int T0, int T1, int T2, int nt1,
+                                                  int nt2, const int32_t *__restrict__ off,
+                                                  const int32_t *__restrict__ list,
+                                                  float *__restrict__ vol) {
+    extern __shared__ float acc[];
+    const int tvox = T0 * T1 * T2;
+    for (int i = threadIdx.x; i < C * tvox; i += blockDim.x) acc[i] = 0.0f;
+    const int t = blockIdx.x;
+    const int tz = t % nt2, ty = (t / nt2) % nt1, tx = t / (nt2 * nt1);
+    const int b0 = tx * T0, b1 = ty * T1, b2 = tz * T2;
+    const int e0 = min(b0 + T0, g.n[0]) - 1, e1 = min(b1 + T1, g.n[1]) - 1,
+              e2 = min(b2 + T2, g.n[2]) - 1;
+    __syncthreads();
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nw = blockDim.x >> 6;
+    const int beg = off[t], end = off[t + 1];
+    for (int e = beg + wave; e < end; e += nw) {
+        const int gi = __builtin_amdgcn_readfirstlane(list[e]);
+        const GaussK p = rec[gi];
+        const int lo0 = max(p.lo0, b0), lo1 = max(p.lo1, b1), lo2 = max(p.lo2, b2);
+        const int hi0 = min(p.hi0, e0), hi1 = min(p.hi1, e1), hi2 = min(p.hi2, e2);
+        if (lo0 > hi0 || lo1 > hi1 || lo2 > hi2) continue;
+        const float *vv = value + (int64_t)gi * C;
+        splat_box(p, g, k2, lo0, lo1, lo2, hi0, hi1, hi2, [&](int ix, int iy, int iz, float ev) {
+            const int li = ((ix - b0) * T1 + (iy - b1)) * T2 + (iz - b2);
+            for (int c = 0; c < C; ++c) atomicAdd(&acc[c * tvox + li], vv[c] * ev);
+        });
+    }
+    __syncthreads();
+    const int64_t N = grid_size(g);
+    for (int i = threadIdx.x; i < C * tvox; i += blockDim.x) {
+        const int c = i / tvox, li = i % tvox;
+        const int z = li % T2, y = (li / T2) % T1, x = li / (T2 * T1);
+        const int gx = b0 + x, gy = b1 + y, gz = b2 + z;
+        if (gx < g.n[0] && gy < g.n[1] && gz < g.n[2])
+            vol[(int64_t)c * N + ((int64_t)gx * g.n[1] + gy) * g.n[2] + gz] = acc[i];
+    }
+}
+
+// Gaussians too large for the bins: one wave each, global atomics.
+__global__ __launch_bounds__(256) void k_vox_large(const GaussK *__restrict__ rec,
+                                                   const float *__restrict__ value, int C,
+                                                   GridK g, float k2,
+                                                   const int32_t *__restrict__ large,
+                                                   const int32_t *__restrict__ nlarge,
+                                                   float *__restrict__ vol) {
+    const int64_t N = grid_size(g);
+    const int nl = *nlarge;
+    const int gw = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int nwaves = gridDim.x * (blockDim.x >> 6);
+    for (int e = __builtin_amdgcn_readfirstlane(gw); e < nl; e += nwaves) {
+        const int gi = __builtin_amdgcn_readfirstlane(large[e]);
+        const GaussK p = rec[gi];
+        if (p.lo0 > p.hi0 || p.lo1 > p.hi1 || p.lo2 > p.hi2) continue;
+        const float *vv = value + (int64_t)gi * C;
+        splat_box(p, g, k2, p.lo0, p.lo1, p.lo2, p.hi0, p.hi1, p.hi2,
+                  [&](int ix, int iy, int iz, float ev) {
+                      const int64_t j = ((int64_t)ix * g.n[1] + iy) * g.n[2] + iz;
+                      for (int c = 0; c < C; ++c) unsafeAtomicAdd(&vol[c * N + j], vv[c] * ev);
+                  });
+    }
+}
+
+VoxPlan vox_plan(int64_t m, int c, const GridK &g) {
+    VoxPlan p;
+    int T[3];
+    if (c <= 1) {
+        T[0] = 16; T[1] = 16; T[2] = 16;
+    } else if (c <= 4) {
+        T[0] = 8; T[1] = 16; T[2] = 16;
+    } else if (c <= 9) {
+        T[0] = 8; T[1] = 8; T[2] = 16;
+    } else {
+        T[0] = 8; T[1] = 8; T[2] = 8;
+    }
+    p.ntiles = 1;
+    for (int a = 0; a < 3; ++a) {
+        p.T[a] = T[a];
+        p.nt[a] = (g.n[a] + T[a] - 1) / T[a];
+        p.ntiles *= p.nt[a];
+    }
+    p.maxtiles = 32;
+    p.cap = m * p.maxtiles;
+    return p;
+}
+
+size_t vox_workspace(const VoxPlan &p, int64_t m) {
+    size_t s = 0;
+    s += align256(sizeof(GaussK) * (size_t)(m > 0 ? m : 1));  // records
+    s += align256(sizeof(int32_t) * (size_t)p.ntiles);        // counts
+    s += align256(sizeof(int32_t) * (size_t)(p.ntiles + 1));  // offsets
+    s += align256(sizeof(int32_t) * (size_t)p.ntiles);        // cursors
+    s += align256(sizeof(int32_t) * (size_t)(p.cap > 0 ? p.cap : 1));  // list
+    s += align256(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));  // large list
+    s += align256(sizeof(int32_t));                            // large count
+    return s;
+}
+
+hipError_t launch_voxelize(const pmf_gauss_t &gs, const GridK &g, float k, float *vol,
+                           const VoxPlan &p, void *ws, hipStream_t s) {
+    char *w = (char *)ws;
+    const int64_t m = gs.m;
+    GaussK *rec = (GaussK *)w;
+    w += align256(sizeof(GaussK) * (size_t)(m > 0 ? m : 1));
+    int32_t *cnt = (int32_t *)w;
+    w += align256(sizeof(int32_t) * (size_t)p.ntiles);
+    int32_t *off = (int32_t *)w;
+    w += align256(sizeof(int32_t) * (size_t)(p.ntiles + 1));
+    int32_t *cur = (int32_t *)w;
+    w += align256(sizeof(int32_t) * (size_t)p.ntiles);
+    int32_t *list = (int32_t *)w;
+    w += align256(sizeof(int32_t) * (size_t)(p.cap > 0 ? p.cap : 1));
+    int32_t *large = (int32_t *)w;
+    w += align256(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+    int32_t *nlarge = (int32_t *)w;
+
+    const float k2 = isinf(k) ? INFINITY : k * k;
+    hipError_t e = launch_fill_i32(cnt, p.ntiles, 0, s);
+    if (e != hipSuccess) return e;
+    e = launch_fill_i32(nlarge, 1, 0, s);
+    if (e != hipSuccess) return e;
+    if (m > 0) {
+        {
+            ProfScope prof_("voxelize_prep", s);
+            k_vox_prep<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(
+                gs, g, k, p.T[0], p.T[1], p.T[2], p.nt[1], p.nt[2], p.maxtiles, rec, cnt, large, nlarge);
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    {
+        ProfScope prof_("voxelize_scan", s);
+        k_scan<<<1, 1024, 0, s>>>(cnt, p.ntiles, off, cur);
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (m > 0) {
+        {
+            ProfScope prof_("voxelize_fill", s);
+            k_vox_fill<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(m, rec, p.T[0], p.T[1], p.T[2],
+                                                                  p.nt[1], p.nt[2], p.maxtiles, cur,
+                                                                  list);
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    const size_t lds = sizeof(float) * (size_t)gs.c * p.T[0] * p.T[1] * p.T[2];
+    {
+        ProfScope prof_("voxelize_tile", s);
+        k_vox_tile<<<(unsigned)p.ntiles, 256, lds, s>>>(rec, gs.value, gs.c, g, k2, p.T[0], p.T[1],
+                                                        p.T[2], p.nt[1], p.nt[2], off, list, vol);
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (m > 0) {
+        int64_t nb = (m + 3) / 4;
+        if (nb > 2048) nb = 2048;
+        {
+            ProfScope prof_("voxelize_large", s);
+            k_vox_large<<<(unsigned)nb, 256, 0, s>>>(rec, gs.value, gs.c, g, k2, large, nlarge, vol);
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// ------------------------------------------------------------- backward
+constexpr int MAXC = 16;
+
+__global__ __launch_bounds__(256) void k_vox_bwd(pmf_gauss_t gs, GridK g, float k,
+                                                 const float *__restrict__ g_vol,
+                                                 pmf_gauss_grad_t gr) {
+    const int64_t gi = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (gi >= gs.m) return;
+    const int lane = threadIdx.x & 63;
+    const int C = gs.c;
+    GaussFull G;
+    gauss_full(gs.mean, gs.scale, gs.quat, gi, k, g, G);
+    GaussK p;
+    for (int a = 0; a < 3; ++a) p.mu[a] = G.mu[a];
+    p.a00 = G.A[0][0];
+    p.a01 = G.A[0][1];
+    p.a02 = G.A[0][2];
+    p.a11 = G.A[1][1];
+    p.a12 = G.A[1][2];
+    p.a22 = G.A[2][2];
+    const float k2 = isinf(k) ? INFINITY : k * k;
+    const float *vv = gs.value + gi * C;
+    float val[MAXC];
+#pragma unroll
+    for (int c = 0; c < MAXC; ++c) val[c] = c < C ? vv[c] : 0.0f;
+    float gv[MAXC];
+#pragma unroll
+    for (int c = 0; c < MAXC; ++c) gv[c] = 0.0f;
+    float gm0 = 0, gm1 = 0, gm2 = 0;
+    float M00 = 0, M01 = 0, M02 = 0, M11 = 0, M12 = 0, M22 = 0;
+    const int64_t N = grid_size(g);
+    if (G.lo[0] <= G.hi[0] && G.lo[1] <= G.hi[1] && G.lo[2] <= G.hi[2]) {
+        splat_box(p, g, k2, G.lo[0], G.lo[1], G.lo[2], G.hi[0], G.hi[1], G.hi[2],
+                  [&](int ix, int iy, int iz, float ev) {
+                      const int64_t j = ((int64_t)ix * g.n[1] + iy) * g.n[2] + iz;
+                      float Gj = 0.0f;
+#pragma unroll
+                      for (int c = 0; c < MAXC; ++c) {
+                          if (c < C) {
+                              const float gc = g_vol[c * N + j];
+                              gv[c] = fmaf(gc, ev, gv[c]);
+                              Gj = fmaf(val[c], gc, Gj);
+                          }
+                      }
+                      const float t = Gj * ev;
+                      const float d0 = fmaf((float)ix, g.h[0], g.c0[0]) - p.mu[0];
+                      const float d1 = fmaf((float)iy, g.h[1], g.c0[1]) - p.mu[1];
+                      const float d2 = fmaf((float)iz, g.h[2], g.c0[2]) - p.mu[2];
+                      const float A0 = fmaf(p.a00, d0, fmaf(p.a01, d1, p.a02 * d2));
+                      const float A1 = fmaf(p.a01, d0, fmaf(p.a11, d1, p.a12 * d2));
+                      const float A2 = fmaf(p.a02, d0, fmaf(p.a12, d1, p.a22 * d2));
+                      gm0 = fmaf(t, A0, gm0);
+                      gm1 = fmaf(t, A1, gm1);
+                      gm2 = fmaf(t, A2, gm2);
+                      const float ht = -0.5f * t;
+                      M00 = fmaf(ht * d0, d0, M00);
+                      M01 = fmaf(ht * d0, d1, M01);
+                      M02 = fmaf(ht * d0, d2, M02);
+                      M11 = fmaf(ht * d1, d1, M11);
+                      M12 = fmaf(ht * d1, d2, M12);
+                      M22 = fmaf(ht * d2, d2, M22);
+                  });
+    }
+#pragma unroll
+    for (int c = 0; c < MAXC; ++c)
+        if (c < C) gv[c] = warp_sum(gv[c]);
+    gm0 = warp_sum(gm0);
+    gm1 = warp_sum(gm1);
+    gm2 = warp_sum(gm2);
+    M00 = warp_sum(M00);
+    M01 = warp_sum(M01);
+    M02 = warp_sum(M02);
+    M11 = warp_sum(M11);
+    M12 = warp_sum(M12);
+    M22 = warp_sum(M22);
+    if (lane != 0) return;
+#pragma unroll
+    for (int c = 0; c < MAXC; ++c)
+        if (c < C) gr.value[gi * C + c] = gv[c];
+    gr.mean[3 * gi + 0] = gm0;
+    gr.mean[3 * gi + 1] = gm1;
+    gr.mean[3 * gi + 2] = gm2;
+    const float M[3][3] = {{M00, M01, M02}, {M01, M11, M12}, {M02, M12, M22}};
+    float MR[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            MR[a][b] = M[a][0] * G.R[0][b] + M[a][1] * G.R[1][b] + M[a][2] * G.R[2][b];
+    for (int kk = 0; kk < 3; ++kk) {
+        const float d = G.R[0][kk] * MR[0][kk] + G.R[1][kk] * MR[1][kk] + G.R[2][kk] * MR[2][kk];
+        gr.scale[3 * gi + kk] = -2.0f * d / (G.s[kk] * G.s[kk] * G.s[kk]);
+    }
+    float GR[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) GR[a][b] = 2.0f * MR[a][b] / (G.s[b] * G.s[b]);
+    const float w = G.qh[0], x = G.qh[1], y = G.qh[2], z = G.qh[3];
+    float gq[4];
+    gq[0] = 2.0f * (-z * GR[0][1] + y * GR[0][2] + z * GR[1][0] - x * GR[1][2] - y * GR[2][0] +
+                    x * GR[2][1]);
+    gq[1] = 2.0f * (y * GR[0][1] + z * GR[0][2] + y * GR[1][0] - 2.0f * x * GR[1][1] -
+                    w * GR[1][2] + z * GR[2][0] + w * GR[2][1] - 2.0f * x * GR[2][2]);
+    gq[2] = 2.0f * (-2.0f * y * GR[0][0] + x * GR[0][1] + w * GR[0][2] + x * GR[1][0] +
+                    z * GR[1][2] - w * GR[2][0] + z * GR[2][1] - 2.0f * y * GR[2][2]);
+    gq[3] = 2.0f * (-2.0f * z * GR[0][0] - w * GR[0][1] + x * GR[0][2] + w * GR[1][0] -
+                    2.0f * z * GR[1][1] + y * GR[1][2] + x * GR[2][0] + y * GR[2][1]);
+    const float dot = gq[0] * w + gq[1] * x + gq[2] * y + gq[3] * z;
+    for (int c = 0; c < 4; ++c) gr.quat[4 * gi + c] = (gq[c] - G.qh[c] * dot) / G.qn;
+}
+
+hipError_t launch_voxelize_bwd(const pmf_gauss_t &gs, const GridK &g, float k, const float *g_vol,
+                               const pmf_gauss_grad_t &gr, hipStream_t s) {
+    if (gs.m <= 0) return hipSuccess;
+    {
+        ProfScope prof_("voxelize_bwd", s);
+        k_vox_bwd<<<(unsigned)((gs.m + 3) / 4), 256, 0, s>>>(gs, g, k, g_vol, gr);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace pmf

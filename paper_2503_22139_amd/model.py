@@ -1,0 +1,131 @@
+"""One fwd+bwd iteration of the motion path, in two schedules.
+
+``MotionModel`` holds the device copies of a workload's parameters (reference
+Gaussians, MBC Gaussians per level, per-view temporal coefficients, view
+angles) and runs the Stage 2/3 forward model of Sec. 2.3.2 with an L2
+projection loss:
+
+  plain   -- one view at a time, as a per-view projector would be driven:
+             combine (Eq. 3), warp (Eq. 2) and project (Eq. 6) for view v,
+             then the adjoints of view v in reverse, per-view DVFs kept.
+  batched -- all views at once: the fused motion path (DVFs never stored,
+             bases read once) and its fused adjoint.
+
+Both return the same loss and gradients (up to float32 summation order).
+Every step is a libpmf.so call; Python only orders the calls.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Dict, List, Optional
+
+import numpy as np
+import torch
+
+from . import ops
+from .synth import GaussSet, Workload
+
+
+@dataclasses.dataclass
+class GaussT:
+    mean: torch.Tensor
+    scale: torch.Tensor
+    quat: torch.Tensor
+    value: torch.Tensor
+
+    @staticmethod
+    def from_set(s: GaussSet, device) -> "GaussT":
+        f = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(device)
+        return GaussT(f(s.mean), f(s.scale), f(s.quat), f(s.value))
+
+
+class MotionModel:
+    def __init__(self, w: Workload, device="cuda"):
+        self.w = w
+        self.device = torch.device(device)
+        self.grid = w.grid
+        self.cone = w.cone
+        self.levels = list(w.levels)
+        self.k = float(w.trunc_k)
+        self.ref = GaussT.from_set(w.ref, self.device)
+        self.mbc = [GaussT.from_set(s, self.device) for s in w.mbc]
+        self.coeff = torch.from_numpy(np.ascontiguousarray(w.coeff, np.float32)).to(self.device)
+        self.angles = torch.from_numpy(np.ascontiguousarray(w.angles, np.float32)).to(self.device)
+        self.V = int(self.angles.numel())
+
+    # ------------------------------------------------------------ volumes
+    def volumes(self):
+        ref = ops.pmf_voxelize(self.ref.mean, self.ref.scale, self.ref.quat, self.ref.value,
+                               self.grid, self.k)[0]
+        bases = [ops.pmf_voxelize(g.mean, g.scale, g.quat, g.value, lg, self.k)
+                 for g, lg in zip(self.mbc, self.levels)]
+        return ref, bases
+
+    def volumes_bwd(self, g_ref, g_bases) -> Dict[str, object]:
+        r = ops.pmf_voxelize_bwd(self.ref.mean, self.ref.scale, self.ref.quat, self.ref.value,
+                                 self.grid, self.k, g_ref.reshape(1, -1))
+        out = {"ref": dict(zip(("mean", "scale", "quat", "value"), r)), "mbc": []}
+        for g, lg, gb in zip(self.mbc, self.levels, g_bases):
+            r = ops.pmf_voxelize_bwd(g.mean, g.scale, g.quat, g.value, lg, self.k, gb)
+            out["mbc"].append(dict(zip(("mean", "scale", "quat", "value"), r)))
+        return out
+
+    # ------------------------------------------------------------ forward
+    def forward_plain(self, ref=None, bases=None):
+        if ref is None:
+            ref, bases = self.volumes()
+        proj = torch.empty((self.V, self.cone.nv, self.cone.nu), device=self.device)
+        for v in range(self.V):
+            dvf = ops.pmf_combine_dvf(bases, self.levels, self.coeff[v:v + 1], self.grid)
+            wv = ops.pmf_warp(ref, self.grid, dvf)
+            ops.pmf_project(wv, self.grid, self.cone, self.angles[v:v + 1], shared=False,
+                            out=proj[v:v + 1])
+        return proj
+
+    def forward_batched(self, ref=None, bases=None):
+        if ref is None:
+            ref, bases = self.volumes()
+        return ops.pmf_warp_project(ref, self.grid, bases, self.levels, self.coeff, self.cone,
+                                    self.angles)
+
+    # ------------------------------------------------------- fwd + bwd
+    def step_plain(self, target):
+        """One iteration, one view at a time (per-view DVFs kept for the backward)."""
+        ref, bases = self.volumes()
+        proj = torch.empty((self.V, self.cone.nv, self.cone.nu), device=self.device)
+        dvfs = []
+        for v in range(self.V):
+            dvf = ops.pmf_combine_dvf(bases, self.levels, self.coeff[v:v + 1], self.grid)
+            wv = ops.pmf_warp(ref, self.grid, dvf)
+            ops.pmf_project(wv, self.grid, self.cone, self.angles[v:v + 1], shared=False,
+                            out=proj[v:v + 1])
+            dvfs.append(dvf)
+        loss, g_proj = ops.pmf_l2_loss(proj, target)
+        g_ref, g_bases = None, None
+        g_coeff = torch.empty_like(self.coeff)
+        for v in reversed(range(self.V)):
+            g_wv = ops.pmf_project_bwd(g_proj[v:v + 1], self.grid, self.cone, self.angles[v:v + 1])
+            gr, gd = ops.pmf_warp_bwd(ref, self.grid, dvfs[v], g_wv)
+            gb, _ = ops.pmf_combine_dvf_bwd(bases, self.levels, self.coeff[v:v + 1], self.grid, gd,
+                                            g_coeff_out=g_coeff[v:v + 1])
+            if g_ref is None:
+                g_ref, g_bases = gr, gb
+            else:
+                ops.pmf_accumulate(g_ref, gr)
+                for a, b in zip(g_bases, gb):
+                    ops.pmf_accumulate(a, b)
+        grads = self.volumes_bwd(g_ref, g_bases)
+        grads["coeff"] = g_coeff
+        return loss, grads
+
+    def step_batched(self, target):
+        """One iteration with the fused motion path (no stored DVFs or warped volumes)."""
+        ref, bases = self.volumes()
+        proj = ops.pmf_warp_project(ref, self.grid, bases, self.levels, self.coeff, self.cone,
+                                    self.angles)
+        loss, g_proj = ops.pmf_l2_loss(proj, target)
+        g_ref, g_bases, g_coeff = ops.pmf_warp_project_bwd(ref, self.grid, bases, self.levels,
+                                                           self.coeff, self.cone, self.angles, g_proj)
+        grads = self.volumes_bwd(g_ref, g_bases)
+        grads["coeff"] = g_coeff
+        return loss, grads

@@ -1,0 +1,438 @@
+"""Python binding of libpmf.so: argument marshalling only.
+
+Each ``pmf_*`` function here has the name and meaning of the C entry point in
+``include/pmf.h``; tensors are CUDA (HIP) float32 tensors whose device
+pointers are handed to the library together with torch's current stream.
+Nothing is computed in Python: if the library is missing this module raises.
+
+Autograd wrappers (``Voxelize``, ``CombineDVF``, ``Warp``, ``Project``,
+``WarpProject``) call the forward entry point in ``forward`` and the adjoint
+entry point in ``backward``; they save inputs only, never intermediate
+volumes (``WarpProject`` recomputes every view's DVF in its backward).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from typing import List, Optional, Sequence, Tuple
+
+import torch
+
+from .synth import Cone, Grid
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpmf.so")
+
+PMF_OK, PMF_EINVAL, PMF_EHIP, PMF_EWORKSPACE, PMF_EUNSUPPORTED = 0, -1, -2, -3, -4
+
+
+class PmfError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"pmf status {code}: {msg}")
+        self.code = code
+
+
+class PmfGrid(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("h", C.c_float * 3), ("center", C.c_float * 3)]
+
+
+class PmfCone(C.Structure):
+    _fields_ = [("sad", C.c_float), ("sdd", C.c_float), ("nu", C.c_int32), ("nv", C.c_int32),
+                ("du", C.c_float), ("dv", C.c_float), ("off_u", C.c_float), ("off_v", C.c_float),
+                ("step", C.c_float)]
+
+
+class PmfGauss(C.Structure):
+    _fields_ = [("mean", C.c_void_p), ("scale", C.c_void_p), ("quat", C.c_void_p),
+                ("value", C.c_void_p), ("m", C.c_int64), ("c", C.c_int32)]
+
+
+class PmfGaussGrad(C.Structure):
+    _fields_ = [("mean", C.c_void_p), ("scale", C.c_void_p), ("quat", C.c_void_p),
+                ("value", C.c_void_p)]
+
+
+_P = C.c_void_p
+_SZ = C.c_size_t
+_SIGS = {
+    "pmf_version": ([], C.c_int),
+    "pmf_last_error": ([], C.c_char_p),
+    "pmf_voxelize_workspace": ([C.c_int64, C.c_int32, C.POINTER(PmfGrid)], _SZ),
+    "pmf_voxelize": ([C.POINTER(PmfGauss), C.POINTER(PmfGrid), C.c_float, _P, _P, _SZ, _P], C.c_int),
+    "pmf_voxelize_bwd": ([C.POINTER(PmfGauss), C.POINTER(PmfGrid), C.c_float, _P,
+                          C.POINTER(PmfGaussGrad), _P], C.c_int),
+    "pmf_combine_dvf": ([C.c_int, C.c_int, _P, C.POINTER(PmfGrid), _P, C.c_int, C.POINTER(PmfGrid),
+                         _P, _P], C.c_int),
+    "pmf_combine_dvf_bwd_workspace": ([C.c_int, C.c_int, C.POINTER(PmfGrid), C.c_int,
+                                       C.POINTER(PmfGrid)], _SZ),
+    "pmf_combine_dvf_bwd": ([C.c_int, C.c_int, _P, C.POINTER(PmfGrid), _P, C.c_int,
+                             C.POINTER(PmfGrid), _P, _P, _P, _P, _SZ, _P], C.c_int),
+    "pmf_warp": ([_P, C.POINTER(PmfGrid), _P, C.c_int, _P, _P], C.c_int),
+    "pmf_warp_bwd": ([_P, C.POINTER(PmfGrid), _P, C.c_int, _P, _P, _P, _P], C.c_int),
+    "pmf_project": ([_P, C.c_int64, C.POINTER(PmfGrid), C.POINTER(PmfCone), _P, C.c_int, _P, _P],
+                    C.c_int),
+    "pmf_project_bwd_workspace": ([C.POINTER(PmfCone), C.c_int], _SZ),
+    "pmf_project_bwd": ([_P, C.POINTER(PmfGrid), C.POINTER(PmfCone), _P, C.c_int, _P, C.c_int64,
+                         _P, _SZ, _P], C.c_int),
+    "pmf_l2_loss_workspace": ([C.c_int64, C.c_int], _SZ),
+    "pmf_l2_loss": ([_P, _P, C.c_int64, C.c_int, _P, _P, _P, _SZ, _P], C.c_int),
+    "pmf_accumulate": ([_P, _P, C.c_int64, _P], C.c_int),
+    "pmf_profile": ([C.c_int], C.c_int),
+    "pmf_profile_read": ([C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
+    "pmf_profile_names": ([C.c_char_p, _SZ], _SZ),
+    "pmf_warp_project_workspace": ([C.c_int, C.c_int, C.POINTER(PmfGrid), C.c_int,
+                                    C.POINTER(PmfGrid), C.POINTER(PmfCone)], _SZ),
+    "pmf_warp_project": ([_P, C.POINTER(PmfGrid), C.c_int, C.c_int, _P, C.POINTER(PmfGrid), _P,
+                          C.c_int, C.POINTER(PmfCone), _P, _P, _P, _SZ, _P], C.c_int),
+    "pmf_warp_project_bwd_workspace": ([C.c_int, C.c_int, C.POINTER(PmfGrid), C.c_int,
+                                        C.POINTER(PmfGrid), C.POINTER(PmfCone)], _SZ),
+    "pmf_warp_project_bwd": ([_P, C.POINTER(PmfGrid), C.c_int, C.c_int, _P, C.POINTER(PmfGrid),
+                              _P, C.c_int, C.POINTER(PmfCone), _P, _P, _P, _P, _P, _P, _SZ, _P],
+                             C.c_int),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libpmf.so (built in-tree); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run paper_2503_22139_amd.build.build()")
+        l = C.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(l, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = l
+    return _lib
+
+
+def exported_symbols() -> List[str]:
+    return list(_SIGS)
+
+
+def _check(rc: int):
+    if rc != PMF_OK:
+        raise PmfError(rc, lib().pmf_last_error().decode())
+
+
+# ------------------------------------------------------------ marshalling
+
+def make_grid(g: Grid) -> PmfGrid:
+    s = PmfGrid()
+    for a in range(3):
+        s.n[a] = int(g.n[a])
+        s.h[a] = float(g.h[a])
+        s.center[a] = float(g.center[a])
+    return s
+
+
+def make_cone(c: Cone) -> PmfCone:
+    return PmfCone(float(c.sad), float(c.sdd), int(c.nu), int(c.nv), float(c.du), float(c.dv),
+                   float(c.off_u), float(c.off_v), float(c.step))
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous() and t.dtype == torch.float32, (t.device, t.dtype)
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+_ws_cache = {}
+
+
+def workspace(nbytes: int, device) -> torch.Tensor:
+    """A reusable device scratch buffer of at least nbytes (grown on demand)."""
+    key = (str(device),)
+    buf = _ws_cache.get(key)
+    if buf is None or buf.numel() < nbytes:
+        buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+        _ws_cache[key] = buf
+    return buf
+
+
+def _gauss(mean, scale, quat, value) -> PmfGauss:
+    m = mean.shape[0]
+    return PmfGauss(_ptr(mean), _ptr(scale), _ptr(quat), _ptr(value), m, value.shape[1])
+
+
+def _levels(grids: Sequence[Grid]):
+    arr = (PmfGrid * len(grids))(*[make_grid(g) for g in grids])
+    return arr
+
+
+def _ptr_array(ts: Sequence[torch.Tensor]):
+    return (C.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
+
+
+# ------------------------------------------------------------ entry points
+
+def pmf_version() -> int:
+    return int(lib().pmf_version())
+
+
+def pmf_voxelize(mean, scale, quat, value, grid: Grid, trunc_k: float = 3.0, out=None):
+    c = value.shape[1]
+    if out is None:
+        out = torch.empty((c,) + tuple(grid.n), device=mean.device, dtype=torch.float32)
+    g = make_grid(grid)
+    nbytes = lib().pmf_voxelize_workspace(mean.shape[0], c, C.byref(g))
+    ws = workspace(nbytes, mean.device)
+    gs = _gauss(mean, scale, quat, value)
+    _check(lib().pmf_voxelize(C.byref(gs), C.byref(g), float(trunc_k), _ptr(out),
+                              C.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return out
+
+
+def pmf_voxelize_bwd(mean, scale, quat, value, grid: Grid, trunc_k: float, g_vol):
+    gm, gsc, gq, gv = (torch.empty_like(mean), torch.empty_like(scale), torch.empty_like(quat),
+                       torch.empty_like(value))
+    g = make_grid(grid)
+    gs = _gauss(mean, scale, quat, value)
+    gr = PmfGaussGrad(_ptr(gm), _ptr(gsc), _ptr(gq), _ptr(gv))
+    _check(lib().pmf_voxelize_bwd(C.byref(gs), C.byref(g), float(trunc_k), _ptr(g_vol.contiguous()),
+                                  C.byref(gr), _stream()))
+    return gm, gsc, gq, gv
+
+
+def pmf_combine_dvf(bases: Sequence[torch.Tensor], levels: Sequence[Grid], coeff, grid: Grid, out=None):
+    V, L, B, _ = coeff.shape
+    if out is None:
+        out = torch.empty((V, 3) + tuple(grid.n), device=coeff.device, dtype=torch.float32)
+    lv = _levels(levels)
+    og = make_grid(grid)
+    _check(lib().pmf_combine_dvf(L, B, _ptr_array(bases), lv, _ptr(coeff), V, C.byref(og), _ptr(out),
+                                 _stream()))
+    return out
+
+
+def pmf_combine_dvf_bwd(bases, levels, coeff, grid: Grid, g_dvf, g_coeff_out=None):
+    V, L, B, _ = coeff.shape
+    lv = _levels(levels)
+    og = make_grid(grid)
+    g_bases = [torch.empty_like(b) for b in bases]
+    g_coeff = torch.empty_like(coeff) if g_coeff_out is None else g_coeff_out
+    nbytes = lib().pmf_combine_dvf_bwd_workspace(L, B, lv, V, C.byref(og))
+    ws = workspace(nbytes, coeff.device)
+    _check(lib().pmf_combine_dvf_bwd(L, B, _ptr_array(bases), lv, _ptr(coeff), V, C.byref(og),
+                                     _ptr(g_dvf.contiguous()), _ptr_array(g_bases), _ptr(g_coeff),
+                                     C.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return g_bases, g_coeff
+
+
+def pmf_warp(ref, grid: Grid, dvf, out=None):
+    V = dvf.shape[0]
+    if out is None:
+        out = torch.empty((V,) + tuple(grid.n), device=ref.device, dtype=torch.float32)
+    g = make_grid(grid)
+    _check(lib().pmf_warp(_ptr(ref), C.byref(g), _ptr(dvf), V, _ptr(out), _stream()))
+    return out
+
+
+def pmf_warp_bwd(ref, grid: Grid, dvf, g_out):
+    V = dvf.shape[0]
+    g_ref = torch.empty_like(ref)
+    g_dvf = torch.empty_like(dvf)
+    g = make_grid(grid)
+    _check(lib().pmf_warp_bwd(_ptr(ref), C.byref(g), _ptr(dvf), V, _ptr(g_out.contiguous()),
+                              _ptr(g_ref), _ptr(g_dvf), _stream()))
+    return g_ref, g_dvf
+
+
+def pmf_project(vol, grid: Grid, cone: Cone, angles, shared: Optional[bool] = None, out=None):
+    V = angles.numel()
+    N = grid.size
+    if shared is None:
+        shared = vol.numel() == N
+    stride = 0 if shared else N
+    if out is None:
+        out = torch.empty((V, cone.nv, cone.nu), device=vol.device, dtype=torch.float32)
+    g = make_grid(grid)
+    cn = make_cone(cone)
+    _check(lib().pmf_project(_ptr(vol), stride, C.byref(g), C.byref(cn), _ptr(angles), V, _ptr(out),
+                             _stream()))
+    return out
+
+
+def pmf_project_bwd(g_proj, grid: Grid, cone: Cone, angles, shared: bool = False, out=None):
+    V = angles.numel()
+    N = grid.size
+    if out is None:
+        shape = tuple(grid.n) if shared else (V,) + tuple(grid.n)
+        out = torch.empty(shape, device=g_proj.device, dtype=torch.float32)
+    g = make_grid(grid)
+    cn = make_cone(cone)
+    nbytes = lib().pmf_project_bwd_workspace(C.byref(cn), V)
+    ws = workspace(nbytes, g_proj.device)
+    _check(lib().pmf_project_bwd(_ptr(g_proj.contiguous()), C.byref(g), C.byref(cn), _ptr(angles), V,
+                                 _ptr(out), 0 if shared else N, C.c_void_p(ws.data_ptr()),
+                                 ws.numel(), _stream()))
+    return out
+
+
+def pmf_l2_loss(proj, target, want_grad: bool = True):
+    V = proj.shape[0]
+    npix = proj[0].numel()
+    loss = torch.empty((), device=proj.device, dtype=torch.float32)
+    g = torch.empty_like(proj) if want_grad else None
+    nbytes = lib().pmf_l2_loss_workspace(npix, V)
+    ws = workspace(nbytes, proj.device)
+    _check(lib().pmf_l2_loss(_ptr(proj), _ptr(target), npix, V, _ptr(loss), _ptr(g),
+                             C.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return loss, g
+
+
+def pmf_accumulate(dst, src):
+    """dst += src (same numel), in the library."""
+    assert dst.numel() == src.numel()
+    _check(lib().pmf_accumulate(_ptr(dst), _ptr(src.contiguous()), dst.numel(), _stream()))
+    return dst
+
+
+def pmf_profile(enable: bool) -> bool:
+    return bool(lib().pmf_profile(1 if enable else 0))
+
+
+def pmf_profile_names() -> List[str]:
+    n = lib().pmf_profile_names(None, 0)
+    buf = C.create_string_buffer(n + 1)
+    lib().pmf_profile_names(buf, n + 1)
+    s = buf.value.decode()
+    return [x for x in s.split(",") if x]
+
+
+def pmf_profile_read(kernel: str) -> Tuple[float, int]:
+    """(total milliseconds, launches) recorded for one kernel name; clears them."""
+    t = C.c_double()
+    n = C.c_int64()
+    _check(lib().pmf_profile_read(kernel.encode(), C.byref(t), C.byref(n)))
+    return float(t.value), int(n.value)
+
+
+def pmf_warp_project(ref, grid: Grid, bases, levels, coeff, cone: Cone, angles, out=None):
+    V, L, B, _ = coeff.shape
+    if out is None:
+        out = torch.empty((V, cone.nv, cone.nu), device=ref.device, dtype=torch.float32)
+    g = make_grid(grid)
+    lv = _levels(levels)
+    cn = make_cone(cone)
+    nbytes = lib().pmf_warp_project_workspace(L, B, lv, V, C.byref(g), C.byref(cn))
+    ws = workspace(nbytes, ref.device)
+    _check(lib().pmf_warp_project(_ptr(ref), C.byref(g), L, B, _ptr_array(bases), lv, _ptr(coeff), V,
+                                  C.byref(cn), _ptr(angles), _ptr(out), C.c_void_p(ws.data_ptr()),
+                                  ws.numel(), _stream()))
+    return out
+
+
+def pmf_warp_project_bwd(ref, grid: Grid, bases, levels, coeff, cone: Cone, angles, g_proj):
+    V, L, B, _ = coeff.shape
+    g = make_grid(grid)
+    lv = _levels(levels)
+    cn = make_cone(cone)
+    g_ref = torch.empty_like(ref)
+    g_bases = [torch.empty_like(b) for b in bases]
+    g_coeff = torch.empty_like(coeff)
+    nbytes = lib().pmf_warp_project_bwd_workspace(L, B, lv, V, C.byref(g), C.byref(cn))
+    ws = workspace(nbytes, ref.device)
+    _check(lib().pmf_warp_project_bwd(_ptr(ref), C.byref(g), L, B, _ptr_array(bases), lv,
+                                      _ptr(coeff), V, C.byref(cn), _ptr(angles),
+                                      _ptr(g_proj.contiguous()), _ptr(g_ref), _ptr_array(g_bases),
+                                      _ptr(g_coeff), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                      _stream()))
+    return g_ref, g_bases, g_coeff
+
+
+# ------------------------------------------------------------ autograd
+
+class Voxelize(torch.autograd.Function):
+    """Eq. 5: (mean, scale, quat, value) -> volume [c][n0][n1][n2]."""
+
+    @staticmethod
+    def forward(ctx, mean, scale, quat, value, grid: Grid, trunc_k: float = 3.0):
+        ctx.save_for_backward(mean, scale, quat, value)
+        ctx.grid, ctx.k = grid, trunc_k
+        return pmf_voxelize(mean.contiguous(), scale.contiguous(), quat.contiguous(),
+                            value.contiguous(), grid, trunc_k)
+
+    @staticmethod
+    def backward(ctx, g):
+        mean, scale, quat, value = ctx.saved_tensors
+        gm, gs, gq, gv = pmf_voxelize_bwd(mean, scale, quat, value, ctx.grid, ctx.k, g.contiguous())
+        return gm, gs, gq, gv, None, None
+
+
+class CombineDVF(torch.autograd.Function):
+    """Eq. 3: (coeff [V][L][B][3], bases_l [3B][...]) -> dvf [V][3][...]."""
+
+    @staticmethod
+    def forward(ctx, coeff, grid: Grid, levels, *bases):
+        ctx.save_for_backward(coeff, *bases)
+        ctx.grid, ctx.levels = grid, levels
+        return pmf_combine_dvf([b.contiguous() for b in bases], levels, coeff.contiguous(), grid)
+
+    @staticmethod
+    def backward(ctx, g):
+        coeff, *bases = ctx.saved_tensors
+        gb, gc = pmf_combine_dvf_bwd(bases, ctx.levels, coeff, ctx.grid, g.contiguous())
+        return (gc, None, None, *gb)
+
+
+class Warp(torch.autograd.Function):
+    """Eq. 2: (ref [...], dvf [V][3][...]) -> [V][...]."""
+
+    @staticmethod
+    def forward(ctx, ref, dvf, grid: Grid):
+        ctx.save_for_backward(ref, dvf)
+        ctx.grid = grid
+        return pmf_warp(ref.contiguous(), grid, dvf.contiguous())
+
+    @staticmethod
+    def backward(ctx, g):
+        ref, dvf = ctx.saved_tensors
+        g_ref, g_dvf = pmf_warp_bwd(ref, ctx.grid, dvf, g.contiguous())
+        return g_ref, g_dvf, None
+
+
+class Project(torch.autograd.Function):
+    """Eq. 6: volume [V][...] (or one shared [...]) -> projections [V][nv][nu]."""
+
+    @staticmethod
+    def forward(ctx, vol, angles, grid: Grid, cone: Cone):
+        ctx.save_for_backward(angles)
+        ctx.grid, ctx.cone = grid, cone
+        ctx.shared = vol.numel() == grid.size
+        ctx.shape = vol.shape
+        return pmf_project(vol.contiguous(), grid, cone, angles, shared=ctx.shared)
+
+    @staticmethod
+    def backward(ctx, g):
+        (angles,) = ctx.saved_tensors
+        gv = pmf_project_bwd(g.contiguous(), ctx.grid, ctx.cone, angles, shared=ctx.shared)
+        return gv.reshape(ctx.shape), None, None, None
+
+
+class WarpProject(torch.autograd.Function):
+    """Batched Eq. 3 + Eq. 2 + Eq. 6 for all views; the backward recomputes
+    each view's DVF instead of storing DVFs or warped volumes."""
+
+    @staticmethod
+    def forward(ctx, ref, coeff, angles, grid: Grid, levels, cone: Cone, *bases):
+        ctx.save_for_backward(ref, coeff, angles, *bases)
+        ctx.grid, ctx.levels, ctx.cone = grid, levels, cone
+        return pmf_warp_project(ref.contiguous(), grid, [b.contiguous() for b in bases], levels,
+                                coeff.contiguous(), cone, angles)
+
+    @staticmethod
+    def backward(ctx, g):
+        ref, coeff, angles, *bases = ctx.saved_tensors
+        g_ref, g_bases, g_coeff = pmf_warp_project_bwd(ref, ctx.grid, bases, ctx.levels, coeff,
+                                                       ctx.cone, angles, g.contiguous())
+        return (g_ref, g_coeff, None, None, None, None, *g_bases)

@@ -1,0 +1,126 @@
+"""The C ABI: libpmf.so loads, exports every function include/pmf.h declares,
+and rejects invalid arguments on the host (no GPU needed: argument checks run
+before any HIP call, so these calls never reach the runtime)."""
+import ctypes as C
+import math
+import os
+import re
+
+import pytest
+
+from paper_2503_22139_amd import ops
+from paper_2503_22139_amd.synth import Cone, Grid
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "pmf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pmf_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(ops.LIB_PATH):
+        from paper_2503_22139_amd import build
+        build.build(verbose=False)
+    return ops.lib()
+
+
+def test_exports_every_declared_function(lib):
+    names = header_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(ops.exported_symbols())
+
+
+def test_version(lib):
+    assert lib.pmf_version() == 100
+
+
+def grid(n=(8, 8, 8), h=(1.0, 1.0, 1.0)):
+    return ops.make_grid(Grid(n, h))
+
+
+def err(lib):
+    return lib.pmf_last_error().decode()
+
+
+def test_voxelize_rejects_bad_arguments(lib):
+    g = grid()
+    gs = ops.PmfGauss(C.c_void_p(16), C.c_void_p(16), C.c_void_p(16), C.c_void_p(16), 10, 1)
+    ws = C.c_void_p(256)
+    big = 1 << 40
+    # null gaussians, bad grid, bad k, too many channels, null output, small workspace
+    assert lib.pmf_voxelize(None, C.byref(g), 3.0, C.c_void_p(16), ws, big, None) == ops.PMF_EINVAL
+    bad = grid(n=(1, 8, 8))
+    assert lib.pmf_voxelize(C.byref(gs), C.byref(bad), 3.0, C.c_void_p(16), ws, big, None) == ops.PMF_EINVAL
+    assert "n[0]" in err(lib)
+    badh = grid(h=(1.0, 0.0, 1.0))
+    assert lib.pmf_voxelize(C.byref(gs), C.byref(badh), 3.0, C.c_void_p(16), ws, big, None) == ops.PMF_EINVAL
+    assert lib.pmf_voxelize(C.byref(gs), C.byref(g), 0.0, C.c_void_p(16), ws, big, None) == ops.PMF_EINVAL
+    assert lib.pmf_voxelize(C.byref(gs), C.byref(g), float("nan"), C.c_void_p(16), ws, big, None) == ops.PMF_EINVAL
+    gs17 = ops.PmfGauss(C.c_void_p(16), C.c_void_p(16), C.c_void_p(16), C.c_void_p(16), 10, 17)
+    assert lib.pmf_voxelize(C.byref(gs17), C.byref(g), 3.0, C.c_void_p(16), ws, big, None) == ops.PMF_EUNSUPPORTED
+    gs0 = ops.PmfGauss(C.c_void_p(16), C.c_void_p(16), C.c_void_p(16), C.c_void_p(16), 10, 0)
+    assert lib.pmf_voxelize(C.byref(gs0), C.byref(g), 3.0, C.c_void_p(16), ws, big, None) == ops.PMF_EINVAL
+    nullarr = ops.PmfGauss(None, C.c_void_p(16), C.c_void_p(16), C.c_void_p(16), 10, 1)
+    assert lib.pmf_voxelize(C.byref(nullarr), C.byref(g), 3.0, C.c_void_p(16), ws, big, None) == ops.PMF_EINVAL
+    assert lib.pmf_voxelize(C.byref(gs), C.byref(g), 3.0, None, ws, big, None) == ops.PMF_EINVAL
+    need = lib.pmf_voxelize_workspace(10, 1, C.byref(g))
+    assert need > 0
+    assert lib.pmf_voxelize(C.byref(gs), C.byref(g), 3.0, C.c_void_p(16), ws, need - 1, None) == ops.PMF_EWORKSPACE
+    assert lib.pmf_voxelize(C.byref(gs), C.byref(g), 3.0, C.c_void_p(16), None, need, None) == ops.PMF_EWORKSPACE
+    assert "workspace" in err(lib)
+
+
+def test_project_rejects_bad_geometry(lib):
+    g = grid()
+    p = C.c_void_p(16)
+    for cone in (Cone(1500.0, 1000.0, 8, 8, 1.0, 1.0),      # SDD < SAD
+                 Cone(0.0, 1500.0, 8, 8, 1.0, 1.0),
+                 Cone(1000.0, 1500.0, 0, 8, 1.0, 1.0),
+                 Cone(1000.0, 1500.0, 8, 8, -1.0, 1.0),
+                 Cone(1000.0, 1500.0, 8, 8, 1.0, 1.0, step=float("inf")),
+                 Cone(3.0, 1500.0, 8, 8, 1.0, 1.0)):         # source inside the volume box
+        c = ops.make_cone(cone)
+        assert lib.pmf_project(p, 0, C.byref(g), C.byref(c), p, 1, p, None) == ops.PMF_EINVAL, cone
+    c = ops.make_cone(Cone(1000.0, 1500.0, 8, 8, 1.0, 1.0))
+    assert lib.pmf_project(p, 0, C.byref(g), C.byref(c), p, 0, p, None) == ops.PMF_EINVAL
+    assert lib.pmf_project(p, 5, C.byref(g), C.byref(c), p, 1, p, None) == ops.PMF_EINVAL  # stride < N
+    assert lib.pmf_project(None, 0, C.byref(g), C.byref(c), p, 1, p, None) == ops.PMF_EINVAL
+    need = lib.pmf_project_bwd_workspace(C.byref(c), 3)
+    assert need >= 3 * 64 * 32
+    assert lib.pmf_project_bwd(p, C.byref(g), C.byref(c), p, 3, p, 0, p, need - 1, None) == ops.PMF_EWORKSPACE
+
+
+def test_combine_and_warp_reject_bad_arguments(lib):
+    g = grid()
+    lv = (ops.PmfGrid * 2)(grid(), grid(n=(4, 4, 4)))
+    bases = (C.c_void_p * 2)(16, 16)
+    p = C.c_void_p(16)
+    assert lib.pmf_combine_dvf(0, 1, bases, lv, p, 1, C.byref(g), p, None) == ops.PMF_EINVAL
+    assert lib.pmf_combine_dvf(5, 1, bases, lv, p, 1, C.byref(g), p, None) == ops.PMF_EUNSUPPORTED
+    assert lib.pmf_combine_dvf(2, 5, bases, lv, p, 1, C.byref(g), p, None) == ops.PMF_EUNSUPPORTED
+    nb = (C.c_void_p * 2)(16, None)
+    assert lib.pmf_combine_dvf(2, 1, nb, lv, p, 1, C.byref(g), p, None) == ops.PMF_EINVAL
+    assert lib.pmf_combine_dvf(2, 1, bases, lv, p, 0, C.byref(g), p, None) == ops.PMF_EINVAL
+    assert lib.pmf_warp(p, C.byref(g), p, 0, p, None) == ops.PMF_EINVAL
+    assert lib.pmf_warp(None, C.byref(g), p, 1, p, None) == ops.PMF_EINVAL
+    assert lib.pmf_warp_bwd(p, C.byref(g), p, 1, p, None, p, None) == ops.PMF_EINVAL
+    assert lib.pmf_l2_loss(p, p, 0, 1, p, p, p, 1 << 20, None) == ops.PMF_EINVAL
+    assert lib.pmf_accumulate(None, p, 5, None) == ops.PMF_EINVAL
+    assert lib.pmf_combine_dvf_bwd_workspace(2, 3, lv, 4, C.byref(g)) > 0
+
+
+def test_workspace_queries_reject_invalid(lib):
+    g = grid()
+    assert lib.pmf_voxelize_workspace(-1, 1, C.byref(g)) == 0
+    assert lib.pmf_voxelize_workspace(10, 1, None) == 0
+    assert lib.pmf_project_bwd_workspace(None, 1) == 0
+    c = ops.make_cone(Cone(1000.0, 1500.0, 8, 8, 1.0, 1.0))
+    lv = (ops.PmfGrid * 1)(grid())
+    assert lib.pmf_warp_project_workspace(1, 1, lv, 2, C.byref(g), C.byref(c)) >= 2 * 512 * 4
+    assert lib.pmf_warp_project_bwd_workspace(1, 1, lv, 2, C.byref(g), C.byref(c)) > 0

@@ -1,0 +1,349 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars (relative L2 error per output tensor): 1e-4 for volumes and
+projections, 1e-3 for gradients; integer-free paths only.  Inputs are the
+seeded generators' float32 arrays, fed to both sides; expected values come
+from the oracle only.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2503_22139_amd import ops, synth
+from paper_2503_22139_amd.model import MotionModel
+from paper_2503_22139_amd.synth import Cone, GaussSet, Grid
+
+pytestmark = pytest.mark.gpu
+
+VOL_TOL = 1e-4
+GRAD_TOL = 1e-3
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ops.lib()           # raises if libpmf.so is missing
+    oracle.build()
+    yield
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def T(a):
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+
+
+def N(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def gauss_t(s):
+    return T(s.mean), T(s.scale), T(s.quat), T(s.value)
+
+
+def f32(a):
+    return np.asarray(a, np.float32)
+
+
+# ---------------------------------------------------------------- voxelize
+
+@pytest.mark.parametrize("case", ["c1", "small_ref", "small_mbc", "fd32_untruncated", "large_list",
+                                  "edge"])
+def test_voxelize_forward(case):
+    say("voxelize", case)
+    if case == "c1":
+        w = synth.c1(); gs, grid, k = w.ref, w.grid, 3.0
+    elif case == "small_ref":
+        w = synth.small_motion(); gs, grid, k = w.ref, w.grid, 3.0
+    elif case == "small_mbc":
+        w = synth.small_motion(); gs, grid, k = w.mbc[2], w.levels[2], 3.0
+    elif case == "fd32_untruncated":
+        w = synth.fd32(); gs, grid, k = w.mbc[1], w.levels[1], math.inf
+    elif case == "large_list":   # untruncated on a grid of 45 tiles: every Gaussian overflows the bins
+        grid = Grid((70, 40, 40), (1.0, 1.2, 1.1))
+        gs = synth.gaussians(np.random.default_rng(4), 200, grid)
+        k = math.inf
+    else:   # Gaussians beyond the grid, huge and tiny scales, ragged grid
+        rng = np.random.default_rng(5)
+        grid = Grid((19, 7, 33), (1.3, 2.1, 0.7), (3.0, -2.0, 1.0))
+        gs = synth.gaussians(rng, 300, Grid((40, 20, 60), (1.3, 2.1, 0.7), (3.0, -2.0, 1.0)),
+                             s_vox=(0.05, 12.0), c=3, value_sigma=1.0)
+        k = 3.0
+    want = oracle.voxelize(gs, grid, k)
+    got = N(ops.pmf_voxelize(*gauss_t(gs), grid, k))
+    assert got.shape == want.shape
+    assert rel(got, want) < VOL_TOL, rel(got, want)
+
+
+def test_voxelize_empty_set():
+    grid = Grid((9, 8, 7), (1.0, 1.0, 1.0))
+    z = np.zeros((0, 3), np.float32)
+    gs = GaussSet(z, z, np.zeros((0, 4), np.float32), np.zeros((0, 2), np.float32))
+    out = ops.pmf_voxelize(*gauss_t(gs), grid, 3.0, out=torch.full((2, 9, 8, 7), 7.0, device="cuda"))
+    assert np.all(N(out) == 0.0)
+
+
+def test_voxelize_c2_full_size():
+    """200k-Gaussian reference at 256x256x128 (the benchmark's reference volume)."""
+    say("voxelize c2 full")
+    w = synth.c2()
+    want = oracle.voxelize(w.ref, w.grid, 3.0)
+    got = N(ops.pmf_voxelize(*gauss_t(w.ref), w.grid, 3.0))
+    assert rel(got, want) < VOL_TOL, rel(got, want)
+
+
+@pytest.mark.parametrize("case", ["c1", "small_mbc", "fd32_untruncated"])
+def test_voxelize_backward(case):
+    say("voxelize_bwd", case)
+    if case == "c1":
+        w = synth.c1(); gs, grid, k = w.ref, w.grid, 3.0
+    elif case == "small_mbc":
+        w = synth.small_motion(); gs, grid, k = w.mbc[1], w.levels[1], 3.0
+    else:
+        w = synth.fd32(); gs, grid, k = w.ref, w.grid, math.inf
+    gv = synth.random_normal(3, (gs.c,) + tuple(grid.n))
+    want = oracle.voxelize_bwd(gs, grid, k, gv)
+    got = ops.pmf_voxelize_bwd(*gauss_t(gs), grid, k, T(gv))
+    for name, g in zip(("mean", "scale", "quat", "value"), got):
+        r = rel(N(g), want[name])
+        assert r < GRAD_TOL, (name, r)
+
+
+# ------------------------------------------------------------------ project
+
+def _proj_case(case):
+    if case == "c1":
+        w = synth.c1()
+        vol = f32(oracle.voxelize(w.ref, w.grid, 3.0)[0])
+        return vol, w.grid, w.cone, w.angles
+    if case == "aniso":   # odd detector, offsets, anisotropic off-centre grid
+        grid = Grid((23, 17, 12), (1.7, 1.1, 2.3), (4.0, -3.0, 2.0))
+        vol = synth.random_volume(8, grid.n)
+        cone = Cone(800.0, 1300.0, 37, 29, 1.3, 1.1, off_u=0.3, off_v=-1.7, step=0.0)
+        return vol, grid, cone, synth.evenly_spaced_angles(7) + np.float32(0.1)
+    raise ValueError(case)
+
+
+@pytest.mark.parametrize("case", ["c1", "aniso"])
+def test_project_forward(case):
+    say("project", case)
+    vol, grid, cone, ang = _proj_case(case)
+    want = oracle.project(vol, grid, cone, ang)
+    got = N(ops.pmf_project(T(vol), grid, cone, T(ang)))
+    assert rel(got, want) < VOL_TOL, rel(got, want)
+    # per-view volumes
+    vols = np.stack([vol, 2.0 * vol])
+    want2 = oracle.project(vols, grid, cone, ang[:2], shared=False)
+    got2 = N(ops.pmf_project(T(vols), grid, cone, T(ang[:2]), shared=False))
+    assert rel(got2, want2) < VOL_TOL
+
+
+def test_project_c2_full_size_sampled():
+    """Full 256x256x128 volume, 8 views of 512x384: 4,000 sampled rays."""
+    say("project c2 sampled")
+    w = synth.c2()
+    vol = f32(oracle.voxelize(w.ref, w.grid, 3.0)[0])
+    got = N(ops.pmf_project(T(vol), w.grid, w.cone, T(w.angles)))
+    rng = np.random.default_rng(9)
+    rays = np.stack([rng.integers(0, 8, 4000), rng.integers(0, w.cone.nu, 4000),
+                     rng.integers(0, w.cone.nv, 4000)], 1)
+    want = oracle.project_rays(vol, w.grid, w.cone, w.angles, rays)
+    g = got[rays[:, 0], rays[:, 2], rays[:, 1]]
+    assert rel(g, want) < VOL_TOL, rel(g, want)
+
+
+@pytest.mark.parametrize("case", ["c1", "aniso"])
+def test_project_backward(case):
+    say("project_bwd", case)
+    vol, grid, cone, ang = _proj_case(case)
+    V = len(ang)
+    gp = synth.random_normal(4, (V, cone.nv, cone.nu))
+    want = oracle.project_bwd(gp, grid, cone, ang, shared=False)
+    got = N(ops.pmf_project_bwd(T(gp), grid, cone, T(ang), shared=False))
+    assert rel(got, want) < VOL_TOL, rel(got, want)
+    want_s = oracle.project_bwd(gp, grid, cone, ang, shared=True)
+    got_s = N(ops.pmf_project_bwd(T(gp), grid, cone, T(ang), shared=True))
+    assert rel(got_s, want_s) < VOL_TOL, rel(got_s, want_s)
+
+
+def test_project_adjoint_identity_fp32():
+    vol, grid, cone, ang = _proj_case("aniso")
+    V = len(ang)
+    x = synth.random_normal(10, (V,) + grid.n)
+    y = synth.random_normal(11, (V, cone.nv, cone.nu))
+    px = N(ops.pmf_project(T(x), grid, cone, T(ang), shared=False))
+    pty = N(ops.pmf_project_bwd(T(y), grid, cone, T(ang), shared=False))
+    lhs, rhs = np.sum(px * y), np.sum(x * pty)
+    assert abs(lhs - rhs) / max(abs(lhs), 1e-30) < 1e-5
+
+
+# ------------------------------------------------------------ combine, warp
+
+@pytest.fixture(scope="module")
+def small():
+    w = synth.small_motion()
+    bases = [f32(oracle.voxelize(s, g, 3.0)) for s, g in zip(w.mbc, w.levels)]
+    ref = f32(oracle.voxelize(w.ref, w.grid, 3.0)[0])
+    return w, ref, bases
+
+
+def test_combine_forward(small):
+    w, ref, bases = small
+    want = oracle.combine(bases, w.levels, w.coeff, w.grid)
+    got = N(ops.pmf_combine_dvf([T(b) for b in bases], w.levels, T(w.coeff), w.grid))
+    assert rel(got, want) < VOL_TOL, rel(got, want)
+
+
+def test_combine_backward(small):
+    w, ref, bases = small
+    gd = synth.random_normal(12, (len(w.angles), 3) + w.grid.n)
+    wb, wc = oracle.combine_bwd(bases, w.levels, w.coeff, w.grid, gd)
+    gb, gc = ops.pmf_combine_dvf_bwd([T(b) for b in bases], w.levels, T(w.coeff), w.grid, T(gd))
+    for a, b in zip(gb, wb):
+        assert rel(N(a), b) < GRAD_TOL
+    assert rel(N(gc), wc) < GRAD_TOL
+
+
+def test_warp_forward_backward(small):
+    w, ref, bases = small
+    dvf = synth.random_normal(13, (3, 3) + w.grid.n, sigma=3.0)
+    want = oracle.warp(ref, w.grid, dvf)
+    got = N(ops.pmf_warp(T(ref), w.grid, T(dvf)))
+    assert rel(got, want) < VOL_TOL
+    go = synth.random_normal(14, (3,) + w.grid.n)
+    wr, wd = oracle.warp_bwd(ref, w.grid, dvf, go)
+    gr, gd = ops.pmf_warp_bwd(T(ref), w.grid, T(dvf), T(go))
+    assert rel(N(gr), wr) < GRAD_TOL
+    assert rel(N(gd), wd) < GRAD_TOL
+
+
+def test_l2_loss():
+    p = synth.random_normal(15, (3, 7, 9))
+    t = synth.random_normal(16, (3, 7, 9))
+    want_l, want_g = oracle.l2_loss(p, t)
+    l, g = ops.pmf_l2_loss(T(p), T(t))
+    assert abs(float(N(l)) - want_l) / want_l < 1e-5
+    assert rel(N(g), want_g) < 1e-6
+
+
+# ------------------------------------------------------------ fused path
+
+def test_warp_project_forward(small):
+    w, ref, bases = small
+    want = np.stack([oracle.project(oracle.warp(ref, w.grid, oracle.combine(bases, w.levels,
+                                                                             w.coeff[v:v + 1], w.grid)),
+                                    w.grid, w.cone, w.angles[v:v + 1])[0] for v in range(len(w.angles))])
+    got = N(ops.pmf_warp_project(T(ref), w.grid, [T(b) for b in bases], w.levels, T(w.coeff), w.cone,
+                                 T(w.angles)))
+    assert rel(got, want) < VOL_TOL, rel(got, want)
+
+
+def _oracle_target(w):
+    truth = synth.perturbed_truth(w)
+    return synth.add_target_noise(oracle.forward(truth))
+
+
+def _compare_grads(got, want, tag):
+    for name in ("mean", "scale", "quat", "value"):
+        r = rel(N(got["ref"][name]), want["ref"][name])
+        assert r < GRAD_TOL, (tag, "ref", name, r)
+    for l, (a, b) in enumerate(zip(got["mbc"], want["mbc"])):
+        for name in ("mean", "scale", "quat", "value"):
+            r = rel(N(a[name]), b[name])
+            assert r < GRAD_TOL, (tag, "mbc", l, name, r)
+    r = rel(N(got["coeff"]), want["coeff"])
+    assert r < GRAD_TOL, (tag, "coeff", r)
+
+
+@pytest.mark.parametrize("case", ["small", "fd32"])
+def test_full_step_plain_and_batched(case):
+    say("step", case)
+    w = synth.small_motion() if case == "small" else synth.fd32()
+    target = _oracle_target(w)
+    want_loss, want = oracle.step(w, target)
+    m = MotionModel(w)
+    for name, fn in (("plain", m.step_plain), ("batched", m.step_batched)):
+        loss, grads = fn(T(target))
+        assert abs(float(N(loss)) - want_loss) / want_loss < VOL_TOL, (name, float(N(loss)), want_loss)
+        _compare_grads(grads, want, name)
+
+
+def test_batched_equals_plain_ragged():
+    """Ragged sizes, more views than one chunk of the fused adjoint."""
+    w = synth.small_motion(seed=21, n=(13, 21, 10), level_dims=((5, 6, 4), (13, 21, 10), (7, 11, 5)),
+                           nviews=70, det=(17, 13))
+    target = synth.random_volume(22, (70, 13, 17), 0.0, 1.0)
+    m = MotionModel(w)
+    lp, gp = m.step_plain(T(target))
+    lb, gb = m.step_batched(T(target))
+    assert abs(float(N(lp)) - float(N(lb))) <= 1e-5 * abs(float(N(lp)))
+    for name in ("mean", "scale", "quat", "value"):
+        assert rel(N(gb["ref"][name]), N(gp["ref"][name])) < 1e-4
+        for a, b in zip(gb["mbc"], gp["mbc"]):
+            assert rel(N(a[name]), N(b[name])) < 1e-4
+    assert rel(N(gb["coeff"]), N(gp["coeff"])) < 1e-4
+
+
+# -------------------------------------------------- full size (benchmark)
+
+def test_headline_full_size_sampled():
+    """The benchmark iteration (32 views, 256x256x128, 200k + 21k Gaussians)
+    in the batched launch configuration: sampled projection rays of two views
+    and the view-0 coefficient gradient against the oracle; the adjoint
+    identity in the reference volume; batched equals plain."""
+    say("headline: build")
+    w = synth.headline()
+    m = MotionModel(w)
+    V = len(w.angles)
+    target = synth.random_volume(23, (V, w.cone.nv, w.cone.nu), 0.0, 20.0)
+    say("headline: gpu step")
+    proj = N(m.forward_batched())
+    loss_b, grads_b = m.step_batched(T(target))
+    say("headline: oracle volumes")
+    ref, bases = oracle.forward_volumes(w)
+    rng = np.random.default_rng(24)
+    for v in (0, 17):
+        dvf = oracle.combine(bases, w.levels, w.coeff[v:v + 1], w.grid)
+        wv = oracle.warp(ref, w.grid, dvf)
+        rays = np.stack([np.zeros(1500, np.int64), rng.integers(0, w.cone.nu, 1500),
+                         rng.integers(0, w.cone.nv, 1500)], 1)
+        want = oracle.project_rays(wv, w.grid, w.cone, w.angles[v:v + 1], rays)
+        got = proj[v][rays[:, 2], rays[:, 1]]
+        say("headline: view", v, "rel", rel(got, want))
+        assert rel(got, want) < VOL_TOL, (v, rel(got, want))
+    say("headline: oracle view-0 gradient")
+    _, og = oracle.step(w, target, views=[0])
+    r = rel(N(grads_b["coeff"][0]), og["coeff"][0])
+    say("headline: g_coeff[0] rel", r)
+    assert r < GRAD_TOL, r
+    say("headline: plain")
+    loss_p, grads_p = m.step_plain(T(target))
+    assert abs(float(N(loss_p)) - float(N(loss_b))) <= 1e-5 * float(N(loss_p))
+    assert rel(N(grads_b["coeff"]), N(grads_p["coeff"])) < 1e-4
+    for name in ("mean", "scale", "quat", "value"):
+        assert rel(N(grads_b["ref"][name]), N(grads_p["ref"][name])) < 1e-4, name
+    say("headline: adjoint identity in ref")
+    ref_g, bases_g = m.volumes()
+    x = T(synth.random_normal(25, w.grid.n))
+    y = T(synth.random_normal(26, (V, w.cone.nv, w.cone.nu)))
+    px = ops.pmf_warp_project(x, w.grid, bases_g, w.levels, m.coeff, w.cone, m.angles)
+    gx, _, _ = ops.pmf_warp_project_bwd(ref_g, w.grid, bases_g, w.levels, m.coeff, w.cone, m.angles, y)
+    lhs = float(torch.sum(px.double() * y.double()))
+    rhs = float(torch.sum(x.double() * gx.double()))
+    assert abs(lhs - rhs) / abs(lhs) < 1e-5, (lhs, rhs)
