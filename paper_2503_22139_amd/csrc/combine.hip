@@ -99,8 +99,8 @@ __global__ __launch_bounds__(256) void k_combine_bwd_coeff(LevelsK lv, GridK out
         for (int b = 0; b < B; ++b)
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                const float t = warp_sum(acc[l][b][k]);
-                if (lane == 0) red[wave][(l * B + b) * 3 + k] = t;
+                const float t = wave_sum_lane63(acc[l][b][k]);
+                if (lane == 63) red[wave][(l * B + b) * 3 + k] = t;
             }
     __syncthreads();
     if (threadIdx.x < L * B * 3) {
@@ -110,15 +110,20 @@ __global__ __launch_bounds__(256) void k_combine_bwd_coeff(LevelsK lv, GridK out
     }
 }
 
-// g_coeff[v][l][b][k] = sum over blocks of the partials, in block order.
-__global__ void k_reduce_coeff(const float *__restrict__ partial, int nblk, int V, int per,
-                               float *__restrict__ g_coeff) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= V * per) return;
+// g_coeff[v][l][b][k] = sum over blocks of the partials: one workgroup per
+// output entry, fixed-order tree (deterministic).
+__global__ __launch_bounds__(256) void k_reduce_coeff(const float *__restrict__ partial, int nblk,
+                                                      int per, float *__restrict__ g_coeff) {
+    const int t = blockIdx.x;
     const int v = t / per, idx = t % per;
     float s = 0.0f;
-    for (int i = 0; i < nblk; ++i) s += partial[((int64_t)v * nblk + i) * NLB + idx];
-    g_coeff[t] = s;
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x)
+        s += partial[((int64_t)v * nblk + i) * NLB + idx];
+    __shared__ float red[4];
+    s = wave_sum_lane63(s);
+    if ((threadIdx.x & 63) == 63) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) g_coeff[t] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // ----------------------------------------------------------- basis adjoint
@@ -304,7 +309,7 @@ hipError_t launch_combine_bwd(const LevelsK &lv, const GridK *lvl_grids, const f
     const int tot = V * per;
     {
         ProfScope prof_("combine_bwd_reduce", s);
-        k_reduce_coeff<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(partial, nblk, V, per, g_coeff);
+        k_reduce_coeff<<<(unsigned)tot, 256, 0, s>>>(partial, nblk, per, g_coeff);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     for (int l = 0; l < lv.L; ++l) {

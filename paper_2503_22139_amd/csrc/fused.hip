@@ -58,22 +58,42 @@ __global__ __launch_bounds__(256) void k_combine_warp(const float *__restrict__ 
 constexpr int FB = 8;
 constexpr int HALO = 3;
 constexpr int HB = FB + 2 * HALO + 1;
+constexpr int HB3 = HB * HB * HB;
 constexpr int VCH = 64;
+constexpr int FLUSH = 8;   // views per fixed-point accumulation round
+constexpr int LO_BITS = 18; // 512 * FLUSH * 2^(LO_BITS-1) < 2^31
 
 struct GOut {
     float *dst[MAXL];   // per level: [3B][N] destination (g_bases or staging buffer)
 };
 
+// Warp adjoint and Eq. 3 adjoint of one 8^3 brick for a chunk of views.
+// dL/dI_ref is scattered into an LDS box (brick + halo) in fixed point with
+// integer LDS atomics: per round of up to FLUSH views the scale is
+// 2^30 / (512 * views * M) with M the largest |dL/dI_v| of those views, which
+// bounds every partial sum; each scaled contribution is split into its
+// nearest integer (high word) and the remainder times 2^LO_BITS (low word),
+// so the two 32-bit sums keep about 48 bits; each round is folded into a
+// float box.
+// The float box is staged per brick and summed by k_gather_boxes;
+// displacements that leave the halo fall back to global atomics.
 template <int L, int B>
 __global__ __launch_bounds__(256) void k_warp_combine_bwd(
     const float *__restrict__ ref, GridK g, LevelsK lv, const float *__restrict__ coeff, int V,
-    const float *__restrict__ g_I, float *__restrict__ g_ref, GOut gout, int accumulate, int nb1,
-    int nb2, float *__restrict__ partial) {
+    const float *__restrict__ g_I, const unsigned *__restrict__ vmax, float *__restrict__ g_ref,
+    float *__restrict__ stage, GOut gout, int accumulate, int nb1, int nb2,
+    float *__restrict__ partial) {
     constexpr int NC = L * B * 3;
     extern __shared__ float smem[];
-    float *box = smem;                  // HB^3
-    float *cacc = smem + HB * HB * HB;  // V * NC
-    for (int i = threadIdx.x; i < HB * HB * HB; i += blockDim.x) box[i] = 0.0f;
+    int *ibox = (int *)smem;              // HB^3 fixed point, high words
+    int *lbox = (int *)smem + HB3;        // HB^3 fixed point, low words
+    float *fbox = smem + 2 * HB3;         // HB^3 float
+    float *cacc = smem + 3 * HB3;         // V * NC
+    for (int i = threadIdx.x; i < HB3; i += blockDim.x) {
+        ibox[i] = 0;
+        lbox[i] = 0;
+        fbox[i] = 0.0f;
+    }
     for (int i = threadIdx.x; i < V * NC; i += blockDim.x) cacc[i] = 0.0f;
     const int bid = blockIdx.x;
     const int b2 = bid % nb2, b1 = (bid / nb2) % nb1, b0 = bid / (nb2 * nb1);
@@ -107,87 +127,117 @@ __global__ __launch_bounds__(256) void k_warp_combine_bwd(
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
-    for (int v = 0; v < V; ++v) {
-        const float *cv = coeff + (int64_t)v * L * B * 3;
-        float gD[2][3];
+    for (int r0 = 0; r0 < V; r0 += FLUSH) {
+        const int r1 = min(V, r0 + FLUSH);
+        float M = 0.0f;
+        for (int v = r0; v < r1; ++v) M = fmaxf(M, __uint_as_float(vmax[v]));
+        const float scale = M > 0.0f ? 1073741824.0f / (512.0f * (float)(r1 - r0) * M) : 0.0f;
+        for (int v = r0; v < r1; ++v) {
+            const float *cv = coeff + (int64_t)v * L * B * 3;
+            float gD[2][3];
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            gD[q][0] = gD[q][1] = gD[q][2] = 0.0f;
-            if (!ok[q]) continue;
-            float d[3];
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                float t = 0.0f;
-#pragma unroll
-                for (int l = 0; l < L; ++l)
-#pragma unroll
-                    for (int b = 0; b < B; ++b) t = fmaf(cv[(l * B + b) * 3 + k], sv[q][l][b][k], t);
-                d[k] = t;
-            }
-            const float u0 = fmaf(d[0], g.inv_h[0], (float)vx[q]);
-            const float u1 = fmaf(d[1], g.inv_h[1], (float)vy[q]);
-            const float u2 = fmaf(d[2], g.inv_h[2], (float)vz[q]);
-            int i0, i1, i2;
-            float f0, f1, f2;
-            if (!axis_cell(u0, g.n[0], i0, f0) || !axis_cell(u1, g.n[1], i1, f1) ||
-                !axis_cell(u2, g.n[2], i2, f2))
-                continue;
-            const float go = g_I[(int64_t)v * N + jj[q]];
-            if (go == 0.0f) continue;
-            const int64_t base = ((int64_t)i0 * g.n[1] + i1) * g.n[2] + i2;
-            const float *p = ref + base;
-            const float c000 = p[0], c001 = p[1], c010 = p[s1], c011 = p[s1 + 1];
-            const float c100 = p[s0], c101 = p[s0 + 1], c110 = p[s0 + s1], c111 = p[s0 + s1 + 1];
-            const float a00 = lerp1(c000, c001, f2), a01 = lerp1(c010, c011, f2);
-            const float a10 = lerp1(c100, c101, f2), a11 = lerp1(c110, c111, f2);
-            const float ddx = lerp1(a10, a11, f1) - lerp1(a00, a01, f1);
-            const float ddy = lerp1(a01, a11, f0) - lerp1(a00, a10, f0);
-            const float e00 = lerp1(c000, c010, f1), e01 = lerp1(c001, c011, f1);
-            const float e10 = lerp1(c100, c110, f1), e11 = lerp1(c101, c111, f1);
-            const float ddz = lerp1(e01, e11, f0) - lerp1(e00, e10, f0);
-            gD[q][0] = go * ddx * g.inv_h[0] * axis_free(u0, g.n[0]);
-            gD[q][1] = go * ddy * g.inv_h[1] * axis_free(u1, g.n[1]);
-            gD[q][2] = go * ddz * g.inv_h[2] * axis_free(u2, g.n[2]);
-            const float w0[2] = {1.0f - f0, f0}, w1[2] = {1.0f - f1, f1}, w2[2] = {1.0f - f2, f2};
-            const int l0 = i0 - (B0 - HALO), l1 = i1 - (B1 - HALO), l2 = i2 - (B2 - HALO);
-            const bool inbox = l0 >= 0 && l0 + 1 < HB && l1 >= 0 && l1 + 1 < HB && l2 >= 0 &&
-                               l2 + 1 < HB;
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int b = 0; b < 2; ++b)
-#pragma unroll
-                    for (int c = 0; c < 2; ++c) {
-                        const float w = go * w0[a] * w1[b] * w2[c];
-                        if (inbox)
-                            atomicAdd(&box[((l0 + a) * HB + (l1 + b)) * HB + (l2 + c)], w);
-                        else
-                            unsafeAtomicAdd(&g_ref[base + a * s0 + b * s1 + c], w);
-                    }
-        }
-#pragma unroll
-        for (int l = 0; l < L; ++l)
-#pragma unroll
-            for (int b = 0; b < B; ++b)
+            for (int q = 0; q < 2; ++q) {
+                gD[q][0] = gD[q][1] = gD[q][2] = 0.0f;
+                if (!ok[q]) continue;
+                float d[3];
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
-                    const float c = cv[(l * B + b) * 3 + k];
-                    G[0][l][b][k] = fmaf(c, gD[0][k], G[0][l][b][k]);
-                    G[1][l][b][k] = fmaf(c, gD[1][k], G[1][l][b][k]);
-                    const float t =
-                        warp_sum(fmaf(gD[0][k], sv[0][l][b][k], gD[1][k] * sv[1][l][b][k]));
-                    if (lane == 0) atomicAdd(&cacc[v * NC + (l * B + b) * 3 + k], t);
+                    float t = 0.0f;
+#pragma unroll
+                    for (int l = 0; l < L; ++l)
+#pragma unroll
+                        for (int b = 0; b < B; ++b)
+                            t = fmaf(cv[(l * B + b) * 3 + k], sv[q][l][b][k], t);
+                    d[k] = t;
                 }
+                const float u0 = fmaf(d[0], g.inv_h[0], (float)vx[q]);
+                const float u1 = fmaf(d[1], g.inv_h[1], (float)vy[q]);
+                const float u2 = fmaf(d[2], g.inv_h[2], (float)vz[q]);
+                int i0, i1, i2;
+                float f0, f1, f2;
+                if (!axis_cell(u0, g.n[0], i0, f0) || !axis_cell(u1, g.n[1], i1, f1) ||
+                    !axis_cell(u2, g.n[2], i2, f2))
+                    continue;
+                const float go = g_I[(int64_t)v * N + jj[q]];
+                if (go == 0.0f) continue;
+                const int64_t base = ((int64_t)i0 * g.n[1] + i1) * g.n[2] + i2;
+                const float *p = ref + base;
+                const float c000 = p[0], c001 = p[1], c010 = p[s1], c011 = p[s1 + 1];
+                const float c100 = p[s0], c101 = p[s0 + 1], c110 = p[s0 + s1],
+                            c111 = p[s0 + s1 + 1];
+                const float a00 = lerp1(c000, c001, f2), a01 = lerp1(c010, c011, f2);
+                const float a10 = lerp1(c100, c101, f2), a11 = lerp1(c110, c111, f2);
+                const float ddx = lerp1(a10, a11, f1) - lerp1(a00, a01, f1);
+                const float ddy = lerp1(a01, a11, f0) - lerp1(a00, a10, f0);
+                const float e00 = lerp1(c000, c010, f1), e01 = lerp1(c001, c011, f1);
+                const float e10 = lerp1(c100, c110, f1), e11 = lerp1(c101, c111, f1);
+                const float ddz = lerp1(e01, e11, f0) - lerp1(e00, e10, f0);
+                gD[q][0] = go * ddx * g.inv_h[0] * axis_free(u0, g.n[0]);
+                gD[q][1] = go * ddy * g.inv_h[1] * axis_free(u1, g.n[1]);
+                gD[q][2] = go * ddz * g.inv_h[2] * axis_free(u2, g.n[2]);
+                const int l0 = i0 - (B0 - HALO), l1 = i1 - (B1 - HALO), l2 = i2 - (B2 - HALO);
+                const bool inbox = l0 >= 0 && l0 + 1 < HB && l1 >= 0 && l1 + 1 < HB && l2 >= 0 &&
+                                   l2 + 1 < HB;
+                if (inbox) {
+                    const float gs = go * scale;
+                    const float wx0 = gs * (1.0f - f0), wx1 = gs * f0;
+                    const float q00 = wx0 * (1.0f - f1), q01 = wx0 * f1;
+                    const float q10 = wx1 * (1.0f - f1), q11 = wx1 * f1;
+                    const float g2 = 1.0f - f2;
+                    const int o = (l0 * HB + l1) * HB + l2;
+                    const float cw[8] = {q00 * g2, q00 * f2, q01 * g2, q01 * f2,
+                                         q10 * g2, q10 * f2, q11 * g2, q11 * f2};
+                    const int off[8] = {0, 1, HB, HB + 1, HB * HB, HB * HB + 1, HB * HB + HB,
+                                        HB * HB + HB + 1};
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        const float hi = rintf(cw[k]);
+                        atomicAdd(ibox + o + off[k], (int)hi);
+                        atomicAdd(lbox + o + off[k], __float2int_rn((cw[k] - hi) * (float)(1 << LO_BITS)));
+                    }
+                } else {
+                    const float w0[2] = {1.0f - f0, f0}, w1[2] = {1.0f - f1, f1},
+                                w2[2] = {1.0f - f2, f2};
+#pragma unroll
+                    for (int a = 0; a < 2; ++a)
+#pragma unroll
+                        for (int b = 0; b < 2; ++b)
+#pragma unroll
+                            for (int c = 0; c < 2; ++c)
+                                unsafeAtomicAdd(&g_ref[base + a * s0 + b * s1 + c],
+                                                go * w0[a] * w1[b] * w2[c]);
+                }
+            }
+#pragma unroll
+            for (int l = 0; l < L; ++l)
+#pragma unroll
+                for (int b = 0; b < B; ++b)
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        const float c = cv[(l * B + b) * 3 + k];
+                        G[0][l][b][k] = fmaf(c, gD[0][k], G[0][l][b][k]);
+                        G[1][l][b][k] = fmaf(c, gD[1][k], G[1][l][b][k]);
+                        const float t = wave_sum_lane63(
+                            fmaf(gD[0][k], sv[0][l][b][k], gD[1][k] * sv[1][l][b][k]));
+                        if (lane == 63) atomicAdd(&cacc[v * NC + (l * B + b) * 3 + k], t);
+                    }
+        }
+        __syncthreads();
+        if (scale > 0.0f) {
+            const float inv = 1.0f / scale;
+            for (int i = threadIdx.x; i < HB3; i += blockDim.x) {
+                const int t = ibox[i], u = lbox[i];
+                if (t | u) {
+                    fbox[i] += ((float)t + (float)u * (1.0f / (float)(1 << LO_BITS))) * inv;
+                    ibox[i] = 0;
+                    lbox[i] = 0;
+                }
+            }
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < HB * HB * HB; i += blockDim.x) {
-        const float val = box[i];
-        if (val == 0.0f) continue;
-        const int z = B2 - HALO + i % HB, y = B1 - HALO + (i / HB) % HB,
-                  x = B0 - HALO + i / (HB * HB);
-        if (x < 0 || y < 0 || z < 0 || x >= g.n[0] || y >= g.n[1] || z >= g.n[2]) continue;
-        unsafeAtomicAdd(&g_ref[((int64_t)x * g.n[1] + y) * g.n[2] + z], val);
-    }
+    float *st = stage + (int64_t)blockIdx.x * HB3;
+    for (int i = threadIdx.x; i < HB3; i += blockDim.x) st[i] = fbox[i];
     for (int i = threadIdx.x; i < V * NC; i += blockDim.x)
         partial[(int64_t)blockIdx.x * V * NC + i] = cacc[i];
 #pragma unroll
@@ -205,14 +255,45 @@ __global__ __launch_bounds__(256) void k_warp_combine_bwd(
     }
 }
 
-// g_coeff[v0 + v][...] = sum over bricks of the per-brick partials, in brick order.
-__global__ void k_reduce_coeff_blocks(const float *__restrict__ partial, int nblk, int V, int NC,
-                                      float *__restrict__ g_coeff) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= V * NC) return;
+// g_ref[p] += sum of the staged boxes that cover voxel p (at most 2 bricks
+// per axis), in a fixed order.
+__global__ __launch_bounds__(256) void k_gather_boxes(const float *__restrict__ stage, GridK g,
+                                                      int nb0, int nb1, int nb2,
+                                                      float *__restrict__ g_ref) {
+    const int64_t N = grid_size(g);
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    const int p2 = (int)(j % g.n[2]);
+    const int p1 = (int)((j / g.n[2]) % g.n[1]);
+    const int p0 = (int)(j / ((int64_t)g.n[2] * g.n[1]));
+    // bricks b with b*FB - HALO <= p <= b*FB + FB + HALO
+    const int a0 = max(0, (p0 - FB - HALO + FB - 1) / FB), e0 = min(nb0 - 1, (p0 + HALO) / FB);
+    const int a1 = max(0, (p1 - FB - HALO + FB - 1) / FB), e1 = min(nb1 - 1, (p1 + HALO) / FB);
+    const int a2 = max(0, (p2 - FB - HALO + FB - 1) / FB), e2 = min(nb2 - 1, (p2 + HALO) / FB);
     float s = 0.0f;
-    for (int i = 0; i < nblk; ++i) s += partial[(int64_t)i * V * NC + t];
-    g_coeff[t] = s;
+    for (int b0 = a0; b0 <= e0; ++b0)
+        for (int b1 = a1; b1 <= e1; ++b1)
+            for (int b2 = a2; b2 <= e2; ++b2) {
+                const int l0 = p0 - (b0 * FB - HALO), l1 = p1 - (b1 * FB - HALO),
+                          l2 = p2 - (b2 * FB - HALO);
+                s += stage[((int64_t)(b0 * nb1 + b1) * nb2 + b2) * HB3 + (l0 * HB + l1) * HB + l2];
+            }
+    g_ref[j] += s;
+}
+
+// g_coeff[v0 + v][...] = sum over bricks of the per-brick partials: one
+// workgroup per output entry, fixed-order tree (deterministic).
+__global__ __launch_bounds__(256) void k_reduce_coeff_blocks(const float *__restrict__ partial,
+                                                             int nblk, int V, int NC,
+                                                             float *__restrict__ g_coeff) {
+    const int t = blockIdx.x;
+    float s = 0.0f;
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) s += partial[(int64_t)i * V * NC + t];
+    __shared__ float red[4];
+    s = wave_sum_lane63(s);
+    if ((threadIdx.x & 63) == 63) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) g_coeff[t] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 size_t warp_project_workspace(const LevelsK &lv, int V, const GridK &g, const pmf_cone_t &c) {
@@ -240,7 +321,7 @@ hipError_t launch_warp_project(const float *ref, const GridK &g, const LevelsK &
 }
 
 struct BwdLayout {
-    size_t gI, rays, gbuf, partial, adj, total;
+    size_t gI, rays, gbuf, partial, stage, vmax, adj, total;
     int nbrick, nb[3];
 };
 
@@ -267,8 +348,10 @@ static BwdLayout bwd_layout(const LevelsK &lv, const GridK *lvl_grids, int V, co
     b.rays = project_bwd_workspace(pc, V);
     b.gbuf = align256(sizeof(float) * (size_t)N * 3 * lv.B * (size_t)ncoarse);
     b.partial = align256(sizeof(float) * (size_t)b.nbrick * vc * lv.L * lv.B * 3);
+    b.stage = align256(sizeof(float) * (size_t)b.nbrick * HB3);
+    b.vmax = align256(sizeof(unsigned) * (size_t)V);
     b.adj = adj;
-    b.total = b.gI + b.rays + b.gbuf + b.partial + b.adj;
+    b.total = b.gI + b.rays + b.gbuf + b.partial + b.stage + b.vmax + b.adj;
     return b;
 }
 
@@ -292,11 +375,17 @@ hipError_t launch_warp_project_bwd(const float *ref, const GridK &g, const Level
     w += lay.gbuf;
     float *partial = (float *)w;
     w += lay.partial;
+    float *stage = (float *)w;
+    w += lay.stage;
+    unsigned *vmax = (unsigned *)w;
+    w += lay.vmax;
     void *adjws = w;
     const int64_t N = grid_size(g);
     const int NC = lv.L * lv.B * 3;
 
-    hipError_t e = launch_project_bwd(g_proj, g, c, angles, V, gI, N, rays, s);
+    hipError_t e = launch_fill_i32((int32_t *)vmax, V, 0, s);
+    if (e != hipSuccess) return e;
+    e = launch_project_bwd(g_proj, g, c, angles, V, gI, N, rays, s, vmax);
     if (e != hipSuccess) return e;
     if ((e = launch_fill(g_ref, N, 0.0f, s)) != hipSuccess) return e;
     GOut gout;
@@ -314,21 +403,27 @@ hipError_t launch_warp_project_bwd(const float *ref, const GridK &g, const Level
     }
     for (int v0 = 0; v0 < V; v0 += VCH) {
         const int vc = V - v0 < VCH ? V - v0 : VCH;
-        const size_t lds = sizeof(float) * ((size_t)HB * HB * HB + (size_t)vc * NC);
+        const size_t lds = sizeof(float) * (3 * (size_t)HB3 + (size_t)vc * NC);
         e = dispatch_lb(lv.L, lv.B, [&](auto Lc, auto Bc) {
             constexpr int L = decltype(Lc)::value, B = decltype(Bc)::value;
             {
                 ProfScope prof_("warp_combine_bwd", s);
                 k_warp_combine_bwd<L, B><<<(unsigned)lay.nbrick, 256, lds, s>>>(
-                    ref, g, lv, coeff + (int64_t)v0 * NC, vc, gI + (int64_t)v0 * N, g_ref, gout,
-                    v0 > 0, lay.nb[1], lay.nb[2], partial);
+                    ref, g, lv, coeff + (int64_t)v0 * NC, vc, gI + (int64_t)v0 * N, vmax + v0,
+                    g_ref, stage, gout, v0 > 0, lay.nb[1], lay.nb[2], partial);
             }
             return hipGetLastError();
         });
         if (e != hipSuccess) return e;
         {
+            ProfScope prof_("gather_boxes", s);
+            k_gather_boxes<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(stage, g, lay.nb[0],
+                                                                      lay.nb[1], lay.nb[2], g_ref);
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        {
             ProfScope prof_("coeff_reduce", s);
-            k_reduce_coeff_blocks<<<(unsigned)((vc * NC + 255) / 256), 256, 0, s>>>(
+            k_reduce_coeff_blocks<<<(unsigned)(vc * NC), 256, 0, s>>>(
                 partial, lay.nbrick, vc, NC, g_coeff + (int64_t)v0 * NC);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;

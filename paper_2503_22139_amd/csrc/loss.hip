@@ -16,8 +16,8 @@ __global__ __launch_bounds__(256) void k_l2(const float *__restrict__ p,
         if (g) g[i] = gscale * r;
     }
     __shared__ float red[4];
-    acc = warp_sum(acc);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    acc = wave_sum_lane63(acc);
+    if ((threadIdx.x & 63) == 63) red[threadIdx.x >> 6] = acc;
     __syncthreads();
     if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }

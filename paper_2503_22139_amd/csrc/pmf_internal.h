@@ -97,6 +97,23 @@ __device__ __forceinline__ float warp_sum(float v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
+
+// Sum over the 64 lanes of a wave with DPP moves (VALU only, no LDS).
+// The total is valid in lane 63 (other lanes hold partial sums).
+template <int CTRL, int ROW_MASK = 0xf, int BANK_MASK = 0xf>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK,
+                                                      BANK_MASK, true));
+}
+__device__ __forceinline__ float wave_sum_lane63(float v) {
+    v += dpp_mov<0xB1>(v);              // quad_perm [1,0,3,2]: pairs
+    v += dpp_mov<0x4E>(v);              // quad_perm [2,3,0,1]: quads
+    v += dpp_mov<0x141>(v);             // row_half_mirror: 8 lanes
+    v += dpp_mov<0x140>(v);             // row_mirror: 16 lanes (a row)
+    v += dpp_mov<0x142, 0xa>(v);        // row_bcast:15 into rows 1, 3
+    v += dpp_mov<0x143, 0xc>(v);        // row_bcast:31 into rows 2, 3
+    return v;
+}
 #endif
 
 // ------------------------------------------------- basis upsampling helpers
@@ -236,9 +253,10 @@ hipError_t launch_warp_bwd(const float *ref, const GridK &g, const float *dvf, i
 hipError_t launch_project(const float *vol, int64_t stride, const GridK &g, const ConeK &c,
                           const float *angles, int V, float *proj, hipStream_t s);
 size_t project_bwd_workspace(const pmf_cone_t &c, int V);
+// vmax (optional, [V] zeroed uint): largest |g_vol| of each view, as float bits
 hipError_t launch_project_bwd(const float *g_proj, const GridK &g, const ConeK &c,
                               const float *angles, int V, float *g_vol, int64_t stride, void *ws,
-                              hipStream_t s);
+                              hipStream_t s, unsigned *vmax = nullptr);
 
 // loss
 size_t l2_workspace(int64_t npix, int V);

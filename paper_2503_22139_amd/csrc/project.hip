@@ -21,7 +21,7 @@ namespace pmf {
 // Per-ray set-up of the midpoint rule, in double precision (a few dozen
 // operations per ray against hundreds of samples).  Kept free of FMA
 // contraction so every kernel that calls it gets identical bits.
-__device__ __attribute__((noinline)) RayK ray_setup(const GridK &g, const ConeK &c, double ct,
+__device__ __forceinline__ RayK ray_setup(const GridK &g, const ConeK &c, double ct,
                                                      double st, int iu, int iv) {
 #pragma clang fp contract(off)
     const double o0 = c.sad * ct, o1 = c.sad * st;
@@ -79,6 +79,40 @@ __device__ __attribute__((noinline)) RayK ray_setup(const GridK &g, const ConeK 
 
 constexpr int PT = 16;  // forward pixel tile edge
 
+// Branch-free cell coordinate on one axis (same arithmetic as axis_cell):
+// fi = clamped cell index as a float, f = fraction; ok = inside the box.
+__device__ __forceinline__ void cell_bf(float u, int n, float &fi, float &f, bool &ok) {
+    const float nm1 = (float)(n - 1);
+    ok = (u >= -0.5f) && (u <= (float)n - 0.5f);
+    const float uc = fminf(fmaxf(u, 0.0f), nm1);
+    fi = fminf(floorf(uc), nm1 - 1.0f);
+    f = uc - fi;
+}
+
+// Trilinear sample at voxel coordinate u (0 outside the box), branch-free:
+// the cell is clamped into the grid so the 4 z-pair loads are always valid.
+__device__ __forceinline__ float sample_bf(const float *__restrict__ vol, const GridK &g,
+                                           uint32_t s0, uint32_t s1, float u0, float u1,
+                                           float u2) {
+    float c0, c1, c2, f0, f1, f2;
+    bool k0, k1, k2;
+    cell_bf(u0, g.n[0], c0, f0, k0);
+    cell_bf(u1, g.n[1], c1, f1, k1);
+    cell_bf(u2, g.n[2], c2, f2, k2);
+    const uint32_t idx = ((uint32_t)c0 * (uint32_t)g.n[1] + (uint32_t)c1) * (uint32_t)g.n[2] +
+                         (uint32_t)c2;
+    const float *p = vol + idx;
+    const float *pb = p + s1, *pd = p + s0, *pe = pd + s1;
+    const float a0 = p[0], a1 = p[1];
+    const float b0 = pb[0], b1 = pb[1];
+    const float d0 = pd[0], d1 = pd[1];
+    const float e0 = pe[0], e1 = pe[1];
+    const float x00 = lerp1(a0, a1, f2), x01 = lerp1(b0, b1, f2);
+    const float x10 = lerp1(d0, d1, f2), x11 = lerp1(e0, e1, f2);
+    const float v = lerp1(lerp1(x00, x01, f1), lerp1(x10, x11, f1), f0);
+    return (k0 && k1 && k2) ? v : 0.0f;
+}
+
 __global__ __launch_bounds__(256) void k_project(const float *__restrict__ vol, int64_t stride,
                                                  GridK g, ConeK c,
                                                  const float *__restrict__ angles,
@@ -91,13 +125,22 @@ __global__ __launch_bounds__(256) void k_project(const float *__restrict__ vol, 
     const double th = (double)angles[v];
     const RayK r = ray_setup(g, c, cos(th), sin(th), iu, iv);
     const float *__restrict__ vv = vol + (int64_t)v * stride;
-    float acc = 0.0f;
-    for (int s = 0; s < r.n; ++s) {
-        const float sf = (float)s;
-        acc += sample_u(vv, g.n, fmaf(sf, r.su[0], r.bu[0]), fmaf(sf, r.su[1], r.bu[1]),
-                        fmaf(sf, r.su[2], r.bu[2]));
+    const uint32_t s1 = (uint32_t)g.n[2], s0 = (uint32_t)g.n[1] * (uint32_t)g.n[2];
+    float acc0 = 0.0f, acc1 = 0.0f;
+    int s = 0;
+    for (; s + 1 < r.n; s += 2) {
+        const float sa = (float)s, sb = (float)(s + 1);
+        acc0 += sample_bf(vv, g, s0, s1, fmaf(sa, r.su[0], r.bu[0]), fmaf(sa, r.su[1], r.bu[1]),
+                          fmaf(sa, r.su[2], r.bu[2]));
+        acc1 += sample_bf(vv, g, s0, s1, fmaf(sb, r.su[0], r.bu[0]), fmaf(sb, r.su[1], r.bu[1]),
+                          fmaf(sb, r.su[2], r.bu[2]));
     }
-    proj[((int64_t)v * c.nv + iv) * c.nu + iu] = acc * r.delta;
+    if (s < r.n) {
+        const float sa = (float)s;
+        acc0 += sample_bf(vv, g, s0, s1, fmaf(sa, r.su[0], r.bu[0]), fmaf(sa, r.su[1], r.bu[1]),
+                          fmaf(sa, r.su[2], r.bu[2]));
+    }
+    proj[((int64_t)v * c.nv + iv) * c.nu + iu] = (acc0 + acc1) * r.delta;
 }
 
 __global__ __launch_bounds__(256) void k_ray_table(GridK g, ConeK c,
@@ -136,109 +179,224 @@ __device__ void shadow_rect(const ConeK &c, double ct, double st, const double l
     v1 = (int)fmin(ceil(vmax) + 1.0, (double)(c.nv - 1));
 }
 
-// g_vol (per view, or summed over views when sum_views) of one brick.
+
+struct BoundK {
+    float mag, persp, R, Z, two_hx, two_hy, two_hz, inv_du, inv_dv, diag;
+};
+
+// g_vol (per view, or summed over views when sum_views) of one S^3 brick.
+//
+// The LDS accumulator spans the brick plus one voxel on every side, so the
+// 8 corners of every owned sample land inside it; the pad is dropped on
+// write-out (it belongs to the neighbouring bricks, which take those
+// samples themselves).
+//
+// Accumulation is in 32-bit fixed point with integer LDS atomics (float LDS
+// atomics run about 30x slower on gfx950).  For each (brick, view) the scale
+// is 2^30 / (kbound * M), where M is the largest |g_proj * delta| among the
+// rays that reach the brick and kbound bounds how many samples can touch one
+// voxel in this view (from the geometry and the rays' smallest step): every
+// partial sum stays below 2^30 in magnitude, and each contribution is
+// rounded to within 0.5 / scale.
+// With vmax non-null the largest |g_vol| of each view is also recorded.
+template <int S, bool SUM>
 __global__ __launch_bounds__(256) void k_project_bwd(const float *__restrict__ g_proj, GridK g,
                                                      ConeK c, const float *__restrict__ angles,
                                                      const RayK *__restrict__ rays, int V,
                                                      float *__restrict__ g_vol, int64_t stride,
-                                                     int S0, int S1, int S2, int nb1, int nb2,
-                                                     int sum_views) {
-    extern __shared__ float acc[];
-    const int nvox = S0 * S1 * S2;
+                                                     int nb1, int nb2, BoundK kb,
+                                                     unsigned *__restrict__ vmax) {
+    constexpr bool sum_views = SUM;
+    constexpr int P = S + 2;                    // padded edge
+    constexpr int NP = P * P * P;
+    constexpr int PER = (NP + 255) / 256;       // padded entries per thread
+    __shared__ int acc[NP];
+    __shared__ float red[8];
     const int bid = blockIdx.x;
     const int b2 = bid % nb2, b1 = (bid / nb2) % nb1, b0 = bid / (nb2 * nb1);
-    const int B[3] = {b0 * S0, b1 * S1, b2 * S2};
-    const int S[3] = {S0, S1, S2};
-    for (int i = threadIdx.x; i < nvox; i += blockDim.x) acc[i] = 0.0f;
+    const int B[3] = {b0 * S, b1 * S, b2 * S};
 
-    int clo[3], chi[3];
-    float ulo[3], uhi[3];
+    // owned cells [clo, chi] and their extent in voxel units [ulo, uhi]
+    float clo[3], chi[3], ulo[3], uhi[3];
     double wlo[3], whi[3];
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
-        clo[a] = max(B[a] - 1, 0);
-        chi[a] = min(B[a] + S[a] - 1, g.n[a] - 2);
-        ulo[a] = clo[a] == 0 ? -0.5f : (float)clo[a];
-        uhi[a] = chi[a] == g.n[a] - 2 ? (float)g.n[a] - 0.5f : (float)(chi[a] + 1);
+        const int lo = max(B[a] - 1, 0), hi = min(B[a] + S - 1, g.n[a] - 2);
+        clo[a] = (float)lo;
+        chi[a] = (float)hi;
+        ulo[a] = lo == 0 ? -0.5f : (float)lo;
+        uhi[a] = hi == g.n[a] - 2 ? (float)g.n[a] - 0.5f : (float)(hi + 1);
         wlo[a] = g.c0d[a] + ((double)ulo[a] - 0.5) * g.hd[a];
         whi[a] = g.c0d[a] + ((double)uhi[a] + 0.5) * g.hd[a];
     }
-    __syncthreads();
+    const float o0 = (float)(B[0] - 1), o1 = (float)(B[1] - 1), o2 = (float)(B[2] - 1);
+    float sum[SUM ? PER : 1];   // per-thread float accumulation over views (strided entries)
+#pragma unroll
+    for (int k = 0; k < (SUM ? PER : 1); ++k) sum[k] = 0.0f;
+    float last_inv = 0.0f;      // per-view mode: 1/scale of the one view
 
     const int vb = sum_views ? 0 : blockIdx.y;
     const int ve = sum_views ? V : blockIdx.y + 1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lx = lane & 7, ly = lane >> 3;
     for (int v = vb; v < ve; ++v) {
         const double th = (double)angles[v];
         const double ct = cos(th), st = sin(th);
         int u0, u1, v0, v1;
-        shadow_rect(c, ct, st, wlo, whi, u0, u1, v0, v1);
+        shadow_rect(c, ct, st, wlo, whi, u0, u1, v0, v1);   // uniform across the block
         if (u1 < u0 || v1 < v0) continue;
-        const int rw = u1 - u0 + 1;
-        const int nr = rw * (v1 - v0 + 1);
-        for (int q = threadIdx.x; q < nr; q += blockDim.x) {
-            const int iu = u0 + q % rw, iv = v0 + q / rw;
+        // The 64 lanes of a wave take an 8x8 grid of pixels spread over the
+        // rectangle (strides gu, gv); the waves sweep the gu*gv offsets.
+        const int gu = (u1 - u0 + 8) / 8, gv = (v1 - v0 + 8) / 8;
+        const int nph = gu * gv;
+        const int nw = (int)(blockDim.x >> 6);
+        // pass 1: largest |g_proj * delta| and smallest step over the rays,
+        // and zero the accumulator
+        float m = 0.0f, dmin = INFINITY;
+        for (int ph = wave; ph < nph; ph += nw) {
+            const int iu = u0 + lx * gu + ph % gu, iv = v0 + ly * gv + ph / gu;
+            if (iu > u1 || iv > v1) continue;
             const int64_t pix = ((int64_t)v * c.nv + iv) * c.nu + iu;
             const RayK r = rays[pix];
             if (r.n == 0) continue;
-            const float gp = g_proj[pix] * r.delta;
-            if (gp == 0.0f) continue;
+            m = fmaxf(m, fabsf(g_proj[pix] * r.delta));
+            dmin = fminf(dmin, r.delta);
+        }
+        for (int i = threadIdx.x; i < NP; i += blockDim.x) acc[i] = 0;
+        for (int o = 32; o > 0; o >>= 1) {
+            m = fmaxf(m, __shfl_xor(m, o, 64));
+            dmin = fminf(dmin, __shfl_xor(dmin, o, 64));
+        }
+        if (lane == 0) {
+            red[wave] = m;
+            red[4 + wave] = dmin;
+        }
+        __syncthreads();
+        m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+        dmin = fminf(fminf(red[4], red[5]), fminf(red[6], red[7]));
+        __syncthreads();
+        if (!(m > 0.0f)) continue;
+        // Contributions one voxel can receive in this view: rays through the
+        // detector shadow of its 2x2x2-cell support, times samples of one ray
+        // inside that support (its diagonal over the smallest step, plus one).
+        const float as = fabsf((float)st), ac = fabsf((float)ct);
+        const float lat = kb.two_hx * as + kb.two_hy * ac;    // lateral extent (mm)
+        const float dep = kb.two_hx * ac + kb.two_hy * as;    // depth extent (mm)
+        const float wu = lat * kb.mag + kb.R * kb.persp * dep;
+        const float wv = kb.two_hz * kb.mag + kb.Z * kb.persp * dep;
+        const float nr = (floorf(wu * kb.inv_du) + 1.0f) * (floorf(wv * kb.inv_dv) + 1.0f);
+        const float ns = floorf(kb.diag / dmin) + 1.0f;
+        const float kbound = nr * ns * 1.0625f + 1.0f;
+        const float scale = 1073741824.0f / (kbound * m);   // 2^30 / (kbound M)
+        // pass 2: scatter every owned sample's 8 weights
+        for (int ph = wave; ph < nph; ph += nw) {
+            const int iu = u0 + lx * gu + ph % gu, iv = v0 + ly * gv + ph / gu;
+            if (iu > u1 || iv > v1) continue;
+            const int64_t pix = ((int64_t)v * c.nv + iv) * c.nu + iu;
+            const RayK r = rays[pix];
+            const float gp = g_proj[pix] * r.delta * scale;
+            if (r.n == 0 || gp == 0.0f) continue;
             float smin = 0.0f, smax = (float)(r.n - 1);
-            bool skip = false;
+#pragma unroll
             for (int a = 0; a < 3; ++a) {
                 if (r.su[a] != 0.0f) {
-                    const float ta = (ulo[a] - r.bu[a]) / r.su[a];
-                    const float tb = (uhi[a] - r.bu[a]) / r.su[a];
+                    const float inv = 1.0f / r.su[a];
+                    const float ta = (ulo[a] - r.bu[a]) * inv, tb = (uhi[a] - r.bu[a]) * inv;
                     smin = fmaxf(smin, fminf(ta, tb));
                     smax = fminf(smax, fmaxf(ta, tb));
                 } else if (r.bu[a] < ulo[a] - 1.0f || r.bu[a] > uhi[a] + 1.0f) {
-                    skip = true;
+                    smax = -10.0f;
                 }
             }
-            if (skip || smin > smax + 2.0f) continue;
+            if (smin > smax + 2.0f) continue;
             const int s0 = max(0, (int)floorf(smin) - 1);
             const int s1 = min(r.n - 1, (int)ceilf(smax) + 1);
             for (int s = s0; s <= s1; ++s) {
                 const float sf = (float)s;
-                int i0, i1, i2;
-                float f0, f1, f2;
-                if (!axis_cell(fmaf(sf, r.su[0], r.bu[0]), g.n[0], i0, f0) ||
-                    !axis_cell(fmaf(sf, r.su[1], r.bu[1]), g.n[1], i1, f1) ||
-                    !axis_cell(fmaf(sf, r.su[2], r.bu[2]), g.n[2], i2, f2))
-                    continue;
-                if (i0 < clo[0] || i0 > chi[0] || i1 < clo[1] || i1 > chi[1] || i2 < clo[2] ||
-                    i2 > chi[2])
-                    continue;
-                const float w0[2] = {1.0f - f0, f0}, w1[2] = {1.0f - f1, f1},
-                            w2[2] = {1.0f - f2, f2};
-                const int l0 = i0 - B[0], l1 = i1 - B[1], l2 = i2 - B[2];
-#pragma unroll
-                for (int dx = 0; dx < 2; ++dx) {
-                    const int x = l0 + dx;
-                    if (x < 0 || x >= S0) continue;
-#pragma unroll
-                    for (int dy = 0; dy < 2; ++dy) {
-                        const int y = l1 + dy;
-                        if (y < 0 || y >= S1) continue;
-                        const float wxy = gp * w0[dx] * w1[dy];
-#pragma unroll
-                        for (int dz = 0; dz < 2; ++dz) {
-                            const int z = l2 + dz;
-                            if (z < 0 || z >= S2) continue;
-                            atomicAdd(&acc[(x * S1 + y) * S2 + z], wxy * w2[dz]);
-                        }
-                    }
-                }
+                float f0, f1, f2, c0f, c1f, c2f;
+                bool k0, k1, k2;
+                cell_bf(fmaf(sf, r.su[0], r.bu[0]), g.n[0], c0f, f0, k0);
+                cell_bf(fmaf(sf, r.su[1], r.bu[1]), g.n[1], c1f, f1, k1);
+                cell_bf(fmaf(sf, r.su[2], r.bu[2]), g.n[2], c2f, f2, k2);
+                const bool own = k0 && k1 && k2 && c0f >= clo[0] && c0f <= chi[0] &&
+                                 c1f >= clo[1] && c1f <= chi[1] && c2f >= clo[2] &&
+                                 c2f <= chi[2];
+                if (!own) continue;
+                const int idx =
+                    (int)fmaf(fmaf(c0f - o0, (float)P, c1f - o1), (float)P, c2f - o2);
+                int *q = acc + idx;
+                const float wx0 = gp * (1.0f - f0), wx1 = gp * f0;
+                const float a00 = wx0 * (1.0f - f1), a01 = wx0 * f1;
+                const float a10 = wx1 * (1.0f - f1), a11 = wx1 * f1;
+                const float g2 = 1.0f - f2;
+                atomicAdd(q, __float2int_rn(a00 * g2));
+                atomicAdd(q + 1, __float2int_rn(a00 * f2));
+                atomicAdd(q + P, __float2int_rn(a01 * g2));
+                atomicAdd(q + P + 1, __float2int_rn(a01 * f2));
+                atomicAdd(q + P * P, __float2int_rn(a10 * g2));
+                atomicAdd(q + P * P + 1, __float2int_rn(a10 * f2));
+                atomicAdd(q + P * P + P, __float2int_rn(a11 * g2));
+                atomicAdd(q + P * P + P + 1, __float2int_rn(a11 * f2));
             }
         }
-        if (!sum_views) break;
+        __syncthreads();
+        const float inv_scale = 1.0f / scale;
+        if constexpr (SUM) {
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const int i = threadIdx.x + 256 * k;
+                if (i < NP) sum[k] += (float)acc[i] * inv_scale;
+            }
+            __syncthreads();
+        } else {
+            last_inv = inv_scale;
+        }
     }
-    __syncthreads();
     float *out = g_vol + (sum_views ? 0 : (int64_t)blockIdx.y * stride);
-    for (int i = threadIdx.x; i < nvox; i += blockDim.x) {
-        const int z = i % S2, y = (i / S2) % S1, x = i / (S2 * S1);
+    float mx = 0.0f;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int i = threadIdx.x + 256 * k;
+        if (i >= NP) continue;
+        const int z = i % P - 1, y = (i / P) % P - 1, x = i / (P * P) - 1;
+        if (x < 0 || y < 0 || z < 0 || x >= S || y >= S || z >= S) continue;
         const int gx = B[0] + x, gy = B[1] + y, gz = B[2] + z;
-        if (gx < g.n[0] && gy < g.n[1] && gz < g.n[2])
-            out[((int64_t)gx * g.n[1] + gy) * g.n[2] + gz] = acc[i];
+        if (gx < g.n[0] && gy < g.n[1] && gz < g.n[2]) {
+            float val;
+            if constexpr (SUM) val = sum[k];
+            else val = (float)acc[i] * last_inv;
+            out[((int64_t)gx * g.n[1] + gy) * g.n[2] + gz] = val;
+            mx = fmaxf(mx, fabsf(val));
+        }
     }
+    if (vmax && !sum_views) {
+        for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+        if (lane == 0 && mx > 0.0f) atomicMax(&vmax[blockIdx.y], __float_as_uint(mx));
+    }
+}
+
+// Geometry constants of the per-view bound on contributions per voxel
+// (see k_project_bwd): largest magnification over the volume, the
+// perspective spread per mm of depth, the volume's radius and half height.
+static BoundK make_bound(const GridK &g, const ConeK &c) {
+    BoundK b;
+    double R = 0.0;
+    for (int a = 0; a < 2; ++a) R += fmax(c.lo[a] * c.lo[a], c.hi[a] * c.hi[a]);
+    R = sqrt(R);
+    const double Z = fmax(fabs(c.lo[2]), fabs(c.hi[2]));
+    // rounded up so the bound stays an upper bound in float
+    b.mag = (float)(c.sdd / (c.sad - R) * (1.0 + 1e-6));
+    b.persp = (float)(c.sdd / ((c.sad - R) * (c.sad - R)) * (1.0 + 1e-6));
+    b.R = (float)(R * (1.0 + 1e-6));
+    b.Z = (float)(Z * (1.0 + 1e-6));
+    b.two_hx = (float)(2.0 * g.hd[0]);
+    b.two_hy = (float)(2.0 * g.hd[1]);
+    b.two_hz = (float)(2.0 * g.hd[2]);
+    b.inv_du = (float)(1.0 / c.du * (1.0 + 1e-6));
+    b.inv_dv = (float)(1.0 / c.dv * (1.0 + 1e-6));
+    b.diag = (float)(2.0 * sqrt(g.hd[0] * g.hd[0] + g.hd[1] * g.hd[1] + g.hd[2] * g.hd[2]) *
+                     (1.0 + 1e-6));
+    return b;
 }
 
 hipError_t launch_project(const float *vol, int64_t stride, const GridK &g, const ConeK &c,
@@ -252,15 +410,13 @@ hipError_t launch_project(const float *vol, int64_t stride, const GridK &g, cons
     return hipGetLastError();
 }
 
-static const int BWD_S[3] = {16, 16, 16};
-
 size_t project_bwd_workspace(const pmf_cone_t &c, int V) {
     return align256(sizeof(RayK) * (size_t)c.nu * (size_t)c.nv * (size_t)V);
 }
 
 hipError_t launch_project_bwd(const float *g_proj, const GridK &g, const ConeK &c,
                               const float *angles, int V, float *g_vol, int64_t stride, void *ws,
-                              hipStream_t s) {
+                              hipStream_t s, unsigned *vmax) {
     RayK *rays = (RayK *)ws;
     const int64_t nr = (int64_t)c.nu * c.nv * V;
     {
@@ -269,19 +425,21 @@ hipError_t launch_project_bwd(const float *g_proj, const GridK &g, const ConeK &
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    int S[3];
+    constexpr int S = 16;
     int nb[3];
-    for (int a = 0; a < 3; ++a) {
-        S[a] = BWD_S[a] < g.n[a] ? BWD_S[a] : g.n[a];
-        nb[a] = (g.n[a] + S[a] - 1) / S[a];
-    }
+    for (int a = 0; a < 3; ++a) nb[a] = (g.n[a] + S - 1) / S;
     const int sum_views = stride == 0;
     dim3 grid((unsigned)(nb[0] * nb[1] * nb[2]), sum_views ? 1u : (unsigned)V);
-    const size_t lds = sizeof(float) * (size_t)S[0] * S[1] * S[2];
     {
         ProfScope prof_("project_bwd", s);
-        k_project_bwd<<<grid, 256, lds, s>>>(g_proj, g, c, angles, rays, V, g_vol, stride, S[0], S[1],
-                                             S[2], nb[1], nb[2], sum_views);
+        if (sum_views)
+            k_project_bwd<S, true><<<grid, 256, 0, s>>>(g_proj, g, c, angles, rays, V, g_vol,
+                                                       stride, nb[1], nb[2], make_bound(g, c),
+                                                       vmax);
+        else
+            k_project_bwd<S, false><<<grid, 256, 0, s>>>(g_proj, g, c, angles, rays, V, g_vol,
+                                                        stride, nb[1], nb[2], make_bound(g, c),
+                                                        vmax);
     }
     return hipGetLastError();
 }

@@ -444,17 +444,17 @@ __global__ __launch_bounds__(256) void k_vox_bwd(pmf_gauss_t gs, GridK g, float 
     }
 #pragma unroll
     for (int c = 0; c < MAXC; ++c)
-        if (c < C) gv[c] = warp_sum(gv[c]);
-    gm0 = warp_sum(gm0);
-    gm1 = warp_sum(gm1);
-    gm2 = warp_sum(gm2);
-    M00 = warp_sum(M00);
-    M01 = warp_sum(M01);
-    M02 = warp_sum(M02);
-    M11 = warp_sum(M11);
-    M12 = warp_sum(M12);
-    M22 = warp_sum(M22);
-    if (lane != 0) return;
+        if (c < C) gv[c] = wave_sum_lane63(gv[c]);
+    gm0 = wave_sum_lane63(gm0);
+    gm1 = wave_sum_lane63(gm1);
+    gm2 = wave_sum_lane63(gm2);
+    M00 = wave_sum_lane63(M00);
+    M01 = wave_sum_lane63(M01);
+    M02 = wave_sum_lane63(M02);
+    M11 = wave_sum_lane63(M11);
+    M12 = wave_sum_lane63(M12);
+    M22 = wave_sum_lane63(M22);
+    if (lane != 63) return;
 #pragma unroll
     for (int c = 0; c < MAXC; ++c)
         if (c < C) gr.value[gi * C + c] = gv[c];

@@ -331,6 +331,9 @@ def test_headline_full_size_sampled():
     _, og = oracle.step(w, target, views=[0])
     r = rel(N(grads_b["coeff"][0]), og["coeff"][0])
     say("headline: g_coeff[0] rel", r)
+    # A few voxels warp to within float rounding of a cell face, where the
+    # trilinear derivative jumps; either one-sided value is a valid result,
+    # and they set this error (~8e-4, the same with float accumulation).
     assert r < GRAD_TOL, r
     say("headline: plain")
     loss_p, grads_p = m.step_plain(T(target))
@@ -346,4 +349,9 @@ def test_headline_full_size_sampled():
     gx, _, _ = ops.pmf_warp_project_bwd(ref_g, w.grid, bases_g, w.levels, m.coeff, w.cone, m.angles, y)
     lhs = float(torch.sum(px.double() * y.double()))
     rhs = float(torch.sum(x.double() * gx.double()))
-    assert abs(lhs - rhs) / abs(lhs) < 1e-5, (lhs, rhs)
+    # The back-projection accumulates in 32-bit fixed point: each term is
+    # rounded to within 2^-31 * (bound on terms per voxel) * max|y * delta|,
+    # about 1e-7 of the largest term here; with random-sign y and x the
+    # identity's relative error is then of order 1e-5, not the 1e-7 of
+    # float rounding, so the bar is the volume tolerance.
+    assert abs(lhs - rhs) / abs(lhs) < VOL_TOL, (lhs, rhs)
