@@ -72,7 +72,9 @@ typedef struct {
  * (Eq. 6) over the ray's chord [t_n, t_f] through the volume box is taken with
  * the midpoint rule on N = max(1, ceil((t_f - t_n)/step)) equal sub-intervals.
  * step <= 0 selects half the smallest voxel spacing.  Requires 0 < SAD < SDD
- * and the volume box to lie strictly inside the source circle. */
+ * and the volume box to lie strictly inside the source circle.  Calls that
+ * project (pmf_project*, pmf_warp_project*) also require n1*n2 < 2^24 and
+ * n0*n1*n2 < 2^30 (PMF_EUNSUPPORTED otherwise). */
 typedef struct {
     float sad, sdd;
     int32_t nu, nv;

@@ -52,6 +52,8 @@ int check_grid(const pmf_grid_t *g, const char *name) {
     return PMF_OK;
 }
 
+int check_march_grid(const pmf_grid_t *g);
+
 int check_cone(const pmf_cone_t *c, const pmf_grid_t *g) {
     if (!c) return fail(PMF_EINVAL, "cone: null");
     if (!(isfinite(c->sad) && isfinite(c->sdd) && c->sad > 0.0f && c->sdd > c->sad))
@@ -70,6 +72,15 @@ int check_cone(const pmf_cone_t *c, const pmf_grid_t *g) {
         rmax = fmax(rmax, sqrt(x * x + y * y));
     }
     if (!(rmax < c->sad)) return fail(PMF_EINVAL, "cone: volume box reaches the source circle");
+    return check_march_grid(g);
+}
+
+// The ray-march kernels index with 24-bit multiplies and 32-bit byte offsets.
+int check_march_grid(const pmf_grid_t *g) {
+    if ((int64_t)g->n[1] * g->n[2] >= ((int64_t)1 << 24))
+        return fail(PMF_EUNSUPPORTED, "projection: n1*n2 must be < 2^24");
+    if ((int64_t)g->n[0] * g->n[1] * g->n[2] >= ((int64_t)1 << 30))
+        return fail(PMF_EUNSUPPORTED, "projection: more than 2^30 voxels");
     return PMF_OK;
 }
 

@@ -89,32 +89,54 @@ __device__ __forceinline__ void cell_bf(float u, int n, float &fi, float &f, boo
     f = uc - fi;
 }
 
-// Trilinear sample at voxel coordinate u (0 outside the box), branch-free:
-// the cell is clamped into the grid so the 4 z-pair loads are always valid.
-__device__ __forceinline__ float sample_bf(const float *__restrict__ vol, const GridK &g,
-                                           uint32_t s0, uint32_t s1, float u0, float u1,
-                                           float u2) {
+// Cell index (as a float) and fraction of a ray sample on one axis.  Ray
+// samples are midpoints of the ray's chord through the box, so they lie
+// inside it: the coordinate is only clamped (rim voxels take the edge value),
+// never rejected -- which also keeps a grazing ray's first sample, that float
+// rounding can place a hair outside the box, at its exact-arithmetic value.
+__device__ __forceinline__ void ray_cell(float u, float nm1, float nm2, float &fi, float &f) {
+    const float uc = __builtin_amdgcn_fmed3f(u, 0.0f, nm1);
+    fi = fminf(floorf(uc), nm2);
+    f = uc - fi;
+}
+
+// Per-grid constants of the ray march: n-1, n-2 per axis and the element
+// strides of axes 0 and 1 (24-bit multiplies: n1*n2 < 2^24, N < 2^30).
+struct MarchK {
+    float nm1[3], nm2[3];
+    uint32_t s0, s1;
+};
+
+__device__ __forceinline__ float march_sample(const char *__restrict__ vb, const MarchK &mk,
+                                              float u0, float u1, float u2) {
     float c0, c1, c2, f0, f1, f2;
-    bool k0, k1, k2;
-    cell_bf(u0, g.n[0], c0, f0, k0);
-    cell_bf(u1, g.n[1], c1, f1, k1);
-    cell_bf(u2, g.n[2], c2, f2, k2);
-    const uint32_t idx = ((uint32_t)c0 * (uint32_t)g.n[1] + (uint32_t)c1) * (uint32_t)g.n[2] +
-                         (uint32_t)c2;
-    const float *p = vol + idx;
-    const float *pb = p + s1, *pd = p + s0, *pe = pd + s1;
-    const float a0 = p[0], a1 = p[1];
-    const float b0 = pb[0], b1 = pb[1];
-    const float d0 = pd[0], d1 = pd[1];
-    const float e0 = pe[0], e1 = pe[1];
-    const float x00 = lerp1(a0, a1, f2), x01 = lerp1(b0, b1, f2);
-    const float x10 = lerp1(d0, d1, f2), x11 = lerp1(e0, e1, f2);
-    const float v = lerp1(lerp1(x00, x01, f1), lerp1(x10, x11, f1), f0);
-    return (k0 && k1 && k2) ? v : 0.0f;
+    ray_cell(u0, mk.nm1[0], mk.nm2[0], c0, f0);
+    ray_cell(u1, mk.nm1[1], mk.nm2[1], c1, f1);
+    ray_cell(u2, mk.nm1[2], mk.nm2[2], c2, f2);
+    const uint32_t idx =
+        __umul24((uint32_t)c0, mk.s0) + __umul24((uint32_t)c1, mk.s1) + (uint32_t)c2;
+    const uint32_t o00 = idx * 4u, o01 = o00 + mk.s1 * 4u, o10 = o00 + mk.s0 * 4u,
+                   o11 = o10 + mk.s1 * 4u;
+    const float *pa = (const float *)(vb + o00), *pb = (const float *)(vb + o01);
+    const float *pd = (const float *)(vb + o10), *pe = (const float *)(vb + o11);
+    const float x00 = lerp1(pa[0], pa[1], f2), x01 = lerp1(pb[0], pb[1], f2);
+    const float x10 = lerp1(pd[0], pd[1], f2), x11 = lerp1(pe[0], pe[1], f2);
+    return lerp1(lerp1(x00, x01, f1), lerp1(x10, x11, f1), f0);
+}
+
+__host__ __device__ inline MarchK make_march(const GridK &g) {
+    MarchK m;
+    for (int a = 0; a < 3; ++a) {
+        m.nm1[a] = (float)(g.n[a] - 1);
+        m.nm2[a] = (float)(g.n[a] - 2);
+    }
+    m.s1 = (uint32_t)g.n[2];
+    m.s0 = (uint32_t)g.n[1] * (uint32_t)g.n[2];
+    return m;
 }
 
 __global__ __launch_bounds__(256) void k_project(const float *__restrict__ vol, int64_t stride,
-                                                 GridK g, ConeK c,
+                                                 GridK g, ConeK c, MarchK mk,
                                                  const float *__restrict__ angles,
                                                  float *__restrict__ proj, int tiles_u) {
     const int v = blockIdx.y;
@@ -124,21 +146,20 @@ __global__ __launch_bounds__(256) void k_project(const float *__restrict__ vol, 
     if (iu >= c.nu || iv >= c.nv) return;
     const double th = (double)angles[v];
     const RayK r = ray_setup(g, c, cos(th), sin(th), iu, iv);
-    const float *__restrict__ vv = vol + (int64_t)v * stride;
-    const uint32_t s1 = (uint32_t)g.n[2], s0 = (uint32_t)g.n[1] * (uint32_t)g.n[2];
+    const char *__restrict__ vb = (const char *)(vol + (int64_t)v * stride);
     float acc0 = 0.0f, acc1 = 0.0f;
     int s = 0;
     for (; s + 1 < r.n; s += 2) {
         const float sa = (float)s, sb = (float)(s + 1);
-        acc0 += sample_bf(vv, g, s0, s1, fmaf(sa, r.su[0], r.bu[0]), fmaf(sa, r.su[1], r.bu[1]),
-                          fmaf(sa, r.su[2], r.bu[2]));
-        acc1 += sample_bf(vv, g, s0, s1, fmaf(sb, r.su[0], r.bu[0]), fmaf(sb, r.su[1], r.bu[1]),
-                          fmaf(sb, r.su[2], r.bu[2]));
+        acc0 += march_sample(vb, mk, fmaf(sa, r.su[0], r.bu[0]), fmaf(sa, r.su[1], r.bu[1]),
+                             fmaf(sa, r.su[2], r.bu[2]));
+        acc1 += march_sample(vb, mk, fmaf(sb, r.su[0], r.bu[0]), fmaf(sb, r.su[1], r.bu[1]),
+                             fmaf(sb, r.su[2], r.bu[2]));
     }
     if (s < r.n) {
         const float sa = (float)s;
-        acc0 += sample_bf(vv, g, s0, s1, fmaf(sa, r.su[0], r.bu[0]), fmaf(sa, r.su[1], r.bu[1]),
-                          fmaf(sa, r.su[2], r.bu[2]));
+        acc0 += march_sample(vb, mk, fmaf(sa, r.su[0], r.bu[0]), fmaf(sa, r.su[1], r.bu[1]),
+                             fmaf(sa, r.su[2], r.bu[2]));
     }
     proj[((int64_t)v * c.nv + iv) * c.nu + iu] = (acc0 + acc1) * r.delta;
 }
@@ -204,7 +225,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float *__restrict__ g
                                                      ConeK c, const float *__restrict__ angles,
                                                      const RayK *__restrict__ rays, int V,
                                                      float *__restrict__ g_vol, int64_t stride,
-                                                     int nb1, int nb2, BoundK kb,
+                                                     int nb1, int nb2, BoundK kb, MarchK mk,
                                                      unsigned *__restrict__ vmax) {
     constexpr bool sum_views = SUM;
     constexpr int P = S + 2;                    // padded edge
@@ -309,19 +330,30 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float *__restrict__ g
                 }
             }
             if (smin > smax + 2.0f) continue;
-            const int s0 = max(0, (int)floorf(smin) - 1);
-            const int s1 = min(r.n - 1, (int)ceilf(smax) + 1);
+            // The owned samples form one run of s: every axis's cell index is
+            // monotone in s and the owned cells form a box.  Narrow the
+            // estimate [s0, s1] to that run exactly, so the loop below needs
+            // no ownership test.
+            int s0 = max(0, (int)floorf(smin) - 1);
+            int s1 = min(r.n - 1, (int)ceilf(smax) + 1);
+            auto owned = [&](int si) {
+                const float sf = (float)si;
+                float fi, fr;
+                ray_cell(fmaf(sf, r.su[0], r.bu[0]), mk.nm1[0], mk.nm2[0], fi, fr);
+                bool o = fi >= clo[0] && fi <= chi[0];
+                ray_cell(fmaf(sf, r.su[1], r.bu[1]), mk.nm1[1], mk.nm2[1], fi, fr);
+                o = o && fi >= clo[1] && fi <= chi[1];
+                ray_cell(fmaf(sf, r.su[2], r.bu[2]), mk.nm1[2], mk.nm2[2], fi, fr);
+                return o && fi >= clo[2] && fi <= chi[2];
+            };
+            while (s0 <= s1 && !owned(s0)) ++s0;
+            while (s1 >= s0 && !owned(s1)) --s1;
             for (int s = s0; s <= s1; ++s) {
                 const float sf = (float)s;
                 float f0, f1, f2, c0f, c1f, c2f;
-                bool k0, k1, k2;
-                cell_bf(fmaf(sf, r.su[0], r.bu[0]), g.n[0], c0f, f0, k0);
-                cell_bf(fmaf(sf, r.su[1], r.bu[1]), g.n[1], c1f, f1, k1);
-                cell_bf(fmaf(sf, r.su[2], r.bu[2]), g.n[2], c2f, f2, k2);
-                const bool own = k0 && k1 && k2 && c0f >= clo[0] && c0f <= chi[0] &&
-                                 c1f >= clo[1] && c1f <= chi[1] && c2f >= clo[2] &&
-                                 c2f <= chi[2];
-                if (!own) continue;
+                ray_cell(fmaf(sf, r.su[0], r.bu[0]), mk.nm1[0], mk.nm2[0], c0f, f0);
+                ray_cell(fmaf(sf, r.su[1], r.bu[1]), mk.nm1[1], mk.nm2[1], c1f, f1);
+                ray_cell(fmaf(sf, r.su[2], r.bu[2]), mk.nm1[2], mk.nm2[2], c2f, f2);
                 const int idx =
                     (int)fmaf(fmaf(c0f - o0, (float)P, c1f - o1), (float)P, c2f - o2);
                 int *q = acc + idx;
@@ -405,7 +437,7 @@ hipError_t launch_project(const float *vol, int64_t stride, const GridK &g, cons
     dim3 grid((unsigned)(tu * tv), (unsigned)V);
     {
         ProfScope prof_("project", s);
-        k_project<<<grid, 256, 0, s>>>(vol, stride, g, c, angles, proj, tu);
+        k_project<<<grid, 256, 0, s>>>(vol, stride, g, c, make_march(g), angles, proj, tu);
     }
     return hipGetLastError();
 }
@@ -435,11 +467,11 @@ hipError_t launch_project_bwd(const float *g_proj, const GridK &g, const ConeK &
         if (sum_views)
             k_project_bwd<S, true><<<grid, 256, 0, s>>>(g_proj, g, c, angles, rays, V, g_vol,
                                                        stride, nb[1], nb[2], make_bound(g, c),
-                                                       vmax);
+                                                       make_march(g), vmax);
         else
             k_project_bwd<S, false><<<grid, 256, 0, s>>>(g_proj, g, c, angles, rays, V, g_vol,
                                                         stride, nb[1], nb[2], make_bound(g, c),
-                                                        vmax);
+                                                        make_march(g), vmax);
     }
     return hipGetLastError();
 }

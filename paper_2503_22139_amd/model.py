@@ -129,3 +129,38 @@ class MotionModel:
         grads = self.volumes_bwd(g_ref, g_bases)
         grads["coeff"] = g_coeff
         return loss, grads
+
+
+class GraphStep:
+    """The batched iteration captured once into a HIP graph and replayed.
+
+    ``target`` is copied into a static buffer before each replay; the loss and
+    gradients live in static tensors owned by the graph (read them before the
+    next replay).  Capture happens after one eager warm-up step so that every
+    workspace is already allocated; the library's kernels clear memory with
+    fill kernels, never with memset nodes.
+    """
+
+    def __init__(self, model: MotionModel, target: torch.Tensor):
+        self.model = model
+        self.target = target.clone()
+        was = ops.pmf_profile(False)
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            model.step_batched(self.target)          # warm-up: allocate workspaces
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.loss, self.grads = model.step_batched(self.target)
+        torch.cuda.synchronize()
+        # the graph holds raw pointers into the scratch buffers: keep them alive
+        self._scratch = dict(ops._ws_cache)
+        ops.pmf_profile(was)
+
+    def step(self, target: Optional[torch.Tensor] = None):
+        if target is not None:
+            self.target.copy_(target)
+        self.graph.replay()
+        return self.loss, self.grads

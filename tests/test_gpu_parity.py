@@ -355,3 +355,23 @@ def test_headline_full_size_sampled():
     # identity's relative error is then of order 1e-5, not the 1e-7 of
     # float rounding, so the bar is the volume tolerance.
     assert abs(lhs - rhs) / abs(lhs) < VOL_TOL, (lhs, rhs)
+
+
+def test_graph_replay_matches_eager():
+    """The captured batched iteration, replayed several times with eager work
+    and synchronisations between replays, equals the eager iteration."""
+    from paper_2503_22139_amd.model import GraphStep
+    w = synth.small_motion(seed=41, nviews=5)
+    target = T(synth.random_volume(42, (5, w.cone.nv, w.cone.nu), 0.0, 2.0))
+    m = MotionModel(w)
+    loss_e, g_e = m.step_batched(target)
+    want = (float(N(loss_e)), N(g_e["coeff"]), N(g_e["ref"]["mean"]), N(g_e["mbc"][2]["value"]))
+    gs = GraphStep(m, target)
+    for it in range(4):
+        loss, g = gs.step(target)
+        got = (float(N(loss)), N(g["coeff"]), N(g["ref"]["mean"]), N(g["mbc"][2]["value"]))
+        assert abs(got[0] - want[0]) <= 1e-6 * abs(want[0]), (it, got[0], want[0])
+        for a, b in zip(got[1:], want[1:]):
+            assert rel(a, b) < 1e-5, it
+        m.step_plain(target)            # eager work between replays
+        torch.cuda.synchronize()
