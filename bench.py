@@ -121,6 +121,8 @@ def main():
     ap.add_argument("--views", type=int, default=32)
     ap.add_argument("--bases", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="time the eager batched steps instead of graph replays (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -133,6 +135,12 @@ def main():
     from paper_2503_22139_amd.model import GraphStep, MotionModel
 
     torch.cuda.init()
+    # A plain device copy of known size (256 MiB read, 256 MiB written): under
+    # rocprofv3 --pmc its FETCH_SIZE / WRITE_SIZE calibrate the HBM counters.
+    src = torch.ones(64 << 20, device="cuda")
+    torch.empty_like(src).copy_(src)
+    torch.cuda.synchronize()
+    del src
     w = synth.headline(nviews=args.views, nbases=args.bases)
     m = MotionModel(w)
     truth = MotionModel(synth.perturbed_truth(w))
@@ -166,27 +174,33 @@ def main():
     print(f"[bench] batched eager {ms_eager:.2f} ms/step", file=sys.stderr, flush=True)
 
     # the timed region: the batched iteration replayed from a HIP graph
-    gs = GraphStep(m, target)
-    for _ in range(2):
-        gs.step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        loss, grads = gs.step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms = (t1 - t0) / args.steps * 1e3
-    print(f"[bench] batched graph {ms:.2f} ms/step", file=sys.stderr, flush=True)
+    if args.no_graph:
+        ms = ms_eager
+        loss, grads = m.step_batched(target)
+    else:
+        gs = GraphStep(m, target)
+        for _ in range(2):
+            gs.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            loss, grads = gs.step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ms = (t1 - t0) / args.steps * 1e3
+        print(f"[bench] batched graph {ms:.2f} ms/step", file=sys.stderr, flush=True)
 
     # plain schedule (one view at a time)
-    m.step_plain(target)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.plain_steps):
+    ms_plain = float("nan")
+    if args.plain_steps > 0:
         m.step_plain(target)
-    torch.cuda.synchronize()
-    ms_plain = (time.perf_counter() - t0) / args.plain_steps * 1e3
-    print(f"[bench] plain {ms_plain:.2f} ms/step", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.plain_steps):
+            m.step_plain(target)
+        torch.cuda.synchronize()
+        ms_plain = (time.perf_counter() - t0) / args.plain_steps * 1e3
+        print(f"[bench] plain {ms_plain:.2f} ms/step", file=sys.stderr, flush=True)
 
     samples = ray_samples(w.grid, w.cone, w.angles)
     dom = max((k for k in kern if kernel_model(k, w, V, samples)), key=lambda k: kern[k]["ms_per_step"])
@@ -216,10 +230,11 @@ def main():
                                 f"@256x256x128 (1.5x1.5x2 mm), MBC 1k/4k/16k @64^3/128^3/256x256x128, "
                                 f"B={args.bases}, detector 512x384 @0.776 mm, SAD/SDD 1000/1500, step 0.75 mm"),
                    "views": V, "grid": list(w.grid.n), "detector": [w.cone.nu, w.cone.nv],
-                   "schedule": "batched, replayed from a HIP graph"},
+                   "schedule": "batched, " + ("eager" if args.no_graph else "replayed from a HIP graph")},
         "batched_eager_ms_per_step": ms_eager,
-        "plain": {"value": 1e3 / ms_plain, "ms_per_step": ms_plain, "steps": args.plain_steps},
-        "speedup_vs_plain": ms_plain / ms,
+        "plain": ({"value": 1e3 / ms_plain, "ms_per_step": ms_plain, "steps": args.plain_steps}
+                  if args.plain_steps > 0 else None),
+        "speedup_vs_plain": ms_plain / ms if args.plain_steps > 0 else None,
         "loss": float(loss),
         "kernels": kern,
         "roofline": roof,

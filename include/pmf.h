@@ -210,6 +210,26 @@ int pmf_profile(int enable);
 int pmf_profile_read(const char *kernel, double *total_ms, int64_t *count);
 size_t pmf_profile_names(char *buf, size_t len);
 
+/* ------------------------------------------------------- launch shapes
+ * Tunable launch shapes (process-wide; results do not depend on them beyond
+ * float summation order).  Knobs:
+ *   PMF_TUNE_PROJECT_TILE      ray tile of the forward projection: the pixels
+ *                              one wavefront marches (u x v) and the
+ *                              workgroup's tile: 0 = 16x4 in 16x16,
+ *                              1 = 8x8 in 16x16, 2 = 4x16 in 16x16,
+ *                              3 = 2x32 in 8x32, 4 = 32x2 in 32x8,
+ *                              5 = 1x64 in 4x64 (default), 6 = 2x32 in 4x64,
+ *                              7 = 1x64 in 2x128, 8 = 2x32 in 2x128;
+ *   PMF_TUNE_BACKPROJECT_BRICK voxel brick of the adjoint projection.
+ * pmf_tune_candidates returns the number of choices of a knob (0 for an
+ * unknown knob); pmf_tune_set returns the previous choice or PMF_EINVAL for an
+ * unknown knob or a choice out of range; pmf_tune_get returns the current
+ * choice.  Not to be changed while another thread launches library work. */
+enum { PMF_TUNE_PROJECT_TILE = 0, PMF_TUNE_BACKPROJECT_BRICK = 1 };
+int pmf_tune_candidates(int knob);
+int pmf_tune_get(int knob);
+int pmf_tune_set(int knob, int choice);
+
 /* ----------------------------------------- batched motion path (fused)
  * All V views of the motion path in one pass over the bases:
  *   proj[v] = P_v( warp(ref, combine(bases, coeff[v])) )

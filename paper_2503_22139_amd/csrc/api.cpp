@@ -319,6 +319,20 @@ int pmf_profile_read(const char *kernel, double *total_ms, int64_t *count) {
 
 size_t pmf_profile_names(char *buf, size_t len) { return profile_names(buf, len); }
 
+// ------------------------------------------------------------ launch shapes
+int pmf_tune_candidates(int knob) { return tune_candidates(knob); }
+
+int pmf_tune_get(int knob) {
+    if (tune_candidates(knob) == 0) return fail(PMF_EINVAL, "tune_get: unknown knob");
+    return tune_get(knob);
+}
+
+int pmf_tune_set(int knob, int choice) {
+    const int prev = tune_set(knob, choice);
+    if (prev < 0) return fail(PMF_EINVAL, "tune_set: unknown knob or choice out of range");
+    return prev;
+}
+
 // ------------------------------------------------------ fused motion path
 size_t pmf_warp_project_workspace(int L, int B, const pmf_grid_t *lvl, int V,
                                   const pmf_grid_t *grid, const pmf_cone_t *cone) {

@@ -41,6 +41,21 @@ ProfScope::~ProfScope() {
 
 int profile_enable(int on) { return g_prof_on.exchange(on ? 1 : 0); }
 
+// ------------------------------------------------------------- launch shapes
+static const int g_tune_count[KNOB_COUNT] = {9, 1};
+static std::atomic<int> g_tune[KNOB_COUNT] = {{5}, {0}};
+
+int tune_candidates(int knob) { return knob >= 0 && knob < KNOB_COUNT ? g_tune_count[knob] : 0; }
+
+int tune_get(int knob) {
+    return knob >= 0 && knob < KNOB_COUNT ? g_tune[knob].load(std::memory_order_relaxed) : 0;
+}
+
+int tune_set(int knob, int value) {
+    if (knob < 0 || knob >= KNOB_COUNT || value < 0 || value >= g_tune_count[knob]) return -1;
+    return g_tune[knob].exchange(value);
+}
+
 int profile_read(const char *name, double *total_ms, int64_t *count) {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
     {

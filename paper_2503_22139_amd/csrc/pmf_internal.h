@@ -208,6 +208,14 @@ int profile_enable(int on);
 int profile_read(const char *name, double *total_ms, int64_t *count);
 size_t profile_names(char *buf, size_t len);
 
+// ------------------------------------------------------------- launch shapes
+// Process-wide choice of launch shape per tunable kernel (index into that
+// kernel's candidate list); set by pmf_tune_set or the autotuner.
+enum Knob { KNOB_PROJECT_TILE = 0, KNOB_BACKPROJECT_BRICK = 1, KNOB_COUNT = 2 };
+int tune_get(int knob);
+int tune_set(int knob, int value);   // returns the previous value, or -1 if out of range
+int tune_candidates(int knob);
+
 // ------------------------------------------------------------- launchers
 // Each returns hipSuccess or the launch error.  Arguments were validated.
 hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t s);

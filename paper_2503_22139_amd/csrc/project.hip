@@ -77,7 +77,6 @@ __device__ __forceinline__ RayK ray_setup(const GridK &g, const ConeK &c, double
     return r;
 }
 
-constexpr int PT = 16;  // forward pixel tile edge
 
 // Branch-free cell coordinate on one axis (same arithmetic as axis_cell):
 // fi = clamped cell index as a float, f = fraction; ok = inside the box.
@@ -135,14 +134,23 @@ __host__ __device__ inline MarchK make_march(const GridK &g) {
     return m;
 }
 
+// Forward pixel tiles: a wave takes WU x WV pixels (u x v), the four waves of
+// a workgroup sit AU across and 4/AU down.  The wave's footprint decides how
+// many distinct cache lines each of its gathers touches: v runs along z, the
+// fastest (contiguous) axis of the volume, so narrow-and-tall wave tiles touch
+// fewer lines per load.
+template <int WU, int WV, int AU>
 __global__ __launch_bounds__(256) void k_project(const float *__restrict__ vol, int64_t stride,
                                                  GridK g, ConeK c, MarchK mk,
                                                  const float *__restrict__ angles,
                                                  float *__restrict__ proj, int tiles_u) {
+    static_assert(WU * WV == 64 && AU >= 1 && 4 % AU == 0, "wave tile must hold 64 pixels");
+    constexpr int BU = WU * AU, BV = WV * (4 / AU);
     const int v = blockIdx.y;
     const int tu = blockIdx.x % tiles_u, tv = blockIdx.x / tiles_u;
-    const int iu = tu * PT + (threadIdx.x & (PT - 1));
-    const int iv = tv * PT + (threadIdx.x / PT);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int iu = tu * BU + (w % AU) * WU + l % WU;
+    const int iv = tv * BV + (w / AU) * WV + l / WU;
     if (iu >= c.nu || iv >= c.nv) return;
     const double th = (double)angles[v];
     const RayK r = ray_setup(g, c, cos(th), sin(th), iu, iv);
@@ -201,16 +209,64 @@ __device__ void shadow_rect(const ConeK &c, double ct, double st, const double l
 }
 
 
+// Round to the nearest integer (halves up) in one instruction.
+__device__ __forceinline__ int round_int(float x) {
+    int r;
+    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
+// Orders the LDS accesses of one wavefront (a compiler barrier: the hardware
+// performs a wavefront's LDS operations in order).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ int dpp_i(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROW_MASK, 0xf, true);
+}
+
+// Inclusive prefix sum over the 64 lanes (lanes shifted in from outside a
+// row read 0).
+__device__ __forceinline__ int wave_incl_sum(int x) {
+    x += dpp_i<0x111>(x);          // row_shr:1
+    x += dpp_i<0x112>(x);          // row_shr:2
+    x += dpp_i<0x114>(x);          // row_shr:4
+    x += dpp_i<0x118>(x);          // row_shr:8
+    x += dpp_i<0x142, 0xa>(x);     // row_bcast:15 into rows 1, 3
+    x += dpp_i<0x143, 0xc>(x);     // row_bcast:31 into rows 2, 3
+    return x;
+}
+
+// One ray's owned run, staged in LDS for the lanes that take its samples:
+// item q of the wave's flattened list is sample q + off of the ray.
+struct RunP {
+    float bu[3], su[3], gp;
+    int off;
+};
+
+
 struct BoundK {
     float mag, persp, R, Z, two_hx, two_hy, two_hz, inv_du, inv_dv, diag;
 };
 
-// g_vol (per view, or summed over views when sum_views) of one S^3 brick.
+// g_vol (per view, or summed over views when SUM) of one S^3 brick.
 //
 // The LDS accumulator spans the brick plus one voxel on every side, so the
 // 8 corners of every owned sample land inside it; the pad is dropped on
 // write-out (it belongs to the neighbouring bricks, which take those
 // samples themselves).
+//
+// Work distribution: each wave takes 64 rays of the brick's detector shadow
+// at a time (an 8x8 grid of pixels spread over the shadow rectangle), finds
+// each ray's run of owned samples, and flattens the runs into one list of
+// (ray, sample) items by a prefix sum over the lanes; each lane then walks
+// an equal slice of that list, so every lane does a sample per iteration
+// however the run lengths differ, and the lanes of a wave stay in different
+// rays (their LDS atomics seldom hit the same word).
 //
 // Accumulation is in 32-bit fixed point with integer LDS atomics (float LDS
 // atomics run about 30x slower on gfx950).  For each (brick, view) the scale
@@ -227,12 +283,13 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float *__restrict__ g
                                                      float *__restrict__ g_vol, int64_t stride,
                                                      int nb1, int nb2, BoundK kb, MarchK mk,
                                                      unsigned *__restrict__ vmax) {
-    constexpr bool sum_views = SUM;
     constexpr int P = S + 2;                    // padded edge
     constexpr int NP = P * P * P;
     constexpr int PER = (NP + 255) / 256;       // padded entries per thread
     __shared__ int acc[NP];
     __shared__ float red[8];
+    __shared__ RunP runs[4][64];
+    __shared__ int ends[4][64];
     const int bid = blockIdx.x;
     const int b2 = bid % nb2, b1 = (bid / nb2) % nb1, b0 = bid / (nb2 * nb1);
     const int B[3] = {b0 * S, b1 * S, b2 * S};
@@ -240,26 +297,33 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float *__restrict__ g
     // owned cells [clo, chi] and their extent in voxel units [ulo, uhi]
     float clo[3], chi[3], ulo[3], uhi[3];
     double wlo[3], whi[3];
+    bool interior = true;       // no owned cell touches the clamped rim cells
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const int lo = max(B[a] - 1, 0), hi = min(B[a] + S - 1, g.n[a] - 2);
         clo[a] = (float)lo;
         chi[a] = (float)hi;
+        interior = interior && lo >= 1 && hi <= g.n[a] - 3;
         ulo[a] = lo == 0 ? -0.5f : (float)lo;
         uhi[a] = hi == g.n[a] - 2 ? (float)g.n[a] - 0.5f : (float)(hi + 1);
         wlo[a] = g.c0d[a] + ((double)ulo[a] - 0.5) * g.hd[a];
         whi[a] = g.c0d[a] + ((double)uhi[a] + 0.5) * g.hd[a];
     }
-    const float o0 = (float)(B[0] - 1), o1 = (float)(B[1] - 1), o2 = (float)(B[2] - 1);
+    // byte offset in acc of cell (c0, c1, c2): c0*K0 + c1*K1 + c2*4 + KC,
+    // exact in float (every term is an integer below 2^24)
+    const float K0 = 4.0f * P * P, K1 = 4.0f * P;
+    const float KC = -4.0f * ((float)(B[0] - 1) * P * P + (float)(B[1] - 1) * P + (float)(B[2] - 1));
     float sum[SUM ? PER : 1];   // per-thread float accumulation over views (strided entries)
 #pragma unroll
     for (int k = 0; k < (SUM ? PER : 1); ++k) sum[k] = 0.0f;
     float last_inv = 0.0f;      // per-view mode: 1/scale of the one view
 
-    const int vb = sum_views ? 0 : blockIdx.y;
-    const int ve = sum_views ? V : blockIdx.y + 1;
+    const int vb = SUM ? 0 : blockIdx.y;
+    const int ve = SUM ? V : blockIdx.y + 1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lx = lane & 7, ly = lane >> 3;
+    RunP *const wr = runs[wave];
+    int *const we = ends[wave];
     for (int v = vb; v < ve; ++v) {
         const double th = (double)angles[v];
         const double ct = cos(th), st = sin(th);
@@ -270,11 +334,10 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float *__restrict__ g
         // rectangle (strides gu, gv); the waves sweep the gu*gv offsets.
         const int gu = (u1 - u0 + 8) / 8, gv = (v1 - v0 + 8) / 8;
         const int nph = gu * gv;
-        const int nw = (int)(blockDim.x >> 6);
         // pass 1: largest |g_proj * delta| and smallest step over the rays,
         // and zero the accumulator
         float m = 0.0f, dmin = INFINITY;
-        for (int ph = wave; ph < nph; ph += nw) {
+        for (int ph = wave; ph < nph; ph += 4) {
             const int iu = u0 + lx * gu + ph % gu, iv = v0 + ly * gv + ph / gu;
             if (iu > u1 || iv > v1) continue;
             const int64_t pix = ((int64_t)v * c.nv + iv) * c.nu + iu;
@@ -310,66 +373,123 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float *__restrict__ g
         const float kbound = nr * ns * 1.0625f + 1.0f;
         const float scale = 1073741824.0f / (kbound * m);   // 2^30 / (kbound M)
         // pass 2: scatter every owned sample's 8 weights
-        for (int ph = wave; ph < nph; ph += nw) {
+        for (int ph = wave; ph < nph; ph += 4) {             // uniform per wave
             const int iu = u0 + lx * gu + ph % gu, iv = v0 + ly * gv + ph / gu;
-            if (iu > u1 || iv > v1) continue;
-            const int64_t pix = ((int64_t)v * c.nv + iv) * c.nu + iu;
-            const RayK r = rays[pix];
-            const float gp = g_proj[pix] * r.delta * scale;
-            if (r.n == 0 || gp == 0.0f) continue;
-            float smin = 0.0f, smax = (float)(r.n - 1);
+            int s0 = 0, len = 0;
+            RayK r;
+            float gp = 0.0f;
+            if (iu <= u1 && iv <= v1) {
+                const int64_t pix = ((int64_t)v * c.nv + iv) * c.nu + iu;
+                r = rays[pix];
+                gp = g_proj[pix] * r.delta * scale;
+                if (r.n > 0 && gp != 0.0f) {
+                    float smin = 0.0f, smax = (float)(r.n - 1);
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                if (r.su[a] != 0.0f) {
-                    const float inv = 1.0f / r.su[a];
-                    const float ta = (ulo[a] - r.bu[a]) * inv, tb = (uhi[a] - r.bu[a]) * inv;
-                    smin = fmaxf(smin, fminf(ta, tb));
-                    smax = fminf(smax, fmaxf(ta, tb));
-                } else if (r.bu[a] < ulo[a] - 1.0f || r.bu[a] > uhi[a] + 1.0f) {
-                    smax = -10.0f;
+                    for (int a = 0; a < 3; ++a) {
+                        if (r.su[a] != 0.0f) {
+                            const float inv = 1.0f / r.su[a];
+                            const float ta = (ulo[a] - r.bu[a]) * inv, tb = (uhi[a] - r.bu[a]) * inv;
+                            smin = fmaxf(smin, fminf(ta, tb));
+                            smax = fminf(smax, fmaxf(ta, tb));
+                        } else if (r.bu[a] < ulo[a] - 1.0f || r.bu[a] > uhi[a] + 1.0f) {
+                            smax = -10.0f;
+                        }
+                    }
+                    if (smin <= smax + 2.0f) {
+                        // The owned samples form one run of s: every axis's cell
+                        // index is monotone in s and the owned cells form a box.
+                        // Narrow the estimate [s0, s1] to that run exactly.
+                        s0 = max(0, (int)floorf(smin) - 1);
+                        int s1 = min(r.n - 1, (int)ceilf(smax) + 1);
+                        auto owned = [&](int si) {
+                            const float sf = (float)si;
+                            float fi, fr;
+                            ray_cell(fmaf(sf, r.su[0], r.bu[0]), mk.nm1[0], mk.nm2[0], fi, fr);
+                            bool o = fi >= clo[0] && fi <= chi[0];
+                            ray_cell(fmaf(sf, r.su[1], r.bu[1]), mk.nm1[1], mk.nm2[1], fi, fr);
+                            o = o && fi >= clo[1] && fi <= chi[1];
+                            ray_cell(fmaf(sf, r.su[2], r.bu[2]), mk.nm1[2], mk.nm2[2], fi, fr);
+                            return o && fi >= clo[2] && fi <= chi[2];
+                        };
+                        while (s0 <= s1 && !owned(s0)) ++s0;
+                        while (s1 >= s0 && !owned(s1)) --s1;
+                        len = max(s1 - s0 + 1, 0);
+                    }
                 }
             }
-            if (smin > smax + 2.0f) continue;
-            // The owned samples form one run of s: every axis's cell index is
-            // monotone in s and the owned cells form a box.  Narrow the
-            // estimate [s0, s1] to that run exactly, so the loop below needs
-            // no ownership test.
-            int s0 = max(0, (int)floorf(smin) - 1);
-            int s1 = min(r.n - 1, (int)ceilf(smax) + 1);
-            auto owned = [&](int si) {
-                const float sf = (float)si;
-                float fi, fr;
-                ray_cell(fmaf(sf, r.su[0], r.bu[0]), mk.nm1[0], mk.nm2[0], fi, fr);
-                bool o = fi >= clo[0] && fi <= chi[0];
-                ray_cell(fmaf(sf, r.su[1], r.bu[1]), mk.nm1[1], mk.nm2[1], fi, fr);
-                o = o && fi >= clo[1] && fi <= chi[1];
-                ray_cell(fmaf(sf, r.su[2], r.bu[2]), mk.nm1[2], mk.nm2[2], fi, fr);
-                return o && fi >= clo[2] && fi <= chi[2];
-            };
-            while (s0 <= s1 && !owned(s0)) ++s0;
-            while (s1 >= s0 && !owned(s1)) --s1;
-            for (int s = s0; s <= s1; ++s) {
-                const float sf = (float)s;
-                float f0, f1, f2, c0f, c1f, c2f;
-                ray_cell(fmaf(sf, r.su[0], r.bu[0]), mk.nm1[0], mk.nm2[0], c0f, f0);
-                ray_cell(fmaf(sf, r.su[1], r.bu[1]), mk.nm1[1], mk.nm2[1], c1f, f1);
-                ray_cell(fmaf(sf, r.su[2], r.bu[2]), mk.nm1[2], mk.nm2[2], c2f, f2);
-                const int idx =
-                    (int)fmaf(fmaf(c0f - o0, (float)P, c1f - o1), (float)P, c2f - o2);
-                int *q = acc + idx;
-                const float wx0 = gp * (1.0f - f0), wx1 = gp * f0;
-                const float a00 = wx0 * (1.0f - f1), a01 = wx0 * f1;
-                const float a10 = wx1 * (1.0f - f1), a11 = wx1 * f1;
-                const float g2 = 1.0f - f2;
-                atomicAdd(q, __float2int_rn(a00 * g2));
-                atomicAdd(q + 1, __float2int_rn(a00 * f2));
-                atomicAdd(q + P, __float2int_rn(a01 * g2));
-                atomicAdd(q + P + 1, __float2int_rn(a01 * f2));
-                atomicAdd(q + P * P, __float2int_rn(a10 * g2));
-                atomicAdd(q + P * P + 1, __float2int_rn(a10 * f2));
-                atomicAdd(q + P * P + P, __float2int_rn(a11 * g2));
-                atomicAdd(q + P * P + P + 1, __float2int_rn(a11 * f2));
+            // flatten the wave's runs: item q in [start, start + len) is
+            // sample q - start + s0 of this lane's ray
+            const int incl = wave_incl_sum(len);
+            const int T = __builtin_amdgcn_readlane(incl, 63);
+            if (T == 0) continue;
+            {
+                RunP rp;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    rp.bu[a] = r.bu[a];
+                    rp.su[a] = r.su[a];
+                }
+                rp.gp = gp;
+                rp.off = s0 - (incl - len);
+                if (len > 0) wr[lane] = rp;
+                we[lane] = incl;
             }
+            wave_lds_sync();
+            // Lane j takes items [j K, j K + K): at any step the lanes sit in
+            // different rays, so their LDS atomics rarely meet.
+            const int K = (T + 63) >> 6;
+            int q = lane * K;
+            const int qe = min(q + K, T);
+            // first ray of the slice: the smallest r with end_r > q (binary lifting)
+            int ri = 0;
+#pragma unroll
+            for (int step = 32; step > 0; step >>= 1)
+                if (we[ri + step - 1] <= q) ri += step;
+            int rend = we[min(ri, 63)];
+            RunP rp = wr[min(ri, 63)];
+            for (int it = 0; it < K; ++it, ++q) {                 // uniform
+                if (q >= qe) continue;
+                if (q >= rend) {
+                    do {
+                        rend = we[++ri];
+                    } while (q >= rend);
+                    rp = wr[ri];
+                }
+                const float sf = (float)(q + rp.off);
+                const float x0 = fmaf(sf, rp.su[0], rp.bu[0]);
+                const float x1 = fmaf(sf, rp.su[1], rp.bu[1]);
+                const float x2 = fmaf(sf, rp.su[2], rp.bu[2]);
+                float c0f, c1f, c2f, f0, f1, f2;
+                if (interior) {
+                    c0f = floorf(x0);
+                    c1f = floorf(x1);
+                    c2f = floorf(x2);
+                    f0 = x0 - c0f;
+                    f1 = x1 - c1f;
+                    f2 = x2 - c2f;
+                } else {
+                    ray_cell(x0, mk.nm1[0], mk.nm2[0], c0f, f0);
+                    ray_cell(x1, mk.nm1[1], mk.nm2[1], c1f, f1);
+                    ray_cell(x2, mk.nm1[2], mk.nm2[2], c2f, f2);
+                }
+                const int off = (int)fmaf(c0f, K0, fmaf(c1f, K1, fmaf(c2f, 4.0f, KC)));
+                char *qb = (char *)acc + off;
+                const float w = rp.gp;
+                const float wx1 = w * f0, wx0 = w - wx1;
+                const float a01 = wx0 * f1, a00 = wx0 - a01;
+                const float a11 = wx1 * f1, a10 = wx1 - a11;
+                const float e001 = a00 * f2, e011 = a01 * f2;
+                const float e101 = a10 * f2, e111 = a11 * f2;
+                atomicAdd((int *)qb, round_int(a00 - e001));
+                atomicAdd((int *)(qb + 4), round_int(e001));
+                atomicAdd((int *)(qb + 4 * P), round_int(a01 - e011));
+                atomicAdd((int *)(qb + 4 * P + 4), round_int(e011));
+                atomicAdd((int *)(qb + 4 * P * P), round_int(a10 - e101));
+                atomicAdd((int *)(qb + 4 * P * P + 4), round_int(e101));
+                atomicAdd((int *)(qb + 4 * P * P + 4 * P), round_int(a11 - e111));
+                atomicAdd((int *)(qb + 4 * P * P + 4 * P + 4), round_int(e111));
+            }
+            wave_lds_sync();
         }
         __syncthreads();
         const float inv_scale = 1.0f / scale;
@@ -384,7 +504,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float *__restrict__ g
             last_inv = inv_scale;
         }
     }
-    float *out = g_vol + (sum_views ? 0 : (int64_t)blockIdx.y * stride);
+    float *out = g_vol + (SUM ? 0 : (int64_t)blockIdx.y * stride);
     float mx = 0.0f;
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
@@ -401,7 +521,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float *__restrict__ g
             mx = fmaxf(mx, fabsf(val));
         }
     }
-    if (vmax && !sum_views) {
+    if (vmax && !SUM) {
         for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
         if (lane == 0 && mx > 0.0f) atomicMax(&vmax[blockIdx.y], __float_as_uint(mx));
     }
@@ -431,13 +551,28 @@ static BoundK make_bound(const GridK &g, const ConeK &c) {
     return b;
 }
 
+template <int WU, int WV, int AU>
+static void project_tiled(const float *vol, int64_t stride, const GridK &g, const ConeK &c,
+                          const float *angles, int V, float *proj, hipStream_t s) {
+    constexpr int BU = WU * AU, BV = WV * (4 / AU);
+    const int tu = (c.nu + BU - 1) / BU, tv = (c.nv + BV - 1) / BV;
+    dim3 grid((unsigned)(tu * tv), (unsigned)V);
+    k_project<WU, WV, AU><<<grid, 256, 0, s>>>(vol, stride, g, c, make_march(g), angles, proj, tu);
+}
+
 hipError_t launch_project(const float *vol, int64_t stride, const GridK &g, const ConeK &c,
                           const float *angles, int V, float *proj, hipStream_t s) {
-    const int tu = (c.nu + PT - 1) / PT, tv = (c.nv + PT - 1) / PT;
-    dim3 grid((unsigned)(tu * tv), (unsigned)V);
-    {
-        ProfScope prof_("project", s);
-        k_project<<<grid, 256, 0, s>>>(vol, stride, g, c, make_march(g), angles, proj, tu);
+    ProfScope prof_("project", s);
+    switch (tune_get(KNOB_PROJECT_TILE)) {
+        case 0: project_tiled<16, 4, 1>(vol, stride, g, c, angles, V, proj, s); break;
+        case 1: project_tiled<8, 8, 2>(vol, stride, g, c, angles, V, proj, s); break;
+        case 2: project_tiled<4, 16, 4>(vol, stride, g, c, angles, V, proj, s); break;
+        case 3: project_tiled<2, 32, 4>(vol, stride, g, c, angles, V, proj, s); break;
+        case 4: project_tiled<32, 2, 1>(vol, stride, g, c, angles, V, proj, s); break;
+        case 5: project_tiled<1, 64, 4>(vol, stride, g, c, angles, V, proj, s); break;
+        case 6: project_tiled<2, 32, 2>(vol, stride, g, c, angles, V, proj, s); break;
+        case 7: project_tiled<1, 64, 2>(vol, stride, g, c, angles, V, proj, s); break;
+        default: project_tiled<2, 32, 1>(vol, stride, g, c, angles, V, proj, s); break;
     }
     return hipGetLastError();
 }

@@ -81,6 +81,9 @@ _SIGS = {
     "pmf_profile": ([C.c_int], C.c_int),
     "pmf_profile_read": ([C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
     "pmf_profile_names": ([C.c_char_p, _SZ], _SZ),
+    "pmf_tune_candidates": ([C.c_int], C.c_int),
+    "pmf_tune_get": ([C.c_int], C.c_int),
+    "pmf_tune_set": ([C.c_int, C.c_int], C.c_int),
     "pmf_warp_project_workspace": ([C.c_int, C.c_int, C.POINTER(PmfGrid), C.c_int,
                                     C.POINTER(PmfGrid), C.POINTER(PmfCone)], _SZ),
     "pmf_warp_project": ([_P, C.POINTER(PmfGrid), C.c_int, C.c_int, _P, C.POINTER(PmfGrid), _P,
@@ -315,6 +318,29 @@ def pmf_profile_read(kernel: str) -> Tuple[float, int]:
     n = C.c_int64()
     _check(lib().pmf_profile_read(kernel.encode(), C.byref(t), C.byref(n)))
     return float(t.value), int(n.value)
+
+
+PMF_TUNE_PROJECT_TILE = 0
+PMF_TUNE_BACKPROJECT_BRICK = 1
+
+
+def pmf_tune_candidates(knob: int) -> int:
+    return int(lib().pmf_tune_candidates(knob))
+
+
+def pmf_tune_get(knob: int) -> int:
+    rc = lib().pmf_tune_get(knob)
+    if rc < 0:
+        _check(rc)
+    return int(rc)
+
+
+def pmf_tune_set(knob: int, choice: int) -> int:
+    """Select a launch shape; returns the previous choice."""
+    rc = lib().pmf_tune_set(knob, choice)
+    if rc < 0:
+        _check(rc)
+    return int(rc)
 
 
 def pmf_warp_project(ref, grid: Grid, bases, levels, coeff, cone: Cone, angles, out=None):

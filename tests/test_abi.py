@@ -124,3 +124,19 @@ def test_workspace_queries_reject_invalid(lib):
     lv = (ops.PmfGrid * 1)(grid())
     assert lib.pmf_warp_project_workspace(1, 1, lv, 2, C.byref(g), C.byref(c)) >= 2 * 512 * 4
     assert lib.pmf_warp_project_bwd_workspace(1, 1, lv, 2, C.byref(g), C.byref(c)) > 0
+
+
+def test_tune_knobs(lib):
+    knob = ops.PMF_TUNE_PROJECT_TILE
+    n = lib.pmf_tune_candidates(knob)
+    assert n >= 2
+    assert lib.pmf_tune_candidates(99) == 0
+    prev = lib.pmf_tune_get(knob)
+    assert 0 <= prev < n
+    assert lib.pmf_tune_set(knob, n - 1) == prev
+    assert lib.pmf_tune_get(knob) == n - 1
+    assert lib.pmf_tune_set(knob, n) == ops.PMF_EINVAL
+    assert lib.pmf_tune_set(knob, -1) == ops.PMF_EINVAL
+    assert lib.pmf_tune_set(99, 0) == ops.PMF_EINVAL
+    assert lib.pmf_tune_get(99) == ops.PMF_EINVAL
+    assert lib.pmf_tune_set(knob, prev) == n - 1
