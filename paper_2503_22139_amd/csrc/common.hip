@@ -161,6 +161,14 @@ __global__ void k_fill_i32(int32_t *__restrict__ p, int64_t n, int32_t v) {
     for (; i < n; i += stride) p[i] = v;
 }
 
+__global__ void k_fill_pair_u32(uint32_t *__restrict__ p, int64_t n, uint32_t a, uint32_t b) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        p[2 * i] = a;
+        p[2 * i + 1] = b;
+    }
+}
+
 __global__ void k_accumulate(float *__restrict__ dst, const float *__restrict__ src, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -188,6 +196,15 @@ hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
     {
         ProfScope prof_("fill", s);
         k_fill_i32<<<fill_blocks(n), 256, 0, s>>>(p, n, v);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_pair_u32(uint32_t *p, int64_t n, uint32_t a, uint32_t b, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    {
+        ProfScope prof_("fill", s);
+        k_fill_pair_u32<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, n, a, b);
     }
     return hipGetLastError();
 }

@@ -220,6 +220,8 @@ int tune_candidates(int knob);
 // Each returns hipSuccess or the launch error.  Arguments were validated.
 hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+// p[2i] = a, p[2i+1] = b for i < n
+hipError_t launch_fill_pair_u32(uint32_t *p, int64_t n, uint32_t a, uint32_t b, hipStream_t s);
 hipError_t launch_accumulate(float *dst, const float *src, int64_t n, hipStream_t s);
 
 // voxelize

@@ -172,16 +172,47 @@ __global__ __launch_bounds__(256) void k_project(const float *__restrict__ vol, 
     proj[((int64_t)v * c.nv + iv) * c.nu + iu] = (acc0 + acc1) * r.delta;
 }
 
+// Per-ray constants of every view, and per view the two figures that set the
+// back-projection's fixed-point scale: the largest |g_proj * delta| over the
+// rays, and the smallest step over the rays with at least two samples (a ray
+// with one sample gives any voxel at most one contribution).  The grid is
+// (workgroups per view, V): a workgroup strides over the rays of one view and
+// adds its two figures with one atomic each.
 __global__ __launch_bounds__(256) void k_ray_table(GridK g, ConeK c,
-                                                   const float *__restrict__ angles, int V,
-                                                   RayK *__restrict__ out) {
-    const int64_t npix = (int64_t)c.nu * c.nv;
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= npix * V) return;
-    const int v = (int)(q / npix);
-    const int p = (int)(q % npix);
+                                                   const float *__restrict__ angles,
+                                                   const float *__restrict__ g_proj,
+                                                   RayK *__restrict__ out,
+                                                   unsigned *__restrict__ stats) {
+    __shared__ float red[8];
+    const int npix = c.nu * c.nv;
+    const int v = blockIdx.y;
     const double th = (double)angles[v];
-    out[q] = ray_setup(g, c, cos(th), sin(th), p % c.nu, p / c.nu);
+    const double ct = cos(th), st = sin(th);
+    float m = 0.0f, d = INFINITY;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += gridDim.x * blockDim.x) {
+        const RayK r = ray_setup(g, c, ct, st, p % c.nu, p / c.nu);
+        const int64_t q = (int64_t)v * npix + p;
+        out[q] = r;
+        if (r.n > 0) m = fmaxf(m, fabsf(g_proj[q] * r.delta));
+        if (r.n > 1) d = fminf(d, r.delta);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        m = fmaxf(m, __shfl_xor(m, o, 64));
+        d = fminf(d, __shfl_xor(d, o, 64));
+    }
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[wave] = m;
+        red[4 + wave] = d;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+        d = fminf(fminf(red[4], red[5]), fminf(red[6], red[7]));
+        // non-negative floats order like their bit patterns
+        if (m > 0.0f) atomicMax(&stats[2 * v], __float_as_uint(m));
+        if (d < INFINITY) atomicMin(&stats[2 * v + 1], __float_as_uint(d));
+    }
 }
 
 // Bounding detector rectangle of the shadow of a world box (double).
@@ -271,25 +302,28 @@ struct BoundK {
 // Accumulation is in 32-bit fixed point with integer LDS atomics (float LDS
 // atomics run about 30x slower on gfx950).  For each (brick, view) the scale
 // is 2^30 / (kbound * M), where M is the largest |g_proj * delta| among the
-// rays that reach the brick and kbound bounds how many samples can touch one
-// voxel in this view (from the geometry and the rays' smallest step): every
-// partial sum stays below 2^30 in magnitude, and each contribution is
-// rounded to within 0.5 / scale.
+// view's rays and kbound bounds how many samples can touch one voxel in this
+// view (from the geometry and the smallest step of the rays with two or more
+// samples): every partial sum stays below 2^30 in magnitude, and each
+// contribution is rounded to within 0.5 / scale.
 // With vmax non-null the largest |g_vol| of each view is also recorded.
+constexpr int BWD_WAVES = 8;    // wavefronts per back-projection workgroup
+
 template <int S, bool SUM>
-__global__ __launch_bounds__(256) void k_project_bwd(const float *__restrict__ g_proj, GridK g,
+__global__ __launch_bounds__(64 * BWD_WAVES) void k_project_bwd(const float *__restrict__ g_proj, GridK g,
                                                      ConeK c, const float *__restrict__ angles,
-                                                     const RayK *__restrict__ rays, int V,
+                                                     const RayK *__restrict__ rays,
+                                                     const unsigned *__restrict__ stats, int V,
                                                      float *__restrict__ g_vol, int64_t stride,
                                                      int nb1, int nb2, BoundK kb, MarchK mk,
                                                      unsigned *__restrict__ vmax) {
     constexpr int P = S + 2;                    // padded edge
     constexpr int NP = P * P * P;
-    constexpr int PER = (NP + 255) / 256;       // padded entries per thread
+    constexpr int NT = 64 * BWD_WAVES;
+    constexpr int PER = (NP + NT - 1) / NT;     // padded entries per thread
     __shared__ int acc[NP];
-    __shared__ float red[8];
-    __shared__ RunP runs[4][64];
-    __shared__ int ends[4][64];
+    __shared__ RunP runs[BWD_WAVES][64];
+    __shared__ int ends[BWD_WAVES][64];
     const int bid = blockIdx.x;
     const int b2 = bid % nb2, b1 = (bid / nb2) % nb1, b0 = bid / (nb2 * nb1);
     const int B[3] = {b0 * S, b1 * S, b2 * S};
@@ -331,35 +365,15 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float *__restrict__ g
         shadow_rect(c, ct, st, wlo, whi, u0, u1, v0, v1);   // uniform across the block
         if (u1 < u0 || v1 < v0) continue;
         // The 64 lanes of a wave take an 8x8 grid of pixels spread over the
-        // rectangle (strides gu, gv); the waves sweep the gu*gv offsets.
+        // rectangle (strides gu, gv); the waves sweep the gu*gv offsets.  Rays
+        // that far apart keep the lanes' LDS atomics on unrelated words.
         const int gu = (u1 - u0 + 8) / 8, gv = (v1 - v0 + 8) / 8;
         const int nph = gu * gv;
-        // pass 1: largest |g_proj * delta| and smallest step over the rays,
-        // and zero the accumulator
-        float m = 0.0f, dmin = INFINITY;
-        for (int ph = wave; ph < nph; ph += 4) {
-            const int iu = u0 + lx * gu + ph % gu, iv = v0 + ly * gv + ph / gu;
-            if (iu > u1 || iv > v1) continue;
-            const int64_t pix = ((int64_t)v * c.nv + iv) * c.nu + iu;
-            const RayK r = rays[pix];
-            if (r.n == 0) continue;
-            m = fmaxf(m, fabsf(g_proj[pix] * r.delta));
-            dmin = fminf(dmin, r.delta);
-        }
-        for (int i = threadIdx.x; i < NP; i += blockDim.x) acc[i] = 0;
-        for (int o = 32; o > 0; o >>= 1) {
-            m = fmaxf(m, __shfl_xor(m, o, 64));
-            dmin = fminf(dmin, __shfl_xor(dmin, o, 64));
-        }
-        if (lane == 0) {
-            red[wave] = m;
-            red[4 + wave] = dmin;
-        }
-        __syncthreads();
-        m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
-        dmin = fminf(fminf(red[4], red[5]), fminf(red[6], red[7]));
-        __syncthreads();
+        const float m = __uint_as_float(stats[2 * v]);
+        const float dmin = __uint_as_float(stats[2 * v + 1]);
         if (!(m > 0.0f)) continue;
+        for (int i = threadIdx.x; i < NP; i += NT) acc[i] = 0;
+        __syncthreads();
         // Contributions one voxel can receive in this view: rays through the
         // detector shadow of its 2x2x2-cell support, times samples of one ray
         // inside that support (its diagonal over the smallest step, plus one).
@@ -369,11 +383,11 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float *__restrict__ g
         const float wu = lat * kb.mag + kb.R * kb.persp * dep;
         const float wv = kb.two_hz * kb.mag + kb.Z * kb.persp * dep;
         const float nr = (floorf(wu * kb.inv_du) + 1.0f) * (floorf(wv * kb.inv_dv) + 1.0f);
-        const float ns = floorf(kb.diag / dmin) + 1.0f;
+        const float ns = floorf(kb.diag / dmin) + 1.0f;     // 1 when no ray has two samples
         const float kbound = nr * ns * 1.0625f + 1.0f;
         const float scale = 1073741824.0f / (kbound * m);   // 2^30 / (kbound M)
         // pass 2: scatter every owned sample's 8 weights
-        for (int ph = wave; ph < nph; ph += 4) {             // uniform per wave
+        for (int ph = wave; ph < nph; ph += BWD_WAVES) {     // uniform per wave
             const int iu = u0 + lx * gu + ph % gu, iv = v0 + ly * gv + ph / gu;
             int s0 = 0, len = 0;
             RayK r;
@@ -387,7 +401,8 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float *__restrict__ g
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
                         if (r.su[a] != 0.0f) {
-                            const float inv = 1.0f / r.su[a];
+                            // an estimate only: the run is made exact below
+                            const float inv = __builtin_amdgcn_rcpf(r.su[a]);
                             const float ta = (ulo[a] - r.bu[a]) * inv, tb = (uhi[a] - r.bu[a]) * inv;
                             smin = fmaxf(smin, fminf(ta, tb));
                             smax = fminf(smax, fmaxf(ta, tb));
@@ -398,9 +413,9 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float *__restrict__ g
                     if (smin <= smax + 2.0f) {
                         // The owned samples form one run of s: every axis's cell
                         // index is monotone in s and the owned cells form a box.
-                        // Narrow the estimate [s0, s1] to that run exactly.
-                        s0 = max(0, (int)floorf(smin) - 1);
-                        int s1 = min(r.n - 1, (int)ceilf(smax) + 1);
+                        // The estimate puts the run at [ceil(smin), ceil(smax) - 1]
+                        // up to rounding far below one sample; start one sample
+                        // outside each end and move to the exact ends.
                         auto owned = [&](int si) {
                             const float sf = (float)si;
                             float fi, fr;
@@ -411,9 +426,28 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float *__restrict__ g
                             ray_cell(fmaf(sf, r.su[2], r.bu[2]), mk.nm1[2], mk.nm2[2], fi, fr);
                             return o && fi >= clo[2] && fi <= chi[2];
                         };
-                        while (s0 <= s1 && !owned(s0)) ++s0;
-                        while (s1 >= s0 && !owned(s1)) --s1;
-                        len = max(s1 - s0 + 1, 0);
+                        const int last = r.n - 1;
+                        s0 = min(max(0, (int)ceilf(smin) - 1), last);
+                        int s1 = min(max(0, (int)ceilf(smax)), last);
+                        bool found;
+                        if (owned(s0)) {
+                            while (s0 > 0 && owned(s0 - 1)) --s0;
+                            found = true;
+                        } else {
+                            ++s0;
+                            while (s0 <= s1 && !owned(s0)) ++s0;
+                            found = s0 <= s1;
+                        }
+                        if (found) {
+                            s1 = max(s1, s0);
+                            if (owned(s1)) {
+                                while (s1 < last && owned(s1 + 1)) ++s1;
+                            } else {
+                                --s1;
+                                while (s1 > s0 && !owned(s1)) --s1;
+                            }
+                            len = s1 - s0 + 1;
+                        }
                     }
                 }
             }
@@ -435,8 +469,8 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float *__restrict__ g
                 we[lane] = incl;
             }
             wave_lds_sync();
-            // Lane j takes items [j K, j K + K): at any step the lanes sit in
-            // different rays, so their LDS atomics rarely meet.
+            // Lane j takes items [j K, j K + K): every lane does a sample per
+            // step however the run lengths differ.
             const int K = (T + 63) >> 6;
             int q = lane * K;
             const int qe = min(q + K, T);
@@ -445,8 +479,8 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float *__restrict__ g
 #pragma unroll
             for (int step = 32; step > 0; step >>= 1)
                 if (we[ri + step - 1] <= q) ri += step;
-            int rend = we[min(ri, 63)];
-            RunP rp = wr[min(ri, 63)];
+            int rend = we[ri];
+            RunP rp = wr[ri];
             for (int it = 0; it < K; ++it, ++q) {                 // uniform
                 if (q >= qe) continue;
                 if (q >= rend) {
@@ -496,7 +530,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float *__restrict__ g
         if constexpr (SUM) {
 #pragma unroll
             for (int k = 0; k < PER; ++k) {
-                const int i = threadIdx.x + 256 * k;
+                const int i = threadIdx.x + NT * k;
                 if (i < NP) sum[k] += (float)acc[i] * inv_scale;
             }
             __syncthreads();
@@ -508,7 +542,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(const float *__restrict__ g
     float mx = 0.0f;
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-        const int i = threadIdx.x + 256 * k;
+        const int i = threadIdx.x + NT * k;
         if (i >= NP) continue;
         const int z = i % P - 1, y = (i / P) % P - 1, x = i / (P * P) - 1;
         if (x < 0 || y < 0 || z < 0 || x >= S || y >= S || z >= S) continue;
@@ -577,20 +611,28 @@ hipError_t launch_project(const float *vol, int64_t stride, const GridK &g, cons
     return hipGetLastError();
 }
 
+// Workspace: the per-ray table, then two words of statistics per view.
 size_t project_bwd_workspace(const pmf_cone_t &c, int V) {
-    return align256(sizeof(RayK) * (size_t)c.nu * (size_t)c.nv * (size_t)V);
+    return align256(sizeof(RayK) * (size_t)c.nu * (size_t)c.nv * (size_t)V) +
+           align256(sizeof(unsigned) * 2 * (size_t)V);
 }
 
 hipError_t launch_project_bwd(const float *g_proj, const GridK &g, const ConeK &c,
                               const float *angles, int V, float *g_vol, int64_t stride, void *ws,
                               hipStream_t s, unsigned *vmax) {
     RayK *rays = (RayK *)ws;
-    const int64_t nr = (int64_t)c.nu * c.nv * V;
+    unsigned *stats =
+        (unsigned *)((char *)ws + align256(sizeof(RayK) * (size_t)c.nu * (size_t)c.nv * (size_t)V));
+    // stats[2v] = 0 (max), stats[2v+1] = +inf (min): one fill of the pair pattern
+    hipError_t e = launch_fill_pair_u32(stats, V, 0u, 0x7f800000u, s);
+    if (e != hipSuccess) return e;
     {
         ProfScope prof_("ray_table", s);
-        k_ray_table<<<(unsigned)((nr + 255) / 256), 256, 0, s>>>(g, c, angles, V, rays);
+        const int per_view = (c.nu * c.nv + 255) / 256;
+        dim3 grid((unsigned)(per_view < 64 ? per_view : 64), (unsigned)V);
+        k_ray_table<<<grid, 256, 0, s>>>(g, c, angles, g_proj, rays, stats);
     }
-    hipError_t e = hipGetLastError();
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     constexpr int S = 16;
     int nb[3];
@@ -600,11 +642,11 @@ hipError_t launch_project_bwd(const float *g_proj, const GridK &g, const ConeK &
     {
         ProfScope prof_("project_bwd", s);
         if (sum_views)
-            k_project_bwd<S, true><<<grid, 256, 0, s>>>(g_proj, g, c, angles, rays, V, g_vol,
+            k_project_bwd<S, true><<<grid, 64 * BWD_WAVES, 0, s>>>(g_proj, g, c, angles, rays, stats, V, g_vol,
                                                        stride, nb[1], nb[2], make_bound(g, c),
                                                        make_march(g), vmax);
         else
-            k_project_bwd<S, false><<<grid, 256, 0, s>>>(g_proj, g, c, angles, rays, V, g_vol,
+            k_project_bwd<S, false><<<grid, 64 * BWD_WAVES, 0, s>>>(g_proj, g, c, angles, rays, stats, V, g_vol,
                                                         stride, nb[1], nb[2], make_bound(g, c),
                                                         make_march(g), vmax);
     }
