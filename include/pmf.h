@@ -255,6 +255,47 @@ int pmf_warp_project_bwd(const float *ref, const pmf_grid_t *grid, int L, int B,
                            const float *g_proj, float *g_ref, float *const *g_bases,
                            float *g_coeff, void *ws, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------ ragged batch of scans
+ * Up to PMF_MAX_SCANS independent scans (each its own reference volume,
+ * grids, geometry and views; one motion model shape L, B for all) through
+ * the motion path together: each stage is one kernel launch over the items
+ * (voxels, detector tiles, bricks) of every scan, so small scans do not leave
+ * the GPU idle and the whole batch is a handful of launches (the batched form
+ * of the motion path extended to several instances; the views of a scan are
+ * independent as in Sec. 2.3.2).
+ *
+ * pmf_scan_t describes one scan; all pointers are device pointers except
+ * that the struct itself lives on the host.  Fields used by the forward call:
+ * ref, grid, bases[0..L-1], lvl[0..L-1], coeff, V, cone, angles, proj.  The
+ * adjoint call also reads g_proj and writes g_ref, g_bases[0..L-1], g_coeff
+ * (layouts as in pmf_warp_project / pmf_warp_project_bwd).  Results equal
+ * n_scans separate calls of pmf_warp_project / pmf_warp_project_bwd.
+ * Workspaces are the sums of the per-scan workspaces; errors name the scan. */
+#define PMF_MAX_SCANS 4
+#define PMF_MAX_LEVELS 4
+typedef struct {
+    const float *ref;
+    pmf_grid_t grid;
+    const float *bases[PMF_MAX_LEVELS];
+    pmf_grid_t lvl[PMF_MAX_LEVELS];
+    const float *coeff;
+    int32_t V;
+    pmf_cone_t cone;
+    const float *angles;
+    float *proj;
+    const float *g_proj;
+    float *g_ref;
+    float *g_bases[PMF_MAX_LEVELS];
+    float *g_coeff;
+} pmf_scan_t;
+
+size_t pmf_warp_project_scans_workspace(int L, int B, const pmf_scan_t *scans, int n_scans);
+int pmf_warp_project_scans(int L, int B, const pmf_scan_t *scans, int n_scans, void *ws,
+                           size_t ws_bytes, void *stream);
+size_t pmf_warp_project_bwd_scans_workspace(int L, int B, const pmf_scan_t *scans, int n_scans);
+int pmf_warp_project_bwd_scans(int L, int B, const pmf_scan_t *scans, int n_scans, void *ws,
+                               size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

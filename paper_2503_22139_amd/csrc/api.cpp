@@ -401,4 +401,116 @@ int pmf_warp_project_bwd(const float *ref, const pmf_grid_t *grid, int L, int B,
                       "warp_project_bwd");
 }
 
+// ------------------------------------------------ ragged batch of scans
+}  // extern "C"
+
+namespace {
+
+static_assert(PMF_MAX_SCANS == MAXS && PMF_MAX_LEVELS == MAXL, "table sizes");
+
+// Validates scan k's forward fields; fills its kernel descriptors.
+int scan_fwd(int L, int B, const pmf_scan_t &sc, int k, GridK &g, GridK *lg, LevelsK &lv,
+             ConeK &c) {
+    char what[64];
+    snprintf(what, sizeof what, "scan %d", k);
+    PMF_CHECK(check_grid(&sc.grid, what));
+    PMF_CHECK(check_levels(L, B, sc.bases, sc.lvl, what));
+    PMF_CHECK(check_cone(&sc.cone, &sc.grid));
+    if (sc.V < 1) return fail(PMF_EINVAL, "%s: V must be >= 1", what);
+    if (!sc.ref || !sc.coeff || !sc.angles) return fail(PMF_EINVAL, "%s: null pointer", what);
+    g = make_grid(sc.grid);
+    lv = make_levels(L, B, sc.bases, sc.lvl, g, lg);
+    c = make_cone(sc.cone, g);
+    return PMF_OK;
+}
+
+int check_scans(const pmf_scan_t *scans, int n) {
+    if (!scans) return fail(PMF_EINVAL, "scans: null");
+    if (n < 1 || n > MAXS) return fail(PMF_EINVAL, "scans: n_scans must be in [1, %d]", MAXS);
+    return PMF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pmf_warp_project_scans_workspace(int L, int B, const pmf_scan_t *scans, int n) {
+    if (!scans || n < 1 || n > MAXS) return 0;
+    size_t total = 0;
+    for (int k = 0; k < n; ++k) {
+        size_t w = pmf_warp_project_workspace(L, B, scans[k].lvl, scans[k].V, &scans[k].grid,
+                                              &scans[k].cone);
+        if (w == 0) return 0;
+        total += align256(w);
+    }
+    return total;
+}
+
+int pmf_warp_project_scans(int L, int B, const pmf_scan_t *scans, int n, void *ws,
+                           size_t ws_bytes, void *stream) {
+    PMF_CHECK(check_scans(scans, n));
+    WPJob jobs[MAXS];
+    char *w = (char *)ws;
+    size_t need = 0;
+    for (int k = 0; k < n; ++k) {
+        const pmf_scan_t &sc = scans[k];
+        GridK lg[MAXL];
+        WPJob &j = jobs[k];
+        PMF_CHECK(scan_fwd(L, B, sc, k, j.g, lg, j.lv, j.c));
+        if (!sc.proj) return fail(PMF_EINVAL, "scan %d: null proj", k);
+        j.ref = sc.ref;
+        j.coeff = sc.coeff;
+        j.V = sc.V;
+        j.angles = sc.angles;
+        j.proj = sc.proj;
+        j.ws = w ? w + need : nullptr;
+        need += align256(warp_project_workspace(j.lv, sc.V, j.g, sc.cone));
+    }
+    PMF_CHECK(check_ws(ws, ws_bytes, need));
+    return hip_status(launch_warp_project_jobs(jobs, n, as_stream(stream)), "warp_project_scans");
+}
+
+size_t pmf_warp_project_bwd_scans_workspace(int L, int B, const pmf_scan_t *scans, int n) {
+    if (!scans || n < 1 || n > MAXS) return 0;
+    size_t total = 0;
+    for (int k = 0; k < n; ++k) {
+        size_t w = pmf_warp_project_bwd_workspace(L, B, scans[k].lvl, scans[k].V, &scans[k].grid,
+                                                  &scans[k].cone);
+        if (w == 0) return 0;
+        total += align256(w);
+    }
+    return total;
+}
+
+int pmf_warp_project_bwd_scans(int L, int B, const pmf_scan_t *scans, int n, void *ws,
+                               size_t ws_bytes, void *stream) {
+    PMF_CHECK(check_scans(scans, n));
+    WPBJob jobs[MAXS];
+    char *w = (char *)ws;
+    size_t need = 0;
+    for (int k = 0; k < n; ++k) {
+        const pmf_scan_t &sc = scans[k];
+        WPBJob &j = jobs[k];
+        PMF_CHECK(scan_fwd(L, B, sc, k, j.g, j.lvl_grids, j.lv, j.c));
+        if (!sc.g_proj || !sc.g_ref || !sc.g_coeff)
+            return fail(PMF_EINVAL, "scan %d: null adjoint pointer", k);
+        for (int l = 0; l < MAXL; ++l) {
+            if (l < L && !sc.g_bases[l]) return fail(PMF_EINVAL, "scan %d: null g_bases[%d]", k, l);
+            j.g_bases[l] = l < L ? sc.g_bases[l] : nullptr;
+        }
+        j.ref = sc.ref;
+        j.coeff = sc.coeff;
+        j.V = sc.V;
+        j.angles = sc.angles;
+        j.g_proj = sc.g_proj;
+        j.g_ref = sc.g_ref;
+        j.g_coeff = sc.g_coeff;
+        j.ws = w ? w + need : nullptr;
+        need += align256(warp_project_bwd_workspace(j.lv, j.lvl_grids, sc.V, j.g, sc.cone));
+    }
+    PMF_CHECK(check_ws(ws, ws_bytes, need));
+    return hip_status(launch_warp_project_bwd_jobs(jobs, n, as_stream(stream)),
+                      "warp_project_bwd_scans");
+}
+
 }  // extern "C"

@@ -22,12 +22,34 @@
 
 namespace pmf {
 
+// One scan's share of a ragged launch: workgroups [first[k], first[k+1])
+// belong to scan k.
+struct CWK {
+    const float *ref;
+    GridK g;
+    LevelsK lv;
+    const float *coeff;
+    int V;
+    float *warped;
+};
+struct CWTab {
+    CWK s[MAXS];
+    int first[MAXS + 1];
+    int n;
+};
+
 template <int L, int B>
-__global__ __launch_bounds__(256) void k_combine_warp(const float *__restrict__ ref, GridK g,
-                                                      LevelsK lv, const float *__restrict__ coeff,
-                                                      int V, float *__restrict__ warped) {
+__global__ __launch_bounds__(256) void k_combine_warp(CWTab t) {
+    const int job = job_of(t, (int)blockIdx.x);
+    const CWK &cj = t.s[job];
+    const GridK &g = cj.g;
+    const LevelsK &lv = cj.lv;
+    const float *__restrict__ ref = cj.ref;
+    const float *__restrict__ coeff = cj.coeff;
+    const int V = cj.V;
+    float *__restrict__ warped = cj.warped;
     const int64_t N = grid_size(g);
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t j = (int64_t)((int)blockIdx.x - t.first[job]) * blockDim.x + threadIdx.x;
     if (j >= N) return;
     const int iz = (int)(j % g.n[2]);
     const int iy = (int)((j / g.n[2]) % g.n[1]);
@@ -77,13 +99,44 @@ struct GOut {
 // float box.
 // The float box is staged per brick and summed by k_gather_boxes;
 // displacements that leave the halo fall back to global atomics.
+struct WCK {
+    const float *ref;
+    GridK g;
+    LevelsK lv;
+    const float *coeff;     // this chunk's first view
+    int V;                  // views in this chunk
+    const float *g_I;
+    const unsigned *vmax;
+    float *g_ref;
+    float *stage;
+    GOut gout;
+    int accumulate;
+    int nb1, nb2;
+    float *partial;
+};
+struct WCTab {
+    WCK s[MAXS];
+    int first[MAXS + 1];
+    int n;
+};
+
 template <int L, int B>
-__global__ __launch_bounds__(256) void k_warp_combine_bwd(
-    const float *__restrict__ ref, GridK g, LevelsK lv, const float *__restrict__ coeff, int V,
-    const float *__restrict__ g_I, const unsigned *__restrict__ vmax, float *__restrict__ g_ref,
-    float *__restrict__ stage, GOut gout, int accumulate, int nb1, int nb2,
-    float *__restrict__ partial) {
+__global__ __launch_bounds__(256) void k_warp_combine_bwd(WCTab t) {
     constexpr int NC = L * B * 3;
+    const int job = job_of(t, (int)blockIdx.x);
+    const WCK &wj = t.s[job];
+    const GridK &g = wj.g;
+    const LevelsK &lv = wj.lv;
+    const float *__restrict__ ref = wj.ref;
+    const float *__restrict__ coeff = wj.coeff;
+    const int V = wj.V;
+    const float *__restrict__ g_I = wj.g_I;
+    const unsigned *__restrict__ vmax = wj.vmax;
+    float *__restrict__ g_ref = wj.g_ref;
+    const GOut &gout = wj.gout;
+    const int accumulate = wj.accumulate;
+    const int nb1 = wj.nb1, nb2 = wj.nb2;
+    const int blk = (int)blockIdx.x - t.first[job];
     extern __shared__ float smem[];
     int *ibox = (int *)smem;              // HB^3 fixed point, high words
     int *lbox = (int *)smem + HB3;        // HB^3 fixed point, low words
@@ -95,7 +148,7 @@ __global__ __launch_bounds__(256) void k_warp_combine_bwd(
         fbox[i] = 0.0f;
     }
     for (int i = threadIdx.x; i < V * NC; i += blockDim.x) cacc[i] = 0.0f;
-    const int bid = blockIdx.x;
+    const int bid = blk;
     const int b2 = bid % nb2, b1 = (bid / nb2) % nb1, b0 = bid / (nb2 * nb1);
     const int B0 = b0 * FB, B1 = b1 * FB, B2 = b2 * FB;
     const int64_t N = grid_size(g);
@@ -236,10 +289,10 @@ __global__ __launch_bounds__(256) void k_warp_combine_bwd(
         }
         __syncthreads();
     }
-    float *st = stage + (int64_t)blockIdx.x * HB3;
+    float *st = wj.stage + (int64_t)blk * HB3;
     for (int i = threadIdx.x; i < HB3; i += blockDim.x) st[i] = fbox[i];
     for (int i = threadIdx.x; i < V * NC; i += blockDim.x)
-        partial[(int64_t)blockIdx.x * V * NC + i] = cacc[i];
+        wj.partial[(int64_t)blk * V * NC + i] = cacc[i];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         if (!ok[q]) continue;
@@ -302,22 +355,55 @@ size_t warp_project_workspace(const LevelsK &lv, int V, const GridK &g, const pm
     return align256(sizeof(float) * (size_t)grid_size(g) * (size_t)V);
 }
 
-hipError_t launch_warp_project(const float *ref, const GridK &g, const LevelsK &lv,
-                               const float *coeff, int V, const ConeK &c, const float *angles,
-                               float *proj, void *ws, hipStream_t s) {
-    const int64_t N = grid_size(g);
-    float *warped = (float *)ws;
-    hipError_t e = dispatch_lb(lv.L, lv.B, [&](auto Lc, auto Bc) {
-        constexpr int L = decltype(Lc)::value, B = decltype(Bc)::value;
+// Forward of the motion path for a ragged batch: one combine+warp launch and
+// one projection launch over every scan's voxels / tiles.
+hipError_t launch_warp_project_jobs(const WPJob *jobs, int n, hipStream_t s) {
+    if (n < 1 || n > MAXS) return hipErrorInvalidValue;
+    const int L = jobs[0].lv.L, Bb = jobs[0].lv.B;
+    CWTab t{};
+    t.n = n;
+    ProjJob pj[MAXS];
+    for (int k = 0; k < n; ++k) {
+        const WPJob &j = jobs[k];
+        if (j.lv.L != L || j.lv.B != Bb) return hipErrorInvalidValue;
+        const int64_t N = grid_size(j.g);
+        CWK &c = t.s[k];
+        c.ref = j.ref;
+        c.g = j.g;
+        c.lv = j.lv;
+        c.coeff = j.coeff;
+        c.V = j.V;
+        c.warped = (float *)j.ws;
+        t.first[k + 1] = t.first[k] + (int)((N + 255) / 256);
+        pj[k] = ProjJob{c.warped, N, j.g, j.c, j.angles, j.V, j.proj};
+    }
+    for (int k = n + 1; k <= MAXS; ++k) t.first[k] = t.first[n];
+    hipError_t e = dispatch_lb(L, Bb, [&](auto Lc, auto Bc) {
+        constexpr int LL = decltype(Lc)::value, BB = decltype(Bc)::value;
         {
             ProfScope prof_("combine_warp", s);
-            k_combine_warp<L, B><<<(unsigned)((N + 255) / 256), 256, 0, s>>>(ref, g, lv, coeff, V,
-                                                                              warped);
+            k_combine_warp<LL, BB><<<(unsigned)t.first[n], 256, 0, s>>>(t);
         }
         return hipGetLastError();
     });
     if (e != hipSuccess) return e;
-    return launch_project(warped, N, g, c, angles, V, proj, s);
+    return launch_project_jobs(pj, n, s);
+}
+
+hipError_t launch_warp_project(const float *ref, const GridK &g, const LevelsK &lv,
+                               const float *coeff, int V, const ConeK &c, const float *angles,
+                               float *proj, void *ws, hipStream_t s) {
+    WPJob j;
+    j.ref = ref;
+    j.g = g;
+    j.lv = lv;
+    j.coeff = coeff;
+    j.V = V;
+    j.c = c;
+    j.angles = angles;
+    j.proj = proj;
+    j.ws = ws;
+    return launch_warp_project_jobs(&j, 1, s);
 }
 
 struct BwdLayout {
@@ -360,81 +446,170 @@ size_t warp_project_bwd_workspace(const LevelsK &lv, const GridK *lvl_grids, int
     return bwd_layout(lv, lvl_grids, V, g, c.nu, c.nv).total;
 }
 
+namespace {
+// One scan's pieces of the adjoint workspace.
+struct BwdScan {
+    BwdLayout lay;
+    float *gI, *gbuf, *partial, *stage;
+    void *rays, *adjws;
+    unsigned *vmax;
+    GOut gout;
+    const float *staged[MAXL];
+};
+
+BwdScan bwd_scan(const WPBJob &j) {
+    BwdScan b;
+    b.lay = bwd_layout(j.lv, j.lvl_grids, j.V, j.g, j.c.nu, j.c.nv);
+    char *w = (char *)j.ws;
+    b.gI = (float *)w;
+    w += b.lay.gI;
+    b.rays = w;
+    w += b.lay.rays;
+    b.gbuf = (float *)w;
+    w += b.lay.gbuf;
+    b.partial = (float *)w;
+    w += b.lay.partial;
+    b.stage = (float *)w;
+    w += b.lay.stage;
+    b.vmax = (unsigned *)w;
+    w += b.lay.vmax;
+    b.adjws = w;
+    const int64_t N = grid_size(j.g);
+    int nst = 0;
+    for (int l = 0; l < MAXL; ++l) {
+        b.gout.dst[l] = nullptr;
+        b.staged[l] = nullptr;
+    }
+    for (int l = 0; l < j.lv.L; ++l) {
+        const AxisMap &m = j.lv.map[l];
+        if (m.ident[0] && m.ident[1] && m.ident[2]) {
+            b.gout.dst[l] = j.g_bases[l];
+        } else {
+            b.gout.dst[l] = b.gbuf + (int64_t)(nst++) * N * 3 * j.lv.B;
+            b.staged[l] = b.gout.dst[l];
+        }
+    }
+    return b;
+}
+}  // namespace
+
+// Adjoint of the motion path for a ragged batch: one back-projection launch
+// and, per chunk of up to VCH views, one warp/combine adjoint launch over
+// every scan's bricks; the small per-scan reductions follow.
+hipError_t launch_warp_project_bwd_jobs(const WPBJob *jobs, int n, hipStream_t s) {
+    if (n < 1 || n > MAXS) return hipErrorInvalidValue;
+    const int L = jobs[0].lv.L, Bb = jobs[0].lv.B;
+    const int NC = L * Bb * 3;
+    BwdScan sc[MAXS];
+    BwdJob bj[MAXS];
+    int vmax_views = 0;
+    hipError_t e;
+    for (int k = 0; k < n; ++k) {
+        const WPBJob &j = jobs[k];
+        if (j.lv.L != L || j.lv.B != Bb) return hipErrorInvalidValue;
+        sc[k] = bwd_scan(j);
+        if ((e = launch_fill_i32((int32_t *)sc[k].vmax, j.V, 0, s)) != hipSuccess) return e;
+        bj[k] = BwdJob{j.g_proj, j.g, j.c, j.angles, j.V, sc[k].gI, grid_size(j.g), sc[k].rays,
+                       sc[k].vmax};
+        if (j.V > vmax_views) vmax_views = j.V;
+    }
+    if ((e = launch_project_bwd_jobs(bj, n, s)) != hipSuccess) return e;
+    for (int k = 0; k < n; ++k)
+        if ((e = launch_fill(jobs[k].g_ref, grid_size(jobs[k].g), 0.0f, s)) != hipSuccess) return e;
+    for (int v0 = 0; v0 < vmax_views; v0 += VCH) {
+        WCTab t{};
+        int idx[MAXS];
+        int vcs[MAXS];
+        int vc_max = 0;
+        for (int k = 0; k < n; ++k) {
+            const WPBJob &j = jobs[k];
+            if (j.V <= v0) continue;
+            const int vc = j.V - v0 < VCH ? j.V - v0 : VCH;
+            const int64_t N = grid_size(j.g);
+            WCK &w = t.s[t.n];
+            w.ref = j.ref;
+            w.g = j.g;
+            w.lv = j.lv;
+            w.coeff = j.coeff + (int64_t)v0 * NC;
+            w.V = vc;
+            w.g_I = sc[k].gI + (int64_t)v0 * N;
+            w.vmax = sc[k].vmax + v0;
+            w.g_ref = j.g_ref;
+            w.stage = sc[k].stage;
+            w.gout = sc[k].gout;
+            w.accumulate = v0 > 0;
+            w.nb1 = sc[k].lay.nb[1];
+            w.nb2 = sc[k].lay.nb[2];
+            w.partial = sc[k].partial;
+            t.first[t.n + 1] = t.first[t.n] + sc[k].lay.nbrick;
+            idx[t.n] = k;
+            vcs[t.n] = vc;
+            if (vc > vc_max) vc_max = vc;
+            ++t.n;
+        }
+        for (int k = t.n + 1; k <= MAXS; ++k) t.first[k] = t.first[t.n];
+        const size_t lds = sizeof(float) * (3 * (size_t)HB3 + (size_t)vc_max * NC);
+        e = dispatch_lb(L, Bb, [&](auto Lc, auto Bc) {
+            constexpr int LL = decltype(Lc)::value, BB = decltype(Bc)::value;
+            {
+                ProfScope prof_("warp_combine_bwd", s);
+                k_warp_combine_bwd<LL, BB><<<(unsigned)t.first[t.n], 256, lds, s>>>(t);
+            }
+            return hipGetLastError();
+        });
+        if (e != hipSuccess) return e;
+        for (int q = 0; q < t.n; ++q) {
+            const WPBJob &j = jobs[idx[q]];
+            const BwdScan &b = sc[idx[q]];
+            const int64_t N = grid_size(j.g);
+            {
+                ProfScope prof_("gather_boxes", s);
+                k_gather_boxes<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(
+                    b.stage, j.g, b.lay.nb[0], b.lay.nb[1], b.lay.nb[2], j.g_ref);
+            }
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            {
+                ProfScope prof_("coeff_reduce", s);
+                k_reduce_coeff_blocks<<<(unsigned)(vcs[q] * NC), 256, 0, s>>>(
+                    b.partial, b.lay.nbrick, vcs[q], NC, j.g_coeff + (int64_t)v0 * NC);
+            }
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+    }
+    for (int k = 0; k < n; ++k) {
+        const WPBJob &j = jobs[k];
+        for (int l = 0; l < L; ++l) {
+            if (!sc[k].staged[l]) continue;
+            e = launch_upsample_adjoint(j.lv, l, j.lvl_grids[l], j.coeff, 1, j.g, nullptr,
+                                        sc[k].staged[l], j.g_bases[l], sc[k].adjws, s);
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
 hipError_t launch_warp_project_bwd(const float *ref, const GridK &g, const LevelsK &lv,
                                    const GridK *lvl_grids, const float *coeff, int V,
                                    const ConeK &c, const float *angles, const float *g_proj,
                                    float *g_ref, float *const *g_bases, float *g_coeff, void *ws,
                                    hipStream_t s) {
-    const BwdLayout lay = bwd_layout(lv, lvl_grids, V, g, c.nu, c.nv);
-    char *w = (char *)ws;
-    float *gI = (float *)w;
-    w += lay.gI;
-    void *rays = w;
-    w += lay.rays;
-    float *gbuf = (float *)w;
-    w += lay.gbuf;
-    float *partial = (float *)w;
-    w += lay.partial;
-    float *stage = (float *)w;
-    w += lay.stage;
-    unsigned *vmax = (unsigned *)w;
-    w += lay.vmax;
-    void *adjws = w;
-    const int64_t N = grid_size(g);
-    const int NC = lv.L * lv.B * 3;
-
-    hipError_t e = launch_fill_i32((int32_t *)vmax, V, 0, s);
-    if (e != hipSuccess) return e;
-    e = launch_project_bwd(g_proj, g, c, angles, V, gI, N, rays, s, vmax);
-    if (e != hipSuccess) return e;
-    if ((e = launch_fill(g_ref, N, 0.0f, s)) != hipSuccess) return e;
-    GOut gout;
-    const float *staged[MAXL] = {nullptr, nullptr, nullptr, nullptr};
-    int nst = 0;
-    for (int l = 0; l < MAXL; ++l) gout.dst[l] = nullptr;
-    for (int l = 0; l < lv.L; ++l) {
-        const AxisMap &m = lv.map[l];
-        if (m.ident[0] && m.ident[1] && m.ident[2]) {
-            gout.dst[l] = g_bases[l];
-        } else {
-            gout.dst[l] = gbuf + (int64_t)(nst++) * N * 3 * lv.B;
-            staged[l] = gout.dst[l];
-        }
+    WPBJob j;
+    j.ref = ref;
+    j.g = g;
+    j.lv = lv;
+    for (int l = 0; l < MAXL; ++l) {
+        j.lvl_grids[l] = l < lv.L ? lvl_grids[l] : GridK{};
+        j.g_bases[l] = l < lv.L ? g_bases[l] : nullptr;
     }
-    for (int v0 = 0; v0 < V; v0 += VCH) {
-        const int vc = V - v0 < VCH ? V - v0 : VCH;
-        const size_t lds = sizeof(float) * (3 * (size_t)HB3 + (size_t)vc * NC);
-        e = dispatch_lb(lv.L, lv.B, [&](auto Lc, auto Bc) {
-            constexpr int L = decltype(Lc)::value, B = decltype(Bc)::value;
-            {
-                ProfScope prof_("warp_combine_bwd", s);
-                k_warp_combine_bwd<L, B><<<(unsigned)lay.nbrick, 256, lds, s>>>(
-                    ref, g, lv, coeff + (int64_t)v0 * NC, vc, gI + (int64_t)v0 * N, vmax + v0,
-                    g_ref, stage, gout, v0 > 0, lay.nb[1], lay.nb[2], partial);
-            }
-            return hipGetLastError();
-        });
-        if (e != hipSuccess) return e;
-        {
-            ProfScope prof_("gather_boxes", s);
-            k_gather_boxes<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(stage, g, lay.nb[0],
-                                                                      lay.nb[1], lay.nb[2], g_ref);
-        }
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        {
-            ProfScope prof_("coeff_reduce", s);
-            k_reduce_coeff_blocks<<<(unsigned)(vc * NC), 256, 0, s>>>(
-                partial, lay.nbrick, vc, NC, g_coeff + (int64_t)v0 * NC);
-        }
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    for (int l = 0; l < lv.L; ++l) {
-        if (!staged[l]) continue;
-        e = launch_upsample_adjoint(lv, l, lvl_grids[l], coeff, 1, g, nullptr, staged[l],
-                                    g_bases[l], adjws, s);
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    j.coeff = coeff;
+    j.V = V;
+    j.c = c;
+    j.angles = angles;
+    j.g_proj = g_proj;
+    j.g_ref = g_ref;
+    j.g_coeff = g_coeff;
+    j.ws = ws;
+    return launch_warp_project_bwd_jobs(&j, 1, s);
 }
 
 }  // namespace pmf

@@ -116,6 +116,22 @@ __device__ __forceinline__ float wave_sum_lane63(float v) {
 }
 #endif
 
+// ------------------------------------------------------ ragged launches
+// A ragged batch launches one kernel per stage for up to MAXS scans; a table
+// in the kernel arguments gives each scan's parameters and its first
+// workgroup.
+constexpr int MAXS = 4;
+#ifdef __HIPCC__
+// index of the table entry that owns workgroup b (first[] is non-decreasing)
+template <class Tab>
+__device__ __forceinline__ int job_of(const Tab &t, int b) {
+    int k = 0;
+#pragma unroll
+    for (int j = 1; j < MAXS; ++j) k += (j < t.n && b >= t.first[j]) ? 1 : 0;
+    return k;
+}
+#endif
+
 // ------------------------------------------------- basis upsampling helpers
 constexpr int MAXL = 4, MAXB = 4;
 struct LevelsK {
@@ -260,8 +276,30 @@ hipError_t launch_warp_bwd(const float *ref, const GridK &g, const float *dvf, i
                            const float *g_out, float *g_ref, float *g_dvf, hipStream_t s);
 
 // projection
+struct ProjJob {            // one scan's forward projection
+    const float *vol;
+    int64_t stride;         // elements between views' volumes (0: one volume)
+    GridK g;
+    ConeK c;
+    const float *angles;
+    int V;
+    float *proj;
+};
+hipError_t launch_project_jobs(const ProjJob *jobs, int n, hipStream_t s);
 hipError_t launch_project(const float *vol, int64_t stride, const GridK &g, const ConeK &c,
                           const float *angles, int V, float *proj, hipStream_t s);
+struct BwdJob {             // one scan's back-projection (all jobs per view, or all summed)
+    const float *g_proj;
+    GridK g;
+    ConeK c;
+    const float *angles;
+    int V;
+    float *g_vol;
+    int64_t stride;         // 0: sum over views into one volume
+    void *ws;               // project_bwd_workspace(c, V) bytes
+    unsigned *vmax;         // optional [V], zeroed: largest |g_vol| per view (float bits)
+};
+hipError_t launch_project_bwd_jobs(const BwdJob *jobs, int n, hipStream_t s);
 size_t project_bwd_workspace(const pmf_cone_t &c, int V);
 // vmax (optional, [V] zeroed uint): largest |g_vol| of each view, as float bits
 hipError_t launch_project_bwd(const float *g_proj, const GridK &g, const ConeK &c,
@@ -274,6 +312,35 @@ hipError_t launch_l2(const float *proj, const float *target, int64_t npix, int V
                      float *g, void *ws, hipStream_t s);
 
 // fused motion path
+struct WPJob {              // one scan's forward: ws = warp_project_workspace bytes
+    const float *ref;
+    GridK g;
+    LevelsK lv;
+    const float *coeff;
+    int V;
+    ConeK c;
+    const float *angles;
+    float *proj;
+    void *ws;
+};
+struct WPBJob {             // one scan's adjoint: ws = warp_project_bwd_workspace bytes
+    const float *ref;
+    GridK g;
+    LevelsK lv;
+    GridK lvl_grids[MAXL];
+    const float *coeff;
+    int V;
+    ConeK c;
+    const float *angles;
+    const float *g_proj;
+    float *g_ref;
+    float *g_bases[MAXL];
+    float *g_coeff;
+    void *ws;
+};
+// All jobs share L and B.
+hipError_t launch_warp_project_jobs(const WPJob *jobs, int n, hipStream_t s);
+hipError_t launch_warp_project_bwd_jobs(const WPBJob *jobs, int n, hipStream_t s);
 size_t warp_project_workspace(const LevelsK &lv, int V, const GridK &g, const pmf_cone_t &c);
 hipError_t launch_warp_project(const float *ref, const GridK &g, const LevelsK &lv,
                                const float *coeff, int V, const ConeK &c, const float *angles,

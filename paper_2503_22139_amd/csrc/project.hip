@@ -139,22 +139,44 @@ __host__ __device__ inline MarchK make_march(const GridK &g) {
 // many distinct cache lines each of its gathers touches: v runs along z, the
 // fastest (contiguous) axis of the volume, so narrow-and-tall wave tiles touch
 // fewer lines per load.
+//
+// One launch serves up to MAXS scans (a ragged batch): workgroups
+// [first[k], first[k+1]) belong to scan k, view-major, tiles row-major.
+struct ProjK {
+    const float *vol;
+    int64_t stride;
+    GridK g;
+    ConeK c;
+    MarchK mk;
+    const float *angles;
+    float *proj;
+    int tiles_u, ntiles;
+};
+struct ProjTab {
+    ProjK s[MAXS];
+    int first[MAXS + 1];
+    int n;
+};
+
 template <int WU, int WV, int AU>
-__global__ __launch_bounds__(256) void k_project(const float *__restrict__ vol, int64_t stride,
-                                                 GridK g, ConeK c, MarchK mk,
-                                                 const float *__restrict__ angles,
-                                                 float *__restrict__ proj, int tiles_u) {
+__global__ __launch_bounds__(256) void k_project(ProjTab t) {
     static_assert(WU * WV == 64 && AU >= 1 && 4 % AU == 0, "wave tile must hold 64 pixels");
     constexpr int BU = WU * AU, BV = WV * (4 / AU);
-    const int v = blockIdx.y;
-    const int tu = blockIdx.x % tiles_u, tv = blockIdx.x / tiles_u;
+    const int job = job_of(t, (int)blockIdx.x);
+    const ProjK &pj = t.s[job];
+    const GridK &g = pj.g;
+    const ConeK &c = pj.c;
+    const MarchK &mk = pj.mk;
+    const int local = (int)blockIdx.x - t.first[job];
+    const int v = local / pj.ntiles, tile = local - v * pj.ntiles;
+    const int tu = tile % pj.tiles_u, tv = tile / pj.tiles_u;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int iu = tu * BU + (w % AU) * WU + l % WU;
     const int iv = tv * BV + (w / AU) * WV + l / WU;
     if (iu >= c.nu || iv >= c.nv) return;
-    const double th = (double)angles[v];
+    const double th = (double)pj.angles[v];
     const RayK r = ray_setup(g, c, cos(th), sin(th), iu, iv);
-    const char *__restrict__ vb = (const char *)(vol + (int64_t)v * stride);
+    const char *__restrict__ vb = (const char *)(pj.vol + (int64_t)v * pj.stride);
     float acc0 = 0.0f, acc1 = 0.0f;
     int s = 0;
     for (; s + 1 < r.n; s += 2) {
@@ -169,7 +191,7 @@ __global__ __launch_bounds__(256) void k_project(const float *__restrict__ vol, 
         acc0 += march_sample(vb, mk, fmaf(sa, r.su[0], r.bu[0]), fmaf(sa, r.su[1], r.bu[1]),
                              fmaf(sa, r.su[2], r.bu[2]));
     }
-    proj[((int64_t)v * c.nv + iv) * c.nu + iu] = (acc0 + acc1) * r.delta;
+    pj.proj[((int64_t)v * c.nv + iv) * c.nu + iu] = (acc0 + acc1) * r.delta;
 }
 
 // Per-ray constants of every view, and per view the two figures that set the
@@ -309,14 +331,32 @@ struct BoundK {
 // With vmax non-null the largest |g_vol| of each view is also recorded.
 constexpr int BWD_WAVES = 8;    // wavefronts per back-projection workgroup
 
+// One scan's share of a ragged back-projection launch: workgroups
+// [first[k], first[k+1]) belong to scan k, view-major (one view per
+// workgroup) or one per brick when summing over views.
+struct BwdK {
+    const float *g_proj;
+    GridK g;
+    ConeK c;
+    const float *angles;
+    const RayK *rays;
+    const unsigned *stats;
+    int V;
+    float *g_vol;
+    int64_t stride;
+    int nb1, nb2, nbricks;
+    BoundK kb;
+    MarchK mk;
+    unsigned *vmax;
+};
+struct BwdTab {
+    BwdK s[MAXS];
+    int first[MAXS + 1];
+    int n;
+};
+
 template <int S, bool SUM>
-__global__ __launch_bounds__(64 * BWD_WAVES) void k_project_bwd(const float *__restrict__ g_proj, GridK g,
-                                                     ConeK c, const float *__restrict__ angles,
-                                                     const RayK *__restrict__ rays,
-                                                     const unsigned *__restrict__ stats, int V,
-                                                     float *__restrict__ g_vol, int64_t stride,
-                                                     int nb1, int nb2, BoundK kb, MarchK mk,
-                                                     unsigned *__restrict__ vmax) {
+__global__ __launch_bounds__(64 * BWD_WAVES) void k_project_bwd(BwdTab t) {
     constexpr int P = S + 2;                    // padded edge
     constexpr int NP = P * P * P;
     constexpr int NT = 64 * BWD_WAVES;
@@ -324,7 +364,19 @@ __global__ __launch_bounds__(64 * BWD_WAVES) void k_project_bwd(const float *__r
     __shared__ int acc[NP];
     __shared__ RunP runs[BWD_WAVES][64];
     __shared__ int ends[BWD_WAVES][64];
-    const int bid = blockIdx.x;
+    const int job = job_of(t, (int)blockIdx.x);
+    const BwdK &bj = t.s[job];
+    const GridK &g = bj.g;
+    const ConeK &c = bj.c;
+    const BoundK &kb = bj.kb;
+    const MarchK &mk = bj.mk;
+    const float *__restrict__ g_proj = bj.g_proj;
+    const RayK *__restrict__ rays = bj.rays;
+    const int V = bj.V;
+    const int nb1 = bj.nb1, nb2 = bj.nb2;
+    const int local = (int)blockIdx.x - t.first[job];
+    const int view = SUM ? 0 : local / bj.nbricks;
+    const int bid = SUM ? local : local - view * bj.nbricks;
     const int b2 = bid % nb2, b1 = (bid / nb2) % nb1, b0 = bid / (nb2 * nb1);
     const int B[3] = {b0 * S, b1 * S, b2 * S};
 
@@ -352,14 +404,14 @@ __global__ __launch_bounds__(64 * BWD_WAVES) void k_project_bwd(const float *__r
     for (int k = 0; k < (SUM ? PER : 1); ++k) sum[k] = 0.0f;
     float last_inv = 0.0f;      // per-view mode: 1/scale of the one view
 
-    const int vb = SUM ? 0 : blockIdx.y;
-    const int ve = SUM ? V : blockIdx.y + 1;
+    const int vb = SUM ? 0 : view;
+    const int ve = SUM ? V : view + 1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lx = lane & 7, ly = lane >> 3;
     RunP *const wr = runs[wave];
     int *const we = ends[wave];
     for (int v = vb; v < ve; ++v) {
-        const double th = (double)angles[v];
+        const double th = (double)bj.angles[v];
         const double ct = cos(th), st = sin(th);
         int u0, u1, v0, v1;
         shadow_rect(c, ct, st, wlo, whi, u0, u1, v0, v1);   // uniform across the block
@@ -369,8 +421,8 @@ __global__ __launch_bounds__(64 * BWD_WAVES) void k_project_bwd(const float *__r
         // that far apart keep the lanes' LDS atomics on unrelated words.
         const int gu = (u1 - u0 + 8) / 8, gv = (v1 - v0 + 8) / 8;
         const int nph = gu * gv;
-        const float m = __uint_as_float(stats[2 * v]);
-        const float dmin = __uint_as_float(stats[2 * v + 1]);
+        const float m = __uint_as_float(bj.stats[2 * v]);
+        const float dmin = __uint_as_float(bj.stats[2 * v + 1]);
         if (!(m > 0.0f)) continue;
         for (int i = threadIdx.x; i < NP; i += NT) acc[i] = 0;
         __syncthreads();
@@ -538,7 +590,7 @@ __global__ __launch_bounds__(64 * BWD_WAVES) void k_project_bwd(const float *__r
             last_inv = inv_scale;
         }
     }
-    float *out = g_vol + (SUM ? 0 : (int64_t)blockIdx.y * stride);
+    float *out = bj.g_vol + (SUM ? 0 : (int64_t)view * bj.stride);
     float mx = 0.0f;
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
@@ -555,9 +607,9 @@ __global__ __launch_bounds__(64 * BWD_WAVES) void k_project_bwd(const float *__r
             mx = fmaxf(mx, fabsf(val));
         }
     }
-    if (vmax && !SUM) {
+    if (bj.vmax && !SUM) {
         for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
-        if (lane == 0 && mx > 0.0f) atomicMax(&vmax[blockIdx.y], __float_as_uint(mx));
+        if (lane == 0 && mx > 0.0f) atomicMax(&bj.vmax[view], __float_as_uint(mx));
     }
 }
 
@@ -586,29 +638,50 @@ static BoundK make_bound(const GridK &g, const ConeK &c) {
 }
 
 template <int WU, int WV, int AU>
-static void project_tiled(const float *vol, int64_t stride, const GridK &g, const ConeK &c,
-                          const float *angles, int V, float *proj, hipStream_t s) {
+static void project_tiled(const ProjJob *jobs, int n, hipStream_t s) {
     constexpr int BU = WU * AU, BV = WV * (4 / AU);
-    const int tu = (c.nu + BU - 1) / BU, tv = (c.nv + BV - 1) / BV;
-    dim3 grid((unsigned)(tu * tv), (unsigned)V);
-    k_project<WU, WV, AU><<<grid, 256, 0, s>>>(vol, stride, g, c, make_march(g), angles, proj, tu);
+    ProjTab t{};
+    t.n = n;
+    t.first[0] = 0;
+    for (int k = 0; k < n; ++k) {
+        const ProjJob &j = jobs[k];
+        ProjK &p = t.s[k];
+        p.vol = j.vol;
+        p.stride = j.stride;
+        p.g = j.g;
+        p.c = j.c;
+        p.mk = make_march(j.g);
+        p.angles = j.angles;
+        p.proj = j.proj;
+        p.tiles_u = (j.c.nu + BU - 1) / BU;
+        p.ntiles = p.tiles_u * ((j.c.nv + BV - 1) / BV);
+        t.first[k + 1] = t.first[k] + p.ntiles * j.V;
+    }
+    for (int k = n + 1; k <= MAXS; ++k) t.first[k] = t.first[n];
+    if (t.first[n] > 0) k_project<WU, WV, AU><<<(unsigned)t.first[n], 256, 0, s>>>(t);
+}
+
+hipError_t launch_project_jobs(const ProjJob *jobs, int n, hipStream_t s) {
+    if (n < 1 || n > MAXS) return hipErrorInvalidValue;
+    ProfScope prof_("project", s);
+    switch (tune_get(KNOB_PROJECT_TILE)) {
+        case 0: project_tiled<16, 4, 1>(jobs, n, s); break;
+        case 1: project_tiled<8, 8, 2>(jobs, n, s); break;
+        case 2: project_tiled<4, 16, 4>(jobs, n, s); break;
+        case 3: project_tiled<2, 32, 4>(jobs, n, s); break;
+        case 4: project_tiled<32, 2, 1>(jobs, n, s); break;
+        case 5: project_tiled<1, 64, 4>(jobs, n, s); break;
+        case 6: project_tiled<2, 32, 2>(jobs, n, s); break;
+        case 7: project_tiled<1, 64, 2>(jobs, n, s); break;
+        default: project_tiled<2, 32, 1>(jobs, n, s); break;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_project(const float *vol, int64_t stride, const GridK &g, const ConeK &c,
                           const float *angles, int V, float *proj, hipStream_t s) {
-    ProfScope prof_("project", s);
-    switch (tune_get(KNOB_PROJECT_TILE)) {
-        case 0: project_tiled<16, 4, 1>(vol, stride, g, c, angles, V, proj, s); break;
-        case 1: project_tiled<8, 8, 2>(vol, stride, g, c, angles, V, proj, s); break;
-        case 2: project_tiled<4, 16, 4>(vol, stride, g, c, angles, V, proj, s); break;
-        case 3: project_tiled<2, 32, 4>(vol, stride, g, c, angles, V, proj, s); break;
-        case 4: project_tiled<32, 2, 1>(vol, stride, g, c, angles, V, proj, s); break;
-        case 5: project_tiled<1, 64, 4>(vol, stride, g, c, angles, V, proj, s); break;
-        case 6: project_tiled<2, 32, 2>(vol, stride, g, c, angles, V, proj, s); break;
-        case 7: project_tiled<1, 64, 2>(vol, stride, g, c, angles, V, proj, s); break;
-        default: project_tiled<2, 32, 1>(vol, stride, g, c, angles, V, proj, s); break;
-    }
-    return hipGetLastError();
+    const ProjJob j{vol, stride, g, c, angles, V, proj};
+    return launch_project_jobs(&j, 1, s);
 }
 
 // Workspace: the per-ray table, then two words of statistics per view.
@@ -617,40 +690,66 @@ size_t project_bwd_workspace(const pmf_cone_t &c, int V) {
            align256(sizeof(unsigned) * 2 * (size_t)V);
 }
 
-hipError_t launch_project_bwd(const float *g_proj, const GridK &g, const ConeK &c,
-                              const float *angles, int V, float *g_vol, int64_t stride, void *ws,
-                              hipStream_t s, unsigned *vmax) {
-    RayK *rays = (RayK *)ws;
-    unsigned *stats =
-        (unsigned *)((char *)ws + align256(sizeof(RayK) * (size_t)c.nu * (size_t)c.nv * (size_t)V));
-    // stats[2v] = 0 (max), stats[2v+1] = +inf (min): one fill of the pair pattern
-    hipError_t e = launch_fill_pair_u32(stats, V, 0u, 0x7f800000u, s);
-    if (e != hipSuccess) return e;
-    {
-        ProfScope prof_("ray_table", s);
-        const int per_view = (c.nu * c.nv + 255) / 256;
-        dim3 grid((unsigned)(per_view < 64 ? per_view : 64), (unsigned)V);
-        k_ray_table<<<grid, 256, 0, s>>>(g, c, angles, g_proj, rays, stats);
-    }
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
+hipError_t launch_project_bwd_jobs(const BwdJob *jobs, int n, hipStream_t s) {
+    if (n < 1 || n > MAXS) return hipErrorInvalidValue;
     constexpr int S = 16;
-    int nb[3];
-    for (int a = 0; a < 3; ++a) nb[a] = (g.n[a] + S - 1) / S;
-    const int sum_views = stride == 0;
-    dim3 grid((unsigned)(nb[0] * nb[1] * nb[2]), sum_views ? 1u : (unsigned)V);
+    const bool sum_views = jobs[0].stride == 0;
+    BwdTab t{};
+    t.n = n;
+    t.first[0] = 0;
+    for (int k = 0; k < n; ++k) {
+        const BwdJob &j = jobs[k];
+        if ((j.stride == 0) != sum_views) return hipErrorInvalidValue;
+        RayK *rays = (RayK *)j.ws;
+        unsigned *stats = (unsigned *)((char *)j.ws +
+                                       align256(sizeof(RayK) * (size_t)j.c.nu * (size_t)j.c.nv *
+                                                (size_t)j.V));
+        // stats[2v] = 0 (max), stats[2v+1] = +inf (min)
+        hipError_t e = launch_fill_pair_u32(stats, j.V, 0u, 0x7f800000u, s);
+        if (e != hipSuccess) return e;
+        {
+            ProfScope prof_("ray_table", s);
+            const int per_view = (j.c.nu * j.c.nv + 255) / 256;
+            dim3 grid((unsigned)(per_view < 64 ? per_view : 64), (unsigned)j.V);
+            k_ray_table<<<grid, 256, 0, s>>>(j.g, j.c, j.angles, j.g_proj, rays, stats);
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        BwdK &b = t.s[k];
+        b.g_proj = j.g_proj;
+        b.g = j.g;
+        b.c = j.c;
+        b.angles = j.angles;
+        b.rays = rays;
+        b.stats = stats;
+        b.V = j.V;
+        b.g_vol = j.g_vol;
+        b.stride = j.stride;
+        int nb[3];
+        for (int a = 0; a < 3; ++a) nb[a] = (j.g.n[a] + S - 1) / S;
+        b.nb1 = nb[1];
+        b.nb2 = nb[2];
+        b.nbricks = nb[0] * nb[1] * nb[2];
+        b.kb = make_bound(j.g, j.c);
+        b.mk = make_march(j.g);
+        b.vmax = j.vmax;
+        t.first[k + 1] = t.first[k] + b.nbricks * (sum_views ? 1 : j.V);
+    }
+    for (int k = n + 1; k <= MAXS; ++k) t.first[k] = t.first[n];
     {
         ProfScope prof_("project_bwd", s);
         if (sum_views)
-            k_project_bwd<S, true><<<grid, 64 * BWD_WAVES, 0, s>>>(g_proj, g, c, angles, rays, stats, V, g_vol,
-                                                       stride, nb[1], nb[2], make_bound(g, c),
-                                                       make_march(g), vmax);
+            k_project_bwd<S, true><<<(unsigned)t.first[n], 64 * BWD_WAVES, 0, s>>>(t);
         else
-            k_project_bwd<S, false><<<grid, 64 * BWD_WAVES, 0, s>>>(g_proj, g, c, angles, rays, stats, V, g_vol,
-                                                        stride, nb[1], nb[2], make_bound(g, c),
-                                                        make_march(g), vmax);
+            k_project_bwd<S, false><<<(unsigned)t.first[n], 64 * BWD_WAVES, 0, s>>>(t);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_project_bwd(const float *g_proj, const GridK &g, const ConeK &c,
+                              const float *angles, int V, float *g_vol, int64_t stride, void *ws,
+                              hipStream_t s, unsigned *vmax) {
+    const BwdJob j{g_proj, g, c, angles, V, g_vol, stride, ws, vmax};
+    return launch_project_bwd_jobs(&j, 1, s);
 }
 
 }  // namespace pmf

@@ -131,19 +131,75 @@ class MotionModel:
         return loss, grads
 
 
-class GraphStep:
-    """The batched iteration captured once into a HIP graph and replayed.
+class MultiScanModel:
+    """Several independent scans (different grids, geometries and view counts,
+    one motion-model shape L, B) stepped together: per scan the voxelization
+    and its adjoint, and for all scans at once the ragged batched motion path
+    (each stage one kernel launch over every scan's voxels, tiles and bricks)."""
 
-    ``target`` is copied into a static buffer before each replay; the loss and
-    gradients live in static tensors owned by the graph (read them before the
-    next replay).  Capture happens after one eager warm-up step so that every
-    workspace is already allocated; the library's kernels clear memory with
-    fill kernels, never with memset nodes.
+    def __init__(self, workloads, device="cuda"):
+        self.models = [MotionModel(w, device) for w in workloads]
+        shapes = {tuple(m.coeff.shape[1:]) for m in self.models}
+        if len(shapes) != 1:
+            raise ValueError(f"scans must share the motion-model shape (L, B, 3): {shapes}")
+
+    def _scans(self, vols):
+        return [dict(ref=r, grid=m.grid, bases=b, levels=m.levels, coeff=m.coeff, cone=m.cone,
+                     angles=m.angles) for m, (r, b) in zip(self.models, vols)]
+
+    def forward_batched(self):
+        return ops.pmf_warp_project_scans(self._scans([m.volumes() for m in self.models]))
+
+    def step_batched(self, targets):
+        """One iteration of every scan; returns [(loss, grads)] per scan."""
+        scans = self._scans([m.volumes() for m in self.models])
+        projs = ops.pmf_warp_project_scans(scans)
+        losses = []
+        for sc, p, t in zip(scans, projs, targets):
+            loss, g_proj = ops.pmf_l2_loss(p, t)
+            sc["g_proj"] = g_proj
+            losses.append(loss)
+        outs = ops.pmf_warp_project_bwd_scans(scans)
+        res = []
+        for m, (g_ref, g_bases, g_coeff), loss in zip(self.models, outs, losses):
+            grads = m.volumes_bwd(g_ref, g_bases)
+            grads["coeff"] = g_coeff
+            res.append((loss, grads))
+        return res
+
+    def step_separate(self, targets):
+        """The same iteration scan by scan (one batched motion path per scan)."""
+        return [m.step_batched(t) for m, t in zip(self.models, targets)]
+
+
+def _clone(x):
+    return [t.clone() for t in x] if isinstance(x, (list, tuple)) else x.clone()
+
+
+def _copy(dst, src):
+    if isinstance(dst, (list, tuple)):
+        for d, s_ in zip(dst, src):
+            d.copy_(s_)
+    else:
+        dst.copy_(src)
+
+
+class GraphStep:
+    """A batched iteration captured once into a HIP graph and replayed.
+
+    ``model`` is a MotionModel (target: one tensor) or a MultiScanModel
+    (targets: one tensor per scan).  Before each replay the new targets, and
+    optionally new per-view coefficients and angles (the views drawn for this
+    iteration), are copied into the device buffers the graph reads; the loss
+    and gradients live in static tensors owned by the graph (read them before
+    the next replay).  Capture happens after one eager warm-up step so that
+    every workspace is already allocated; the library's kernels clear memory
+    with fill kernels, never with memset nodes.
     """
 
-    def __init__(self, model: MotionModel, target: torch.Tensor):
+    def __init__(self, model, target):
         self.model = model
-        self.target = target.clone()
+        self.target = _clone(target)
         was = ops.pmf_profile(False)
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
@@ -153,14 +209,26 @@ class GraphStep:
         torch.cuda.synchronize()
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
-            self.loss, self.grads = model.step_batched(self.target)
+            self.out = model.step_batched(self.target)
         torch.cuda.synchronize()
         # the graph holds raw pointers into the scratch buffers: keep them alive
         self._scratch = dict(ops._ws_cache)
         ops.pmf_profile(was)
 
-    def step(self, target: Optional[torch.Tensor] = None):
+    def _models(self):
+        return self.model.models if isinstance(self.model, MultiScanModel) else [self.model]
+
+    def step(self, target=None, coeff=None, angles=None):
+        """Replay; coeff / angles (per scan for a MultiScanModel) replace the
+        views' temporal coefficients and angles in place (same shapes)."""
         if target is not None:
-            self.target.copy_(target)
+            _copy(self.target, target)
+        ms = self._models()
+        if coeff is not None:
+            for m, c in zip(ms, coeff if len(ms) > 1 else [coeff]):
+                m.coeff.copy_(c)
+        if angles is not None:
+            for m, a in zip(ms, angles if len(ms) > 1 else [angles]):
+                m.angles.copy_(a)
         self.graph.replay()
-        return self.loss, self.grads
+        return self.out

@@ -53,6 +53,18 @@ class PmfGaussGrad(C.Structure):
                 ("value", C.c_void_p)]
 
 
+MAX_SCANS = 4
+MAX_LEVELS = 4
+
+
+class PmfScan(C.Structure):
+    _fields_ = [("ref", C.c_void_p), ("grid", PmfGrid), ("bases", C.c_void_p * MAX_LEVELS),
+                ("lvl", PmfGrid * MAX_LEVELS), ("coeff", C.c_void_p), ("V", C.c_int32),
+                ("cone", PmfCone), ("angles", C.c_void_p), ("proj", C.c_void_p),
+                ("g_proj", C.c_void_p), ("g_ref", C.c_void_p),
+                ("g_bases", C.c_void_p * MAX_LEVELS), ("g_coeff", C.c_void_p)]
+
+
 _P = C.c_void_p
 _SZ = C.c_size_t
 _SIGS = {
@@ -81,6 +93,11 @@ _SIGS = {
     "pmf_profile": ([C.c_int], C.c_int),
     "pmf_profile_read": ([C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
     "pmf_profile_names": ([C.c_char_p, _SZ], _SZ),
+    "pmf_warp_project_scans_workspace": ([C.c_int, C.c_int, C.POINTER(PmfScan), C.c_int], _SZ),
+    "pmf_warp_project_scans": ([C.c_int, C.c_int, C.POINTER(PmfScan), C.c_int, _P, _SZ, _P], C.c_int),
+    "pmf_warp_project_bwd_scans_workspace": ([C.c_int, C.c_int, C.POINTER(PmfScan), C.c_int], _SZ),
+    "pmf_warp_project_bwd_scans": ([C.c_int, C.c_int, C.POINTER(PmfScan), C.c_int, _P, _SZ, _P],
+                                   C.c_int),
     "pmf_tune_candidates": ([C.c_int], C.c_int),
     "pmf_tune_get": ([C.c_int], C.c_int),
     "pmf_tune_set": ([C.c_int, C.c_int], C.c_int),
@@ -374,6 +391,64 @@ def pmf_warp_project_bwd(ref, grid: Grid, bases, levels, coeff, cone: Cone, angl
                                       _ptr(g_coeff), C.c_void_p(ws.data_ptr()), ws.numel(),
                                       _stream()))
     return g_ref, g_bases, g_coeff
+
+
+def _scan_array(scans):
+    """Host array of PmfScan from dicts with keys ref, grid, bases, levels, coeff,
+    cone, angles and optionally proj, g_proj, g_ref, g_bases, g_coeff (tensors)."""
+    arr = (PmfScan * len(scans))()
+    for k, sc in enumerate(scans):
+        a = arr[k]
+        a.ref = _ptr(sc["ref"]).value
+        a.grid = make_grid(sc["grid"])
+        for l, (b, lg) in enumerate(zip(sc["bases"], sc["levels"])):
+            a.bases[l] = _ptr(b).value
+            a.lvl[l] = make_grid(lg)
+        a.coeff = _ptr(sc["coeff"]).value
+        a.V = int(sc["coeff"].shape[0])
+        a.cone = make_cone(sc["cone"])
+        a.angles = _ptr(sc["angles"]).value
+        for f in ("proj", "g_proj", "g_ref", "g_coeff"):
+            if sc.get(f) is not None:
+                setattr(a, f, _ptr(sc[f]).value)
+        for l, gb in enumerate(sc.get("g_bases") or []):
+            a.g_bases[l] = _ptr(gb).value
+    return arr
+
+
+def pmf_warp_project_scans(scans):
+    """Ragged batch of motion-path forwards: one launch per stage over every
+    scan.  Each scan dict holds ref, grid, bases, levels, coeff [V][L][B][3],
+    cone, angles; returns the list of projections [V][nv][nu]."""
+    L, B = int(scans[0]["coeff"].shape[1]), int(scans[0]["coeff"].shape[2])
+    dev = scans[0]["ref"].device
+    for sc in scans:
+        sc["proj"] = torch.empty((sc["coeff"].shape[0], sc["cone"].nv, sc["cone"].nu), device=dev,
+                                 dtype=torch.float32)
+    arr = _scan_array(scans)
+    nbytes = lib().pmf_warp_project_scans_workspace(L, B, arr, len(scans))
+    ws = workspace(nbytes, dev)
+    _check(lib().pmf_warp_project_scans(L, B, arr, len(scans), C.c_void_p(ws.data_ptr()),
+                                        ws.numel(), _stream()))
+    return [sc["proj"] for sc in scans]
+
+
+def pmf_warp_project_bwd_scans(scans):
+    """Adjoint of pmf_warp_project_scans given each scan's g_proj: returns a
+    list of (g_ref, g_bases, g_coeff)."""
+    L, B = int(scans[0]["coeff"].shape[1]), int(scans[0]["coeff"].shape[2])
+    dev = scans[0]["ref"].device
+    for sc in scans:
+        sc["g_proj"] = sc["g_proj"].contiguous()
+        sc["g_ref"] = torch.empty_like(sc["ref"])
+        sc["g_bases"] = [torch.empty_like(b) for b in sc["bases"]]
+        sc["g_coeff"] = torch.empty_like(sc["coeff"])
+    arr = _scan_array(scans)
+    nbytes = lib().pmf_warp_project_bwd_scans_workspace(L, B, arr, len(scans))
+    ws = workspace(nbytes, dev)
+    _check(lib().pmf_warp_project_bwd_scans(L, B, arr, len(scans), C.c_void_p(ws.data_ptr()),
+                                            ws.numel(), _stream()))
+    return [(sc["g_ref"], sc["g_bases"], sc["g_coeff"]) for sc in scans]
 
 
 # ------------------------------------------------------------ autograd

@@ -140,3 +140,39 @@ def test_tune_knobs(lib):
     assert lib.pmf_tune_set(99, 0) == ops.PMF_EINVAL
     assert lib.pmf_tune_get(99) == ops.PMF_EINVAL
     assert lib.pmf_tune_set(knob, prev) == n - 1
+
+
+def test_scans_reject_bad_arguments(lib):
+    s = ops.PmfScan()
+    arr = (ops.PmfScan * 2)(s, s)
+    assert lib.pmf_warp_project_scans(3, 3, None, 1, None, 0, None) == ops.PMF_EINVAL
+    assert lib.pmf_warp_project_scans(3, 3, arr, 0, None, 0, None) == ops.PMF_EINVAL
+    assert lib.pmf_warp_project_scans(3, 3, arr, 5, None, 0, None) == ops.PMF_EINVAL
+    # scan 1 has a bad grid: the error names it
+    good = ops.PmfScan()
+    good.grid = grid()
+    for l in range(3):
+        good.lvl[l] = grid()
+        good.bases[l] = 16
+        good.g_bases[l] = 16
+    good.ref = good.coeff = good.angles = good.proj = good.g_proj = good.g_ref = good.g_coeff = 16
+    good.V = 2
+    good.cone = ops.make_cone(Cone(1000.0, 1500.0, 16, 16, 1.0, 1.0))
+    bad = ops.PmfScan.from_buffer_copy(good)
+    bad.grid = grid(n=(8, 1, 8))
+    arr = (ops.PmfScan * 2)(good, bad)
+    assert lib.pmf_warp_project_scans(3, 3, arr, 2, C.c_void_p(256), 1 << 40, None) == ops.PMF_EINVAL
+    assert "scan 1" in err(lib)
+    assert lib.pmf_warp_project_bwd_scans(3, 3, arr, 2, C.c_void_p(256), 1 << 40, None) == ops.PMF_EINVAL
+    assert "scan 1" in err(lib)
+    arr = (ops.PmfScan * 2)(good, good)
+    need = lib.pmf_warp_project_scans_workspace(3, 3, arr, 2)
+    assert need > 0
+    assert lib.pmf_warp_project_scans(3, 3, arr, 2, C.c_void_p(256), need - 1, None) == ops.PMF_EWORKSPACE
+    needb = lib.pmf_warp_project_bwd_scans_workspace(3, 3, arr, 2)
+    assert needb > need
+    nullg = ops.PmfScan.from_buffer_copy(good)
+    nullg.g_bases[2] = None
+    arr = (ops.PmfScan * 2)(good, nullg)
+    assert lib.pmf_warp_project_bwd_scans(3, 3, arr, 2, C.c_void_p(256), 1 << 40, None) == ops.PMF_EINVAL
+    assert "g_bases[2]" in err(lib)
