@@ -72,6 +72,89 @@ def kernel_model(name, w, V, samples):
     return None
 
 
+def _timed(fn, steps: int, warmup: int = 1) -> float:
+    """Mean wall milliseconds of fn() over `steps` calls after `warmup` calls,
+    with the device synchronised around the timed region."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps * 1e3
+
+
+def extras(steps: int):
+    """The other configurations (forward-only C1-C3, the 16-view
+    differentiable C4, the ragged three-scan C5 and B = 1 of the benchmark
+    workload), each timed on its own after the headline run."""
+    import torch
+    from paper_2503_22139_amd import ops, synth
+    from paper_2503_22139_amd.model import GraphStep, MotionModel, MultiScanModel
+    out = {}
+
+    def fwd_only(w):
+        ref = T(w)
+        ang = torch.from_numpy(np.ascontiguousarray(w.angles, np.float32)).cuda()
+
+        def run():
+            vol = ops.pmf_voxelize(ref[0], ref[1], ref[2], ref[3], w.grid, float(w.trunc_k))
+            return ops.pmf_project(vol, w.grid, w.cone, ang)
+        return run
+
+    def T(w):
+        f = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+        return f(w.ref.mean), f(w.ref.scale), f(w.ref.quat), f(w.ref.value)
+
+    for name, w in (("c1_forward", synth.c1()), ("c2_forward", synth.c2())):
+        ms = _timed(fwd_only(w), steps)
+        out[name] = {"ms": ms, "views": len(w.angles), "grid": list(w.grid.n), "gaussians": w.ref.m,
+                     "what": "voxelize + project"}
+        print(f"[bench] {name} {ms:.2f} ms", file=sys.stderr, flush=True)
+    w3 = synth.c3()
+    m3 = MotionModel(w3)
+    ms = _timed(m3.forward_batched, steps)
+    out["c3_forward"] = {"ms": ms, "views": len(w3.angles), "what": "voxelize + batched motion path"}
+    print(f"[bench] c3_forward {ms:.2f} ms", file=sys.stderr, flush=True)
+    tgt = torch.from_numpy(synth.add_target_noise(
+        MotionModel(synth.perturbed_truth(w3)).forward_batched().cpu().numpy())).cuda()
+    gs = GraphStep(m3, tgt)
+    ms = _timed(gs.step, steps)
+    out["c4_step"] = {"ms": ms, "iterations_per_s": 1e3 / ms, "views": len(w3.angles),
+                      "what": "fwd+bwd, batched, graph replay"}
+    print(f"[bench] c4_step {ms:.2f} ms", file=sys.stderr, flush=True)
+    del gs, m3, tgt
+    torch.cuda.empty_cache()
+    ws5 = synth.c5_scans()
+    mm = MultiScanModel(ws5)
+    tg5 = [torch.from_numpy(synth.random_volume(90 + k, (len(w.angles), w.cone.nv, w.cone.nu),
+                                                0.0, 20.0)).cuda() for k, w in enumerate(ws5)]
+    gs = GraphStep(mm, tg5)
+    ms = _timed(gs.step, steps)
+    ms_sep = _timed(lambda: mm.step_separate(tg5), steps)
+    out["c5_step"] = {"ms": ms, "iterations_per_s": 1e3 / ms, "separate_eager_ms": ms_sep,
+                      "scans": [{"grid": list(w.grid.n), "gaussians": w.ref.m, "views": len(w.angles)}
+                                for w in ws5],
+                      "what": "3 ragged scans x 32 views, fwd+bwd, one launch per stage, graph replay"}
+    print(f"[bench] c5_step {ms:.2f} ms (separate eager {ms_sep:.2f})", file=sys.stderr, flush=True)
+    del gs, mm, tg5
+    torch.cuda.empty_cache()
+    wb = synth.headline(nbases=1)
+    mb = MotionModel(wb)
+    tb = torch.from_numpy(synth.random_volume(95, (len(wb.angles), wb.cone.nv, wb.cone.nu),
+                                              0.0, 20.0)).cuda()
+    gs = GraphStep(mb, tb)
+    ms = _timed(gs.step, steps)
+    out["b1_step"] = {"ms": ms, "iterations_per_s": 1e3 / ms,
+                      "what": "benchmark workload with B = 1 (9 coefficients per view)"}
+    print(f"[bench] b1_step {ms:.2f} ms", file=sys.stderr, flush=True)
+    del gs, mb
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(w, target, views: int = 2):
     """FP64 oracle on a bounded sample: the volumes, `views` views' fwd+bwd and
     the voxelization adjoints; extrapolated linearly to all views."""
@@ -121,6 +204,8 @@ def main():
     ap.add_argument("--views", type=int, default=32)
     ap.add_argument("--bases", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the other configurations")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--no-graph", action="store_true",
                     help="time the eager batched steps instead of graph replays (for counter runs)")
     args = ap.parse_args()
@@ -148,6 +233,16 @@ def main():
     del truth
     target = torch.from_numpy(target_np).cuda()
     V = len(w.angles)
+
+    tuned = None
+    if not args.no_autotune:
+        # launch shapes for this geometry, timed on per-view volumes of its size
+        vol = torch.from_numpy(synth.random_volume(7, (V,) + tuple(w.grid.n))).cuda()
+        gp = torch.from_numpy(synth.random_normal(8, (V, w.cone.nv, w.cone.nu))).cuda()
+        tuned = ops.pmf_autotune_project(vol, w.grid, w.cone, m.angles, gp, reps=2)
+        del vol, gp
+        torch.cuda.empty_cache()
+        print(f"[bench] autotune {tuned}", file=sys.stderr, flush=True)
 
     print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
@@ -239,6 +334,9 @@ def main():
         "kernels": kern,
         "roofline": roof,
     }
+    out["tuned"] = tuned
+    if not args.no_extras:
+        out["extras"] = extras(max(2, min(args.steps, 5)))
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, target_np)

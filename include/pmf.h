@@ -220,7 +220,9 @@ size_t pmf_profile_names(char *buf, size_t len);
  *                              3 = 2x32 in 8x32, 4 = 32x2 in 32x8,
  *                              5 = 1x64 in 4x64 (default), 6 = 2x32 in 4x64,
  *                              7 = 1x64 in 2x128, 8 = 2x32 in 2x128;
- *   PMF_TUNE_BACKPROJECT_BRICK voxel brick of the adjoint projection.
+ *   PMF_TUNE_BACKPROJECT_BRICK voxel brick of the adjoint projection and the
+ *                              wavefronts sharing it: 0 = 16^3 x 8 (default),
+ *                              1 = 16^3 x 4, 2 = 12^3 x 8, 3 = 8^3 x 4.
  * pmf_tune_candidates returns the number of choices of a knob (0 for an
  * unknown knob); pmf_tune_set returns the previous choice or PMF_EINVAL for an
  * unknown knob or a choice out of range; pmf_tune_get returns the current
@@ -229,6 +231,21 @@ enum { PMF_TUNE_PROJECT_TILE = 0, PMF_TUNE_BACKPROJECT_BRICK = 1 };
 int pmf_tune_candidates(int knob);
 int pmf_tune_get(int knob);
 int pmf_tune_set(int knob, int choice);
+
+/* Autotuner of the projection launch shapes: times every candidate of
+ * PMF_TUNE_PROJECT_TILE with pmf_project and every candidate of
+ * PMF_TUNE_BACKPROJECT_BRICK with pmf_project_bwd (per-view volumes) on the
+ * caller's buffers, one warm-up and `reps` timed launches each (HIP events on
+ * `stream`), and keeps the fastest of each knob.  vol [V][N] and g_proj
+ * [V][nv][nu] are read; proj [V][nv][nu] and g_vol [V][N] are overwritten
+ * (scratch); ws is the pmf_project_bwd workspace.  ms (host, optional)
+ * receives the mean time per launch of each candidate, the projection tiles
+ * first, then the bricks.  Synchronises the stream; returns PMF_OK or an
+ * error (the previous choices are then restored). */
+int pmf_autotune_project(const float *vol, const pmf_grid_t *grid, const pmf_cone_t *cone,
+                         const float *angles, int V, float *proj, const float *g_proj,
+                         float *g_vol, void *ws, size_t ws_bytes, int reps, float *ms,
+                         void *stream);
 
 /* ----------------------------------------- batched motion path (fused)
  * All V views of the motion path in one pass over the bases:

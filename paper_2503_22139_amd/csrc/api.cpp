@@ -333,6 +333,66 @@ int pmf_tune_set(int knob, int choice) {
     return prev;
 }
 
+int pmf_autotune_project(const float *vol, const pmf_grid_t *grid, const pmf_cone_t *cone,
+                         const float *angles, int V, float *proj, const float *g_proj,
+                         float *g_vol, void *ws, size_t ws_bytes, int reps, float *ms,
+                         void *stream) {
+    PMF_CHECK(check_grid(grid, "grid"));
+    PMF_CHECK(check_cone(cone, grid));
+    if (V < 1) return fail(PMF_EINVAL, "autotune: V must be >= 1");
+    if (reps < 1) return fail(PMF_EINVAL, "autotune: reps must be >= 1");
+    if (!vol || !angles || !proj || !g_proj || !g_vol)
+        return fail(PMF_EINVAL, "autotune: null pointer");
+    PMF_CHECK(check_ws(ws, ws_bytes, project_bwd_workspace(*cone, V)));
+    const GridK g = make_grid(*grid);
+    const ConeK c = make_cone(*cone, g);
+    const int64_t N = grid_size(g);
+    hipStream_t st = as_stream(stream);
+    const int knobs[2] = {KNOB_PROJECT_TILE, KNOB_BACKPROJECT_BRICK};
+    const int prev[2] = {tune_get(knobs[0]), tune_get(knobs[1])};
+    const int was_prof = profile_enable(0);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    int slot = 0;
+    for (int q = 0; q < 2 && e == hipSuccess; ++q) {
+        int best = prev[q];
+        float best_ms = INFINITY;
+        for (int k = 0; k < tune_candidates(knobs[q]) && e == hipSuccess; ++k) {
+            tune_set(knobs[q], k);
+            auto run = [&]() {
+                return q == 0 ? launch_project(vol, N, g, c, angles, V, proj, st)
+                              : launch_project_bwd(g_proj, g, c, angles, V, g_vol, N, ws, st);
+            };
+            if ((e = run()) != hipSuccess) break;
+            if ((e = hipEventRecord(e0, st)) != hipSuccess) break;
+            for (int r = 0; r < reps && e == hipSuccess; ++r) e = run();
+            if (e != hipSuccess) break;
+            if ((e = hipEventRecord(e1, st)) != hipSuccess) break;
+            if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+            float t = 0.0f;
+            if ((e = hipEventElapsedTime(&t, e0, e1)) != hipSuccess) break;
+            t /= (float)reps;
+            if (ms) ms[slot] = t;
+            ++slot;
+            if (t < best_ms) {
+                best_ms = t;
+                best = k;
+            }
+        }
+        tune_set(knobs[q], best);
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    profile_enable(was_prof);
+    if (e != hipSuccess) {
+        tune_set(knobs[0], prev[0]);
+        tune_set(knobs[1], prev[1]);
+        return hip_status(e, "autotune_project");
+    }
+    return ok();
+}
+
 // ------------------------------------------------------ fused motion path
 size_t pmf_warp_project_workspace(int L, int B, const pmf_grid_t *lvl, int V,
                                   const pmf_grid_t *grid, const pmf_cone_t *cone) {

@@ -329,7 +329,6 @@ struct BoundK {
 // samples): every partial sum stays below 2^30 in magnitude, and each
 // contribution is rounded to within 0.5 / scale.
 // With vmax non-null the largest |g_vol| of each view is also recorded.
-constexpr int BWD_WAVES = 8;    // wavefronts per back-projection workgroup
 
 // One scan's share of a ragged back-projection launch: workgroups
 // [first[k], first[k+1]) belong to scan k, view-major (one view per
@@ -355,15 +354,16 @@ struct BwdTab {
     int n;
 };
 
-template <int S, bool SUM>
-__global__ __launch_bounds__(64 * BWD_WAVES) void k_project_bwd(BwdTab t) {
+// S: brick edge (voxels); W: wavefronts per workgroup sharing the brick.
+template <int S, bool SUM, int W>
+__global__ __launch_bounds__(64 * W) void k_project_bwd(BwdTab t) {
     constexpr int P = S + 2;                    // padded edge
     constexpr int NP = P * P * P;
-    constexpr int NT = 64 * BWD_WAVES;
+    constexpr int NT = 64 * W;
     constexpr int PER = (NP + NT - 1) / NT;     // padded entries per thread
     __shared__ int acc[NP];
-    __shared__ RunP runs[BWD_WAVES][64];
-    __shared__ int ends[BWD_WAVES][64];
+    __shared__ RunP runs[W][64];
+    __shared__ int ends[W][64];
     const int job = job_of(t, (int)blockIdx.x);
     const BwdK &bj = t.s[job];
     const GridK &g = bj.g;
@@ -439,7 +439,7 @@ __global__ __launch_bounds__(64 * BWD_WAVES) void k_project_bwd(BwdTab t) {
         const float kbound = nr * ns * 1.0625f + 1.0f;
         const float scale = 1073741824.0f / (kbound * m);   // 2^30 / (kbound M)
         // pass 2: scatter every owned sample's 8 weights
-        for (int ph = wave; ph < nph; ph += BWD_WAVES) {     // uniform per wave
+        for (int ph = wave; ph < nph; ph += W) {             // uniform per wave
             const int iu = u0 + lx * gu + ph % gu, iv = v0 + ly * gv + ph / gu;
             int s0 = 0, len = 0;
             RayK r;
@@ -690,9 +690,8 @@ size_t project_bwd_workspace(const pmf_cone_t &c, int V) {
            align256(sizeof(unsigned) * 2 * (size_t)V);
 }
 
-hipError_t launch_project_bwd_jobs(const BwdJob *jobs, int n, hipStream_t s) {
-    if (n < 1 || n > MAXS) return hipErrorInvalidValue;
-    constexpr int S = 16;
+template <int S, int W>
+static hipError_t project_bwd_bricks(const BwdJob *jobs, int n, hipStream_t s) {
     const bool sum_views = jobs[0].stride == 0;
     BwdTab t{};
     t.n = n;
@@ -738,11 +737,21 @@ hipError_t launch_project_bwd_jobs(const BwdJob *jobs, int n, hipStream_t s) {
     {
         ProfScope prof_("project_bwd", s);
         if (sum_views)
-            k_project_bwd<S, true><<<(unsigned)t.first[n], 64 * BWD_WAVES, 0, s>>>(t);
+            k_project_bwd<S, true, W><<<(unsigned)t.first[n], 64 * W, 0, s>>>(t);
         else
-            k_project_bwd<S, false><<<(unsigned)t.first[n], 64 * BWD_WAVES, 0, s>>>(t);
+            k_project_bwd<S, false, W><<<(unsigned)t.first[n], 64 * W, 0, s>>>(t);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_project_bwd_jobs(const BwdJob *jobs, int n, hipStream_t s) {
+    if (n < 1 || n > MAXS) return hipErrorInvalidValue;
+    switch (tune_get(KNOB_BACKPROJECT_BRICK)) {
+        case 1: return project_bwd_bricks<16, 4>(jobs, n, s);
+        case 2: return project_bwd_bricks<12, 8>(jobs, n, s);
+        case 3: return project_bwd_bricks<8, 4>(jobs, n, s);
+        default: return project_bwd_bricks<16, 8>(jobs, n, s);
+    }
 }
 
 hipError_t launch_project_bwd(const float *g_proj, const GridK &g, const ConeK &c,

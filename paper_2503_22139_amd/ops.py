@@ -98,6 +98,8 @@ _SIGS = {
     "pmf_warp_project_bwd_scans_workspace": ([C.c_int, C.c_int, C.POINTER(PmfScan), C.c_int], _SZ),
     "pmf_warp_project_bwd_scans": ([C.c_int, C.c_int, C.POINTER(PmfScan), C.c_int, _P, _SZ, _P],
                                    C.c_int),
+    "pmf_autotune_project": ([_P, C.POINTER(PmfGrid), C.POINTER(PmfCone), _P, C.c_int, _P, _P, _P,
+                              _P, _SZ, C.c_int, C.POINTER(C.c_float), _P], C.c_int),
     "pmf_tune_candidates": ([C.c_int], C.c_int),
     "pmf_tune_get": ([C.c_int], C.c_int),
     "pmf_tune_set": ([C.c_int, C.c_int], C.c_int),
@@ -358,6 +360,29 @@ def pmf_tune_set(knob: int, choice: int) -> int:
     if rc < 0:
         _check(rc)
     return int(rc)
+
+
+def pmf_autotune_project(vol, grid: Grid, cone: Cone, angles, g_proj, reps: int = 3):
+    """Run the library's autotuner on per-view volumes vol [V][...] and
+    residuals g_proj [V][nv][nu]; returns the chosen shapes and the timings
+    (ms per launch) of every candidate."""
+    V = int(angles.numel())
+    g = make_grid(grid)
+    cn = make_cone(cone)
+    proj = torch.empty((V, cone.nv, cone.nu), device=vol.device, dtype=torch.float32)
+    g_vol = torch.empty_like(vol)
+    nbytes = lib().pmf_project_bwd_workspace(C.byref(cn), V)
+    ws = workspace(nbytes, vol.device)
+    nt = pmf_tune_candidates(PMF_TUNE_PROJECT_TILE)
+    nb = pmf_tune_candidates(PMF_TUNE_BACKPROJECT_BRICK)
+    ms = (C.c_float * (nt + nb))()
+    _check(lib().pmf_autotune_project(_ptr(vol), C.byref(g), C.byref(cn), _ptr(angles), V, _ptr(proj),
+                                      _ptr(g_proj.contiguous()), _ptr(g_vol),
+                                      C.c_void_p(ws.data_ptr()), ws.numel(), reps, ms, _stream()))
+    return {"project_tile": pmf_tune_get(PMF_TUNE_PROJECT_TILE),
+            "backproject_brick": pmf_tune_get(PMF_TUNE_BACKPROJECT_BRICK),
+            "project_tile_ms": [float(x) for x in ms[:nt]],
+            "backproject_brick_ms": [float(x) for x in ms[nt:]]}
 
 
 def pmf_warp_project(ref, grid: Grid, bases, levels, coeff, cone: Cone, angles, out=None):

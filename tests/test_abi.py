@@ -176,3 +176,15 @@ def test_scans_reject_bad_arguments(lib):
     arr = (ops.PmfScan * 2)(good, nullg)
     assert lib.pmf_warp_project_bwd_scans(3, 3, arr, 2, C.c_void_p(256), 1 << 40, None) == ops.PMF_EINVAL
     assert "g_bases[2]" in err(lib)
+
+
+def test_autotune_rejects_bad_arguments(lib):
+    g = grid()
+    cn = ops.make_cone(Cone(1000.0, 1500.0, 16, 16, 1.0, 1.0))
+    p = C.c_void_p(256)
+    big = 1 << 40
+    assert lib.pmf_autotune_project(None, C.byref(g), C.byref(cn), p, 2, p, p, p, p, big, 1, None, None) == ops.PMF_EINVAL
+    assert lib.pmf_autotune_project(p, C.byref(g), C.byref(cn), p, 0, p, p, p, p, big, 1, None, None) == ops.PMF_EINVAL
+    assert lib.pmf_autotune_project(p, C.byref(g), C.byref(cn), p, 2, p, p, p, p, big, 0, None, None) == ops.PMF_EINVAL
+    assert "reps" in err(lib)
+    assert lib.pmf_autotune_project(p, C.byref(g), C.byref(cn), p, 2, p, p, p, p, 1, 1, None, None) == ops.PMF_EWORKSPACE

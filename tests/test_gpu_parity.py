@@ -375,3 +375,40 @@ def test_graph_replay_matches_eager():
             assert rel(a, b) < 1e-5, it
         m.step_plain(target)            # eager work between replays
         torch.cuda.synchronize()
+
+
+def test_launch_shapes_agree_and_autotune():
+    """Every forward ray tile and every back-projection brick gives the same
+    bits (per-ray sums, and integer fixed-point sums whose per-view scale does
+    not depend on the brick); the autotuner picks valid shapes."""
+    _, grid, cone, angles = _proj_case("aniso")
+    V = len(angles)
+    ang = T(angles)
+    vol = T(synth.random_volume(80, (V,) + tuple(grid.n), 0.0, 1.0))
+    gp = T(synth.random_normal(81, (V, cone.nv, cone.nu)))
+    tile0 = ops.pmf_tune_get(ops.PMF_TUNE_PROJECT_TILE)
+    brick0 = ops.pmf_tune_get(ops.PMF_TUNE_BACKPROJECT_BRICK)
+    try:
+        ref_p = ref_b = None
+        for k in range(ops.pmf_tune_candidates(ops.PMF_TUNE_PROJECT_TILE)):
+            ops.pmf_tune_set(ops.PMF_TUNE_PROJECT_TILE, k)
+            p = ops.pmf_project(vol, grid, cone, ang, shared=False)
+            ref_p = p.clone() if ref_p is None else ref_p
+            assert torch.equal(p, ref_p), k
+        for k in range(ops.pmf_tune_candidates(ops.PMF_TUNE_BACKPROJECT_BRICK)):
+            ops.pmf_tune_set(ops.PMF_TUNE_BACKPROJECT_BRICK, k)
+            b = ops.pmf_project_bwd(gp, grid, cone, ang, shared=False)
+            ref_b = b.clone() if ref_b is None else ref_b
+            assert torch.equal(b, ref_b), k
+            bs = ops.pmf_project_bwd(gp, grid, cone, ang, shared=True)
+            assert rel(N(bs), N(ref_b.sum(0))) < 1e-6, k
+        want = oracle.project_bwd(N(gp), grid, cone, angles)
+        assert rel(N(ref_b).reshape(-1), np.asarray(want).reshape(-1)) < VOL_TOL
+        res = ops.pmf_autotune_project(vol, grid, cone, ang, gp, reps=2)
+        say("autotune", res)
+        assert 0 <= res["project_tile"] < ops.pmf_tune_candidates(ops.PMF_TUNE_PROJECT_TILE)
+        assert 0 <= res["backproject_brick"] < ops.pmf_tune_candidates(ops.PMF_TUNE_BACKPROJECT_BRICK)
+        assert all(t > 0 for t in res["project_tile_ms"] + res["backproject_brick_ms"])
+    finally:
+        ops.pmf_tune_set(ops.PMF_TUNE_PROJECT_TILE, tile0)
+        ops.pmf_tune_set(ops.PMF_TUNE_BACKPROJECT_BRICK, brick0)

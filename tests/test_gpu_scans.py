@@ -144,19 +144,26 @@ def test_c5_scans_batched_equals_separate():
     mm = MultiScanModel(ws)
     targets = [T(synth.random_volume(70 + k, (len(w.angles), w.cone.nv, w.cone.nu), 0.0, 20.0))
                for k, w in enumerate(ws)]
+    say("c5: ragged forward")
+    pr = mm.forward_batched()
+    for k, (mdl, p) in enumerate(zip(mm.models, pr)):
+        assert rel(N(p), N(mdl.forward_batched())) <= 1e-6, k
     say("c5: ragged step")
     res = mm.step_batched(targets)
     say("c5: separate steps")
     sep = mm.step_separate(targets)
-    # Per-brick coefficient partials are added by LDS float atomics in
-    # whatever order the waves arrive, and the coefficient sums cancel
-    # strongly at this size, so two runs of the same call already differ by
-    # a few 1e-5; the bar is the one between the plain and batched schedules.
+    # Two runs of the same call differ slightly: a few sums are float atomics
+    # in arrival order, and at this size some voxels warp to within float
+    # rounding of a cell face, where the trilinear derivative jumps, which
+    # turns those last-bit differences into up to ~1e-4 of a coefficient
+    # gradient.  Projections and the loss are compared tightly, the
+    # gradients at the gradient tolerance.
     for k, ((l, g), (ls, gsp)) in enumerate(zip(res, sep)):
         assert abs(float(N(l)) - float(N(ls))) <= 1e-6 * abs(float(N(ls))), k
         r = rel(N(g["coeff"]), N(gsp["coeff"]))
         say("c5: scan", k, "coeff rel", r)
-        assert r < 1e-4, (k, r)
+        assert r < GRAD_TOL, (k, r)
         for name in ("mean", "scale", "quat", "value"):
             r = rel(N(g["ref"][name]), N(gsp["ref"][name]))
-            assert r < 1e-4, (k, name, r)
+            say("c5: scan", k, "ref", name, "rel", r)
+            assert r < GRAD_TOL, (k, name, r)
