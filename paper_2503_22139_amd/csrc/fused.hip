@@ -38,18 +38,14 @@ struct CWTab {
     int n;
 };
 
+// Body of one voxel; the restrict-qualified parameters (kept through
+// inlining) let the per-view coefficients come through scalar loads.
 template <int L, int B>
-__global__ __launch_bounds__(256) void k_combine_warp(CWTab t) {
-    const int job = job_of(t, (int)blockIdx.x);
-    const CWK &cj = t.s[job];
-    const GridK &g = cj.g;
-    const LevelsK &lv = cj.lv;
-    const float *__restrict__ ref = cj.ref;
-    const float *__restrict__ coeff = cj.coeff;
-    const int V = cj.V;
-    float *__restrict__ warped = cj.warped;
+__device__ __forceinline__ void combine_warp_voxel(const float *__restrict__ ref, const GridK &g,
+                                                   const LevelsK &lv,
+                                                   const float *__restrict__ coeff, int V,
+                                                   float *__restrict__ warped, int64_t j) {
     const int64_t N = grid_size(g);
-    const int64_t j = (int64_t)((int)blockIdx.x - t.first[job]) * blockDim.x + threadIdx.x;
     if (j >= N) return;
     const int iz = (int)(j % g.n[2]);
     const int iy = (int)((j / g.n[2]) % g.n[1]);
@@ -72,6 +68,14 @@ __global__ __launch_bounds__(256) void k_combine_warp(CWTab t) {
             sample_u(ref, g.n, fmaf(d[0], g.inv_h[0], (float)ix), fmaf(d[1], g.inv_h[1], (float)iy),
                      fmaf(d[2], g.inv_h[2], (float)iz));
     }
+}
+
+template <int L, int B>
+__global__ __launch_bounds__(256) void k_combine_warp(CWTab t) {
+    const int job = job_of(t, (int)blockIdx.x);
+    const CWK &cj = t.s[job];
+    const int64_t j = (int64_t)((int)blockIdx.x - t.first[job]) * blockDim.x + threadIdx.x;
+    combine_warp_voxel<L, B>(cj.ref, cj.g, cj.lv, cj.coeff, cj.V, cj.warped, j);
 }
 
 // Brick of the adjoint pass: 8x8x8 voxels, two per thread; LDS box with a
@@ -121,22 +125,12 @@ struct WCTab {
 };
 
 template <int L, int B>
-__global__ __launch_bounds__(256) void k_warp_combine_bwd(WCTab t) {
+__device__ __forceinline__ void warp_combine_bwd_brick(
+    const float *__restrict__ ref, const GridK &g, const LevelsK &lv,
+    const float *__restrict__ coeff, int V, const float *__restrict__ g_I,
+    const unsigned *__restrict__ vmax, float *__restrict__ g_ref, float *__restrict__ stage,
+    const GOut &gout, int accumulate, int nb1, int nb2, float *__restrict__ partial, int blk) {
     constexpr int NC = L * B * 3;
-    const int job = job_of(t, (int)blockIdx.x);
-    const WCK &wj = t.s[job];
-    const GridK &g = wj.g;
-    const LevelsK &lv = wj.lv;
-    const float *__restrict__ ref = wj.ref;
-    const float *__restrict__ coeff = wj.coeff;
-    const int V = wj.V;
-    const float *__restrict__ g_I = wj.g_I;
-    const unsigned *__restrict__ vmax = wj.vmax;
-    float *__restrict__ g_ref = wj.g_ref;
-    const GOut &gout = wj.gout;
-    const int accumulate = wj.accumulate;
-    const int nb1 = wj.nb1, nb2 = wj.nb2;
-    const int blk = (int)blockIdx.x - t.first[job];
     extern __shared__ float smem[];
     int *ibox = (int *)smem;              // HB^3 fixed point, high words
     int *lbox = (int *)smem + HB3;        // HB^3 fixed point, low words
@@ -289,10 +283,10 @@ __global__ __launch_bounds__(256) void k_warp_combine_bwd(WCTab t) {
         }
         __syncthreads();
     }
-    float *st = wj.stage + (int64_t)blk * HB3;
+    float *st = stage + (int64_t)blk * HB3;
     for (int i = threadIdx.x; i < HB3; i += blockDim.x) st[i] = fbox[i];
     for (int i = threadIdx.x; i < V * NC; i += blockDim.x)
-        wj.partial[(int64_t)blk * V * NC + i] = cacc[i];
+        partial[(int64_t)blk * V * NC + i] = cacc[i];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         if (!ok[q]) continue;
@@ -306,6 +300,15 @@ __global__ __launch_bounds__(256) void k_warp_combine_bwd(WCTab t) {
                     *dst = accumulate ? *dst + G[q][l][b][k] : G[q][l][b][k];
                 }
     }
+}
+
+template <int L, int B>
+__global__ __launch_bounds__(256) void k_warp_combine_bwd(WCTab t) {
+    const int job = job_of(t, (int)blockIdx.x);
+    const WCK &wj = t.s[job];
+    warp_combine_bwd_brick<L, B>(wj.ref, wj.g, wj.lv, wj.coeff, wj.V, wj.g_I, wj.vmax, wj.g_ref,
+                                 wj.stage, wj.gout, wj.accumulate, wj.nb1, wj.nb2, wj.partial,
+                                 (int)blockIdx.x - t.first[job]);
 }
 
 // g_ref[p] += sum of the staged boxes that cover voxel p (at most 2 bricks
