@@ -23,6 +23,7 @@ import argparse
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -58,6 +59,33 @@ def ray_samples(grid, cone, angles) -> np.ndarray:
         L = np.maximum(t1 - np.maximum(t0, 0.0), 0.0)
         out.append(np.where(L > 0, np.maximum(1, np.ceil(L / step)), 0))
     return np.stack(out)
+
+
+PROFILE_COUNTERS = "profiles/motion_fwdbwd_32views_256x256x128_counters.md"
+
+
+def profiled_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, calibrated by a plain copy), or None if
+    there is none or the kernel's source file changed since it was taken."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(root, PROFILE_COUNTERS)
+    if not os.path.exists(path):
+        return None
+    best = None
+    for line in open(path):
+        m = re.match(r"traffic: kernel=(\S+) grid=(\d+) source=(\S+) sha256=(\S+) hbm_bytes=(\S+)", line.strip())
+        if not m or m.group(1) != kernel:
+            continue
+        if best is None or int(m.group(2)) > best[0]:
+            best = (int(m.group(2)), m.group(3), m.group(4), float(m.group(5)))
+    if best is None:
+        return None
+    src = os.path.join(root, best[1])
+    if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != best[2]:
+        return None
+    return best[3]
 
 
 def kernel_model(name, w, V, samples):
@@ -302,11 +330,13 @@ def main():
     bound, flops, byts = kernel_model(dom, w, V, samples)
     avg_s = kern[dom]["avg_ms"] * 1e-3
     achieved = flops / avg_s / 1e12
+    traffic = profiled_traffic(dom)
     roof = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+            "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic,
             "avg_launch_ms": kern[dom]["avg_ms"], "algorithmic_flop": flops,
             "hbm": {"achieved": byts / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": byts / avg_s / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes": byts}}
+                    "frac": byts / avg_s / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes": byts,
+                    "measured_traffic_GBps": (traffic / avg_s / 1e9) if traffic else None}}
 
     out = {
         "metric": "fwd+bwd iterations/s (32 views, 256²×128) batched vs plain; % HBM roofline",
