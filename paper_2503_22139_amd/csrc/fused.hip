@@ -39,8 +39,10 @@ struct CWTab {
 };
 
 // Body of one voxel; the restrict-qualified parameters (kept through
-// inlining) let the per-view coefficients come through scalar loads.
-template <int L, int B>
+// inlining) let the per-view coefficients come through scalar loads.  With
+// PAIRED the warped volumes are written in the y-paired layout the
+// projection reads (two floats per voxel: its value and the next row's).
+template <int L, int B, bool PAIRED>
 __device__ __forceinline__ void combine_warp_voxel(const float *__restrict__ ref, const GridK &g,
                                                    const LevelsK &lv,
                                                    const float *__restrict__ coeff, int V,
@@ -64,18 +66,27 @@ __device__ __forceinline__ void combine_warp_voxel(const float *__restrict__ ref
                 for (int b = 0; b < B; ++b) t = fmaf(cv[(l * B + b) * 3 + k], sv[l][b][k], t);
             d[k] = t;
         }
-        warped[(int64_t)v * N + j] =
+        const float val =
             sample_u(ref, g.n, fmaf(d[0], g.inv_h[0], (float)ix), fmaf(d[1], g.inv_h[1], (float)iy),
                      fmaf(d[2], g.inv_h[2], (float)iz));
+        if (PAIRED) {
+            // y-paired layout: this voxel is the first of its own pair and the
+            // second of the pair that starts one row below
+            float *w = warped + (int64_t)v * 2 * N + 2 * j;
+            w[0] = val;
+            if (iy > 0) w[1 - 2 * (int64_t)g.n[2]] = val;
+        } else {
+            warped[(int64_t)v * N + j] = val;
+        }
     }
 }
 
-template <int L, int B>
+template <int L, int B, bool PAIRED>
 __global__ __launch_bounds__(256) void k_combine_warp(CWTab t) {
     const int job = job_of(t, (int)blockIdx.x);
     const CWK &cj = t.s[job];
     const int64_t j = (int64_t)((int)blockIdx.x - t.first[job]) * blockDim.x + threadIdx.x;
-    combine_warp_voxel<L, B>(cj.ref, cj.g, cj.lv, cj.coeff, cj.V, cj.warped, j);
+    combine_warp_voxel<L, B, PAIRED>(cj.ref, cj.g, cj.lv, cj.coeff, cj.V, cj.warped, j);
 }
 
 // Brick of the adjoint pass: 8x8x8 voxels, two per thread; LDS box with a
@@ -352,10 +363,18 @@ __global__ __launch_bounds__(256) void k_reduce_coeff_blocks(const float *__rest
     if (threadIdx.x == 0) g_coeff[t] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+// The warped volumes go to the workspace in the y-paired layout when the
+// projection's 32-bit byte offsets and 24-bit strides still hold for it
+// (2 N floats < 2^32 bytes, 2 n1 n2 < 2^24).
+static bool use_paired(const GridK &g) {
+    return grid_size(g) * 8 < ((int64_t)1 << 32) &&
+           2 * (int64_t)g.n[1] * g.n[2] < ((int64_t)1 << 24);
+}
+
 size_t warp_project_workspace(const LevelsK &lv, int V, const GridK &g, const pmf_cone_t &c) {
     (void)lv;
     (void)c;
-    return align256(sizeof(float) * (size_t)grid_size(g) * (size_t)V);
+    return align256(sizeof(float) * (size_t)grid_size(g) * (size_t)V * (use_paired(g) ? 2 : 1));
 }
 
 // Forward of the motion path for a ragged batch: one combine+warp launch and
@@ -366,6 +385,8 @@ hipError_t launch_warp_project_jobs(const WPJob *jobs, int n, hipStream_t s) {
     CWTab t{};
     t.n = n;
     ProjJob pj[MAXS];
+    bool paired = true;
+    for (int k = 0; k < n; ++k) paired = paired && use_paired(jobs[k].g);
     for (int k = 0; k < n; ++k) {
         const WPJob &j = jobs[k];
         if (j.lv.L != L || j.lv.B != Bb) return hipErrorInvalidValue;
@@ -378,14 +399,17 @@ hipError_t launch_warp_project_jobs(const WPJob *jobs, int n, hipStream_t s) {
         c.V = j.V;
         c.warped = (float *)j.ws;
         t.first[k + 1] = t.first[k] + (int)((N + 255) / 256);
-        pj[k] = ProjJob{c.warped, N, j.g, j.c, j.angles, j.V, j.proj};
+        pj[k] = ProjJob{c.warped, paired ? 2 * N : N, j.g, j.c, j.angles, j.V, j.proj, paired};
     }
     for (int k = n + 1; k <= MAXS; ++k) t.first[k] = t.first[n];
     hipError_t e = dispatch_lb(L, Bb, [&](auto Lc, auto Bc) {
         constexpr int LL = decltype(Lc)::value, BB = decltype(Bc)::value;
         {
             ProfScope prof_("combine_warp", s);
-            k_combine_warp<LL, BB><<<(unsigned)t.first[n], 256, 0, s>>>(t);
+            if (paired)
+                k_combine_warp<LL, BB, true><<<(unsigned)t.first[n], 256, 0, s>>>(t);
+            else
+                k_combine_warp<LL, BB, false><<<(unsigned)t.first[n], 256, 0, s>>>(t);
         }
         return hipGetLastError();
     });

@@ -284,6 +284,7 @@ struct ProjJob {            // one scan's forward projection
     const float *angles;
     int V;
     float *proj;
+    bool paired;            // vol in the y-paired layout (2 floats per voxel; all jobs alike)
 };
 hipError_t launch_project_jobs(const ProjJob *jobs, int n, hipStream_t s);
 hipError_t launch_project(const float *vol, int64_t stride, const GridK &g, const ConeK &c,

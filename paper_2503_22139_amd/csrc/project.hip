@@ -123,6 +123,29 @@ __device__ __forceinline__ float march_sample(const char *__restrict__ vb, const
     return lerp1(lerp1(x00, x01, f1), lerp1(x10, x11, f1), f0);
 }
 
+// The same trilinear read from a y-paired volume: element (i, j, k) holds the
+// pair (V[i][j][k], V[i][j+1][k]), so the 2x2 (y, z) corners of a cell are 16
+// contiguous bytes and a sample takes two loads (x and x+1) instead of four.
+// The blend is the same arithmetic in the same order as march_sample.
+__device__ __forceinline__ float march_sample_paired(const char *__restrict__ vb,
+                                                     const MarchK &mk, float u0, float u1,
+                                                     float u2) {
+    float c0, c1, c2, f0, f1, f2;
+    ray_cell(u0, mk.nm1[0], mk.nm2[0], c0, f0);
+    ray_cell(u1, mk.nm1[1], mk.nm2[1], c1, f1);
+    ray_cell(u2, mk.nm1[2], mk.nm2[2], c2, f2);
+    const uint32_t idx =
+        __umul24((uint32_t)c0, mk.s0) + __umul24((uint32_t)c1, mk.s1) + (uint32_t)c2 * 2u;
+    const float *pa = (const float *)(vb + idx * 4u);
+    const float *pd = (const float *)(vb + (idx + mk.s0) * 4u);
+    // pa[0..3] = V[c0][c1][c2], V[c0][c1+1][c2], V[c0][c1][c2+1], V[c0][c1+1][c2+1]
+    const float a0 = pa[0], a1 = pa[1], a2 = pa[2], a3 = pa[3];
+    const float d0 = pd[0], d1 = pd[1], d2 = pd[2], d3 = pd[3];
+    const float x00 = lerp1(a0, a2, f2), x01 = lerp1(a1, a3, f2);
+    const float x10 = lerp1(d0, d2, f2), x11 = lerp1(d1, d3, f2);
+    return lerp1(lerp1(x00, x01, f1), lerp1(x10, x11, f1), f0);
+}
+
 __host__ __device__ inline MarchK make_march(const GridK &g) {
     MarchK m;
     for (int a = 0; a < 3; ++a) {
@@ -131,6 +154,14 @@ __host__ __device__ inline MarchK make_march(const GridK &g) {
     }
     m.s1 = (uint32_t)g.n[2];
     m.s0 = (uint32_t)g.n[1] * (uint32_t)g.n[2];
+    return m;
+}
+
+// Strides (elements) of the y-paired layout: two floats per voxel.
+__host__ __device__ inline MarchK make_march_paired(const GridK &g) {
+    MarchK m = make_march(g);
+    m.s1 *= 2u;
+    m.s0 *= 2u;
     return m;
 }
 
@@ -158,7 +189,7 @@ struct ProjTab {
     int n;
 };
 
-template <int WU, int WV, int AU>
+template <int WU, int WV, int AU, bool PAIRED>
 __global__ __launch_bounds__(256) void k_project(ProjTab t) {
     static_assert(WU * WV == 64 && AU >= 1 && 4 % AU == 0, "wave tile must hold 64 pixels");
     constexpr int BU = WU * AU, BV = WV * (4 / AU);
@@ -179,18 +210,16 @@ __global__ __launch_bounds__(256) void k_project(ProjTab t) {
     const char *__restrict__ vb = (const char *)(pj.vol + (int64_t)v * pj.stride);
     float acc0 = 0.0f, acc1 = 0.0f;
     int s = 0;
+    auto sample = [&](float sf) {
+        const float u0 = fmaf(sf, r.su[0], r.bu[0]), u1 = fmaf(sf, r.su[1], r.bu[1]),
+                    u2 = fmaf(sf, r.su[2], r.bu[2]);
+        return PAIRED ? march_sample_paired(vb, mk, u0, u1, u2) : march_sample(vb, mk, u0, u1, u2);
+    };
     for (; s + 1 < r.n; s += 2) {
-        const float sa = (float)s, sb = (float)(s + 1);
-        acc0 += march_sample(vb, mk, fmaf(sa, r.su[0], r.bu[0]), fmaf(sa, r.su[1], r.bu[1]),
-                             fmaf(sa, r.su[2], r.bu[2]));
-        acc1 += march_sample(vb, mk, fmaf(sb, r.su[0], r.bu[0]), fmaf(sb, r.su[1], r.bu[1]),
-                             fmaf(sb, r.su[2], r.bu[2]));
+        acc0 += sample((float)s);
+        acc1 += sample((float)(s + 1));
     }
-    if (s < r.n) {
-        const float sa = (float)s;
-        acc0 += march_sample(vb, mk, fmaf(sa, r.su[0], r.bu[0]), fmaf(sa, r.su[1], r.bu[1]),
-                             fmaf(sa, r.su[2], r.bu[2]));
-    }
+    if (s < r.n) acc0 += sample((float)s);
     pj.proj[((int64_t)v * c.nv + iv) * c.nu + iu] = (acc0 + acc1) * r.delta;
 }
 
@@ -269,6 +298,13 @@ __device__ __forceinline__ int round_int(float x) {
     return r;
 }
 
+// Waits for this wave's outstanding LDS reads (and, LDS operations retiring
+// in order, everything issued before them).  Placed right after the rare
+// reads of a ray switch so the compiler need not put a conservative wait on
+// the common path, where it would also wait for the previous sample's
+// atomics.
+__device__ __forceinline__ void lds_wait() { __builtin_amdgcn_s_waitcnt(0xc07f); }  // lgkmcnt(0)
+
 // Orders the LDS accesses of one wavefront (a compiler barrier: the hardware
 // performs a wavefront's LDS operations in order).
 __device__ __forceinline__ void wave_lds_sync() {
@@ -306,7 +342,7 @@ struct BoundK {
     float mag, persp, R, Z, two_hx, two_hy, two_hz, inv_du, inv_dv, diag;
 };
 
-// g_vol (per view, or summed over views when SUM) of one S^3 brick.
+// g_vol (per view, or summed over views when SUM) of one S0 x S1 x S2 brick.
 //
 // The LDS accumulator spans the brick plus one voxel on every side, so the
 // 8 corners of every owned sample land inside it; the pad is dropped on
@@ -354,11 +390,13 @@ struct BwdTab {
     int n;
 };
 
-// S: brick edge (voxels); W: wavefronts per workgroup sharing the brick.
-template <int S, bool SUM, int W>
+// S0, S1, S2: brick extents (voxels) per axis; W: wavefronts per workgroup
+// sharing the brick.
+template <int S0, int S1, int S2, bool SUM, int W>
 __global__ __launch_bounds__(64 * W) void k_project_bwd(BwdTab t) {
-    constexpr int P = S + 2;                    // padded edge
-    constexpr int NP = P * P * P;
+    constexpr int P0 = S0 + 2, P1 = S1 + 2, P2 = S2 + 2;   // padded edges
+    constexpr int NP = P0 * P1 * P2;
+    constexpr int SZ[3] = {S0, S1, S2};
     constexpr int NT = 64 * W;
     constexpr int PER = (NP + NT - 1) / NT;     // padded entries per thread
     __shared__ int acc[NP];
@@ -378,7 +416,7 @@ __global__ __launch_bounds__(64 * W) void k_project_bwd(BwdTab t) {
     const int view = SUM ? 0 : local / bj.nbricks;
     const int bid = SUM ? local : local - view * bj.nbricks;
     const int b2 = bid % nb2, b1 = (bid / nb2) % nb1, b0 = bid / (nb2 * nb1);
-    const int B[3] = {b0 * S, b1 * S, b2 * S};
+    const int B[3] = {b0 * S0, b1 * S1, b2 * S2};
 
     // owned cells [clo, chi] and their extent in voxel units [ulo, uhi]
     float clo[3], chi[3], ulo[3], uhi[3];
@@ -386,7 +424,7 @@ __global__ __launch_bounds__(64 * W) void k_project_bwd(BwdTab t) {
     bool interior = true;       // no owned cell touches the clamped rim cells
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const int lo = max(B[a] - 1, 0), hi = min(B[a] + S - 1, g.n[a] - 2);
+        const int lo = max(B[a] - 1, 0), hi = min(B[a] + SZ[a] - 1, g.n[a] - 2);
         clo[a] = (float)lo;
         chi[a] = (float)hi;
         interior = interior && lo >= 1 && hi <= g.n[a] - 3;
@@ -397,8 +435,9 @@ __global__ __launch_bounds__(64 * W) void k_project_bwd(BwdTab t) {
     }
     // byte offset in acc of cell (c0, c1, c2): c0*K0 + c1*K1 + c2*4 + KC,
     // exact in float (every term is an integer below 2^24)
-    const float K0 = 4.0f * P * P, K1 = 4.0f * P;
-    const float KC = -4.0f * ((float)(B[0] - 1) * P * P + (float)(B[1] - 1) * P + (float)(B[2] - 1));
+    const float K0 = 4.0f * P1 * P2, K1 = 4.0f * P2;
+    const float KC =
+        -4.0f * ((float)(B[0] - 1) * P1 * P2 + (float)(B[1] - 1) * P2 + (float)(B[2] - 1));
     float sum[SUM ? PER : 1];   // per-thread float accumulation over views (strided entries)
 #pragma unroll
     for (int k = 0; k < (SUM ? PER : 1); ++k) sum[k] = 0.0f;
@@ -408,6 +447,15 @@ __global__ __launch_bounds__(64 * W) void k_project_bwd(BwdTab t) {
     const int ve = SUM ? V : view + 1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lx = lane & 7, ly = lane >> 3;
+    // clamp limits of the rim path, held in registers (a reload from the
+    // argument table inside the sample loop would also wait for the atomics)
+    float nm1[3], nm2[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        nm1[a] = mk.nm1[a];
+        nm2[a] = mk.nm2[a];
+        asm volatile("" : "+s"(nm1[a]), "+s"(nm2[a]));
+    }
     RunP *const wr = runs[wave];
     int *const we = ends[wave];
     for (int v = vb; v < ve; ++v) {
@@ -533,6 +581,7 @@ __global__ __launch_bounds__(64 * W) void k_project_bwd(BwdTab t) {
                 if (we[ri + step - 1] <= q) ri += step;
             int rend = we[ri];
             RunP rp = wr[ri];
+            lds_wait();
             for (int it = 0; it < K; ++it, ++q) {                 // uniform
                 if (q >= qe) continue;
                 if (q >= rend) {
@@ -540,6 +589,7 @@ __global__ __launch_bounds__(64 * W) void k_project_bwd(BwdTab t) {
                         rend = we[++ri];
                     } while (q >= rend);
                     rp = wr[ri];
+                    lds_wait();
                 }
                 const float sf = (float)(q + rp.off);
                 const float x0 = fmaf(sf, rp.su[0], rp.bu[0]);
@@ -554,9 +604,9 @@ __global__ __launch_bounds__(64 * W) void k_project_bwd(BwdTab t) {
                     f1 = x1 - c1f;
                     f2 = x2 - c2f;
                 } else {
-                    ray_cell(x0, mk.nm1[0], mk.nm2[0], c0f, f0);
-                    ray_cell(x1, mk.nm1[1], mk.nm2[1], c1f, f1);
-                    ray_cell(x2, mk.nm1[2], mk.nm2[2], c2f, f2);
+                    ray_cell(x0, nm1[0], nm2[0], c0f, f0);
+                    ray_cell(x1, nm1[1], nm2[1], c1f, f1);
+                    ray_cell(x2, nm1[2], nm2[2], c2f, f2);
                 }
                 const int off = (int)fmaf(c0f, K0, fmaf(c1f, K1, fmaf(c2f, 4.0f, KC)));
                 char *qb = (char *)acc + off;
@@ -568,12 +618,12 @@ __global__ __launch_bounds__(64 * W) void k_project_bwd(BwdTab t) {
                 const float e101 = a10 * f2, e111 = a11 * f2;
                 atomicAdd((int *)qb, round_int(a00 - e001));
                 atomicAdd((int *)(qb + 4), round_int(e001));
-                atomicAdd((int *)(qb + 4 * P), round_int(a01 - e011));
-                atomicAdd((int *)(qb + 4 * P + 4), round_int(e011));
-                atomicAdd((int *)(qb + 4 * P * P), round_int(a10 - e101));
-                atomicAdd((int *)(qb + 4 * P * P + 4), round_int(e101));
-                atomicAdd((int *)(qb + 4 * P * P + 4 * P), round_int(a11 - e111));
-                atomicAdd((int *)(qb + 4 * P * P + 4 * P + 4), round_int(e111));
+                atomicAdd((int *)(qb + 4 * P2), round_int(a01 - e011));
+                atomicAdd((int *)(qb + 4 * P2 + 4), round_int(e011));
+                atomicAdd((int *)(qb + 4 * P1 * P2), round_int(a10 - e101));
+                atomicAdd((int *)(qb + 4 * P1 * P2 + 4), round_int(e101));
+                atomicAdd((int *)(qb + 4 * P1 * P2 + 4 * P2), round_int(a11 - e111));
+                atomicAdd((int *)(qb + 4 * P1 * P2 + 4 * P2 + 4), round_int(e111));
             }
             wave_lds_sync();
         }
@@ -596,8 +646,8 @@ __global__ __launch_bounds__(64 * W) void k_project_bwd(BwdTab t) {
     for (int k = 0; k < PER; ++k) {
         const int i = threadIdx.x + NT * k;
         if (i >= NP) continue;
-        const int z = i % P - 1, y = (i / P) % P - 1, x = i / (P * P) - 1;
-        if (x < 0 || y < 0 || z < 0 || x >= S || y >= S || z >= S) continue;
+        const int z = i % P2 - 1, y = (i / P2) % P1 - 1, x = i / (P1 * P2) - 1;
+        if (x < 0 || y < 0 || z < 0 || x >= S0 || y >= S1 || z >= S2) continue;
         const int gx = B[0] + x, gy = B[1] + y, gz = B[2] + z;
         if (gx < g.n[0] && gy < g.n[1] && gz < g.n[2]) {
             float val;
@@ -650,7 +700,7 @@ static void project_tiled(const ProjJob *jobs, int n, hipStream_t s) {
         p.stride = j.stride;
         p.g = j.g;
         p.c = j.c;
-        p.mk = make_march(j.g);
+        p.mk = j.paired ? make_march_paired(j.g) : make_march(j.g);
         p.angles = j.angles;
         p.proj = j.proj;
         p.tiles_u = (j.c.nu + BU - 1) / BU;
@@ -658,11 +708,17 @@ static void project_tiled(const ProjJob *jobs, int n, hipStream_t s) {
         t.first[k + 1] = t.first[k] + p.ntiles * j.V;
     }
     for (int k = n + 1; k <= MAXS; ++k) t.first[k] = t.first[n];
-    if (t.first[n] > 0) k_project<WU, WV, AU><<<(unsigned)t.first[n], 256, 0, s>>>(t);
+    if (t.first[n] == 0) return;
+    if (jobs[0].paired)
+        k_project<WU, WV, AU, true><<<(unsigned)t.first[n], 256, 0, s>>>(t);
+    else
+        k_project<WU, WV, AU, false><<<(unsigned)t.first[n], 256, 0, s>>>(t);
 }
 
 hipError_t launch_project_jobs(const ProjJob *jobs, int n, hipStream_t s) {
     if (n < 1 || n > MAXS) return hipErrorInvalidValue;
+    for (int k = 1; k < n; ++k)
+        if (jobs[k].paired != jobs[0].paired) return hipErrorInvalidValue;
     ProfScope prof_("project", s);
     switch (tune_get(KNOB_PROJECT_TILE)) {
         case 0: project_tiled<16, 4, 1>(jobs, n, s); break;
@@ -680,7 +736,7 @@ hipError_t launch_project_jobs(const ProjJob *jobs, int n, hipStream_t s) {
 
 hipError_t launch_project(const float *vol, int64_t stride, const GridK &g, const ConeK &c,
                           const float *angles, int V, float *proj, hipStream_t s) {
-    const ProjJob j{vol, stride, g, c, angles, V, proj};
+    const ProjJob j{vol, stride, g, c, angles, V, proj, false};
     return launch_project_jobs(&j, 1, s);
 }
 
@@ -690,8 +746,9 @@ size_t project_bwd_workspace(const pmf_cone_t &c, int V) {
            align256(sizeof(unsigned) * 2 * (size_t)V);
 }
 
-template <int S, int W>
+template <int S0, int S1, int S2, int W>
 static hipError_t project_bwd_bricks(const BwdJob *jobs, int n, hipStream_t s) {
+    const int SZ[3] = {S0, S1, S2};
     const bool sum_views = jobs[0].stride == 0;
     BwdTab t{};
     t.n = n;
@@ -724,7 +781,7 @@ static hipError_t project_bwd_bricks(const BwdJob *jobs, int n, hipStream_t s) {
         b.g_vol = j.g_vol;
         b.stride = j.stride;
         int nb[3];
-        for (int a = 0; a < 3; ++a) nb[a] = (j.g.n[a] + S - 1) / S;
+        for (int a = 0; a < 3; ++a) nb[a] = (j.g.n[a] + SZ[a] - 1) / SZ[a];
         b.nb1 = nb[1];
         b.nb2 = nb[2];
         b.nbricks = nb[0] * nb[1] * nb[2];
@@ -737,9 +794,9 @@ static hipError_t project_bwd_bricks(const BwdJob *jobs, int n, hipStream_t s) {
     {
         ProfScope prof_("project_bwd", s);
         if (sum_views)
-            k_project_bwd<S, true, W><<<(unsigned)t.first[n], 64 * W, 0, s>>>(t);
+            k_project_bwd<S0, S1, S2, true, W><<<(unsigned)t.first[n], 64 * W, 0, s>>>(t);
         else
-            k_project_bwd<S, false, W><<<(unsigned)t.first[n], 64 * W, 0, s>>>(t);
+            k_project_bwd<S0, S1, S2, false, W><<<(unsigned)t.first[n], 64 * W, 0, s>>>(t);
     }
     return hipGetLastError();
 }
@@ -747,10 +804,12 @@ static hipError_t project_bwd_bricks(const BwdJob *jobs, int n, hipStream_t s) {
 hipError_t launch_project_bwd_jobs(const BwdJob *jobs, int n, hipStream_t s) {
     if (n < 1 || n > MAXS) return hipErrorInvalidValue;
     switch (tune_get(KNOB_BACKPROJECT_BRICK)) {
-        case 1: return project_bwd_bricks<16, 4>(jobs, n, s);
-        case 2: return project_bwd_bricks<12, 8>(jobs, n, s);
-        case 3: return project_bwd_bricks<8, 4>(jobs, n, s);
-        default: return project_bwd_bricks<16, 8>(jobs, n, s);
+        case 1: return project_bwd_bricks<16, 16, 16, 4>(jobs, n, s);
+        case 2: return project_bwd_bricks<32, 32, 4, 8>(jobs, n, s);
+        case 3: return project_bwd_bricks<32, 32, 8, 8>(jobs, n, s);
+        case 4: return project_bwd_bricks<24, 24, 8, 8>(jobs, n, s);
+        case 5: return project_bwd_bricks<8, 8, 8, 4>(jobs, n, s);
+        default: return project_bwd_bricks<16, 16, 16, 8>(jobs, n, s);
     }
 }
 
