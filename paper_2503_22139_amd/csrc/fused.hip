@@ -89,6 +89,45 @@ __global__ __launch_bounds__(256) void k_combine_warp(CWTab t) {
     combine_warp_voxel<L, B, PAIRED>(cj.ref, cj.g, cj.lv, cj.coeff, cj.V, cj.warped, j);
 }
 
+// Reduce-scatter of 32 per-lane values over the 64 lanes of a wave: returns
+// the total over all lanes of value 16*b3 + 8*b2 + 4*b1 + 2*b0 + b4 (b_k =
+// bit k of the lane; the same total in lanes L and L+32).  Each step pairs
+// lanes that hold the same set of partial sums, keeps half of the set and
+// adds the partner's copy of that half: 16 + 8 + 4 + 2 + 1 + 1 additions
+// instead of 32 separate six-step reductions.
+__device__ __forceinline__ float wave_reduce_scatter32(const float (&x)[32], int lane) {
+    const bool h3 = lane & 8, h2 = lane & 4, h1 = lane & 2, h0 = lane & 1, h4 = lane & 16;
+    float a[16], b[8], c[4], d[2];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {     // partner: row_mirror (lane ^ 15 within 16)
+        const float keep = h3 ? x[16 + j] : x[j], send = h3 ? x[j] : x[16 + j];
+        a[j] = keep + dpp_mov<0x140>(send);
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {      // partner: row_half_mirror (lane ^ 7 within 8)
+        const float keep = h2 ? a[8 + j] : a[j], send = h2 ? a[j] : a[8 + j];
+        b[j] = keep + dpp_mov<0x141>(send);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {      // partner: lane ^ 2
+        const float keep = h1 ? b[4 + j] : b[j], send = h1 ? b[j] : b[4 + j];
+        c[j] = keep + dpp_mov<0x4E>(send);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {      // partner: lane ^ 1
+        const float keep = h0 ? c[2 + j] : c[j], send = h0 ? c[j] : c[2 + j];
+        d[j] = keep + dpp_mov<0xB1>(send);
+    }
+    const float keep = h4 ? d[1] : d[0], send = h4 ? d[0] : d[1];
+    const float e = keep + __shfl_xor(send, 16, 64);
+    return e + __shfl_xor(e, 32, 64);
+}
+
+__device__ __forceinline__ int scatter32_index(int lane) {
+    return 16 * ((lane >> 3) & 1) + 8 * ((lane >> 2) & 1) + 4 * ((lane >> 1) & 1) +
+           2 * (lane & 1) + ((lane >> 4) & 1);
+}
+
 // Brick of the adjoint pass: 8x8x8 voxels, two per thread; LDS box with a
 // halo of HALO voxels on every side for the g_ref scatter.  Views are taken
 // in chunks of at most VCH per launch.
@@ -266,6 +305,9 @@ __device__ __forceinline__ void warp_combine_bwd_brick(
                                                 go * w0[a] * w1[b] * w2[c]);
                 }
             }
+            // dL/dE: per voxel over views; dL/dw[v]: per-lane products, then
+            // reduce-scattered over the wave in groups of 32 coefficients
+            float pc[NC];
 #pragma unroll
             for (int l = 0; l < L; ++l)
 #pragma unroll
@@ -275,10 +317,18 @@ __device__ __forceinline__ void warp_combine_bwd_brick(
                         const float c = cv[(l * B + b) * 3 + k];
                         G[0][l][b][k] = fmaf(c, gD[0][k], G[0][l][b][k]);
                         G[1][l][b][k] = fmaf(c, gD[1][k], G[1][l][b][k]);
-                        const float t = wave_sum_lane63(
-                            fmaf(gD[0][k], sv[0][l][b][k], gD[1][k] * sv[1][l][b][k]));
-                        if (lane == 63) atomicAdd(&cacc[v * NC + (l * B + b) * 3 + k], t);
+                        pc[(l * B + b) * 3 + k] =
+                            fmaf(gD[0][k], sv[0][l][b][k], gD[1][k] * sv[1][l][b][k]);
                     }
+#pragma unroll
+            for (int g0 = 0; g0 < NC; g0 += 32) {
+                float x[32];
+#pragma unroll
+                for (int q = 0; q < 32; ++q) x[q] = g0 + q < NC ? pc[g0 + q] : 0.0f;
+                const float tot = wave_reduce_scatter32(x, lane);
+                const int ci = g0 + scatter32_index(lane);
+                if (lane < 32 && ci < NC) atomicAdd(&cacc[v * NC + ci], tot);
+            }
         }
         __syncthreads();
         if (scale > 0.0f) {
