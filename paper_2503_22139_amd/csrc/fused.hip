@@ -38,6 +38,36 @@ struct CWTab {
     int n;
 };
 
+// Trilinear read of a y-paired volume (element (i, j, k) holds V[i][j][k] and
+// V[i][j+1][k]): two 16-byte loads, the same blend in the same order as
+// sample_u, 0 outside the box.
+__device__ __forceinline__ float sample_u_paired(const float *__restrict__ vp, const int n[3],
+                                                 float u0, float u1, float u2) {
+    int i0, i1, i2;
+    float f0, f1, f2;
+    if (!axis_cell(u0, n[0], i0, f0) || !axis_cell(u1, n[1], i1, f1) ||
+        !axis_cell(u2, n[2], i2, f2))
+        return 0.0f;
+    const float *pa = vp + 2 * ((i0 * n[1] + i1) * n[2] + i2);
+    const float *pd = pa + 2 * n[1] * n[2];
+    const float a0 = pa[0], a1 = pa[1], a2 = pa[2], a3 = pa[3];
+    const float d0 = pd[0], d1 = pd[1], d2 = pd[2], d3 = pd[3];
+    const float c00 = lerp1(a0, a2, f2), c01 = lerp1(a1, a3, f2);
+    const float c10 = lerp1(d0, d2, f2), c11 = lerp1(d1, d3, f2);
+    return lerp1(lerp1(c00, c01, f1), lerp1(c10, c11, f1), f0);
+}
+
+// y-paired copy of a volume: out[2j] = V[j], out[2j+1] = V[j + n2] (0 on the
+// last row, which no trilinear read takes).
+__global__ __launch_bounds__(256) void k_pair_volume(const float *__restrict__ in, GridK g,
+                                                     float2 *__restrict__ out) {
+    const int64_t N = grid_size(g);
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    const int iy = (int)((j / g.n[2]) % g.n[1]);
+    out[j] = make_float2(in[j], iy + 1 < g.n[1] ? in[j + g.n[2]] : 0.0f);
+}
+
 // Body of one voxel; the restrict-qualified parameters (kept through
 // inlining) let the per-view coefficients come through scalar loads.  With
 // PAIRED the warped volumes are written in the y-paired layout the
@@ -66,9 +96,10 @@ __device__ __forceinline__ void combine_warp_voxel(const float *__restrict__ ref
                 for (int b = 0; b < B; ++b) t = fmaf(cv[(l * B + b) * 3 + k], sv[l][b][k], t);
             d[k] = t;
         }
-        const float val =
-            sample_u(ref, g.n, fmaf(d[0], g.inv_h[0], (float)ix), fmaf(d[1], g.inv_h[1], (float)iy),
-                     fmaf(d[2], g.inv_h[2], (float)iz));
+        const float u0 = fmaf(d[0], g.inv_h[0], (float)ix), u1 = fmaf(d[1], g.inv_h[1], (float)iy),
+                    u2 = fmaf(d[2], g.inv_h[2], (float)iz);
+        // with PAIRED, ref is the y-paired copy of the reference volume
+        const float val = PAIRED ? sample_u_paired(ref, g.n, u0, u1, u2) : sample_u(ref, g.n, u0, u1, u2);
         if (PAIRED) {
             // y-paired layout: this voxel is the first of its own pair and the
             // second of the pair that starts one row below
@@ -421,10 +452,14 @@ static bool use_paired(const GridK &g) {
            2 * (int64_t)g.n[1] * g.n[2] < ((int64_t)1 << 24);
 }
 
+// Workspace: the warped volumes (y-paired when possible), then the y-paired
+// copy of the reference volume.
 size_t warp_project_workspace(const LevelsK &lv, int V, const GridK &g, const pmf_cone_t &c) {
     (void)lv;
     (void)c;
-    return align256(sizeof(float) * (size_t)grid_size(g) * (size_t)V * (use_paired(g) ? 2 : 1));
+    const size_t N = (size_t)grid_size(g);
+    return use_paired(g) ? align256(sizeof(float) * N * V * 2) + align256(sizeof(float) * N * 2)
+                         : align256(sizeof(float) * N * V);
 }
 
 // Forward of the motion path for a ragged batch: one combine+warp launch and
@@ -443,6 +478,17 @@ hipError_t launch_warp_project_jobs(const WPJob *jobs, int n, hipStream_t s) {
         const int64_t N = grid_size(j.g);
         CWK &c = t.s[k];
         c.ref = j.ref;
+        if (paired) {
+            // y-paired copy of the reference volume after the warped volumes
+            float2 *rp = (float2 *)((char *)j.ws + align256(sizeof(float) * (size_t)N * j.V * 2));
+            {
+                ProfScope prof_("pair_volume", s);
+                k_pair_volume<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(j.ref, j.g, rp);
+            }
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            c.ref = (const float *)rp;
+        }
         c.g = j.g;
         c.lv = j.lv;
         c.coeff = j.coeff;
