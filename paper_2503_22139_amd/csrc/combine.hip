@@ -193,6 +193,75 @@ __global__ __launch_bounds__(256) void k_adj_pass(Shape4 in_s, int ax, int nc, f
     out[t] = acc;
 }
 
+// The same transpose, one thread per line along `ax`: the thread walks the
+// line's nf input values in order, each split between its two level cells
+// (weights 1 - f and f, as the forward reads them), and emits the nc outputs
+// in order (a cell is complete once the walk has passed it).  Every input
+// value is read and weighted once.
+__global__ __launch_bounds__(256) void k_adj_line(Shape4 in_s, int ax, int nc, float scale,
+                                                  float off, const float *__restrict__ in,
+                                                  AdjSrc src, float *__restrict__ out) {
+    // lines: all index tuples of (c, d0, d1, d2) with the ax index fixed to 0
+    int ld[3] = {in_s.d[0], in_s.d[1], in_s.d[2]};
+    ld[ax] = 1;
+    const int64_t nlines = (int64_t)in_s.c * ld[0] * ld[1] * ld[2];
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nlines) return;
+    int idx[3];
+    int64_t r = t;
+    idx[2] = (int)(r % ld[2]);
+    r /= ld[2];
+    idx[1] = (int)(r % ld[1]);
+    r /= ld[1];
+    idx[0] = (int)(r % ld[0]);
+    const int c = (int)(r / ld[0]);
+    const int nf = in_s.d[ax];
+    // input strides and base (channel-major [c][d0][d1][d2])
+    const int64_t ist = ax == 2 ? 1 : (ax == 1 ? in_s.d[2] : (int64_t)in_s.d[1] * in_s.d[2]);
+    const int64_t ibase = ((int64_t)idx[0] * in_s.d[1] + idx[1]) * in_s.d[2] + idx[2];
+    const int64_t cbase = (int64_t)c * in_s.d[0] * in_s.d[1] * in_s.d[2];
+    // output shape: ax dimension nc
+    int od[3] = {in_s.d[0], in_s.d[1], in_s.d[2]};
+    od[ax] = nc;
+    const int64_t ost = ax == 2 ? 1 : (ax == 1 ? od[2] : (int64_t)od[1] * od[2]);
+    const int64_t obase = (((int64_t)c * od[0] + idx[0]) * od[1] + idx[1]) * od[2] + idx[2];
+    int next = 0;           // first output not yet written
+    int cur = -1;           // cell of the pending pair (cur, cur + 1)
+    float a0 = 0.0f, a1 = 0.0f;
+    for (int j = 0; j < nf; ++j) {
+        int i;
+        float f;
+        if (!axis_cell(fmaf((float)j, scale, off), nc, i, f)) continue;
+        if (i != cur) {
+            // cells below i are complete: write them (zeros for cells no value reached)
+            if (cur >= 0) {
+                out[obase + (int64_t)cur * ost] = a0;
+                next = cur + 1;
+                a0 = (cur + 1 == i) ? a1 : 0.0f;
+                if (cur + 1 < i) {
+                    out[obase + (int64_t)(cur + 1) * ost] = a1;
+                    next = cur + 2;
+                }
+            } else {
+                a0 = 0.0f;
+            }
+            for (; next < i; ++next) out[obase + (int64_t)next * ost] = 0.0f;
+            a1 = 0.0f;
+            cur = i;
+        }
+        const float x = in ? in[cbase + ibase + (int64_t)j * ist]
+                           : adj_src(src, c, ibase + (int64_t)j * ist);
+        a0 = fmaf(1.0f - f, x, a0);
+        a1 = fmaf(f, x, a1);
+    }
+    if (cur >= 0) {
+        out[obase + (int64_t)cur * ost] = a0;
+        out[obase + (int64_t)(cur + 1) * ost] = a1;
+        next = cur + 2;
+    }
+    for (; next < nc; ++next) out[obase + (int64_t)next * ost] = 0.0f;
+}
+
 // Level grid equals the output grid: the source is the answer.
 __global__ __launch_bounds__(256) void k_adj_copy(int C, int64_t N, AdjSrc src,
                                                   float *__restrict__ out) {
@@ -263,11 +332,11 @@ hipError_t launch_upsample_adjoint(const LevelsK &lv, int l, const GridK &lvl_gr
         float *dst = (p == np - 1) ? g_base : (p == 0 ? bufA : bufB);
         Shape4 os = sh;
         os.d[ax] = m.n[ax];
-        const int64_t tot = (int64_t)os.c * os.d[0] * os.d[1] * os.d[2];
+        const int64_t lines = (int64_t)sh.c * sh.d[0] * sh.d[1] * sh.d[2] / sh.d[ax];
         {
             ProfScope prof_("upsample_adjoint", s);
-            k_adj_pass<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(sh, ax, m.n[ax], m.scale[ax],
-                                                                     m.off[ax], in, src, dst);
+            k_adj_line<<<(unsigned)((lines + 255) / 256), 256, 0, s>>>(sh, ax, m.n[ax], m.scale[ax],
+                                                                       m.off[ax], in, src, dst);
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
