@@ -114,9 +114,10 @@ __device__ __forceinline__ void combine_warp_voxel(const float *__restrict__ ref
 
 template <int L, int B, bool PAIRED>
 __global__ __launch_bounds__(256) void k_combine_warp(CWTab t) {
-    const int job = job_of(t, (int)blockIdx.x);
+    const int wg = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int job = job_of(t, wg);
     const CWK &cj = t.s[job];
-    const int64_t j = (int64_t)((int)blockIdx.x - t.first[job]) * blockDim.x + threadIdx.x;
+    const int64_t j = (int64_t)(wg - t.first[job]) * blockDim.x + threadIdx.x;
     combine_warp_voxel<L, B, PAIRED>(cj.ref, cj.g, cj.lv, cj.coeff, cj.V, cj.warped, j);
 }
 
@@ -396,11 +397,12 @@ __device__ __forceinline__ void warp_combine_bwd_brick(
 
 template <int L, int B>
 __global__ __launch_bounds__(256) void k_warp_combine_bwd(WCTab t) {
-    const int job = job_of(t, (int)blockIdx.x);
+    const int wg = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int job = job_of(t, wg);
     const WCK &wj = t.s[job];
     warp_combine_bwd_brick<L, B>(wj.ref, wj.g, wj.lv, wj.coeff, wj.V, wj.g_I, wj.vmax, wj.g_ref,
                                  wj.stage, wj.gout, wj.accumulate, wj.nb1, wj.nb2, wj.partial,
-                                 (int)blockIdx.x - t.first[job]);
+                                 wg - t.first[job]);
 }
 
 // g_ref[p] += sum of the staged boxes that cover voxel p (at most 2 bricks

@@ -122,6 +122,15 @@ __device__ __forceinline__ float wave_sum_lane63(float v) {
 // workgroup.
 constexpr int MAXS = 4;
 #ifdef __HIPCC__
+// Workgroup b of a G-workgroup launch runs on XCD b % 8 (the dispatcher deals
+// workgroups round-robin over the 8 XCDs, each with its own L2).  The
+// returned index gives each XCD one contiguous range of work items, so items
+// that share cache lines (neighbouring bricks or tiles) share an L2.
+__device__ __forceinline__ int xcd_block(int b, int G) {
+    const int k = b & 7, q = G >> 3, r = G & 7;
+    return k * q + (k < r ? k : r) + (b >> 3);
+}
+
 // index of the table entry that owns workgroup b (first[] is non-decreasing)
 template <class Tab>
 __device__ __forceinline__ int job_of(const Tab &t, int b) {

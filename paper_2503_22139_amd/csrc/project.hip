@@ -193,12 +193,16 @@ template <int WU, int WV, int AU, bool PAIRED>
 __global__ __launch_bounds__(256) void k_project(ProjTab t) {
     static_assert(WU * WV == 64 && AU >= 1 && 4 % AU == 0, "wave tile must hold 64 pixels");
     constexpr int BU = WU * AU, BV = WV * (4 / AU);
-    const int job = job_of(t, (int)blockIdx.x);
+    // each XCD takes one contiguous range of (view, tile) items: whole views
+    // and neighbouring tiles share an L2 (measured faster than sharing each
+    // view across all XCDs)
+    const int wg = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int job = job_of(t, wg);
     const ProjK &pj = t.s[job];
     const GridK &g = pj.g;
     const ConeK &c = pj.c;
     const MarchK &mk = pj.mk;
-    const int local = (int)blockIdx.x - t.first[job];
+    const int local = wg - t.first[job];
     const int v = local / pj.ntiles, tile = local - v * pj.ntiles;
     const int tu = tile % pj.tiles_u, tv = tile / pj.tiles_u;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -402,7 +406,9 @@ __global__ __launch_bounds__(64 * W) void k_project_bwd(BwdTab t) {
     __shared__ int acc[NP];
     __shared__ RunP runs[W][64];
     __shared__ int ends[W][64];
-    const int job = job_of(t, (int)blockIdx.x);
+    // each XCD takes one contiguous range of (view, brick) items
+    const int wg = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int job = job_of(t, wg);
     const BwdK &bj = t.s[job];
     const GridK &g = bj.g;
     const ConeK &c = bj.c;
@@ -412,7 +418,7 @@ __global__ __launch_bounds__(64 * W) void k_project_bwd(BwdTab t) {
     const RayK *__restrict__ rays = bj.rays;
     const int V = bj.V;
     const int nb1 = bj.nb1, nb2 = bj.nb2;
-    const int local = (int)blockIdx.x - t.first[job];
+    const int local = wg - t.first[job];
     const int view = SUM ? 0 : local / bj.nbricks;
     const int bid = SUM ? local : local - view * bj.nbricks;
     const int b2 = bid % nb2, b1 = (bid / nb2) % nb1, b0 = bid / (nb2 * nb1);
