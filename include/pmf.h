@@ -222,9 +222,9 @@ size_t pmf_profile_names(char *buf, size_t len);
  *                              7 = 1x64 in 2x128, 8 = 2x32 in 2x128;
  *   PMF_TUNE_BACKPROJECT_BRICK voxel brick of the adjoint projection (axes
  *                              0 x 1 x 2) and the wavefronts sharing it:
- *                              0 = 16x16x16 x 8 (default), 1 = 16x16x16 x 4,
+ *                              0 = 16x16x16 x 8, 1 = 16x16x16 x 4,
  *                              2 = 32x32x4 x 8, 3 = 32x32x8 x 8,
- *                              4 = 24x24x8 x 8, 5 = 8x8x8 x 4.
+ *                              4 = 24x24x8 x 8 (default), 5 = 8x8x8 x 4.
  * pmf_tune_candidates returns the number of choices of a knob (0 for an
  * unknown knob); pmf_tune_set returns the previous choice or PMF_EINVAL for an
  * unknown knob or a choice out of range; pmf_tune_get returns the current
