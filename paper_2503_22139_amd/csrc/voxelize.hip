@@ -215,6 +215,52 @@ __device__ __forceinline__ void splat_box(const GaussK &p, const GridK &g, float
     }
 }
 
+// The same voxels as splat_box, visited by (x, y) column: each lane takes a
+// column and walks only the z range where the ellipsoid can be, from the
+// roots of the quadratic in d2 widened by one voxel on each side; every voxel
+// visited is still tested with quad() exactly as above, so the voxels added
+// and their order within a column are unchanged.  Columns whose quadratic
+// stays clearly above k2 are skipped.  Untruncated sets walk the whole box.
+template <typename Add>
+__device__ __forceinline__ void splat_cols(const GaussK &p, const GridK &g, float k2, int lo0,
+                                           int lo1, int lo2, int hi0, int hi1, int hi2, Add add) {
+    const int lane = threadIdx.x & 63;
+    const int ny = hi1 - lo1 + 1;
+    const int ncol = (hi0 - lo0 + 1) * ny;
+    const bool untrunc = isinf(k2);
+    const float inv_h2 = g.inv_h[2];
+    for (int c0 = 0; c0 < ncol; c0 += 64) {
+        const int col = c0 + lane;
+        if (col >= ncol) continue;
+        const int ix = lo0 + col / ny, iy = lo1 + col % ny;
+        const float d0 = fmaf((float)ix, g.h[0], g.c0[0]) - p.mu[0];
+        const float d1 = fmaf((float)iy, g.h[1], g.c0[1]) - p.mu[1];
+        int za = lo2, zb = hi2;
+        if (!untrunc) {
+            // quad(d0, d1, d2) = a22 d2^2 + 2 bh d2 + cq
+            const float bh = fmaf(p.a02, d0, p.a12 * d1);
+            const float cq = fmaf(p.a00 * d0, d0, fmaf(2.0f * p.a01 * d0, d1, p.a11 * d1 * d1));
+            float disc = fmaf(bh, bh, -p.a22 * (cq - k2));
+            const float tol = 1e-4f * (fmaf(bh, bh, p.a22 * (fabsf(cq) + k2)));
+            if (disc < -tol) continue;
+            disc = fmaxf(disc, 0.0f);
+            const float r = sqrtf(disc), inv_a = 1.0f / p.a22;
+            // d2 range -> voxel index range: iz = (mu2 + d2 - c0_2) / h2
+            const float zc = (p.mu[2] - g.c0[2]) * inv_h2;
+            const float t_lo = zc + (-bh - r) * inv_a * inv_h2;
+            const float t_hi = zc + (-bh + r) * inv_a * inv_h2;
+            za = max(za, (int)floorf(t_lo) - 1);
+            zb = min(zb, (int)ceilf(t_hi) + 1);
+        }
+        for (int iz = za; iz <= zb; ++iz) {
+            const float d2 = fmaf((float)iz, g.h[2], g.c0[2]) - p.mu[2];
+            const float mm = quad(p, d0, d1, d2);
+            if (!(mm <= k2)) continue;
+            add(ix, iy, iz, __expf(-0.5f * mm));
+        }
+    }
+}
+
 // One workgroup per tile.  Accumulation is in 32-bit fixed point with
 // integer LDS atomics (float LDS atomics are far slower on gfx950): per
 // channel the scale is 2^30 / S with S = sum of |value| over the tile's
@@ -262,7 +308,7 @@ __global__ __launch_bounds__(256) void k_vox_tile(const GaussK *__restrict__ rec
         const int hi0 = min(p.hi0, e0), hi1 = min(p.hi1, e1), hi2 = min(p.hi2, e2);
         if (lo0 > hi0 || lo1 > hi1 || lo2 > hi2) continue;
         const float *vv = value + (int64_t)gi * C;
-        splat_box(p, g, k2, lo0, lo1, lo2, hi0, hi1, hi2, [&](int ix, int iy, int iz, float ev) {
+        splat_cols(p, g, k2, lo0, lo1, lo2, hi0, hi1, hi2, [&](int ix, int iy, int iz, float ev) {
             const int li = ((ix - b0) * T1 + (iy - b1)) * T2 + (iz - b2);
             for (int c = 0; c < C; ++c)
                 atomicAdd(&acc[c * tvox + li], __float2int_rn(vv[c] * scale[c] * ev));
@@ -298,7 +344,7 @@ __global__ __launch_bounds__(256) void k_vox_large(const GaussK *__restrict__ re
         const GaussK p = rec[gi];
         if (p.lo0 > p.hi0 || p.lo1 > p.hi1 || p.lo2 > p.hi2) continue;
         const float *vv = value + (int64_t)gi * C;
-        splat_box(p, g, k2, p.lo0, p.lo1, p.lo2, p.hi0, p.hi1, p.hi2,
+        splat_cols(p, g, k2, p.lo0, p.lo1, p.lo2, p.hi0, p.hi1, p.hi2,
                   [&](int ix, int iy, int iz, float ev) {
                       const int64_t j = ((int64_t)ix * g.n[1] + iy) * g.n[2] + iz;
                       for (int c = 0; c < C; ++c) unsafeAtomicAdd(&vol[c * N + j], vv[c] * ev);
@@ -437,7 +483,7 @@ __global__ __launch_bounds__(256) void k_vox_bwd(pmf_gauss_t gs, GridK g, float 
     float M00 = 0, M01 = 0, M02 = 0, M11 = 0, M12 = 0, M22 = 0;
     const int64_t N = grid_size(g);
     if (G.lo[0] <= G.hi[0] && G.lo[1] <= G.hi[1] && G.lo[2] <= G.hi[2]) {
-        splat_box(p, g, k2, G.lo[0], G.lo[1], G.lo[2], G.hi[0], G.hi[1], G.hi[2],
+        splat_cols(p, g, k2, G.lo[0], G.lo[1], G.lo[2], G.hi[0], G.hi[1], G.hi[2],
                   [&](int ix, int iy, int iz, float ev) {
                       const int64_t j = ((int64_t)ix * g.n[1] + iy) * g.n[2] + iz;
                       float Gj = 0.0f;
