@@ -54,20 +54,45 @@ class MotionModel:
         self.V = int(self.angles.numel())
 
     # ------------------------------------------------------------ volumes
+    def _side_streams(self):
+        """One stream per MBC level (default priority), created on first use:
+        the levels' voxelizations and adjoints run beside the reference's."""
+        if getattr(self, "_streams", None) is None:
+            self._streams = [torch.cuda.Stream(device=self.device) for _ in self.mbc]
+        return self._streams
+
     def volumes(self):
+        cur = torch.cuda.current_stream(self.device)
+        side = self._side_streams()
+        bases = [None] * len(self.mbc)
+        for s_, g, lg, l in zip(side, self.mbc, self.levels, range(len(self.mbc))):
+            s_.wait_stream(cur)
+            with torch.cuda.stream(s_):
+                bases[l] = ops.pmf_voxelize(g.mean, g.scale, g.quat, g.value, lg, self.k)
         ref = ops.pmf_voxelize(self.ref.mean, self.ref.scale, self.ref.quat, self.ref.value,
                                self.grid, self.k)[0]
-        bases = [ops.pmf_voxelize(g.mean, g.scale, g.quat, g.value, lg, self.k)
-                 for g, lg in zip(self.mbc, self.levels)]
+        for s_, b in zip(side, bases):
+            cur.wait_stream(s_)
+            b.record_stream(cur)
         return ref, bases
 
     def volumes_bwd(self, g_ref, g_bases) -> Dict[str, object]:
+        cur = torch.cuda.current_stream(self.device)
+        side = self._side_streams()
+        mbc = [None] * len(self.mbc)
+        for s_, g, lg, gb, l in zip(side, self.mbc, self.levels, g_bases, range(len(self.mbc))):
+            s_.wait_stream(cur)
+            with torch.cuda.stream(s_):
+                mbc[l] = ops.pmf_voxelize_bwd(g.mean, g.scale, g.quat, g.value, lg, self.k, gb)
+            gb.record_stream(s_)
         r = ops.pmf_voxelize_bwd(self.ref.mean, self.ref.scale, self.ref.quat, self.ref.value,
                                  self.grid, self.k, g_ref.reshape(1, -1))
         out = {"ref": dict(zip(("mean", "scale", "quat", "value"), r)), "mbc": []}
-        for g, lg, gb in zip(self.mbc, self.levels, g_bases):
-            r = ops.pmf_voxelize_bwd(g.mean, g.scale, g.quat, g.value, lg, self.k, gb)
-            out["mbc"].append(dict(zip(("mean", "scale", "quat", "value"), r)))
+        for s_, grads in zip(side, mbc):
+            cur.wait_stream(s_)
+            for t in grads:
+                t.record_stream(cur)
+            out["mbc"].append(dict(zip(("mean", "scale", "quat", "value"), grads)))
         return out
 
     # ------------------------------------------------------------ forward

@@ -172,8 +172,9 @@ _ws_cache = {}
 
 
 def workspace(nbytes: int, device) -> torch.Tensor:
-    """A reusable device scratch buffer of at least nbytes (grown on demand)."""
-    key = (str(device),)
+    """A reusable device scratch buffer of at least nbytes (grown on demand),
+    one per device and stream, so calls on different streams never share it."""
+    key = (str(device), torch.cuda.current_stream(device).cuda_stream)
     buf = _ws_cache.get(key)
     if buf is None or buf.numel() < nbytes:
         buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
