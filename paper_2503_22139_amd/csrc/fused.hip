@@ -31,6 +31,7 @@ struct CWK {
     const float *coeff;
     int V;
     float *warped;
+    int items;              // workgroups of 256 voxels
 };
 struct CWTab {
     CWK s[MAXS];
@@ -114,10 +115,11 @@ __device__ __forceinline__ void combine_warp_voxel(const float *__restrict__ ref
 
 template <int L, int B, bool PAIRED>
 __global__ __launch_bounds__(256) void k_combine_warp(CWTab t) {
-    const int wg = xcd_block((int)blockIdx.x, (int)gridDim.x);
-    const int job = job_of(t, wg);
+    const int job = job_of(t, (int)blockIdx.x);
     const CWK &cj = t.s[job];
-    const int64_t j = (int64_t)(wg - t.first[job]) * blockDim.x + threadIdx.x;
+    const int item = job_item(t, job, (int)blockIdx.x);
+    if (item >= cj.items) return;
+    const int64_t j = (int64_t)item * blockDim.x + threadIdx.x;
     combine_warp_voxel<L, B, PAIRED>(cj.ref, cj.g, cj.lv, cj.coeff, cj.V, cj.warped, j);
 }
 
@@ -199,6 +201,7 @@ struct WCK {
     int accumulate;
     int nb1, nb2;
     float *partial;
+    int items;              // bricks
 };
 struct WCTab {
     WCK s[MAXS];
@@ -397,12 +400,13 @@ __device__ __forceinline__ void warp_combine_bwd_brick(
 
 template <int L, int B>
 __global__ __launch_bounds__(256) void k_warp_combine_bwd(WCTab t) {
-    const int wg = xcd_block((int)blockIdx.x, (int)gridDim.x);
-    const int job = job_of(t, wg);
+    const int job = job_of(t, (int)blockIdx.x);
     const WCK &wj = t.s[job];
+    const int item = job_item(t, job, (int)blockIdx.x);
+    if (item >= wj.items) return;
     warp_combine_bwd_brick<L, B>(wj.ref, wj.g, wj.lv, wj.coeff, wj.V, wj.g_I, wj.vmax, wj.g_ref,
                                  wj.stage, wj.gout, wj.accumulate, wj.nb1, wj.nb2, wj.partial,
-                                 wg - t.first[job]);
+                                 item);
 }
 
 // g_ref[p] += sum of the staged boxes that cover voxel p (at most 2 bricks
@@ -496,7 +500,8 @@ hipError_t launch_warp_project_jobs(const WPJob *jobs, int n, hipStream_t s) {
         c.coeff = j.coeff;
         c.V = j.V;
         c.warped = (float *)j.ws;
-        t.first[k + 1] = t.first[k] + (int)((N + 255) / 256);
+        c.items = (int)((N + 255) / 256);
+        t.first[k + 1] = t.first[k] + align8(c.items);
         pj[k] = ProjJob{c.warped, paired ? 2 * N : N, j.g, j.c, j.angles, j.V, j.proj, paired};
     }
     for (int k = n + 1; k <= MAXS; ++k) t.first[k] = t.first[n];
@@ -666,7 +671,8 @@ hipError_t launch_warp_project_bwd_jobs(const WPBJob *jobs, int n, hipStream_t s
             w.nb1 = sc[k].lay.nb[1];
             w.nb2 = sc[k].lay.nb[2];
             w.partial = sc[k].partial;
-            t.first[t.n + 1] = t.first[t.n] + sc[k].lay.nbrick;
+            w.items = sc[k].lay.nbrick;
+            t.first[t.n + 1] = t.first[t.n] + align8(w.items);
             idx[t.n] = k;
             vcs[t.n] = vc;
             if (vc > vc_max) vc_max = vc;

@@ -131,6 +131,16 @@ __device__ __forceinline__ int xcd_block(int b, int G) {
     return k * q + (k < r ? k : r) + (b >> 3);
 }
 
+// Item handled by workgroup b of table entry `job`.  Each entry's workgroup
+// range starts at a multiple of 8 and has a multiple-of-8 length, so within
+// it the XCD of a workgroup is (b - first) % 8 and xcd_block gives every XCD
+// an equal, contiguous share of the entry's items; items past the entry's
+// count (the padding) are left to the caller to skip.
+template <class Tab>
+__device__ __forceinline__ int job_item(const Tab &t, int job, int b) {
+    return xcd_block(b - t.first[job], t.first[job + 1] - t.first[job]);
+}
+
 // index of the table entry that owns workgroup b (first[] is non-decreasing)
 template <class Tab>
 __device__ __forceinline__ int job_of(const Tab &t, int b) {
@@ -364,5 +374,6 @@ hipError_t launch_warp_project_bwd(const float *ref, const GridK &g, const Level
                                    hipStream_t s);
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+inline int align8(int x) { return (x + 7) & ~7; }
 
 }  // namespace pmf

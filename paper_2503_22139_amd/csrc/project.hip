@@ -182,6 +182,7 @@ struct ProjK {
     const float *angles;
     float *proj;
     int tiles_u, ntiles;
+    int items;              // ntiles * V
 };
 struct ProjTab {
     ProjK s[MAXS];
@@ -193,16 +194,17 @@ template <int WU, int WV, int AU, bool PAIRED>
 __global__ __launch_bounds__(256) void k_project(ProjTab t) {
     static_assert(WU * WV == 64 && AU >= 1 && 4 % AU == 0, "wave tile must hold 64 pixels");
     constexpr int BU = WU * AU, BV = WV * (4 / AU);
-    // each XCD takes one contiguous range of (view, tile) items: whole views
-    // and neighbouring tiles share an L2 (measured faster than sharing each
-    // view across all XCDs)
-    const int wg = xcd_block((int)blockIdx.x, (int)gridDim.x);
-    const int job = job_of(t, wg);
+    // within each scan, each XCD takes one contiguous range of its (view,
+    // tile) items: whole views and neighbouring tiles share an L2 (measured
+    // faster than sharing each view across all XCDs), and every XCD gets an
+    // equal share of every scan
+    const int job = job_of(t, (int)blockIdx.x);
     const ProjK &pj = t.s[job];
+    const int local = job_item(t, job, (int)blockIdx.x);
+    if (local >= pj.items) return;
     const GridK &g = pj.g;
     const ConeK &c = pj.c;
     const MarchK &mk = pj.mk;
-    const int local = wg - t.first[job];
     const int v = local / pj.ntiles, tile = local - v * pj.ntiles;
     const int tu = tile % pj.tiles_u, tv = tile / pj.tiles_u;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -384,6 +386,7 @@ struct BwdK {
     float *g_vol;
     int64_t stride;
     int nb1, nb2, nbricks;
+    int items;              // nbricks * V, or nbricks when summing over views
     BoundK kb;
     MarchK mk;
     unsigned *vmax;
@@ -406,10 +409,12 @@ __global__ __launch_bounds__(64 * W) void k_project_bwd(BwdTab t) {
     __shared__ int acc[NP];
     __shared__ RunP runs[W][64];
     __shared__ int ends[W][64];
-    // each XCD takes one contiguous range of (view, brick) items
-    const int wg = xcd_block((int)blockIdx.x, (int)gridDim.x);
-    const int job = job_of(t, wg);
+    // within each scan, each XCD takes one contiguous range of its (view,
+    // brick) items
+    const int job = job_of(t, (int)blockIdx.x);
     const BwdK &bj = t.s[job];
+    const int local = job_item(t, job, (int)blockIdx.x);
+    if (local >= bj.items) return;
     const GridK &g = bj.g;
     const ConeK &c = bj.c;
     const BoundK &kb = bj.kb;
@@ -418,7 +423,6 @@ __global__ __launch_bounds__(64 * W) void k_project_bwd(BwdTab t) {
     const RayK *__restrict__ rays = bj.rays;
     const int V = bj.V;
     const int nb1 = bj.nb1, nb2 = bj.nb2;
-    const int local = wg - t.first[job];
     const int view = SUM ? 0 : local / bj.nbricks;
     const int bid = SUM ? local : local - view * bj.nbricks;
     const int b2 = bid % nb2, b1 = (bid / nb2) % nb1, b0 = bid / (nb2 * nb1);
@@ -711,7 +715,8 @@ static void project_tiled(const ProjJob *jobs, int n, hipStream_t s) {
         p.proj = j.proj;
         p.tiles_u = (j.c.nu + BU - 1) / BU;
         p.ntiles = p.tiles_u * ((j.c.nv + BV - 1) / BV);
-        t.first[k + 1] = t.first[k] + p.ntiles * j.V;
+        p.items = p.ntiles * j.V;
+        t.first[k + 1] = t.first[k] + align8(p.items);
     }
     for (int k = n + 1; k <= MAXS; ++k) t.first[k] = t.first[n];
     if (t.first[n] == 0) return;
@@ -791,10 +796,11 @@ static hipError_t project_bwd_bricks(const BwdJob *jobs, int n, hipStream_t s) {
         b.nb1 = nb[1];
         b.nb2 = nb[2];
         b.nbricks = nb[0] * nb[1] * nb[2];
+        b.items = b.nbricks * (sum_views ? 1 : j.V);
         b.kb = make_bound(j.g, j.c);
         b.mk = make_march(j.g);
         b.vmax = j.vmax;
-        t.first[k + 1] = t.first[k] + b.nbricks * (sum_views ? 1 : j.V);
+        t.first[k + 1] = t.first[k] + align8(b.items);
     }
     for (int k = n + 1; k <= MAXS; ++k) t.first[k] = t.first[n];
     {
