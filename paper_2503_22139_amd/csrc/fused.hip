@@ -157,6 +157,36 @@ __device__ __forceinline__ float wave_reduce_scatter32(const float (&x)[32], int
     return e + __shfl_xor(e, 32, 64);
 }
 
+// The same for 16 values: the total of value 8*b3 + 4*b2 + 2*b1 + b0 (in
+// every lane whose low four bits give that index).
+__device__ __forceinline__ float wave_reduce_scatter16(const float (&x)[16], int lane) {
+    const bool h3 = lane & 8, h2 = lane & 4, h1 = lane & 2, h0 = lane & 1;
+    float b[8], c[4], d[2];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {      // partner: row_mirror (lane ^ 15 within 16)
+        const float keep = h3 ? x[8 + j] : x[j], send = h3 ? x[j] : x[8 + j];
+        b[j] = keep + dpp_mov<0x140>(send);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {      // partner: row_half_mirror (lane ^ 7 within 8)
+        const float keep = h2 ? b[4 + j] : b[j], send = h2 ? b[j] : b[4 + j];
+        c[j] = keep + dpp_mov<0x141>(send);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {      // partner: lane ^ 2
+        const float keep = h1 ? c[2 + j] : c[j], send = h1 ? c[j] : c[2 + j];
+        d[j] = keep + dpp_mov<0x4E>(send);
+    }
+    const float keep = h0 ? d[1] : d[0], send = h0 ? d[0] : d[1];
+    float e = keep + dpp_mov<0xB1>(send);  // partner: lane ^ 1
+    e += __shfl_xor(e, 16, 64);
+    return e + __shfl_xor(e, 32, 64);
+}
+
+__device__ __forceinline__ int scatter16_index(int lane) {
+    return 8 * ((lane >> 3) & 1) + 4 * ((lane >> 2) & 1) + 2 * ((lane >> 1) & 1) + (lane & 1);
+}
+
 __device__ __forceinline__ int scatter32_index(int lane) {
     return 16 * ((lane >> 3) & 1) + 8 * ((lane >> 2) & 1) + 4 * ((lane >> 1) & 1) +
            2 * (lane & 1) + ((lane >> 4) & 1);
@@ -340,9 +370,8 @@ __device__ __forceinline__ void warp_combine_bwd_brick(
                                                 go * w0[a] * w1[b] * w2[c]);
                 }
             }
-            // dL/dE: per voxel over views; dL/dw[v]: per-lane products, then
-            // reduce-scattered over the wave in groups of 32 coefficients
-            float pc[NC];
+            // dL/dE: per voxel over views; dL/dw[v]: per-lane products,
+            // reduce-scattered over the wave in groups of 16 coefficients
 #pragma unroll
             for (int l = 0; l < L; ++l)
 #pragma unroll
@@ -352,17 +381,21 @@ __device__ __forceinline__ void warp_combine_bwd_brick(
                         const float c = cv[(l * B + b) * 3 + k];
                         G[0][l][b][k] = fmaf(c, gD[0][k], G[0][l][b][k]);
                         G[1][l][b][k] = fmaf(c, gD[1][k], G[1][l][b][k]);
-                        pc[(l * B + b) * 3 + k] =
-                            fmaf(gD[0][k], sv[0][l][b][k], gD[1][k] * sv[1][l][b][k]);
                     }
 #pragma unroll
-            for (int g0 = 0; g0 < NC; g0 += 32) {
-                float x[32];
+            for (int g0 = 0; g0 < NC; g0 += 16) {
+                float x[16];
 #pragma unroll
-                for (int q = 0; q < 32; ++q) x[q] = g0 + q < NC ? pc[g0 + q] : 0.0f;
-                const float tot = wave_reduce_scatter32(x, lane);
-                const int ci = g0 + scatter32_index(lane);
-                if (lane < 32 && ci < NC) atomicAdd(&cacc[v * NC + ci], tot);
+                for (int q = 0; q < 16; ++q) {
+                    const int ci = g0 + q;
+                    const int k = ci % 3, lb = ci / 3;
+                    x[q] = ci < NC ? fmaf(gD[0][k], sv[0][lb / B][lb % B][k],
+                                          gD[1][k] * sv[1][lb / B][lb % B][k])
+                                   : 0.0f;
+                }
+                const float tot = wave_reduce_scatter16(x, lane);
+                const int ci = g0 + scatter16_index(lane);
+                if (lane < 16 && ci < NC) atomicAdd(&cacc[v * NC + ci], tot);
             }
         }
         __syncthreads();
