@@ -369,7 +369,8 @@ struct BoundK {
 // view's rays and kbound bounds how many samples can touch one voxel in this
 // view (from the geometry and the smallest step of the rays with two or more
 // samples): every partial sum stays below 2^30 in magnitude, and each
-// contribution is rounded to within 0.5 / scale.
+// contribution is rounded to within 0.5 / scale.  A lane adds consecutive
+// samples that fall in one cell in registers and rounds their sum once.
 // With vmax non-null the largest |g_vol| of each view is also recorded.
 
 // One scan's share of a ragged back-projection launch: workgroups
@@ -592,6 +593,20 @@ __global__ __launch_bounds__(64 * W) void k_project_bwd(BwdTab t) {
             int rend = we[ri];
             RunP rp = wr[ri];
             lds_wait();
+            int cur_off = -1;           // cell (LDS byte offset) whose weights cw holds
+            float cw[8];
+            auto flush = [&]() {
+                if (cur_off < 0) return;
+                char *qb = (char *)acc + cur_off;
+                atomicAdd((int *)qb, round_int(cw[0]));
+                atomicAdd((int *)(qb + 4), round_int(cw[1]));
+                atomicAdd((int *)(qb + 4 * P2), round_int(cw[2]));
+                atomicAdd((int *)(qb + 4 * P2 + 4), round_int(cw[3]));
+                atomicAdd((int *)(qb + 4 * P1 * P2), round_int(cw[4]));
+                atomicAdd((int *)(qb + 4 * P1 * P2 + 4), round_int(cw[5]));
+                atomicAdd((int *)(qb + 4 * P1 * P2 + 4 * P2), round_int(cw[6]));
+                atomicAdd((int *)(qb + 4 * P1 * P2 + 4 * P2 + 4), round_int(cw[7]));
+            };
             for (int it = 0; it < K; ++it, ++q) {                 // uniform
                 if (q >= qe) continue;
                 if (q >= rend) {
@@ -619,22 +634,27 @@ __global__ __launch_bounds__(64 * W) void k_project_bwd(BwdTab t) {
                     ray_cell(x2, nm1[2], nm2[2], c2f, f2);
                 }
                 const int off = (int)fmaf(c0f, K0, fmaf(c1f, K1, fmaf(c2f, 4.0f, KC)));
-                char *qb = (char *)acc + off;
                 const float w = rp.gp;
                 const float wx1 = w * f0, wx0 = w - wx1;
                 const float a01 = wx0 * f1, a00 = wx0 - a01;
                 const float a11 = wx1 * f1, a10 = wx1 - a11;
                 const float e001 = a00 * f2, e011 = a01 * f2;
                 const float e101 = a10 * f2, e111 = a11 * f2;
-                atomicAdd((int *)qb, round_int(a00 - e001));
-                atomicAdd((int *)(qb + 4), round_int(e001));
-                atomicAdd((int *)(qb + 4 * P2), round_int(a01 - e011));
-                atomicAdd((int *)(qb + 4 * P2 + 4), round_int(e011));
-                atomicAdd((int *)(qb + 4 * P1 * P2), round_int(a10 - e101));
-                atomicAdd((int *)(qb + 4 * P1 * P2 + 4), round_int(e101));
-                atomicAdd((int *)(qb + 4 * P1 * P2 + 4 * P2), round_int(a11 - e111));
-                atomicAdd((int *)(qb + 4 * P1 * P2 + 4 * P2 + 4), round_int(e111));
+                const float e[8] = {a00 - e001, e001, a01 - e011, e011,
+                                    a10 - e101, e101, a11 - e111, e111};
+                // consecutive samples in one cell add up in registers; the
+                // cell's 8 corners go to LDS when the lane moves on
+                if (off != cur_off) {
+                    flush();
+                    cur_off = off;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) cw[k] = e[k];
+                } else {
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) cw[k] += e[k];
+                }
             }
+            flush();
             wave_lds_sync();
         }
         __syncthreads();

@@ -378,9 +378,11 @@ def test_graph_replay_matches_eager():
 
 
 def test_launch_shapes_agree_and_autotune():
-    """Every forward ray tile and every back-projection brick gives the same
-    bits (per-ray sums, and integer fixed-point sums whose per-view scale does
-    not depend on the brick); the autotuner picks valid shapes."""
+    """Every forward ray tile gives the same bits (per-ray sums); every
+    back-projection brick gives the same values to within the fixed-point
+    rounding (integer sums with a per-view scale, but a lane merges its
+    consecutive samples in one cell before rounding, and which samples a lane
+    takes depends on the brick); the autotuner picks valid shapes."""
     _, grid, cone, angles = _proj_case("aniso")
     V = len(angles)
     ang = T(angles)
@@ -399,7 +401,7 @@ def test_launch_shapes_agree_and_autotune():
             ops.pmf_tune_set(ops.PMF_TUNE_BACKPROJECT_BRICK, k)
             b = ops.pmf_project_bwd(gp, grid, cone, ang, shared=False)
             ref_b = b.clone() if ref_b is None else ref_b
-            assert torch.equal(b, ref_b), k
+            assert rel(N(b), N(ref_b)) < 1e-6, k
             bs = ops.pmf_project_bwd(gp, grid, cone, ang, shared=True)
             assert rel(N(bs), N(ref_b.sum(0))) < 1e-6, k
         want = oracle.project_bwd(N(gp), grid, cone, angles)
