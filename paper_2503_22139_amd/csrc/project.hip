@@ -304,6 +304,12 @@ __device__ __forceinline__ int round_int(float x) {
     return r;
 }
 
+// acc = acc * k + e, written in place (keeps a loop-carried accumulator in
+// its register instead of a copy per iteration).
+__device__ __forceinline__ void fma_in_place(float &acc, float k, float e) {
+    asm("v_fma_f32 %0, %0, %1, %2" : "+v"(acc) : "v"(k), "v"(e));
+}
+
 // Waits for this wave's outstanding LDS reads (and, LDS operations retiring
 // in order, everything issued before them).  Placed right after the rare
 // reads of a ray switch so the compiler need not put a conservative wait on
@@ -456,7 +462,8 @@ __global__ __launch_bounds__(64 * W) void k_project_bwd(BwdTab t) {
 
     const int vb = SUM ? 0 : view;
     const int ve = SUM ? V : view + 1;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wave
     const int lx = lane & 7, ly = lane >> 3;
     // clamp limits of the rim path, held in registers (a reload from the
     // argument table inside the sample loop would also wait for the atomics)
@@ -585,7 +592,8 @@ __global__ __launch_bounds__(64 * W) void k_project_bwd(BwdTab t) {
             const int K = (T + 63) >> 6;
             int q = lane * K;
             const int qe = min(q + K, T);
-            // first ray of the slice: the smallest r with end_r > q (binary lifting)
+            // first ray of the slice: the smallest r with end_r > q (binary
+            // lifting)
             int ri = 0;
 #pragma unroll
             for (int step = 32; step > 0; step >>= 1)
@@ -593,30 +601,9 @@ __global__ __launch_bounds__(64 * W) void k_project_bwd(BwdTab t) {
             int rend = we[ri];
             RunP rp = wr[ri];
             lds_wait();
-            int cur_off = -1;           // cell (LDS byte offset) whose weights cw holds
-            float cw[8];
-            auto flush = [&]() {
-                if (cur_off < 0) return;
-                char *qb = (char *)acc + cur_off;
-                atomicAdd((int *)qb, round_int(cw[0]));
-                atomicAdd((int *)(qb + 4), round_int(cw[1]));
-                atomicAdd((int *)(qb + 4 * P2), round_int(cw[2]));
-                atomicAdd((int *)(qb + 4 * P2 + 4), round_int(cw[3]));
-                atomicAdd((int *)(qb + 4 * P1 * P2), round_int(cw[4]));
-                atomicAdd((int *)(qb + 4 * P1 * P2 + 4), round_int(cw[5]));
-                atomicAdd((int *)(qb + 4 * P1 * P2 + 4 * P2), round_int(cw[6]));
-                atomicAdd((int *)(qb + 4 * P1 * P2 + 4 * P2 + 4), round_int(cw[7]));
-            };
-            for (int it = 0; it < K; ++it, ++q) {                 // uniform
-                if (q >= qe) continue;
-                if (q >= rend) {
-                    do {
-                        rend = we[++ri];
-                    } while (q >= rend);
-                    rp = wr[ri];
-                    lds_wait();
-                }
-                const float sf = (float)(q + rp.off);
+            // Sample s of ray rp: its cell's LDS byte offset and the 8 corner
+            // weights.
+            auto sample = [&](float sf, int &off, float e[8]) {
                 const float x0 = fmaf(sf, rp.su[0], rp.bu[0]);
                 const float x1 = fmaf(sf, rp.su[1], rp.bu[1]);
                 const float x2 = fmaf(sf, rp.su[2], rp.bu[2]);
@@ -633,28 +620,63 @@ __global__ __launch_bounds__(64 * W) void k_project_bwd(BwdTab t) {
                     ray_cell(x1, nm1[1], nm2[1], c1f, f1);
                     ray_cell(x2, nm1[2], nm2[2], c2f, f2);
                 }
-                const int off = (int)fmaf(c0f, K0, fmaf(c1f, K1, fmaf(c2f, 4.0f, KC)));
+                off = (int)fmaf(c0f, K0, fmaf(c1f, K1, fmaf(c2f, 4.0f, KC)));
                 const float w = rp.gp;
                 const float wx1 = w * f0, wx0 = w - wx1;
                 const float a01 = wx0 * f1, a00 = wx0 - a01;
                 const float a11 = wx1 * f1, a10 = wx1 - a11;
                 const float e001 = a00 * f2, e011 = a01 * f2;
                 const float e101 = a10 * f2, e111 = a11 * f2;
-                const float e[8] = {a00 - e001, e001, a01 - e011, e011,
-                                    a10 - e101, e101, a11 - e111, e111};
-                // consecutive samples in one cell add up in registers; the
-                // cell's 8 corners go to LDS when the lane moves on
-                if (off != cur_off) {
-                    flush();
+                e[0] = a00 - e001;
+                e[1] = e001;
+                e[2] = a01 - e011;
+                e[3] = e011;
+                e[4] = a10 - e101;
+                e[5] = e101;
+                e[6] = a11 - e111;
+                e[7] = e111;
+            };
+            if (q < qe) {
+                // Consecutive samples in one cell add up in registers; the
+                // cell's 8 corners go to LDS when the lane moves on.
+                int cur_off;
+                float cw[8];
+                float sf = (float)(q + rp.off);
+                sample(sf, cur_off, cw);
+                auto flush = [&]() {
+                    char *qb = (char *)acc + cur_off;
+                    atomicAdd((int *)qb, round_int(cw[0]));
+                    atomicAdd((int *)(qb + 4), round_int(cw[1]));
+                    atomicAdd((int *)(qb + 4 * P2), round_int(cw[2]));
+                    atomicAdd((int *)(qb + 4 * P2 + 4), round_int(cw[3]));
+                    atomicAdd((int *)(qb + 4 * P1 * P2), round_int(cw[4]));
+                    atomicAdd((int *)(qb + 4 * P1 * P2 + 4), round_int(cw[5]));
+                    atomicAdd((int *)(qb + 4 * P1 * P2 + 4 * P2), round_int(cw[6]));
+                    atomicAdd((int *)(qb + 4 * P1 * P2 + 4 * P2 + 4), round_int(cw[7]));
+                };
+                for (++q; q < qe; ++q) {
+                    sf += 1.0f;                 // exact: sample indices are small integers
+                    if (q >= rend) {
+                        do {
+                            rend = we[++ri];
+                        } while (q >= rend);
+                        rp = wr[ri];
+                        lds_wait();
+                        sf = (float)(q + rp.off);
+                    }
+                    int off;
+                    float e[8];
+                    sample(sf, off, e);
+                    // a restart is a multiply by 0, so both cases share one fma
+                    const bool moved = off != cur_off;
+                    const float keep = moved ? 0.0f : 1.0f;
+                    if (moved) flush();
                     cur_off = off;
 #pragma unroll
-                    for (int k = 0; k < 8; ++k) cw[k] = e[k];
-                } else {
-#pragma unroll
-                    for (int k = 0; k < 8; ++k) cw[k] += e[k];
+                    for (int k = 0; k < 8; ++k) fma_in_place(cw[k], keep, e[k]);
                 }
+                flush();
             }
-            flush();
             wave_lds_sync();
         }
         __syncthreads();
