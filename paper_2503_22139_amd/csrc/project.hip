@@ -534,14 +534,21 @@ __global__ __launch_bounds__(64 * W) void k_project_bwd(BwdTab t) {
                         // The estimate puts the run at [ceil(smin), ceil(smax) - 1]
                         // up to rounding far below one sample; start one sample
                         // outside each end and move to the exact ends.
+                        // (in an interior brick the clamps cannot change the
+                        // answer: owned cells lie in [1, n-3] on every axis)
+                        auto cell = [&](float x, int a) {
+                            if (interior) return floorf(x);
+                            float fi, fr;
+                            ray_cell(x, nm1[a], nm2[a], fi, fr);
+                            return fi;
+                        };
                         auto owned = [&](int si) {
                             const float sf = (float)si;
-                            float fi, fr;
-                            ray_cell(fmaf(sf, r.su[0], r.bu[0]), mk.nm1[0], mk.nm2[0], fi, fr);
+                            float fi = cell(fmaf(sf, r.su[0], r.bu[0]), 0);
                             bool o = fi >= clo[0] && fi <= chi[0];
-                            ray_cell(fmaf(sf, r.su[1], r.bu[1]), mk.nm1[1], mk.nm2[1], fi, fr);
+                            fi = cell(fmaf(sf, r.su[1], r.bu[1]), 1);
                             o = o && fi >= clo[1] && fi <= chi[1];
-                            ray_cell(fmaf(sf, r.su[2], r.bu[2]), mk.nm1[2], mk.nm2[2], fi, fr);
+                            fi = cell(fmaf(sf, r.su[2], r.bu[2]), 2);
                             return o && fi >= clo[2] && fi <= chi[2];
                         };
                         const int last = r.n - 1;
