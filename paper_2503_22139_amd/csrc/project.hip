@@ -146,6 +146,79 @@ __device__ __forceinline__ float march_sample_paired(const char *__restrict__ vb
     return lerp1(lerp1(x00, x01, f1), lerp1(x10, x11, f1), f0);
 }
 
+// a * b + c on the 24-bit multiplier (a, b < 2^24); written out because the
+// compiler otherwise masks and takes the full 32-bit multiply here.
+__device__ __forceinline__ uint32_t mad_u24(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t r;
+    asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+// Samples whose coordinates lie in (0, n-1) on every axis need none of
+// ray_cell's clamps: the cell index is the truncation and the fraction
+// u - floor(u) is exact for u >= 0 (what v_fract returns), so the two reads
+// below give the same bits as march_sample / march_sample_paired with fewer
+// operations (no clamps, no float floors to convert).
+__device__ __forceinline__ float march_body(const char *__restrict__ vb, const MarchK &mk,
+                                            float u0, float u1, float u2) {
+    const float f0 = __builtin_amdgcn_fractf(u0), f1 = __builtin_amdgcn_fractf(u1),
+                f2 = __builtin_amdgcn_fractf(u2);
+    const uint32_t o00 =
+        mad_u24((uint32_t)u0, mk.s0, mad_u24((uint32_t)u1, mk.s1, (uint32_t)u2)) * 4u;
+    const uint32_t o01 = o00 + mk.s1 * 4u, o10 = o00 + mk.s0 * 4u, o11 = o10 + mk.s1 * 4u;
+    const float *pa = (const float *)(vb + o00), *pb = (const float *)(vb + o01);
+    const float *pd = (const float *)(vb + o10), *pe = (const float *)(vb + o11);
+    const float x00 = lerp1(pa[0], pa[1], f2), x01 = lerp1(pb[0], pb[1], f2);
+    const float x10 = lerp1(pd[0], pd[1], f2), x11 = lerp1(pe[0], pe[1], f2);
+    return lerp1(lerp1(x00, x01, f1), lerp1(x10, x11, f1), f0);
+}
+
+// Byte offset of a body sample's cell in the y-paired layout.
+__device__ __forceinline__ uint32_t body_offset_paired(const MarchK &mk, float u0, float u1,
+                                                       float u2) {
+    return mad_u24((uint32_t)u0, mk.s0, mad_u24((uint32_t)u1, mk.s1, (uint32_t)u2 * 2u)) * 4u;
+}
+
+__device__ __forceinline__ float march_body_paired(const char *__restrict__ vb,
+                                                   const MarchK &mk, float u0, float u1,
+                                                   float u2) {
+    const float f0 = __builtin_amdgcn_fractf(u0), f1 = __builtin_amdgcn_fractf(u1),
+                f2 = __builtin_amdgcn_fractf(u2);
+    const uint32_t o = body_offset_paired(mk, u0, u1, u2);
+    const float *pa = (const float *)(vb + o);
+    const float *pd = (const float *)(vb + (o + mk.s0 * 4u));
+    const float a0 = pa[0], a1 = pa[1], a2 = pa[2], a3 = pa[3];
+    const float d0 = pd[0], d1 = pd[1], d2 = pd[2], d3 = pd[3];
+    const float x00 = lerp1(a0, a2, f2), x01 = lerp1(a1, a3, f2);
+    const float x10 = lerp1(d0, d2, f2), x11 = lerp1(d1, d3, f2);
+    return lerp1(lerp1(x00, x01, f1), lerp1(x10, x11, f1), f0);
+}
+
+// The samples [sb, se) of a ray whose coordinates lie in [1/64, n-1-1/64] on
+// every axis (so march_body applies).  The crossing indices are estimated in
+// float with a 1/64-sample guard; their error, below 1e-4 voxel in
+// coordinate terms, cannot carry a sample from inside the margin to outside
+// (0, n-1).
+__device__ __forceinline__ void body_range(const RayK &r, const MarchK &mk, int &sb, int &se) {
+    constexpr float M = 0.015625f;
+    float lo = 0.0f, hi = (float)r.n;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float xl = M, xh = mk.nm1[a] - M, su = r.su[a], bu = r.bu[a];
+        if (su == 0.0f) {
+            if (!(bu >= xl && bu <= xh)) hi = -1.0f;
+        } else {
+            const float t1 = (xl - bu) / su, t2 = (xh - bu) / su;
+            lo = fmaxf(lo, fminf(t1, t2));
+            hi = fminf(hi, fmaxf(t1, t2));
+        }
+    }
+    lo = fminf(lo, (float)r.n);
+    hi = fmaxf(hi, -1.0f);
+    sb = (int)ceilf(lo + M);
+    se = max((int)floorf(hi - M) + 1, sb);
+}
+
 __host__ __device__ inline MarchK make_march(const GridK &g) {
     MarchK m;
     for (int a = 0; a < 3; ++a) {
@@ -215,17 +288,57 @@ __global__ __launch_bounds__(256) void k_project(ProjTab t) {
     const RayK r = ray_setup(g, c, cos(th), sin(th), iu, iv);
     const char *__restrict__ vb = (const char *)(pj.vol + (int64_t)v * pj.stride);
     float acc0 = 0.0f, acc1 = 0.0f;
-    int s = 0;
     auto sample = [&](float sf) {
         const float u0 = fmaf(sf, r.su[0], r.bu[0]), u1 = fmaf(sf, r.su[1], r.bu[1]),
                     u2 = fmaf(sf, r.su[2], r.bu[2]);
         return PAIRED ? march_sample_paired(vb, mk, u0, u1, u2) : march_sample(vb, mk, u0, u1, u2);
     };
-    for (; s + 1 < r.n; s += 2) {
-        acc0 += sample((float)s);
-        acc1 += sample((float)(s + 1));
+    auto body = [&](float sf) {
+        const float u0 = fmaf(sf, r.su[0], r.bu[0]), u1 = fmaf(sf, r.su[1], r.bu[1]),
+                    u2 = fmaf(sf, r.su[2], r.bu[2]);
+        return PAIRED ? march_body_paired(vb, mk, u0, u1, u2) : march_body(vb, mk, u0, u1, u2);
+    };
+    // clamped head, unclamped body in pairs, clamped tail (a fixed order per
+    // ray whatever the launch shape)
+    int sb, se;
+    body_range(r, mk, sb, se);
+    sb = min(sb, r.n);
+    se = min(se, r.n);
+    int s = 0;
+    for (; s < sb; ++s) acc0 += sample((float)s);
+    if constexpr (PAIRED) {
+        // Consecutive samples of a ray often share a cell: a lane reloads its
+        // eight corners only when the cell changes, which takes that lane out
+        // of the gather (the loads are the limit here, not the arithmetic).
+        uint32_t last = 0xffffffffu;
+        float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f, d0 = 0.0f, d1 = 0.0f, d2 = 0.0f,
+              d3 = 0.0f;
+        float sf = (float)s;
+        for (; s < se; ++s, sf += 1.0f) {
+            const float u0 = fmaf(sf, r.su[0], r.bu[0]), u1 = fmaf(sf, r.su[1], r.bu[1]),
+                        u2 = fmaf(sf, r.su[2], r.bu[2]);
+            const uint32_t o = body_offset_paired(mk, u0, u1, u2);
+            if (o != last) {
+                const float *pa = (const float *)(vb + o);
+                const float *pd = (const float *)(vb + (o + mk.s0 * 4u));
+                a0 = pa[0]; a1 = pa[1]; a2 = pa[2]; a3 = pa[3];
+                d0 = pd[0]; d1 = pd[1]; d2 = pd[2]; d3 = pd[3];
+                last = o;
+            }
+            const float f0 = __builtin_amdgcn_fractf(u0), f1 = __builtin_amdgcn_fractf(u1),
+                        f2 = __builtin_amdgcn_fractf(u2);
+            const float x00 = lerp1(a0, a2, f2), x01 = lerp1(a1, a3, f2);
+            const float x10 = lerp1(d0, d2, f2), x11 = lerp1(d1, d3, f2);
+            acc1 += lerp1(lerp1(x00, x01, f1), lerp1(x10, x11, f1), f0);
+        }
+    } else {
+        float sf = (float)s;
+        for (; s + 1 < se; s += 2, sf += 2.0f) {
+            acc0 += body(sf);
+            acc1 += body(sf + 1.0f);
+        }
     }
-    if (s < r.n) acc0 += sample((float)s);
+    for (; s < r.n; ++s) acc0 += sample((float)s);
     pj.proj[((int64_t)v * c.nv + iv) * c.nu + iu] = (acc0 + acc1) * r.delta;
 }
 
