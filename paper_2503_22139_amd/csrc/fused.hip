@@ -192,7 +192,7 @@ __device__ __forceinline__ int scatter32_index(int lane) {
            2 * (lane & 1) + ((lane >> 4) & 1);
 }
 
-// Brick of the adjoint pass: 8x8x8 voxels, two per thread; LDS box with a
+// Brick of the adjoint pass: 8x8x8 voxels, one per thread; LDS box with a
 // halo of HALO voxels on every side for the g_ref scatter.  Views are taken
 // in chunks of at most VCH per launch.
 constexpr int FB = 8;
@@ -201,6 +201,8 @@ constexpr int HB = FB + 2 * HALO + 1;
 constexpr int HB3 = HB * HB * HB;
 constexpr int VCH = 64;
 constexpr int FLUSH = 8;   // views per fixed-point accumulation round
+constexpr int WB_THREADS = FB * FB * FB;    // one voxel per thread
+constexpr int WB_WAVES = WB_THREADS / 64;
 constexpr int LO_BITS = 18; // 512 * FLUSH * 2^(LO_BITS-1) < 2^31
 
 struct GOut {
@@ -216,9 +218,13 @@ struct GOut {
 // so the two 32-bit sums keep about 48 bits; each round is folded into a
 // float box.
 // The float box is staged per brick and summed by k_gather_boxes;
-// displacements that leave the halo fall back to global atomics.
+// displacements that leave the halo fall back to global atomics.  dL/dw of
+// each view is reduced over a wave, written to that wave's LDS slot, and the
+// slots are summed over the waves in a fixed order into the brick's partials
+// (reduced over bricks by k_reduce_coeff_blocks), so it is deterministic.
 struct WCK {
-    const float *ref;
+    const float *ref;       // y-paired when paired (see k_pair_volume)
+    int paired;
     GridK g;
     LevelsK lv;
     const float *coeff;     // this chunk's first view
@@ -241,7 +247,7 @@ struct WCTab {
 
 template <int L, int B>
 __device__ __forceinline__ void warp_combine_bwd_brick(
-    const float *__restrict__ ref, const GridK &g, const LevelsK &lv,
+    const float *__restrict__ ref, int paired, const GridK &g, const LevelsK &lv,
     const float *__restrict__ coeff, int V, const float *__restrict__ g_I,
     const unsigned *__restrict__ vmax, float *__restrict__ g_ref, float *__restrict__ stage,
     const GOut &gout, int accumulate, int nb1, int nb2, float *__restrict__ partial, int blk) {
@@ -250,45 +256,35 @@ __device__ __forceinline__ void warp_combine_bwd_brick(
     int *ibox = (int *)smem;              // HB^3 fixed point, high words
     int *lbox = (int *)smem + HB3;        // HB^3 fixed point, low words
     float *fbox = smem + 2 * HB3;         // HB^3 float
-    float *cacc = smem + 3 * HB3;         // V * NC
-    for (int i = threadIdx.x; i < HB3; i += blockDim.x) {
+    float *wslot = smem + 3 * HB3;        // [WB_WAVES][FLUSH][NC]: each wave's dL/dw of a round
+    for (int i = threadIdx.x; i < HB3; i += WB_THREADS) {
         ibox[i] = 0;
         lbox[i] = 0;
         fbox[i] = 0.0f;
     }
-    for (int i = threadIdx.x; i < V * NC; i += blockDim.x) cacc[i] = 0.0f;
     const int bid = blk;
     const int b2 = bid % nb2, b1 = (bid / nb2) % nb1, b0 = bid / (nb2 * nb1);
     const int B0 = b0 * FB, B1 = b1 * FB, B2 = b2 * FB;
     const int64_t N = grid_size(g);
     const int s1 = g.n[2], s0 = g.n[1] * g.n[2];
 
-    int vx[2], vy[2], vz[2];
-    bool ok[2];
-    int64_t jj[2];
-    float sv[2][L][B][3];
+    // one voxel per thread
+    const int t = threadIdx.x;
+    const int vx = B0 + t / (FB * FB), vy = B1 + (t / FB) % FB, vz = B2 + t % FB;
+    const bool ok = vx < g.n[0] && vy < g.n[1] && vz < g.n[2];
+    const int64_t jj = ok ? ((int64_t)vx * g.n[1] + vy) * g.n[2] + vz : 0;
+    float sv[L][B][3];
+    basis_samples<L, B>(lv, ok ? vx : 0, ok ? vy : 0, ok ? vz : 0, sv);
+    float G[L][B][3];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const int t = threadIdx.x + q * 256;
-        vx[q] = B0 + t / (FB * FB);
-        vy[q] = B1 + (t / FB) % FB;
-        vz[q] = B2 + t % FB;
-        ok[q] = vx[q] < g.n[0] && vy[q] < g.n[1] && vz[q] < g.n[2];
-        jj[q] = ok[q] ? ((int64_t)vx[q] * g.n[1] + vy[q]) * g.n[2] + vz[q] : 0;
-        basis_samples<L, B>(lv, ok[q] ? vx[q] : 0, ok[q] ? vy[q] : 0, ok[q] ? vz[q] : 0, sv[q]);
-    }
-    float G[2][L][B][3];
+    for (int l = 0; l < L; ++l)
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
+        for (int b = 0; b < B; ++b)
 #pragma unroll
-        for (int l = 0; l < L; ++l)
-#pragma unroll
-            for (int b = 0; b < B; ++b)
-#pragma unroll
-                for (int k = 0; k < 3; ++k) G[q][l][b][k] = 0.0f;
+            for (int k = 0; k < 3; ++k) G[l][b][k] = 0.0f;
     __syncthreads();
 
-    const int lane = threadIdx.x & 63;
+    const int lane = t & 63, wave = t >> 6;
     for (int r0 = 0; r0 < V; r0 += FLUSH) {
         const int r1 = min(V, r0 + FLUSH);
         float M = 0.0f;
@@ -296,37 +292,45 @@ __device__ __forceinline__ void warp_combine_bwd_brick(
         const float scale = M > 0.0f ? 1073741824.0f / (512.0f * (float)(r1 - r0) * M) : 0.0f;
         for (int v = r0; v < r1; ++v) {
             const float *cv = coeff + (int64_t)v * L * B * 3;
-            float gD[2][3];
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                gD[q][0] = gD[q][1] = gD[q][2] = 0.0f;
-                if (!ok[q]) continue;
+            float gD[3] = {0.0f, 0.0f, 0.0f};
+            do {
+                if (!ok) break;
                 float d[3];
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
-                    float t = 0.0f;
+                    float acc = 0.0f;
 #pragma unroll
                     for (int l = 0; l < L; ++l)
 #pragma unroll
                         for (int b = 0; b < B; ++b)
-                            t = fmaf(cv[(l * B + b) * 3 + k], sv[q][l][b][k], t);
-                    d[k] = t;
+                            acc = fmaf(cv[(l * B + b) * 3 + k], sv[l][b][k], acc);
+                    d[k] = acc;
                 }
-                const float u0 = fmaf(d[0], g.inv_h[0], (float)vx[q]);
-                const float u1 = fmaf(d[1], g.inv_h[1], (float)vy[q]);
-                const float u2 = fmaf(d[2], g.inv_h[2], (float)vz[q]);
+                const float u0 = fmaf(d[0], g.inv_h[0], (float)vx);
+                const float u1 = fmaf(d[1], g.inv_h[1], (float)vy);
+                const float u2 = fmaf(d[2], g.inv_h[2], (float)vz);
                 int i0, i1, i2;
                 float f0, f1, f2;
                 if (!axis_cell(u0, g.n[0], i0, f0) || !axis_cell(u1, g.n[1], i1, f1) ||
                     !axis_cell(u2, g.n[2], i2, f2))
-                    continue;
-                const float go = g_I[(int64_t)v * N + jj[q]];
-                if (go == 0.0f) continue;
+                    break;
+                const float go = g_I[(int64_t)v * N + jj];
+                if (go == 0.0f) break;
                 const int64_t base = ((int64_t)i0 * g.n[1] + i1) * g.n[2] + i2;
-                const float *p = ref + base;
-                const float c000 = p[0], c001 = p[1], c010 = p[s1], c011 = p[s1 + 1];
-                const float c100 = p[s0], c101 = p[s0 + 1], c110 = p[s0 + s1],
-                            c111 = p[s0 + s1 + 1];
+                float c000, c001, c010, c011, c100, c101, c110, c111;
+                if (paired) {
+                    // the 2x2 (y, z) corners of a cell are 16 contiguous
+                    // (8-byte aligned) bytes: one load each for x and x+1
+                    typedef float v4a8 __attribute__((ext_vector_type(4), aligned(8)));
+                    const float *pa = ref + 2 * base;
+                    const v4a8 a = *(const v4a8 *)pa, e = *(const v4a8 *)(pa + 2 * (int64_t)s0);
+                    c000 = a.x; c010 = a.y; c001 = a.z; c011 = a.w;
+                    c100 = e.x; c110 = e.y; c101 = e.z; c111 = e.w;
+                } else {
+                    const float *p = ref + base;
+                    c000 = p[0]; c001 = p[1]; c010 = p[s1]; c011 = p[s1 + 1];
+                    c100 = p[s0]; c101 = p[s0 + 1]; c110 = p[s0 + s1]; c111 = p[s0 + s1 + 1];
+                }
                 const float a00 = lerp1(c000, c001, f2), a01 = lerp1(c010, c011, f2);
                 const float a10 = lerp1(c100, c101, f2), a11 = lerp1(c110, c111, f2);
                 const float ddx = lerp1(a10, a11, f1) - lerp1(a00, a01, f1);
@@ -334,9 +338,9 @@ __device__ __forceinline__ void warp_combine_bwd_brick(
                 const float e00 = lerp1(c000, c010, f1), e01 = lerp1(c001, c011, f1);
                 const float e10 = lerp1(c100, c110, f1), e11 = lerp1(c101, c111, f1);
                 const float ddz = lerp1(e01, e11, f0) - lerp1(e00, e10, f0);
-                gD[q][0] = go * ddx * g.inv_h[0] * axis_free(u0, g.n[0]);
-                gD[q][1] = go * ddy * g.inv_h[1] * axis_free(u1, g.n[1]);
-                gD[q][2] = go * ddz * g.inv_h[2] * axis_free(u2, g.n[2]);
+                gD[0] = go * ddx * g.inv_h[0] * axis_free(u0, g.n[0]);
+                gD[1] = go * ddy * g.inv_h[1] * axis_free(u1, g.n[1]);
+                gD[2] = go * ddz * g.inv_h[2] * axis_free(u2, g.n[2]);
                 const int l0 = i0 - (B0 - HALO), l1 = i1 - (B1 - HALO), l2 = i2 - (B2 - HALO);
                 const bool inbox = l0 >= 0 && l0 + 1 < HB && l1 >= 0 && l1 + 1 < HB && l2 >= 0 &&
                                    l2 + 1 < HB;
@@ -369,19 +373,19 @@ __device__ __forceinline__ void warp_combine_bwd_brick(
                                 unsafeAtomicAdd(&g_ref[base + a * s0 + b * s1 + c],
                                                 go * w0[a] * w1[b] * w2[c]);
                 }
-            }
+            } while (false);
             // dL/dE: per voxel over views; dL/dw[v]: per-lane products,
             // reduce-scattered over the wave in groups of 16 coefficients
+            // into this wave's slot (summed over the waves in a fixed order
+            // at the end of the round)
 #pragma unroll
             for (int l = 0; l < L; ++l)
 #pragma unroll
                 for (int b = 0; b < B; ++b)
 #pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        const float c = cv[(l * B + b) * 3 + k];
-                        G[0][l][b][k] = fmaf(c, gD[0][k], G[0][l][b][k]);
-                        G[1][l][b][k] = fmaf(c, gD[1][k], G[1][l][b][k]);
-                    }
+                    for (int k = 0; k < 3; ++k)
+                        G[l][b][k] = fmaf(cv[(l * B + b) * 3 + k], gD[k], G[l][b][k]);
+            float *slot = wslot + (wave * FLUSH + (v - r0)) * NC;
 #pragma unroll
             for (int g0 = 0; g0 < NC; g0 += 16) {
                 float x[16];
@@ -389,57 +393,57 @@ __device__ __forceinline__ void warp_combine_bwd_brick(
                 for (int q = 0; q < 16; ++q) {
                     const int ci = g0 + q;
                     const int k = ci % 3, lb = ci / 3;
-                    x[q] = ci < NC ? fmaf(gD[0][k], sv[0][lb / B][lb % B][k],
-                                          gD[1][k] * sv[1][lb / B][lb % B][k])
-                                   : 0.0f;
+                    x[q] = ci < NC ? gD[k] * sv[lb / B][lb % B][k] : 0.0f;
                 }
                 const float tot = wave_reduce_scatter16(x, lane);
                 const int ci = g0 + scatter16_index(lane);
-                if (lane < 16 && ci < NC) atomicAdd(&cacc[v * NC + ci], tot);
+                if (lane < 16 && ci < NC) slot[ci] = tot;
             }
         }
         __syncthreads();
         if (scale > 0.0f) {
             const float inv = 1.0f / scale;
-            for (int i = threadIdx.x; i < HB3; i += blockDim.x) {
-                const int t = ibox[i], u = lbox[i];
-                if (t | u) {
-                    fbox[i] += ((float)t + (float)u * (1.0f / (float)(1 << LO_BITS))) * inv;
+            for (int i = t; i < HB3; i += WB_THREADS) {
+                const int a = ibox[i], u = lbox[i];
+                if (a | u) {
+                    fbox[i] += ((float)a + (float)u * (1.0f / (float)(1 << LO_BITS))) * inv;
                     ibox[i] = 0;
                     lbox[i] = 0;
                 }
             }
         }
+        for (int i = t; i < (r1 - r0) * NC; i += WB_THREADS) {
+            float sum = 0.0f;
+#pragma unroll
+            for (int w = 0; w < WB_WAVES; ++w) sum += wslot[w * FLUSH * NC + i];
+            partial[((int64_t)blk * V + r0) * NC + i] = sum;
+        }
         __syncthreads();
     }
     float *st = stage + (int64_t)blk * HB3;
-    for (int i = threadIdx.x; i < HB3; i += blockDim.x) st[i] = fbox[i];
-    for (int i = threadIdx.x; i < V * NC; i += blockDim.x)
-        partial[(int64_t)blk * V * NC + i] = cacc[i];
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        if (!ok[q]) continue;
+    for (int i = t; i < HB3; i += WB_THREADS) st[i] = fbox[i];
+    if (ok) {
 #pragma unroll
         for (int l = 0; l < L; ++l)
 #pragma unroll
             for (int b = 0; b < B; ++b)
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
-                    float *dst = gout.dst[l] + (int64_t)(b * 3 + k) * N + jj[q];
-                    *dst = accumulate ? *dst + G[q][l][b][k] : G[q][l][b][k];
+                    float *dst = gout.dst[l] + (int64_t)(b * 3 + k) * N + jj;
+                    *dst = accumulate ? *dst + G[l][b][k] : G[l][b][k];
                 }
     }
 }
 
 template <int L, int B>
-__global__ __launch_bounds__(256) void k_warp_combine_bwd(WCTab t) {
+__global__ __launch_bounds__(WB_THREADS) void k_warp_combine_bwd(WCTab t) {
     const int job = job_of(t, (int)blockIdx.x);
     const WCK &wj = t.s[job];
     const int item = job_item(t, job, (int)blockIdx.x);
     if (item >= wj.items) return;
-    warp_combine_bwd_brick<L, B>(wj.ref, wj.g, wj.lv, wj.coeff, wj.V, wj.g_I, wj.vmax, wj.g_ref,
-                                 wj.stage, wj.gout, wj.accumulate, wj.nb1, wj.nb2, wj.partial,
-                                 item);
+    warp_combine_bwd_brick<L, B>(wj.ref, wj.paired, wj.g, wj.lv, wj.coeff, wj.V, wj.g_I, wj.vmax,
+                                 wj.g_ref, wj.stage, wj.gout, wj.accumulate, wj.nb1, wj.nb2,
+                                 wj.partial, item);
 }
 
 // g_ref[p] += sum of the staged boxes that cover voxel p (at most 2 bricks
@@ -570,7 +574,7 @@ hipError_t launch_warp_project(const float *ref, const GridK &g, const LevelsK &
 }
 
 struct BwdLayout {
-    size_t gI, rays, gbuf, partial, stage, vmax, adj, total;
+    size_t gI, rays, gbuf, partial, stage, vmax, pref, adj, total;
     int nbrick, nb[3];
 };
 
@@ -599,8 +603,9 @@ static BwdLayout bwd_layout(const LevelsK &lv, const GridK *lvl_grids, int V, co
     b.partial = align256(sizeof(float) * (size_t)b.nbrick * vc * lv.L * lv.B * 3);
     b.stage = align256(sizeof(float) * (size_t)b.nbrick * HB3);
     b.vmax = align256(sizeof(unsigned) * (size_t)V);
+    b.pref = use_paired(g) ? align256(sizeof(float) * 2 * (size_t)N) : 0;
     b.adj = adj;
-    b.total = b.gI + b.rays + b.gbuf + b.partial + b.stage + b.vmax + b.adj;
+    b.total = b.gI + b.rays + b.gbuf + b.partial + b.stage + b.vmax + b.pref + b.adj;
     return b;
 }
 
@@ -614,6 +619,7 @@ namespace {
 struct BwdScan {
     BwdLayout lay;
     float *gI, *gbuf, *partial, *stage;
+    float2 *pref;           // y-paired reference volume, or null
     void *rays, *adjws;
     unsigned *vmax;
     GOut gout;
@@ -636,6 +642,8 @@ BwdScan bwd_scan(const WPBJob &j) {
     w += b.lay.stage;
     b.vmax = (unsigned *)w;
     w += b.lay.vmax;
+    b.pref = b.lay.pref ? (float2 *)w : nullptr;
+    w += b.lay.pref;
     b.adjws = w;
     const int64_t N = grid_size(j.g);
     int nst = 0;
@@ -677,20 +685,30 @@ hipError_t launch_warp_project_bwd_jobs(const WPBJob *jobs, int n, hipStream_t s
         if (j.V > vmax_views) vmax_views = j.V;
     }
     if ((e = launch_project_bwd_jobs(bj, n, s)) != hipSuccess) return e;
-    for (int k = 0; k < n; ++k)
-        if ((e = launch_fill(jobs[k].g_ref, grid_size(jobs[k].g), 0.0f, s)) != hipSuccess) return e;
+    for (int k = 0; k < n; ++k) {
+        const WPBJob &j = jobs[k];
+        if ((e = launch_fill(j.g_ref, grid_size(j.g), 0.0f, s)) != hipSuccess) return e;
+        if (sc[k].pref) {
+            const int64_t N = grid_size(j.g);
+            {
+                ProfScope prof_("pair_volume", s);
+                k_pair_volume<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(j.ref, j.g, sc[k].pref);
+            }
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+    }
     for (int v0 = 0; v0 < vmax_views; v0 += VCH) {
         WCTab t{};
         int idx[MAXS];
         int vcs[MAXS];
-        int vc_max = 0;
         for (int k = 0; k < n; ++k) {
             const WPBJob &j = jobs[k];
             if (j.V <= v0) continue;
             const int vc = j.V - v0 < VCH ? j.V - v0 : VCH;
             const int64_t N = grid_size(j.g);
             WCK &w = t.s[t.n];
-            w.ref = j.ref;
+            w.ref = sc[k].pref ? (const float *)sc[k].pref : j.ref;
+            w.paired = sc[k].pref != nullptr;
             w.g = j.g;
             w.lv = j.lv;
             w.coeff = j.coeff + (int64_t)v0 * NC;
@@ -708,16 +726,15 @@ hipError_t launch_warp_project_bwd_jobs(const WPBJob *jobs, int n, hipStream_t s
             t.first[t.n + 1] = t.first[t.n] + align8(w.items);
             idx[t.n] = k;
             vcs[t.n] = vc;
-            if (vc > vc_max) vc_max = vc;
             ++t.n;
         }
         for (int k = t.n + 1; k <= MAXS; ++k) t.first[k] = t.first[t.n];
-        const size_t lds = sizeof(float) * (3 * (size_t)HB3 + (size_t)vc_max * NC);
+        const size_t lds = sizeof(float) * (3 * (size_t)HB3 + (size_t)WB_WAVES * FLUSH * NC);
         e = dispatch_lb(L, Bb, [&](auto Lc, auto Bc) {
             constexpr int LL = decltype(Lc)::value, BB = decltype(Bc)::value;
             {
                 ProfScope prof_("warp_combine_bwd", s);
-                k_warp_combine_bwd<LL, BB><<<(unsigned)t.first[t.n], 256, lds, s>>>(t);
+                k_warp_combine_bwd<LL, BB><<<(unsigned)t.first[t.n], WB_THREADS, lds, s>>>(t);
             }
             return hipGetLastError();
         });
