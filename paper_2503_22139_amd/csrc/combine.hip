@@ -151,49 +151,9 @@ struct Shape4 {
     int c, d[3];
 };
 
-// One 1-D transpose pass along axis `ax`: out[c][..p..] = sum_j W(j,p) in[c][..j..],
-// W(j,p) the forward's linear weight of level index p for fine index j.
-__global__ __launch_bounds__(256) void k_adj_pass(Shape4 in_s, int ax, int nc, float scale,
-                                                  float off, const float *__restrict__ in,
-                                                  AdjSrc src, float *__restrict__ out) {
-    Shape4 os = in_s;
-    os.d[ax] = nc;
-    const int64_t total = (int64_t)os.c * os.d[0] * os.d[1] * os.d[2];
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= total) return;
-    int idx[3];
-    int64_t r = t;
-    idx[2] = (int)(r % os.d[2]);
-    r /= os.d[2];
-    idx[1] = (int)(r % os.d[1]);
-    r /= os.d[1];
-    idx[0] = (int)(r % os.d[0]);
-    const int c = (int)(r / os.d[0]);
-    const int p = idx[ax];
-    const int nf = in_s.d[ax];
-    int jlo = (int)floorf((p - 1.5f - off) / scale) - 1;
-    int jhi = (int)ceilf((p + 1.5f - off) / scale) + 1;
-    jlo = max(jlo, 0);
-    jhi = min(jhi, nf - 1);
-    const int64_t st = ax == 2 ? 1 : (ax == 1 ? in_s.d[2] : (int64_t)in_s.d[1] * in_s.d[2]);
-    int id2[3] = {idx[0], idx[1], idx[2]};
-    id2[ax] = 0;
-    const int64_t base = (((int64_t)c * in_s.d[0] + id2[0]) * in_s.d[1] + id2[1]) * in_s.d[2] + id2[2];
-    const int64_t ibase = ((int64_t)id2[0] * in_s.d[1] + id2[1]) * in_s.d[2] + id2[2];
-    float acc = 0.0f;
-    for (int j = jlo; j <= jhi; ++j) {
-        int i;
-        float f;
-        if (!axis_cell(fmaf((float)j, scale, off), nc, i, f)) continue;
-        float w = (i == p) ? 1.0f - f : ((i + 1 == p) ? f : 0.0f);
-        if (w == 0.0f) continue;
-        const float x = in ? in[base + (int64_t)j * st] : adj_src(src, c, ibase + (int64_t)j * st);
-        acc = fmaf(w, x, acc);
-    }
-    out[t] = acc;
-}
-
-// The same transpose, one thread per line along `ax`: the thread walks the
+// One 1-D transpose pass along axis `ax`, out[c][..p..] = sum_j W(j,p)
+// in[c][..j..] with W(j,p) the forward's linear weight of level index p for
+// fine index j; one thread per line along `ax`: the thread walks the
 // line's nf input values in order, each split between its two level cells
 // (weights 1 - f and f, as the forward reads them), and emits the nc outputs
 // in order (a cell is complete once the walk has passed it).  Every input
