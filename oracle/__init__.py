@@ -325,3 +325,8 @@ def step(w, target, views: Optional[Sequence[int]] = None):
              "mbc": [voxelize_bwd(s, g, w.trunc_k, gb) for s, g, gb in zip(w.mbc, w.levels, g_bases)],
              "coeff": g_coeff}
     return loss, grads
+
+
+# Stage 2/3 losses around the path (plain numpy, float64)
+from .losses import (blur, l1_dssim_loss, mbc_normality_loss, ssim_map,  # noqa: E402,F401
+                     ssim_window, tv_loss)
