@@ -193,6 +193,59 @@ size_t pmf_l2_loss_workspace(int64_t npix, int V);
 int pmf_l2_loss(const float *proj, const float *target, int64_t npix, int V, float *loss,
                 float *g_proj, void *ws, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------- Stage 2/3 loss terms
+ * The loss terms that surround the motion path in Stages 2 and 3 (Sec.
+ * 2.3.2, Eq. 10-14).  The paper leaves their discretisation open; the
+ * readings taken are stated with each call.  All reductions are fixed-order
+ * trees (deterministic).  Device pointers, caller-owned; loss is a device
+ * scalar; stream-ordered, returns at once. */
+
+/* L1 + D-SSIM projection loss of a batch of V views (Eq. 10 per view, batch
+ * mean of Eq. 12), proj and target [V][nv][nu] (u fastest):
+ *   loss = (1/V) sum_v [ mean |proj - target| + lambda_ssim (1 - SSIM_v) ],
+ * SSIM_v the pixel mean of the SSIM map of Zhou et al. (2004): local means,
+ * variances and covariance under an 11 x 11 Gaussian window (sigma 1.5,
+ * normalised), zero padding outside the detector, C1 = 1e-4, C2 = 9e-4
+ * (unit dynamic range); the paper sets lambda_ssim = 0.25.  g_proj (may be
+ * NULL) is overwritten with d loss / d proj (d|r|/dr = 0 at r = 0).  Errors:
+ * PMF_EINVAL for sizes < 1, a negative or non-finite lambda_ssim or a null
+ * proj/target/loss; PMF_EWORKSPACE if the workspace from
+ * pmf_l1_dssim_loss_workspace() is missing or short. */
+size_t pmf_l1_dssim_loss_workspace(int nu, int nv, int V);
+int pmf_l1_dssim_loss(const float *proj, const float *target, int nu, int nv, int V,
+                      float lambda_ssim, float *loss, float *g_proj, void *ws, size_t ws_bytes,
+                      void *stream);
+
+/* Total variation of the D x D x D block of vol (on grid, axis 2 fastest)
+ * whose first voxel is corner[3] (host array; Eq. 11, D = 32 and weight
+ * lambda_tv = 0.05 in the paper; the block stands for the sub-volume
+ * voxelized from the reference Gaussians):
+ *   loss = weight / D^3 * sum over forward differences with both voxels in
+ *          the block of |vol(p + e_a) - vol(p)|  (anisotropic TV),
+ * and g_vol (may be NULL; same grid as vol) ACCUMULATES weight * d(TV)/d vol
+ * on the block (d|r|/dr = 0 at r = 0), so the term adds onto the gradient
+ * of the reference volume from the motion path.  Errors: PMF_EINVAL for a
+ * bad grid, D < 1, a block outside the grid, a non-finite weight or null
+ * vol/loss/corner; PMF_EWORKSPACE as above (pmf_tv_loss_workspace()). */
+size_t pmf_tv_loss_workspace(int D);
+int pmf_tv_loss(const float *vol, const pmf_grid_t *grid, const int32_t *corner, int D,
+                float weight, float *loss, float *g_vol, void *ws, size_t ws_bytes, void *stream);
+
+/* MBC normality loss (Eq. 13, weight lambda_MBC = 1 in Eq. 14) over the
+ * basis volumes of L levels, bases[l] [C][n_l] on lvl[l] (C = 3 B channels
+ * per level):
+ *   loss = weight / (L C) * sum_{l,c} ( |E_l[c]|^2 - 1 )^2,
+ * |E|^2 the sum of squares of the channel over its level's voxels (Eq. 13's
+ * 1/9 is 1/(L C) for L = 3, B = 1).  g_bases (may be NULL; else L non-null
+ * pointers with the shapes of bases) ACCUMULATES weight * d loss / d E, onto
+ * the gradients of the bases from the motion path.  Errors: PMF_EINVAL for
+ * L or C < 1, null pointers or bad grids, PMF_EUNSUPPORTED for L > 4;
+ * PMF_EWORKSPACE as above (pmf_mbc_normality_loss_workspace()). */
+size_t pmf_mbc_normality_loss_workspace(int L, int C);
+int pmf_mbc_normality_loss(int L, int C, const float *const *bases, const pmf_grid_t *lvl,
+                           float weight, float *loss, float *const *g_bases, void *ws,
+                           size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------------ utility
  * dst[i] += src[i] for i < n: accumulation of per-view gradients by callers
  * that run the steps one view at a time. */

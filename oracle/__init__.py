@@ -330,3 +330,40 @@ def step(w, target, views: Optional[Sequence[int]] = None):
 # Stage 2/3 losses around the path (plain numpy, float64)
 from .losses import (blur, l1_dssim_loss, mbc_normality_loss, ssim_map,  # noqa: E402,F401
                      ssim_window, tv_loss)
+
+
+def step_paper_losses(w, target, corner, D: int = 32, lam_ssim: float = 0.25,
+                      lam_tv: float = 0.05, lam_mbc: float = 1.0):
+    """One fwd+bwd iteration with the Stage 2/3 objective of Eq. 14: the
+    L1 + D-SSIM projection loss of Eq. 12 over the batch, lam_mbc times the
+    normality loss of Eq. 13 on the basis volumes and lam_tv times the TV of
+    Eq. 11 on the D^3 block of the reference volume at `corner`.  Returns
+    ({"proj", "tv", "mbc", "total"}, grads) with grads as in step()."""
+    V = len(w.angles)
+    ref, bases = forward_volumes(w)
+    proj = forward(w)
+    l_proj, g_proj = l1_dssim_loss(proj, target, lam_ssim)
+    N = _size(w.grid)
+    g_ref_vol = np.zeros(N)
+    g_bases = [np.zeros_like(b) for b in bases]
+    g_coeff = np.zeros(w.coeff.shape)
+    for v in range(V):
+        cv = w.coeff[v:v + 1]
+        dvf = combine(bases, w.levels, cv, w.grid)
+        gw = project_bwd(g_proj[v:v + 1], w.grid, w.cone, w.angles[v:v + 1])
+        gr, gd = warp_bwd(ref, w.grid, dvf, gw)
+        g_ref_vol += gr.reshape(-1)
+        gb, gc = combine_bwd(bases, w.levels, cv, w.grid, gd)
+        for l in range(len(bases)):
+            g_bases[l] += gb[l]
+        g_coeff[v] = gc[0]
+    l_tv, g_tv = tv_loss(ref.reshape(w.grid.n), corner, D, lam_tv)
+    g_ref_vol += g_tv.reshape(-1)
+    l_mbc, g_mbc = mbc_normality_loss(bases, lam_mbc)
+    for l in range(len(bases)):
+        g_bases[l] += g_mbc[l]
+    grads = {"ref": voxelize_bwd(w.ref, w.grid, w.trunc_k, g_ref_vol),
+             "mbc": [voxelize_bwd(s, g, w.trunc_k, gb) for s, g, gb in zip(w.mbc, w.levels, g_bases)],
+             "coeff": g_coeff}
+    losses = {"proj": l_proj, "tv": l_tv, "mbc": l_mbc, "total": l_proj + l_tv + l_mbc}
+    return losses, grads

@@ -9,6 +9,8 @@
 
 #include <string>
 
+#include <cmath>
+
 #include "pmf_internal.h"
 
 using namespace pmf;
@@ -299,6 +301,74 @@ int pmf_l2_loss(const float *proj, const float *target, int64_t npix, int V, flo
     PMF_CHECK(check_ws(ws, ws_bytes, l2_workspace(npix, V)));
     return hip_status(launch_l2(proj, target, npix, V, loss, g_proj, ws, as_stream(stream)),
                       "l2_loss");
+}
+
+// ------------------------------------------------------ Stage 2/3 loss terms
+size_t pmf_l1_dssim_loss_workspace(int nu, int nv, int V) {
+    if (nu < 1 || nv < 1 || V < 1) return 0;
+    return l1_dssim_workspace(nu, nv, V);
+}
+
+int pmf_l1_dssim_loss(const float *proj, const float *target, int nu, int nv, int V,
+                      float lambda_ssim, float *loss, float *g_proj, void *ws, size_t ws_bytes,
+                      void *stream) {
+    if (nu < 1 || nv < 1 || V < 1) return fail(PMF_EINVAL, "l1_dssim_loss: nu, nv and V must be >= 1");
+    if (!(lambda_ssim >= 0.0f) || !std::isfinite(lambda_ssim))
+        return fail(PMF_EINVAL, "l1_dssim_loss: lambda_ssim must be finite and >= 0");
+    if (!proj || !target || !loss) return fail(PMF_EINVAL, "l1_dssim_loss: null pointer");
+    PMF_CHECK(check_ws(ws, ws_bytes, l1_dssim_workspace(nu, nv, V)));
+    return hip_status(launch_l1_dssim(proj, target, nu, nv, V, lambda_ssim, loss, g_proj, ws,
+                                      as_stream(stream)),
+                      "l1_dssim_loss");
+}
+
+size_t pmf_tv_loss_workspace(int D) {
+    if (D < 1) return 0;
+    return tv_workspace(D);
+}
+
+int pmf_tv_loss(const float *vol, const pmf_grid_t *grid, const int32_t *corner, int D,
+                float weight, float *loss, float *g_vol, void *ws, size_t ws_bytes, void *stream) {
+    PMF_CHECK(check_grid(grid, "grid"));
+    if (!corner) return fail(PMF_EINVAL, "tv_loss: null corner");
+    if (D < 1) return fail(PMF_EINVAL, "tv_loss: D must be >= 1");
+    for (int a = 0; a < 3; ++a)
+        if (corner[a] < 0 || (int64_t)corner[a] + D > grid->n[a])
+            return fail(PMF_EINVAL, "tv_loss: block [%d, %d) outside axis %d of size %d", corner[a],
+                        corner[a] + D, a, grid->n[a]);
+    if (!std::isfinite(weight)) return fail(PMF_EINVAL, "tv_loss: weight must be finite");
+    if (!vol || !loss) return fail(PMF_EINVAL, "tv_loss: null pointer");
+    PMF_CHECK(check_ws(ws, ws_bytes, tv_workspace(D)));
+    const int c[3] = {corner[0], corner[1], corner[2]};
+    return hip_status(launch_tv(vol, make_grid(*grid), c, D, weight, loss, g_vol, ws,
+                                as_stream(stream)),
+                      "tv_loss");
+}
+
+size_t pmf_mbc_normality_loss_workspace(int L, int C) {
+    if (L < 1 || C < 1) return 0;
+    return normality_workspace(L, C);
+}
+
+int pmf_mbc_normality_loss(int L, int C, const float *const *bases, const pmf_grid_t *lvl,
+                           float weight, float *loss, float *const *g_bases, void *ws,
+                           size_t ws_bytes, void *stream) {
+    if (L < 1 || C < 1) return fail(PMF_EINVAL, "mbc_normality_loss: L and C must be >= 1");
+    if (L > MAXL) return fail(PMF_EUNSUPPORTED, "mbc_normality_loss: L <= 4");
+    if (C > 65535) return fail(PMF_EINVAL, "mbc_normality_loss: C too large");
+    if (!bases || !lvl || !loss) return fail(PMF_EINVAL, "mbc_normality_loss: null pointer");
+    if (!std::isfinite(weight)) return fail(PMF_EINVAL, "mbc_normality_loss: weight must be finite");
+    GridK lg[MAXL];
+    for (int l = 0; l < L; ++l) {
+        if (!bases[l]) return fail(PMF_EINVAL, "mbc_normality_loss: null basis pointer %d", l);
+        if (g_bases && !g_bases[l]) return fail(PMF_EINVAL, "mbc_normality_loss: null g_bases[%d]", l);
+        PMF_CHECK(check_grid(&lvl[l], "level grid"));
+        lg[l] = make_grid(lvl[l]);
+    }
+    PMF_CHECK(check_ws(ws, ws_bytes, normality_workspace(L, C)));
+    return hip_status(launch_normality(L, C, bases, lg, weight, loss, g_bases, ws,
+                                       as_stream(stream)),
+                      "mbc_normality_loss");
 }
 
 // ----------------------------------------------------------------- utility

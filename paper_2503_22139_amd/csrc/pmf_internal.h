@@ -327,6 +327,15 @@ hipError_t launch_project_bwd(const float *g_proj, const GridK &g, const ConeK &
                               hipStream_t s, unsigned *vmax = nullptr);
 
 // loss
+size_t l1_dssim_workspace(int nu, int nv, int V);
+hipError_t launch_l1_dssim(const float *proj, const float *target, int nu, int nv, int V,
+                           float lam, float *loss, float *g, void *ws, hipStream_t s);
+size_t tv_workspace(int D);
+hipError_t launch_tv(const float *vol, const GridK &g, const int corner[3], int D, float weight,
+                     float *loss, float *g_vol, void *ws, hipStream_t s);
+size_t normality_workspace(int L, int C);
+hipError_t launch_normality(int L, int C, const float *const *bases, const GridK *lg,
+                            float weight, float *loss, float *const *g, void *ws, hipStream_t s);
 size_t l2_workspace(int64_t npix, int V);
 hipError_t launch_l2(const float *proj, const float *target, int64_t npix, int V, float *loss,
                      float *g, void *ws, hipStream_t s);

@@ -156,6 +156,27 @@ class MotionModel:
         return loss, grads
 
 
+    def step_batched_paper(self, target, corner, D: int = 32, lam_ssim: float = 0.25,
+                           lam_tv: float = 0.05, lam_mbc: float = 1.0):
+        """One iteration with the Stage 2/3 objective (Eq. 14): L1 + D-SSIM
+        projection loss (Eq. 12), lam_mbc x MBC normality (Eq. 13) and lam_tv x
+        TV of the D^3 block of the reference volume at `corner` (Eq. 11); the
+        regularisers add their gradients onto those of the motion path before
+        the voxelization adjoints.  Returns ({"proj", "tv", "mbc"} device
+        scalars, grads)."""
+        ref, bases = self.volumes()
+        proj = ops.pmf_warp_project(ref, self.grid, bases, self.levels, self.coeff, self.cone,
+                                    self.angles)
+        l_proj, g_proj = ops.pmf_l1_dssim_loss(proj, target, lam_ssim)
+        g_ref, g_bases, g_coeff = ops.pmf_warp_project_bwd(ref, self.grid, bases, self.levels,
+                                                           self.coeff, self.cone, self.angles, g_proj)
+        l_tv = ops.pmf_tv_loss(ref, self.grid, corner, D, lam_tv, g_vol=g_ref)
+        l_mbc = ops.pmf_mbc_normality_loss(bases, self.levels, lam_mbc, g_bases=g_bases)
+        grads = self.volumes_bwd(g_ref, g_bases)
+        grads["coeff"] = g_coeff
+        return {"proj": l_proj, "tv": l_tv, "mbc": l_mbc}, grads
+
+
 class MultiScanModel:
     """Several independent scans (different grids, geometries and view counts,
     one motion-model shape L, B) stepped together: per scan the voxelization

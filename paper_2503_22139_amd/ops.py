@@ -90,6 +90,15 @@ _SIGS = {
     "pmf_l2_loss_workspace": ([C.c_int64, C.c_int], _SZ),
     "pmf_l2_loss": ([_P, _P, C.c_int64, C.c_int, _P, _P, _P, _SZ, _P], C.c_int),
     "pmf_accumulate": ([_P, _P, C.c_int64, _P], C.c_int),
+    "pmf_l1_dssim_loss_workspace": ([C.c_int, C.c_int, C.c_int], _SZ),
+    "pmf_l1_dssim_loss": ([_P, _P, C.c_int, C.c_int, C.c_int, C.c_float, _P, _P, _P, _SZ, _P],
+                          C.c_int),
+    "pmf_tv_loss_workspace": ([C.c_int], _SZ),
+    "pmf_tv_loss": ([_P, C.POINTER(PmfGrid), C.POINTER(C.c_int32), C.c_int, C.c_float, _P, _P, _P,
+                     _SZ, _P], C.c_int),
+    "pmf_mbc_normality_loss_workspace": ([C.c_int, C.c_int], _SZ),
+    "pmf_mbc_normality_loss": ([C.c_int, C.c_int, _P, C.POINTER(PmfGrid), C.c_float, _P, _P, _P,
+                                _SZ, _P], C.c_int),
     "pmf_profile": ([C.c_int], C.c_int),
     "pmf_profile_read": ([C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
     "pmf_profile_names": ([C.c_char_p, _SZ], _SZ),
@@ -311,6 +320,49 @@ def pmf_l2_loss(proj, target, want_grad: bool = True):
     _check(lib().pmf_l2_loss(_ptr(proj), _ptr(target), npix, V, _ptr(loss), _ptr(g),
                              C.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
     return loss, g
+
+
+def pmf_l1_dssim_loss(proj, target, lambda_ssim: float = 0.25, want_grad: bool = True):
+    """L1 + lambda_ssim * D-SSIM of a batch of views (Eq. 10 / 12): (loss, g_proj)."""
+    V, nv, nu = proj.shape
+    loss = torch.empty((), device=proj.device, dtype=torch.float32)
+    g = torch.empty_like(proj) if want_grad else None
+    nbytes = lib().pmf_l1_dssim_loss_workspace(nu, nv, V)
+    ws = workspace(nbytes, proj.device)
+    _check(lib().pmf_l1_dssim_loss(_ptr(proj), _ptr(target), nu, nv, V, float(lambda_ssim),
+                                   _ptr(loss), _ptr(g), C.c_void_p(ws.data_ptr()), ws.numel(),
+                                   _stream()))
+    return loss, g
+
+
+def pmf_tv_loss(vol, grid: Grid, corner, D: int, weight: float, g_vol=None):
+    """weight * TV of the D^3 block of vol at corner (Eq. 11); adds
+    weight * d TV / d vol into g_vol when given.  Returns the loss."""
+    loss = torch.empty((), device=vol.device, dtype=torch.float32)
+    g = make_grid(grid)
+    c = (C.c_int32 * 3)(*[int(x) for x in corner])
+    nbytes = lib().pmf_tv_loss_workspace(int(D))
+    ws = workspace(nbytes, vol.device)
+    _check(lib().pmf_tv_loss(_ptr(vol), C.byref(g), c, int(D), float(weight), _ptr(loss),
+                             _ptr(g_vol), C.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return loss
+
+
+def pmf_mbc_normality_loss(bases, levels, weight: float, g_bases=None):
+    """weight * MBC normality loss (Eq. 13) of the basis volumes [C][n_l];
+    adds weight * d loss / d E into g_bases when given.  Returns the loss."""
+    L = len(bases)
+    Cc = bases[0].shape[0]
+    loss = torch.empty((), device=bases[0].device, dtype=torch.float32)
+    lv = _levels(levels)
+    nbytes = lib().pmf_mbc_normality_loss_workspace(L, Cc)
+    ws = workspace(nbytes, bases[0].device)
+    for b in list(bases) + list(g_bases or []):
+        _ptr(b)
+    _check(lib().pmf_mbc_normality_loss(L, Cc, _ptr_array(bases), lv, float(weight), _ptr(loss),
+                                        _ptr_array(g_bases) if g_bases is not None else None,
+                                        C.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return loss
 
 
 def pmf_accumulate(dst, src):

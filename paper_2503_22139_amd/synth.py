@@ -368,3 +368,22 @@ def random_volume(seed: int, shape, lo=0.0, hi=1.0) -> np.ndarray:
 def random_normal(seed: int, shape, sigma=1.0) -> np.ndarray:
     rng = np.random.default_rng(seed)
     return _f32(rng.normal(0.0, sigma, shape))
+
+
+def projection_like(seed: int, V: int, nv: int, nu: int, peak: float = 10.0) -> np.ndarray:
+    """Seeded smooth non-negative images with the look of cone-beam line
+    integrals (a body-shaped ellipse of level ~0.6 peak plus a few bright
+    blobs, zero outside), [V][nv][nu] float32."""
+    rng = np.random.default_rng(seed)
+    vv, uu = np.meshgrid(np.linspace(-1, 1, nv), np.linspace(-1, 1, nu), indexing="ij")
+    out = np.zeros((V, nv, nu))
+    for v in range(V):
+        a, b = rng.uniform(0.55, 0.8), rng.uniform(0.7, 0.95)
+        r2 = (uu / a) ** 2 + (vv / b) ** 2
+        img = 0.6 * peak * np.sqrt(np.clip(1.0 - r2, 0.0, None))
+        for _ in range(6):
+            cu, cv = rng.uniform(-0.5, 0.5, 2)
+            s = rng.uniform(0.03, 0.15)
+            img += rng.uniform(0.1, 0.4) * peak * np.exp(-((uu - cu) ** 2 + (vv - cv) ** 2) / (2 * s * s))
+        out[v] = img
+    return _f32(out)

@@ -188,3 +188,43 @@ def test_autotune_rejects_bad_arguments(lib):
     assert lib.pmf_autotune_project(p, C.byref(g), C.byref(cn), p, 2, p, p, p, p, big, 0, None, None) == ops.PMF_EINVAL
     assert "reps" in err(lib)
     assert lib.pmf_autotune_project(p, C.byref(g), C.byref(cn), p, 2, p, p, p, p, 1, 1, None, None) == ops.PMF_EWORKSPACE
+
+
+def test_loss_terms_reject_bad_arguments(lib):
+    p = C.c_void_p(256)
+    ws = C.c_void_p(256)
+    big = 1 << 40
+    # L1 + D-SSIM: sizes, lambda, null pointers, workspace
+    assert lib.pmf_l1_dssim_loss(p, p, 0, 4, 1, 0.25, p, p, ws, big, None) == ops.PMF_EINVAL
+    assert lib.pmf_l1_dssim_loss(p, p, 4, 4, 1, -1.0, p, p, ws, big, None) == ops.PMF_EINVAL
+    assert lib.pmf_l1_dssim_loss(p, p, 4, 4, 1, float("nan"), p, p, ws, big, None) == ops.PMF_EINVAL
+    assert lib.pmf_l1_dssim_loss(None, p, 4, 4, 1, 0.25, p, p, ws, big, None) == ops.PMF_EINVAL
+    need = lib.pmf_l1_dssim_loss_workspace(4, 4, 1)
+    assert need > 0 and lib.pmf_l1_dssim_loss_workspace(0, 4, 1) == 0
+    assert lib.pmf_l1_dssim_loss(p, p, 4, 4, 1, 0.25, p, p, ws, need - 1, None) == ops.PMF_EWORKSPACE
+    # TV: block outside the grid, D < 1, null corner / volume, workspace
+    g = grid(n=(8, 8, 8))
+    c = (C.c_int32 * 3)(0, 0, 0)
+    assert lib.pmf_tv_loss(p, C.byref(g), c, 9, 0.05, p, p, ws, big, None) == ops.PMF_EINVAL
+    assert "outside" in err(lib)
+    c2 = (C.c_int32 * 3)(0, 5, 0)
+    assert lib.pmf_tv_loss(p, C.byref(g), c2, 4, 0.05, p, p, ws, big, None) == ops.PMF_EINVAL
+    c3 = (C.c_int32 * 3)(-1, 0, 0)
+    assert lib.pmf_tv_loss(p, C.byref(g), c3, 4, 0.05, p, p, ws, big, None) == ops.PMF_EINVAL
+    assert lib.pmf_tv_loss(p, C.byref(g), c, 0, 0.05, p, p, ws, big, None) == ops.PMF_EINVAL
+    assert lib.pmf_tv_loss(p, C.byref(g), None, 4, 0.05, p, p, ws, big, None) == ops.PMF_EINVAL
+    assert lib.pmf_tv_loss(None, C.byref(g), c, 4, 0.05, p, p, ws, big, None) == ops.PMF_EINVAL
+    assert lib.pmf_tv_loss(p, C.byref(g), c, 4, float("inf"), p, p, ws, big, None) == ops.PMF_EINVAL
+    assert lib.pmf_tv_loss(p, C.byref(g), c, 4, 0.05, p, p, ws, 0, None) == ops.PMF_EWORKSPACE
+    # normality: L, C, null pointers, L > 4
+    lv = (ops.PmfGrid * 2)(grid(n=(4, 4, 4)), grid(n=(8, 8, 8)))
+    bp = (C.c_void_p * 2)(256, 256)
+    gp = (C.c_void_p * 2)(256, None)
+    assert lib.pmf_mbc_normality_loss(0, 3, bp, lv, 1.0, p, None, ws, big, None) == ops.PMF_EINVAL
+    assert lib.pmf_mbc_normality_loss(2, 0, bp, lv, 1.0, p, None, ws, big, None) == ops.PMF_EINVAL
+    assert lib.pmf_mbc_normality_loss(5, 3, bp, lv, 1.0, p, None, ws, big, None) == ops.PMF_EUNSUPPORTED
+    assert lib.pmf_mbc_normality_loss(2, 3, None, lv, 1.0, p, None, ws, big, None) == ops.PMF_EINVAL
+    assert lib.pmf_mbc_normality_loss(2, 3, bp, lv, 1.0, p, gp, ws, big, None) == ops.PMF_EINVAL
+    assert "g_bases[1]" in err(lib)
+    need = lib.pmf_mbc_normality_loss_workspace(2, 3)
+    assert lib.pmf_mbc_normality_loss(2, 3, bp, lv, 1.0, p, None, ws, need - 1, None) == ops.PMF_EWORKSPACE
