@@ -195,18 +195,22 @@ __global__ __launch_bounds__(SS_THREADS) void k_ssim_bwd(const float *__restrict
 }
 
 // loss = (1/V) sum_v [ sum|x - y| / npix + lam (1 - sum S / npix) ]: one
-// thread per view over its tiles in order, then the views in order.
+// wave per view sums its tiles (lane-strided, then a fixed DPP tree), then
+// one thread sums the views in order.
 __global__ __launch_bounds__(256) void k_ssim_final(const float *__restrict__ partial, int V,
                                                     int ntiles, float inv_npix, float lam,
                                                     float *__restrict__ vterm,
                                                     float *__restrict__ loss) {
-    for (int v = threadIdx.x; v < V; v += blockDim.x) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int v = wave; v < V; v += 4) {
         float a = 0.0f, s = 0.0f;
-        for (int t = 0; t < ntiles; ++t) {
+        for (int t = lane; t < ntiles; t += 64) {
             a += partial[2 * ((int64_t)v * ntiles + t)];
             s += partial[2 * ((int64_t)v * ntiles + t) + 1];
         }
-        vterm[v] = a * inv_npix + lam * (1.0f - s * inv_npix);
+        a = wave_sum_lane63(a);
+        s = wave_sum_lane63(s);
+        if (lane == 63) vterm[v] = a * inv_npix + lam * (1.0f - s * inv_npix);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -328,7 +332,7 @@ hipError_t launch_tv(const float *vol, const GridK &gk, const int corner[3], int
 }
 
 // ------------------------------------------------------- MBC normality (Eq. 13)
-constexpr int NRM_BLOCKS = 64;          // partial sums per channel
+constexpr int NRM_BLOCKS = 256;         // partial sums per channel
 
 // Sum of squares of each channel of one level ([C][N]): NRM_BLOCKS fixed
 // strided partials per channel.
@@ -346,16 +350,21 @@ __global__ __launch_bounds__(256) void k_sumsq(const float *__restrict__ e, int6
     if (threadIdx.x == 0) partial[(int64_t)ch * NRM_BLOCKS + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// Per channel |e|^2 in order, the factor weight * 4 (|e|^2 - 1) / nch of its
-// gradient, and loss = weight * sum (|e|^2 - 1)^2 / nch.
+// Per channel |e|^2 (one wave per channel, fixed tree), the factor
+// weight * 4 (|e|^2 - 1) / nch of its gradient, and
+// loss = weight * sum (|e|^2 - 1)^2 / nch.
 __global__ __launch_bounds__(256) void k_norm_final(const float *__restrict__ partial, int nch,
                                                     float weight, float *__restrict__ fac,
                                                     float *__restrict__ loss) {
-    for (int ch = threadIdx.x; ch < nch; ch += blockDim.x) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int ch = wave; ch < nch; ch += 4) {
         float s = 0.0f;
-        for (int b = 0; b < NRM_BLOCKS; ++b) s += partial[(int64_t)ch * NRM_BLOCKS + b];
-        fac[nch + ch] = (s - 1.0f) * (s - 1.0f);
-        fac[ch] = weight * 4.0f * (s - 1.0f) / (float)nch;
+        for (int b = lane; b < NRM_BLOCKS; b += 64) s += partial[(int64_t)ch * NRM_BLOCKS + b];
+        s = wave_sum_lane63(s);
+        if (lane == 63) {
+            fac[nch + ch] = (s - 1.0f) * (s - 1.0f);
+            fac[ch] = weight * 4.0f * (s - 1.0f) / (float)nch;
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -365,13 +374,16 @@ __global__ __launch_bounds__(256) void k_norm_final(const float *__restrict__ pa
     }
 }
 
-__global__ __launch_bounds__(256) void k_norm_grad(const float *__restrict__ e, int64_t N, int C,
+// g[c][j] += fac[c] * e[c][j]; grid (blocks per channel, C), 4 values per thread.
+__global__ __launch_bounds__(256) void k_norm_grad(const float *__restrict__ e, int64_t N,
                                                    const float *__restrict__ fac,
                                                    float *__restrict__ g) {
-    const int64_t total = (int64_t)C * N;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total;
-         i += (int64_t)gridDim.x * 256)
-        g[i] = fmaf(fac[i / N], e[i], g[i]);
+    const int ch = blockIdx.y;
+    const float f = fac[ch];
+    const float *ec = e + (int64_t)ch * N;
+    float *gc = g + (int64_t)ch * N;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256)
+        gc[i] = fmaf(f, ec[i], gc[i]);
 }
 
 size_t normality_workspace(int L, int C) {
@@ -395,10 +407,11 @@ hipError_t launch_normality(int L, int C, const float *const *bases, const GridK
     if ((e = hipGetLastError()) != hipSuccess || !g) return e;
     for (int l = 0; l < L; ++l) {
         const int64_t N = grid_size(lg[l]);
-        const int64_t blocks = std::min<int64_t>(((int64_t)C * N + 255) / 256, 8192);
+        const int64_t blocks = std::min<int64_t>((N + 255) / 256, 1024);
         {
             ProfScope prof_("normality", s);
-            k_norm_grad<<<(unsigned)blocks, 256, 0, s>>>(bases[l], N, C, fac + (int64_t)l * C, g[l]);
+            k_norm_grad<<<dim3((unsigned)blocks, (unsigned)C), 256, 0, s>>>(
+                bases[l], N, fac + (int64_t)l * C, g[l]);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }

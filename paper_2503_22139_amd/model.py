@@ -243,19 +243,22 @@ class GraphStep:
     with fill kernels, never with memset nodes.
     """
 
-    def __init__(self, model, target):
+    def __init__(self, model, target, step=None):
+        """step(target) is the iteration to capture (model.step_batched by
+        default, e.g. a closure over model.step_batched_paper)."""
         self.model = model
         self.target = _clone(target)
+        fn = model.step_batched if step is None else step
         was = ops.pmf_profile(False)
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):
-            model.step_batched(self.target)          # warm-up: allocate workspaces
+            fn(self.target)                          # warm-up: allocate workspaces
         torch.cuda.current_stream().wait_stream(s)
         torch.cuda.synchronize()
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
-            self.out = model.step_batched(self.target)
+            self.out = fn(self.target)
         torch.cuda.synchronize()
         # the graph holds raw pointers into the scratch buffers: keep them alive
         self._scratch = dict(ops._ws_cache)
