@@ -193,6 +193,33 @@ size_t pmf_l2_loss_workspace(int64_t npix, int V);
 int pmf_l2_loss(const float *proj, const float *target, int64_t npix, int V, float *loss,
                 float *g_proj, void *ws, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------- Stage 1 rasterizer
+ * X-ray Gaussian splatting (Sec. 2.2, Eq. 7-9): per view each Gaussian of g
+ * (c must be 1: its density rho) is mapped by the local affine approximation
+ * of the cone-beam projection (Eq. 8; geometry of pmf_project: source at
+ * SAD (cos th, sin th, 0), flat detector at SDD, pixel centres as for the
+ * ray march) to a 2-D Gaussian with centre phi(p), covariance Sigma^ (the
+ * projected Sigma~ = J W Sigma W^T J^T without its ray row and column) and
+ * amplitude rho sqrt(2 pi |Sigma~| / |Sigma^|) (Eq. 9); each pixel of proj
+ * [V][nv][nu] (overwritten) is the sum of these at its centre, each cut to
+ * its ellipse (x - mu)^T Sigma^-1 (x - mu) <= trunc_k^2 (INFINITY: uncut;
+ * every Gaussian then covers the whole detector).  Gaussians not in front of
+ * the source are skipped.  Pixel sums are float additions in an order that
+ * depends on scheduling (results vary in the last bits between runs).
+ * pmf_rasterize_bwd overwrites grad (shapes of g) with the gradients of
+ * sum(g_proj * proj), summed over the V views in order (the mask is not
+ * differentiated).  Errors: PMF_EINVAL for null pointers, c != 1, V < 1,
+ * trunc_k <= 0 or a bad cone (0 < SAD < SDD, du, dv > 0, finite offsets);
+ * PMF_EUNSUPPORTED for m * V >= 2^27 or detectors wider than 65536;
+ * PMF_EWORKSPACE if the workspace from pmf_rasterize_workspace() is missing
+ * or short.  m = 0 writes zeros. */
+size_t pmf_rasterize_workspace(int64_t m, const pmf_cone_t *cone, int V);
+int pmf_rasterize(const pmf_gauss_t *g, const pmf_cone_t *cone, const float *angles, int V,
+                  float trunc_k, float *proj, void *ws, size_t ws_bytes, void *stream);
+int pmf_rasterize_bwd(const pmf_gauss_t *g, const pmf_cone_t *cone, const float *angles, int V,
+                      float trunc_k, const float *g_proj, const pmf_gauss_grad_t *grad, void *ws,
+                      size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------- Stage 2/3 loss terms
  * The loss terms that surround the motion path in Stages 2 and 3 (Sec.
  * 2.3.2, Eq. 10-14).  The paper leaves their discretisation open; the

@@ -77,11 +77,16 @@ def splat_params(mean, scale, quat, value, cone, theta: float):
 
 
 def rasterize_t(mean, scale, quat, value, cone, angles: Sequence[float], k: float = 3.0,
-                chunk: int = 256) -> torch.Tensor:
-    """Projections [V][nv][nu] (torch, differentiable in the parameters)."""
-    iv, iu = torch.meshgrid(torch.arange(cone.nv, dtype=torch.float64),
-                            torch.arange(cone.nu, dtype=torch.float64), indexing="ij")
-    pix = torch.stack([iu.reshape(-1), iv.reshape(-1)], -1)     # [P][2] (u, v)
+                chunk: int = 256, pixels=None) -> torch.Tensor:
+    """Projections [V][nv][nu] (torch, differentiable in the parameters), or
+    with pixels = [P][2] integer (iu, iv) pairs the values at those pixels
+    only, [V][P]."""
+    if pixels is None:
+        iv, iu = torch.meshgrid(torch.arange(cone.nv, dtype=torch.float64),
+                                torch.arange(cone.nu, dtype=torch.float64), indexing="ij")
+        pix = torch.stack([iu.reshape(-1), iv.reshape(-1)], -1)     # [P][2] (u, v)
+    else:
+        pix = torch.tensor(np.asarray(pixels, np.float64))
     out = []
     for th in angles:
         mu, Sh, rho, front = splat_params(mean, scale, quat, value, cone, float(th))
@@ -96,7 +101,7 @@ def rasterize_t(mean, scale, quat, value, cone, angles: Sequence[float], k: floa
                 keep = keep & (m.detach() <= k * k)
             e = torch.where(keep, torch.exp(-0.5 * m), torch.zeros_like(m))
             img = img + (rho[sl, None] * e).sum(0)
-        out.append(img.reshape(cone.nv, cone.nu))
+        out.append(img.reshape(cone.nv, cone.nu) if pixels is None else img)
     return torch.stack(out)
 
 
@@ -105,11 +110,12 @@ def _tensors(gs):
     return f(gs.mean), f(gs.scale), f(gs.quat), f(gs.value)
 
 
-def rasterize(gs, cone, angles, k: float = 3.0) -> np.ndarray:
-    """Eq. 9 projections of GaussSet gs, [V][nv][nu] float64."""
+def rasterize(gs, cone, angles, k: float = 3.0, pixels=None) -> np.ndarray:
+    """Eq. 9 projections of GaussSet gs, [V][nv][nu] float64 (or [V][P] at
+    the given (iu, iv) pixels)."""
     with torch.no_grad():
         t = _tensors(gs)
-        return rasterize_t(*t, cone, angles, k).numpy()
+        return rasterize_t(*t, cone, angles, k, pixels=pixels).numpy()
 
 
 def rasterize_bwd(gs, cone, angles, k: float, g_proj) -> Dict[str, np.ndarray]:

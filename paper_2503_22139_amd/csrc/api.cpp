@@ -303,6 +303,59 @@ int pmf_l2_loss(const float *proj, const float *target, int64_t npix, int V, flo
                       "l2_loss");
 }
 
+// ------------------------------------------------------ Stage 1 rasterizer
+static int check_rast(const pmf_gauss_t *gs, const pmf_cone_t *c, const float *angles, int V,
+                      float k, const char *what) {
+    PMF_CHECK(check_gauss(gs));
+    if (gs->c != 1) return fail(PMF_EINVAL, "%s: the rasterizer draws one density channel (c = 1)", what);
+    PMF_CHECK(check_k(k));
+    if (!c) return fail(PMF_EINVAL, "%s: null cone", what);
+    if (!(std::isfinite(c->sad) && std::isfinite(c->sdd) && c->sad > 0.0f && c->sdd > c->sad))
+        return fail(PMF_EINVAL, "%s: need 0 < SAD < SDD", what);
+    if (c->nu < 1 || c->nv < 1) return fail(PMF_EINVAL, "%s: nu, nv must be >= 1", what);
+    if (c->nu > 65536 || c->nv > 65536) return fail(PMF_EUNSUPPORTED, "%s: nu, nv <= 65536", what);
+    if (!(c->du > 0.0f && c->dv > 0.0f && std::isfinite(c->du) && std::isfinite(c->dv)))
+        return fail(PMF_EINVAL, "%s: du, dv must be > 0", what);
+    if (!std::isfinite(c->off_u) || !std::isfinite(c->off_v))
+        return fail(PMF_EINVAL, "%s: offsets must be finite", what);
+    if (V < 1) return fail(PMF_EINVAL, "%s: V must be >= 1", what);
+    if (gs->m * V >= ((int64_t)1 << 31) / 16)
+        return fail(PMF_EUNSUPPORTED, "%s: m * V too large", what);
+    if (!angles) return fail(PMF_EINVAL, "%s: null angles", what);
+    return PMF_OK;
+}
+
+size_t pmf_rasterize_workspace(int64_t m, const pmf_cone_t *cone, int V) {
+    if (m < 0 || !cone || V < 1 || cone->nu < 1 || cone->nv < 1) return 0;
+    return rasterize_workspace(m, *cone, V);
+}
+
+int pmf_rasterize(const pmf_gauss_t *gs, const pmf_cone_t *cone, const float *angles, int V,
+                  float trunc_k, float *proj, void *ws, size_t ws_bytes, void *stream) {
+    PMF_CHECK(check_rast(gs, cone, angles, V, trunc_k, "rasterize"));
+    if (!proj) return fail(PMF_EINVAL, "rasterize: null proj");
+    const int64_t npix = (int64_t)cone->nu * cone->nv * V;
+    if (gs->m == 0)
+        return hip_status(launch_fill(proj, npix, 0.0f, as_stream(stream)), "rasterize");
+    PMF_CHECK(check_ws(ws, ws_bytes, rasterize_workspace(gs->m, *cone, V)));
+    return hip_status(launch_rasterize(*gs, *cone, angles, V, trunc_k, proj, ws, as_stream(stream)),
+                      "rasterize");
+}
+
+int pmf_rasterize_bwd(const pmf_gauss_t *gs, const pmf_cone_t *cone, const float *angles, int V,
+                      float trunc_k, const float *g_proj, const pmf_gauss_grad_t *grad, void *ws,
+                      size_t ws_bytes, void *stream) {
+    PMF_CHECK(check_rast(gs, cone, angles, V, trunc_k, "rasterize_bwd"));
+    if (!grad) return fail(PMF_EINVAL, "rasterize_bwd: null gradient struct");
+    if (gs->m == 0) return ok();
+    if (!g_proj || !grad->mean || !grad->scale || !grad->quat || !grad->value)
+        return fail(PMF_EINVAL, "rasterize_bwd: null array");
+    PMF_CHECK(check_ws(ws, ws_bytes, rasterize_workspace(gs->m, *cone, V)));
+    return hip_status(launch_rasterize_bwd(*gs, *cone, angles, V, trunc_k, g_proj, *grad, ws,
+                                           as_stream(stream)),
+                      "rasterize_bwd");
+}
+
 // ------------------------------------------------------ Stage 2/3 loss terms
 size_t pmf_l1_dssim_loss_workspace(int nu, int nv, int V) {
     if (nu < 1 || nv < 1 || V < 1) return 0;

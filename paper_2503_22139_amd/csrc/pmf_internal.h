@@ -327,6 +327,12 @@ hipError_t launch_project_bwd(const float *g_proj, const GridK &g, const ConeK &
                               hipStream_t s, unsigned *vmax = nullptr);
 
 // loss
+size_t rasterize_workspace(int64_t m, const pmf_cone_t &c, int V);
+hipError_t launch_rasterize(const pmf_gauss_t &gs, const pmf_cone_t &c, const float *angles,
+                            int V, float k, float *proj, void *ws, hipStream_t s);
+hipError_t launch_rasterize_bwd(const pmf_gauss_t &gs, const pmf_cone_t &c, const float *angles,
+                                int V, float k, const float *g_proj, const pmf_gauss_grad_t &gg,
+                                void *ws, hipStream_t s);
 size_t l1_dssim_workspace(int nu, int nv, int V);
 hipError_t launch_l1_dssim(const float *proj, const float *target, int nu, int nv, int V,
                            float lam, float *loss, float *g, void *ws, hipStream_t s);

@@ -90,6 +90,11 @@ _SIGS = {
     "pmf_l2_loss_workspace": ([C.c_int64, C.c_int], _SZ),
     "pmf_l2_loss": ([_P, _P, C.c_int64, C.c_int, _P, _P, _P, _SZ, _P], C.c_int),
     "pmf_accumulate": ([_P, _P, C.c_int64, _P], C.c_int),
+    "pmf_rasterize_workspace": ([C.c_int64, C.POINTER(PmfCone), C.c_int], _SZ),
+    "pmf_rasterize": ([C.POINTER(PmfGauss), C.POINTER(PmfCone), _P, C.c_int, C.c_float, _P, _P,
+                       _SZ, _P], C.c_int),
+    "pmf_rasterize_bwd": ([C.POINTER(PmfGauss), C.POINTER(PmfCone), _P, C.c_int, C.c_float, _P,
+                           C.POINTER(PmfGaussGrad), _P, _SZ, _P], C.c_int),
     "pmf_l1_dssim_loss_workspace": ([C.c_int, C.c_int, C.c_int], _SZ),
     "pmf_l1_dssim_loss": ([_P, _P, C.c_int, C.c_int, C.c_int, C.c_float, _P, _P, _P, _SZ, _P],
                           C.c_int),
@@ -320,6 +325,34 @@ def pmf_l2_loss(proj, target, want_grad: bool = True):
     _check(lib().pmf_l2_loss(_ptr(proj), _ptr(target), npix, V, _ptr(loss), _ptr(g),
                              C.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
     return loss, g
+
+
+def pmf_rasterize(mean, scale, quat, value, cone: Cone, angles, trunc_k: float = 3.0, out=None):
+    """X-ray Gaussian splatting (Eq. 9) of V views: [V][nv][nu]."""
+    V = angles.numel()
+    if out is None:
+        out = torch.empty((V, cone.nv, cone.nu), device=mean.device, dtype=torch.float32)
+    c = make_cone(cone)
+    gs = _gauss(mean, scale, quat, value)
+    ws = workspace(lib().pmf_rasterize_workspace(mean.shape[0], C.byref(c), V), mean.device)
+    _check(lib().pmf_rasterize(C.byref(gs), C.byref(c), _ptr(angles), V, float(trunc_k), _ptr(out),
+                               C.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return out
+
+
+def pmf_rasterize_bwd(mean, scale, quat, value, cone: Cone, angles, trunc_k: float, g_proj):
+    """Gradients of sum(g_proj * rasterize) w.r.t. (mean, scale, quat, value)."""
+    V = angles.numel()
+    gm, gsc, gq, gv = (torch.empty_like(mean), torch.empty_like(scale), torch.empty_like(quat),
+                       torch.empty_like(value))
+    c = make_cone(cone)
+    gs = _gauss(mean, scale, quat, value)
+    gr = PmfGaussGrad(_ptr(gm), _ptr(gsc), _ptr(gq), _ptr(gv))
+    ws = workspace(lib().pmf_rasterize_workspace(mean.shape[0], C.byref(c), V), mean.device)
+    _check(lib().pmf_rasterize_bwd(C.byref(gs), C.byref(c), _ptr(angles), V, float(trunc_k),
+                                   _ptr(g_proj.contiguous()), C.byref(gr),
+                                   C.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return gm, gsc, gq, gv
 
 
 def pmf_l1_dssim_loss(proj, target, lambda_ssim: float = 0.25, want_grad: bool = True):

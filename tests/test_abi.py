@@ -228,3 +228,29 @@ def test_loss_terms_reject_bad_arguments(lib):
     assert "g_bases[1]" in err(lib)
     need = lib.pmf_mbc_normality_loss_workspace(2, 3)
     assert lib.pmf_mbc_normality_loss(2, 3, bp, lv, 1.0, p, None, ws, need - 1, None) == ops.PMF_EWORKSPACE
+
+
+def test_rasterize_rejects_bad_arguments(lib):
+    p = C.c_void_p(256)
+    ws = C.c_void_p(256)
+    big = 1 << 40
+    gs1 = ops.PmfGauss(p, p, p, p, 10, 1)
+    gs3 = ops.PmfGauss(p, p, p, p, 10, 3)
+    cone = ops.make_cone(Cone(1000.0, 1500.0, 32, 24, 1.0, 1.0))
+    bad = ops.make_cone(Cone(1000.0, 900.0, 32, 24, 1.0, 1.0))
+    gg = ops.PmfGaussGrad(p, p, p, p)
+    assert lib.pmf_rasterize(C.byref(gs3), C.byref(cone), p, 2, 3.0, p, ws, big, None) == ops.PMF_EINVAL
+    assert "c = 1" in err(lib)
+    assert lib.pmf_rasterize(C.byref(gs1), C.byref(bad), p, 2, 3.0, p, ws, big, None) == ops.PMF_EINVAL
+    assert lib.pmf_rasterize(C.byref(gs1), C.byref(cone), p, 0, 3.0, p, ws, big, None) == ops.PMF_EINVAL
+    assert lib.pmf_rasterize(C.byref(gs1), C.byref(cone), p, 2, 0.0, p, ws, big, None) == ops.PMF_EINVAL
+    assert lib.pmf_rasterize(C.byref(gs1), C.byref(cone), None, 2, 3.0, p, ws, big, None) == ops.PMF_EINVAL
+    assert lib.pmf_rasterize(C.byref(gs1), C.byref(cone), p, 2, 3.0, None, ws, big, None) == ops.PMF_EINVAL
+    need = lib.pmf_rasterize_workspace(10, C.byref(cone), 2)
+    assert need > 0
+    assert lib.pmf_rasterize(C.byref(gs1), C.byref(cone), p, 2, 3.0, p, ws, need - 1, None) == ops.PMF_EWORKSPACE
+    assert lib.pmf_rasterize_bwd(C.byref(gs1), C.byref(cone), p, 2, 3.0, p, None, ws, big, None) == ops.PMF_EINVAL
+    assert lib.pmf_rasterize_bwd(C.byref(gs1), C.byref(cone), p, 2, 3.0, None, C.byref(gg), ws, big, None) == ops.PMF_EINVAL
+    assert lib.pmf_rasterize_bwd(C.byref(gs1), C.byref(cone), p, 2, 3.0, p, C.byref(gg), ws, need - 1, None) == ops.PMF_EWORKSPACE
+    huge = ops.PmfGauss(p, p, p, p, 1 << 26, 1)
+    assert lib.pmf_rasterize(C.byref(huge), C.byref(cone), p, 4, 3.0, p, ws, big, None) == ops.PMF_EUNSUPPORTED
