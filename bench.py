@@ -199,6 +199,40 @@ def extras(steps: int):
           file=sys.stderr, flush=True)
     del gs, mp, tp
     torch.cuda.empty_cache()
+    # Stage 1 (Eq. 10-11): the 200k reference Gaussians rasterized at one
+    # random view of the 660-view scan per iteration, L1 + 0.25 D-SSIM, and
+    # 0.05 TV of a random 32^3 sub-volume voxelized from the same Gaussians
+    from paper_2503_22139_amd.model import Stage1Model
+    w2 = synth.c2()
+    s1 = Stage1Model(w2)
+    rng1 = np.random.default_rng(98)
+    views = synth.scan_angle(rng1.integers(0, 660, steps + 8))
+    tgt1 = ops.pmf_rasterize(s1.ref.mean, s1.ref.scale, s1.ref.quat, s1.ref.value * 1.05,
+                             w2.cone, torch.from_numpy(np.asarray(views[:1], np.float32)).cuda())
+    cs = [tuple(int(rng1.integers(0, n - 32 + 1)) for n in w2.grid.n) for _ in range(steps + 8)]
+    angs = [torch.from_numpy(np.asarray([a], np.float32)).cuda() for a in views]
+    it1 = iter(range(steps + 8))
+
+    def stage1():
+        i = next(it1)
+        return s1.step(tgt1, angs[i], cs[i])
+    ms1 = _timed(stage1, steps)
+    ops.pmf_profile(True)
+    s1.step(tgt1, angs[0], cs[0])
+    torch.cuda.synchronize()
+    ops.pmf_profile(False)
+    k1 = {}
+    for k in ("rasterize_bin", "rasterize", "rasterize_bwd", "ssim_fwd", "ssim_bwd", "tv",
+              "voxelize_tile", "voxelize_bwd"):
+        tot, cnt = ops.pmf_profile_read(k)
+        k1[k] = tot
+    out["stage1_step"] = {
+        "ms": ms1, "iterations_per_s": 1e3 / ms1, "gaussians": w2.ref.m, "kernels_ms": k1,
+        "what": "Stage 1 iteration: rasterizer (Eq. 9) fwd+bwd at one random view, L1 + 0.25 "
+                "D-SSIM, 0.05 TV of a random 32^3 sub-volume voxelized from the Gaussians; eager"}
+    print(f"[bench] stage1_step {ms1:.2f} ms (kernels {k1})", file=sys.stderr, flush=True)
+    del s1, tgt1
+    torch.cuda.empty_cache()
     wb = synth.headline(nbases=1)
     mb = MotionModel(wb)
     tb = torch.from_numpy(synth.random_volume(95, (len(wb.angles), wb.cone.nv, wb.cone.nu),

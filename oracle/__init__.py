@@ -367,3 +367,26 @@ def step_paper_losses(w, target, corner, D: int = 32, lam_ssim: float = 0.25,
              "coeff": g_coeff}
     losses = {"proj": l_proj, "tv": l_tv, "mbc": l_mbc, "total": l_proj + l_tv + l_mbc}
     return losses, grads
+
+
+def stage1_step(w, target, angle: float, corner, D: int = 32, lam_ssim: float = 0.25,
+                lam_tv: float = 0.05):
+    """One Stage 1 iteration (Eq. 10-11): the rasterized view (Eq. 9) of the
+    reference Gaussians against the measured projection with L1 + lam_ssim
+    D-SSIM, plus lam_tv times the TV of the D^3 block of the reference grid
+    at `corner`, voxelized from the same Gaussians.  Returns
+    ({"proj", "tv"}, {"mean", "scale", "quat", "value"})."""
+    from types import SimpleNamespace
+    from . import rasterize as _r
+    p = _r.rasterize(w.ref, w.cone, [angle], w.trunc_k)
+    l_proj, g_proj = l1_dssim_loss(p, target, lam_ssim)
+    grads = _r.rasterize_bwd(w.ref, w.cone, [angle], w.trunc_k, g_proj)
+    c = [w.grid.center[a] + (corner[a] + (D - 1) / 2.0 - (w.grid.n[a] - 1) / 2.0) * w.grid.h[a]
+         for a in range(3)]
+    sg = SimpleNamespace(n=(D, D, D), h=tuple(w.grid.h), center=tuple(c))
+    sub = voxelize(w.ref, sg, w.trunc_k)[0].reshape(D, D, D)
+    l_tv, g_sub = tv_loss(sub, (0, 0, 0), D, lam_tv)
+    gt = voxelize_bwd(w.ref, sg, w.trunc_k, g_sub.reshape(1, -1))
+    for name in grads:
+        grads[name] = grads[name] + gt[name]
+    return {"proj": l_proj, "tv": l_tv}, grads

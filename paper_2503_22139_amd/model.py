@@ -177,6 +177,46 @@ class MotionModel:
         return {"proj": l_proj, "tv": l_tv, "mbc": l_mbc}, grads
 
 
+def sub_grid(grid, corner, D: int):
+    """The D^3 block of `grid` whose first voxel is `corner`, as a grid of its own."""
+    from .synth import Grid
+    c = [grid.center[a] + (corner[a] + (D - 1) / 2.0 - (grid.n[a] - 1) / 2.0) * grid.h[a]
+         for a in range(3)]
+    return Grid((D, D, D), tuple(grid.h), tuple(c))
+
+
+class Stage1Model:
+    """Stage 1 of the training (Sec. 2.3.2, Eq. 10-11): the reference
+    Gaussians drawn by the X-ray rasterizer (Eq. 9) at one view per
+    iteration, the L1 + D-SSIM loss against the measured projection, and the
+    TV of a D^3 sub-volume voxelized from the same Gaussians (Eq. 11)."""
+
+    def __init__(self, w: Workload, device="cuda"):
+        self.device = torch.device(device)
+        self.grid = w.grid
+        self.cone = w.cone
+        self.k = float(w.trunc_k)
+        self.ref = GaussT.from_set(w.ref, self.device)
+
+    def step(self, target, angle, corner, D: int = 32, lam_ssim: float = 0.25,
+             lam_tv: float = 0.05):
+        """target [1][nv][nu], angle [1] (device); returns ({"proj", "tv"}
+        device scalars, {"mean", "scale", "quat", "value"} gradients)."""
+        g = self.ref
+        proj = ops.pmf_rasterize(g.mean, g.scale, g.quat, g.value, self.cone, angle, self.k)
+        l_proj, g_proj = ops.pmf_l1_dssim_loss(proj, target, lam_ssim)
+        grads = ops.pmf_rasterize_bwd(g.mean, g.scale, g.quat, g.value, self.cone, angle, self.k,
+                                      g_proj)
+        sg = sub_grid(self.grid, corner, D)
+        sub = ops.pmf_voxelize(g.mean, g.scale, g.quat, g.value, sg, self.k)
+        g_sub = torch.zeros_like(sub)
+        l_tv = ops.pmf_tv_loss(sub, sg, (0, 0, 0), D, lam_tv, g_vol=g_sub)
+        tv = ops.pmf_voxelize_bwd(g.mean, g.scale, g.quat, g.value, sg, self.k, g_sub)
+        for a, b in zip(grads, tv):
+            ops.pmf_accumulate(a, b)
+        return {"proj": l_proj, "tv": l_tv}, dict(zip(("mean", "scale", "quat", "value"), grads))
+
+
 class MultiScanModel:
     """Several independent scans (different grids, geometries and view counts,
     one motion-model shape L, B) stepped together: per scan the voxelization
