@@ -193,6 +193,23 @@ size_t pmf_l2_loss_workspace(int64_t npix, int V);
 int pmf_l2_loss(const float *proj, const float *target, int64_t npix, int V, float *loss,
                 float *g_proj, void *ws, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------- FDK initialisation
+ * FDK reconstruction (Feldkamp et al. 1984) of the motion-averaged CBCT the
+ * Gaussians are initialised from (Sec. 2.3.2): proj [V][nv][nu] measured
+ * over a full circle (angles evenly covering 360 degrees; dtheta = 2 pi / V)
+ * in pmf_project's geometry -> vol on grid (overwritten).  Cosine weighting,
+ * ramp filtering of each detector row with the discrete Ram-Lak kernel of
+ * the virtual pitch du SAD / SDD (rows zero-padded), then the voxel-driven
+ * back-projection 1/2 sum dtheta (SAD / U)^2 q(a', b') with bilinear
+ * interpolation between pixel centres (0 off the detector).  Errors:
+ * PMF_EINVAL for null pointers, V outside [1, 65535], a bad grid or cone
+ * (the volume must lie inside the source circle); PMF_EUNSUPPORTED for rows
+ * longer than 8192 pixels; PMF_EWORKSPACE if the workspace from
+ * pmf_fdk_workspace() is missing or short. */
+size_t pmf_fdk_workspace(const pmf_cone_t *cone, int V);
+int pmf_fdk(const float *proj, const pmf_cone_t *cone, const float *angles, int V,
+            const pmf_grid_t *grid, float *vol, void *ws, size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------- Stage 1 rasterizer
  * X-ray Gaussian splatting (Sec. 2.2, Eq. 7-9): per view each Gaussian of g
  * (c must be 1: its density rho) is mapped by the local affine approximation

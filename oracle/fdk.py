@@ -60,14 +60,20 @@ def filter_rows(proj, cone) -> np.ndarray:
     return q
 
 
-def backproject(q, cone, angles, grid) -> np.ndarray:
-    """Step 3: the FDK volume [n0][n1][n2] from filtered projections q."""
+def backproject(q, cone, angles, grid, points=None) -> np.ndarray:
+    """Step 3: the FDK volume [n0][n1][n2] from filtered projections q (or
+    its values at world points [P][3])."""
     q = np.asarray(q, np.float64)
     V, nv, nu = q.shape
-    n = grid.n
-    ax = [np.asarray(grid.center[i]) + (np.arange(n[i]) - (n[i] - 1) / 2.0) * grid.h[i] for i in range(3)]
-    X, Y, Z = np.meshgrid(*ax, indexing="ij")
-    f = np.zeros(tuple(n))
+    if points is None:
+        n = grid.n
+        ax = [np.asarray(grid.center[i]) + (np.arange(n[i]) - (n[i] - 1) / 2.0) * grid.h[i]
+              for i in range(3)]
+        X, Y, Z = np.meshgrid(*ax, indexing="ij")
+    else:
+        pts = np.asarray(points, np.float64)
+        X, Y, Z = pts[:, 0], pts[:, 1], pts[:, 2]
+    f = np.zeros(X.shape)
     tau_u, tau_v = cone.du * cone.sad / cone.sdd, cone.dv * cone.sad / cone.sdd
     dth = 2.0 * math.pi / V
     for v in range(V):
@@ -98,8 +104,8 @@ def backproject(q, cone, angles, grid) -> np.ndarray:
     return f
 
 
-def fdk(proj, cone, angles, grid) -> np.ndarray:
-    return backproject(filter_rows(proj, cone), cone, angles, grid)
+def fdk(proj, cone, angles, grid, points=None) -> np.ndarray:
+    return backproject(filter_rows(proj, cone), cone, angles, grid, points)
 
 
 def ball_projections(center, radius: float, rho: float, cone, angles) -> np.ndarray:

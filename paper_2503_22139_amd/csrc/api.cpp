@@ -303,6 +303,26 @@ int pmf_l2_loss(const float *proj, const float *target, int64_t npix, int V, flo
                       "l2_loss");
 }
 
+// --------------------------------------------------------- FDK initialisation
+size_t pmf_fdk_workspace(const pmf_cone_t *cone, int V) {
+    if (!cone || V < 1 || cone->nu < 1 || cone->nv < 1) return 0;
+    return fdk_workspace(*cone, V);
+}
+
+int pmf_fdk(const float *proj, const pmf_cone_t *cone, const float *angles, int V,
+            const pmf_grid_t *grid, float *vol, void *ws, size_t ws_bytes, void *stream) {
+    PMF_CHECK(check_grid(grid, "grid"));
+    PMF_CHECK(check_cone(cone, grid));
+    if (V < 1 || V > 65535) return fail(PMF_EINVAL, "fdk: V must be in [1, 65535]");
+    if (cone->nu > 8192) return fail(PMF_EUNSUPPORTED, "fdk: detector rows longer than 8192");
+    if (cone->nv > 65535) return fail(PMF_EUNSUPPORTED, "fdk: more than 65535 detector rows");
+    if (!proj || !angles || !vol) return fail(PMF_EINVAL, "fdk: null pointer");
+    PMF_CHECK(check_ws(ws, ws_bytes, fdk_workspace(*cone, V)));
+    return hip_status(launch_fdk(proj, *cone, angles, V, make_grid(*grid), vol, ws,
+                                 as_stream(stream)),
+                      "fdk");
+}
+
 // ------------------------------------------------------ Stage 1 rasterizer
 static int check_rast(const pmf_gauss_t *gs, const pmf_cone_t *c, const float *angles, int V,
                       float k, const char *what) {

@@ -90,6 +90,8 @@ _SIGS = {
     "pmf_l2_loss_workspace": ([C.c_int64, C.c_int], _SZ),
     "pmf_l2_loss": ([_P, _P, C.c_int64, C.c_int, _P, _P, _P, _SZ, _P], C.c_int),
     "pmf_accumulate": ([_P, _P, C.c_int64, _P], C.c_int),
+    "pmf_fdk_workspace": ([C.POINTER(PmfCone), C.c_int], _SZ),
+    "pmf_fdk": ([_P, C.POINTER(PmfCone), _P, C.c_int, C.POINTER(PmfGrid), _P, _P, _SZ, _P], C.c_int),
     "pmf_rasterize_workspace": ([C.c_int64, C.POINTER(PmfCone), C.c_int], _SZ),
     "pmf_rasterize": ([C.POINTER(PmfGauss), C.POINTER(PmfCone), _P, C.c_int, C.c_float, _P, _P,
                        _SZ, _P], C.c_int),
@@ -325,6 +327,19 @@ def pmf_l2_loss(proj, target, want_grad: bool = True):
     _check(lib().pmf_l2_loss(_ptr(proj), _ptr(target), npix, V, _ptr(loss), _ptr(g),
                              C.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
     return loss, g
+
+
+def pmf_fdk(proj, cone: Cone, angles, grid: Grid, out=None):
+    """FDK reconstruction of a full-circle scan proj [V][nv][nu] onto grid."""
+    V = proj.shape[0]
+    if out is None:
+        out = torch.empty(tuple(grid.n), device=proj.device, dtype=torch.float32)
+    c = make_cone(cone)
+    g = make_grid(grid)
+    ws = workspace(lib().pmf_fdk_workspace(C.byref(c), V), proj.device)
+    _check(lib().pmf_fdk(_ptr(proj), C.byref(c), _ptr(angles), V, C.byref(g), _ptr(out),
+                         C.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return out
 
 
 def pmf_rasterize(mean, scale, quat, value, cone: Cone, angles, trunc_k: float = 3.0, out=None):

@@ -254,3 +254,21 @@ def test_rasterize_rejects_bad_arguments(lib):
     assert lib.pmf_rasterize_bwd(C.byref(gs1), C.byref(cone), p, 2, 3.0, p, C.byref(gg), ws, need - 1, None) == ops.PMF_EWORKSPACE
     huge = ops.PmfGauss(p, p, p, p, 1 << 26, 1)
     assert lib.pmf_rasterize(C.byref(huge), C.byref(cone), p, 4, 3.0, p, ws, big, None) == ops.PMF_EUNSUPPORTED
+
+
+def test_fdk_rejects_bad_arguments(lib):
+    p = C.c_void_p(256)
+    ws = C.c_void_p(256)
+    big = 1 << 40
+    g = grid(n=(16, 16, 8), h=(2.0, 2.0, 2.0))
+    cone = ops.make_cone(Cone(1000.0, 1500.0, 32, 24, 1.0, 1.0))
+    assert lib.pmf_fdk(p, C.byref(cone), p, 0, C.byref(g), p, ws, big, None) == ops.PMF_EINVAL
+    assert lib.pmf_fdk(None, C.byref(cone), p, 4, C.byref(g), p, ws, big, None) == ops.PMF_EINVAL
+    assert lib.pmf_fdk(p, C.byref(cone), p, 4, C.byref(g), None, ws, big, None) == ops.PMF_EINVAL
+    wide = ops.make_cone(Cone(1000.0, 1500.0, 9000, 4, 0.1, 1.0))
+    assert lib.pmf_fdk(p, C.byref(wide), p, 4, C.byref(g), p, ws, big, None) == ops.PMF_EUNSUPPORTED
+    huge = grid(n=(2000, 16, 8), h=(2.0, 2.0, 2.0))            # outside the source circle
+    assert lib.pmf_fdk(p, C.byref(cone), p, 4, C.byref(huge), p, ws, big, None) == ops.PMF_EINVAL
+    need = lib.pmf_fdk_workspace(C.byref(cone), 4)
+    assert need > 0
+    assert lib.pmf_fdk(p, C.byref(cone), p, 4, C.byref(g), p, ws, need - 1, None) == ops.PMF_EWORKSPACE
