@@ -314,8 +314,10 @@ int pmf_fdk(const float *proj, const pmf_cone_t *cone, const float *angles, int 
     PMF_CHECK(check_grid(grid, "grid"));
     PMF_CHECK(check_cone(cone, grid));
     if (V < 1 || V > 65535) return fail(PMF_EINVAL, "fdk: V must be in [1, 65535]");
-    if (cone->nu > 8192) return fail(PMF_EUNSUPPORTED, "fdk: detector rows longer than 8192");
+    if (cone->nu > 4096) return fail(PMF_EUNSUPPORTED, "fdk: detector rows longer than 4096");
     if (cone->nv > 65535) return fail(PMF_EUNSUPPORTED, "fdk: more than 65535 detector rows");
+    if ((int64_t)(cone->nu + 2) * (cone->nv + 2) >= ((int64_t)1 << 27))
+        return fail(PMF_EUNSUPPORTED, "fdk: (nu + 2) * (nv + 2) must be < 2^27");
     if (!proj || !angles || !vol) return fail(PMF_EINVAL, "fdk: null pointer");
     PMF_CHECK(check_ws(ws, ws_bytes, fdk_workspace(*cone, V)));
     return hip_status(launch_fdk(proj, *cone, angles, V, make_grid(*grid), vol, ws,

@@ -12,124 +12,239 @@
 // detector), dtheta = 2 pi / V.  The plain Ram-Lak kernel, linear
 // interpolation and full-scan weighting 1/2 are the readings of the paper's
 // "quick FDK reconstruction".
+//
+// Layout of the filtered projections (workspace): per view a zero-bordered
+// plane of (nv + 2) x (nu + 2) float4 "quads"; quad (j, c) holds the four
+// bilinear taps qp(j, c), qp(j, c + 1), qp(j + 1, c), qp(j + 1, c + 1) of the
+// padded image qp(j, c) = q[j - 1][c - 1] (0 on the border and beyond).  A
+// back-projection sample clamps its padded pixel coordinates into
+// [0, nu + 1] x [0, nv + 1] -- any sample that leaves the detector then reads
+// zero taps, exactly as the definition asks -- and fetches its whole 2 x 2
+// neighbourhood with one 16-byte load, with no bounds test.
 #include <math.h>
 
 #include "pmf_internal.h"
 
 namespace pmf {
 
-constexpr int FDK_MAXU = 8192;          // detector row length held in LDS
+constexpr int FDK_R = 8;               // outputs per lane per chunk: n = b0 + lane + 64 j
+constexpr int FDK_CH = 64 * FDK_R;     // outputs per chunk
+constexpr int FDK_PAD = 64;            // zeros on each side of the row in LDS
+constexpr int BP_ZC = 8;               // voxels along axis 2 per back-projection thread
 
-// One workgroup per (row, view): the weighted row in LDS, then per output
-// pixel n: q[n] = p~[n] / (4 tau) - 1 / (pi^2 tau) sum_{d odd} (p~[n-d] +
-// p~[n+d]) / d^2.
-__global__ __launch_bounds__(256) void k_fdk_filter(const float *__restrict__ proj, pmf_cone_t c,
-                                                    float *__restrict__ q) {
-    __shared__ float row[FDK_MAXU];
-    __shared__ float inv_d2[FDK_MAXU / 2];
-    const int iv = blockIdx.x, v = blockIdx.y, nu = c.nu;
-    const int64_t base = ((int64_t)v * c.nv + iv) * nu;
-    const double b = ((double)iv - 0.5 * (c.nv - 1) + c.off_v) * c.dv;
-    const double sdd2 = (double)c.sdd * c.sdd;
-    for (int i = threadIdx.x; i < nu; i += blockDim.x) {
-        const double a = ((double)i - 0.5 * (nu - 1) + c.off_u) * c.du;
-        row[i] = (float)((double)proj[base + i] * (double)c.sdd / sqrt(sdd2 + a * a + b * b));
+// First (odd) lag of the tap table and its number of rows.
+static inline int fdk_t0(int nu) { return 1 - 2 * ((nu + 1) / 2); }
+static inline int fdk_taps(int nu) {
+    const int bmax = ((nu - 1) / FDK_CH) * FDK_CH;
+    return (bmax + 63 - fdk_t0(nu)) / 2 + 1;
+}
+
+// Tap table of the odd lags: wt[k][j] = -1 / (pi^2 tau d^2), d = t0 + 2k +
+// 64j -- the weight of input m for output n when n - m = d.  Uniform per
+// loop step of the filter, so the filter reads eight of them with one
+// scalar load.
+__global__ void k_fdk_taps(double tau, int t0, int K, float *__restrict__ wt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= K * FDK_R) return;
+    const double d = (double)t0 + 2.0 * (i / FDK_R) + 64.0 * (i % FDK_R);
+    wt[i] = (float)(-1.0 / (M_PI * M_PI * tau * d * d));
+}
+
+// One wave per (detector row i, view v): cosine-weighted row into LDS (zero
+// borders), the filtered row q[n] = p~[n] / (4 tau) + sum_{n - m odd}
+// wt(n - m) p~[m] with each lane owning the outputs b0 + lane + 64 j (the
+// lag n - m = t + 64 j then depends on the loop counter t and j only), then
+// the row's taps written into the quads of padded rows i + 1 (top pair) and
+// i (bottom pair).  Block row nv writes the plane's zero border rows.
+__global__ __launch_bounds__(64) void k_fdk_filter(const float *__restrict__ proj, pmf_cone_t c,
+                                                   const float *__restrict__ wt, int t0,
+                                                   float4 *__restrict__ qq) {
+    extern __shared__ float lds[];
+    const int nu = c.nu, nv = c.nv, lane = threadIdx.x;
+    const int i = blockIdx.x, v = blockIdx.y;
+    const int P = nu + 2;
+    float4 *const plane = qq + (int64_t)v * (nv + 2) * P;
+    float2 *const half = (float2 *)plane;           // quad e: half[2e] = top, half[2e + 1] = bottom
+    if (i == nv) {
+        for (int col = lane; col < P; col += 64) {
+            half[2 * (int64_t)col] = make_float2(0.0f, 0.0f);
+            half[2 * ((int64_t)nv * P + col) + 1] = make_float2(0.0f, 0.0f);
+            plane[(int64_t)(nv + 1) * P + col] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
+        return;
     }
-    for (int k = threadIdx.x; k < (nu + 1) / 2; k += blockDim.x) {
-        const double d = 2.0 * k + 1.0;
-        inv_d2[k] = (float)(1.0 / (d * d));
+    float *const row = lds;                          // row[m + FDK_PAD], m in [-64, nu + 64)
+    float *const out = lds + nu + 2 * FDK_PAD;       // out[n + 1] = q[n], out[0] = out[nu + 1] = 0
+    const int64_t base = ((int64_t)v * nv + i) * nu;
+    const double b = ((double)i - 0.5 * (nv - 1) + c.off_v) * c.dv;
+    const double sdd = c.sdd, sb = sdd * sdd + b * b;
+    for (int m = lane - FDK_PAD; m < nu + FDK_PAD; m += 64) {
+        float x = 0.0f;
+        if (m >= 0 && m < nu) {
+            const double a = ((double)m - 0.5 * (nu - 1) + c.off_u) * c.du;
+            x = (float)((double)proj[base + m] * sdd / sqrt(sb + a * a));
+        }
+        row[m + FDK_PAD] = x;
+    }
+    if (lane == 0) {
+        out[0] = 0.0f;
+        out[nu + 1] = 0.0f;
     }
     __syncthreads();
-    const double tau = (double)c.du * c.sad / c.sdd;
-    const float c0 = (float)(1.0 / (4.0 * tau)), c1 = (float)(1.0 / (M_PI * M_PI * tau));
-    for (int n = threadIdx.x; n < nu; n += blockDim.x) {
-        float s = 0.0f;
-        for (int k = 0; 2 * k + 1 < nu; ++k) {
-            const int d = 2 * k + 1;
-            const float lo = n - d >= 0 ? row[n - d] : 0.0f;
-            const float hi = n + d < nu ? row[n + d] : 0.0f;
-            s = fmaf(lo + hi, inv_d2[k], s);
+    const float c0 = (float)((double)c.sdd / (4.0 * (double)c.du * c.sad));
+    for (int b0 = 0; b0 < nu; b0 += FDK_CH) {
+        float acc[FDK_R];
+#pragma unroll
+        for (int j = 0; j < FDK_R; ++j) acc[j] = 0.0f;
+        const int ts = (b0 - nu + 1) | 1;            // first odd lag with an input on the row
+        const float *wk = wt + ((ts - t0) >> 1) * FDK_R;
+        const float *xr = row + FDK_PAD + b0 + lane - ts;
+#pragma unroll 4
+        for (int t = ts; t <= b0 + 63; t += 2, wk += FDK_R, xr -= 2) {
+            const float x = *xr;
+#pragma unroll
+            for (int j = 0; j < FDK_R; ++j) acc[j] = fmaf(wk[j], x, acc[j]);
         }
-        q[base + n] = fmaf(c0, row[n], -c1 * s);
+#pragma unroll
+        for (int j = 0; j < FDK_R; ++j) {
+            const int n = b0 + lane + 64 * j;
+            if (n < nu) out[n + 1] = fmaf(c0, row[FDK_PAD + n], acc[j]);
+        }
+    }
+    __syncthreads();
+    for (int col = lane; col < P; col += 64) {
+        const float2 p = make_float2(out[col], out[col + 1]);
+        half[2 * ((int64_t)(i + 1) * P + col)] = p;
+        half[2 * ((int64_t)i * P + col) + 1] = p;
     }
 }
 
 struct FdkView {
-    float ct, st;
+    float ct, st, sx, sy;    // cos, sin, source position SAD (cos, sin)
 };
 
-__global__ void k_fdk_views(const float *__restrict__ angles, int V, FdkView *__restrict__ out) {
+__global__ void k_fdk_views(const float *__restrict__ angles, int V, float sad,
+                            FdkView *__restrict__ out) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= V) return;
-    const double th = angles[v];
-    out[v].ct = (float)cos(th);
-    out[v].st = (float)sin(th);
+    const double th = angles[v], ct = cos(th), st = sin(th);
+    out[v] = {(float)ct, (float)st, (float)(sad * ct), (float)(sad * st)};
 }
 
-// One thread per voxel (axis 2 fastest), views in order.
-__global__ __launch_bounds__(256) void k_fdk_bp(const float *__restrict__ q, pmf_cone_t c, int V,
-                                                const FdkView *__restrict__ views, GridK g,
+struct FdkBp {
+    float sad, inv_tu, inv_tv, cu, cv, umax, vmax, wsc, hz;
+    unsigned row_bytes;      // (nu + 2) * 16
+    int64_t plane_bytes;     // (nv + 2) * row_bytes
+    int tx, ty;              // 16 x 16 column tiles along axes 0, 1
+};
+
+// Workgroup = 16 x 16 voxel columns (each wave an 8 x 8 patch, so one wave's
+// samples of a view fall on a few neighbouring detector cache lines) x
+// BP_ZC voxels along axis 2 per thread.  Per view the column's geometry
+// (depth U, magnification, u coordinate) is computed once; along the column
+// only v moves, linearly.  Views are summed in order.  Workgroups are
+// numbered so that each XCD gets a contiguous slab along axis 2 (one band of
+// detector rows in every view).  Threads past the grid edge compute on
+// clamped positions and store nothing.
+__global__ __launch_bounds__(256) void k_fdk_bp(const float4 *__restrict__ qq, FdkBp p,
+                                                const FdkView *__restrict__ views, int V, GridK g,
                                                 float *__restrict__ vol) {
-    const int64_t N = grid_size(g);
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= N) return;
-    const int iz = (int)(j % g.n[2]);
-    const int iy = (int)((j / g.n[2]) % g.n[1]);
-    const int ix = (int)(j / ((int64_t)g.n[2] * g.n[1]));
-    const float x = g.c0[0] + ix * g.h[0], y = g.c0[1] + iy * g.h[1], z = g.c0[2] + iz * g.h[2];
-    const float sad = c.sad;
-    const float inv_tu = (float)((double)c.sdd / ((double)c.du * c.sad));
-    const float inv_tv = (float)((double)c.sdd / ((double)c.dv * c.sad));
-    const float cu = 0.5f * (c.nu - 1) - c.off_u, cv = 0.5f * (c.nv - 1) - c.off_v;
-    const float wsc = (float)(0.5 * 2.0 * M_PI / V);
-    float acc = 0.0f;
-    for (int v = 0; v < V; ++v) {
-        const FdkView w = views[v];
-        const float dx = x - sad * w.ct, dy = y - sad * w.st;
-        const float tu = -w.st * dx + w.ct * dy;
-        const float U = -w.ct * dx - w.st * dy;
-        const float r = sad / U;
-        const float fu = r * tu * inv_tu + cu, fv = r * z * inv_tv + cv;
-        const float f0 = floorf(fu), f1 = floorf(fv);
-        const int i0 = (int)f0, k0 = (int)f1;
-        const float wu = fu - f0, wv = fv - f1;
-        const float *qv = q + (int64_t)v * c.nv * c.nu;
-        float s = 0.0f;
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    const int tiles = p.tx * p.ty;
+    const int zc = b / tiles, tile = b - zc * tiles;
+    const int tyi = tile / p.tx, txi = tile - tyi * p.tx;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int ix = txi * 16 + (w & 1) * 8 + (lane & 7);
+    const int iy = tyi * 16 + (w >> 1) * 8 + (lane >> 3);
+    const int iz0 = zc * BP_ZC;
+    const float x = g.c0[0] + min(ix, g.n[0] - 1) * g.h[0];
+    const float y = g.c0[1] + min(iy, g.n[1] - 1) * g.h[1];
+    const float z0 = g.c0[2] + iz0 * g.h[2];
+    float acc[BP_ZC];
 #pragma unroll
-        for (int dk = 0; dk < 2; ++dk) {
-            const int kk = k0 + dk;
-            if (kk < 0 || kk >= c.nv) continue;
-            const float wk = dk ? wv : 1.0f - wv;
-            const float *qr = qv + (int64_t)kk * c.nu;
-            const float a = (i0 >= 0 && i0 < c.nu) ? qr[i0] : 0.0f;
-            const float b = (i0 + 1 >= 0 && i0 + 1 < c.nu) ? qr[i0 + 1] : 0.0f;
-            s = fmaf(wk, fmaf(wu, b - a, a), s);
+    for (int k = 0; k < BP_ZC; ++k) acc[k] = 0.0f;
+    const char *pl = (const char *)qq;
+    for (int v = 0; v < V; ++v, pl += p.plane_bytes) {
+        const FdkView w = views[v];
+        const float dx = x - w.sx, dy = y - w.sy;
+        const float tu = fmaf(-w.st, dx, w.ct * dy);
+        const float U = -fmaf(w.ct, dx, w.st * dy);
+        const float r = p.sad / U;
+        const float fu = __builtin_amdgcn_fmed3f(fmaf(r * tu, p.inv_tu, p.cu), 0.0f, p.umax);
+        const float wu = __builtin_amdgcn_fractf(fu);
+        const unsigned colb = (unsigned)(int)fu * 16u;
+        const float wr2 = p.wsc * r * r;
+        const float rv = r * p.inv_tv;
+        const float fv0 = fmaf(rv, z0, p.cv), dfv = rv * p.hz;
+#pragma unroll
+        for (int k = 0; k < BP_ZC; ++k) {
+            const float fv = __builtin_amdgcn_fmed3f(fmaf((float)k, dfv, fv0), 0.0f, p.vmax);
+            const float wv = __builtin_amdgcn_fractf(fv);
+            const unsigned off = __umul24((unsigned)(int)fv, p.row_bytes) + colb;
+            const float4 e = *(const float4 *)(pl + off);
+            const float top = fmaf(wu, e.y - e.x, e.x), bot = fmaf(wu, e.w - e.z, e.z);
+            acc[k] = fmaf(wr2, fmaf(wv, bot - top, top), acc[k]);
         }
-        acc = fmaf(wsc * r * r, s, acc);
     }
-    vol[j] = acc;
+    if (ix >= g.n[0] || iy >= g.n[1]) return;
+    float *o = vol + ((int64_t)ix * g.n[1] + iy) * g.n[2];
+#pragma unroll
+    for (int k = 0; k < BP_ZC; ++k)
+        if (iz0 + k < g.n[2]) o[iz0 + k] = acc[k];
+}
+
+static size_t fdk_plane_bytes(const pmf_cone_t &c) {
+    return sizeof(float4) * (size_t)(c.nu + 2) * (c.nv + 2);
 }
 
 size_t fdk_workspace(const pmf_cone_t &c, int V) {
-    return align256(sizeof(float) * (size_t)c.nu * c.nv * V) + align256(sizeof(FdkView) * (size_t)V);
+    return align256(fdk_plane_bytes(c) * V) + align256(sizeof(FdkView) * (size_t)V) +
+           align256(sizeof(float) * FDK_R * (size_t)fdk_taps(c.nu));
+}
+
+size_t fdk_filter_lds(const pmf_cone_t &c) {
+    return sizeof(float) * (size_t)(2 * c.nu + 2 * FDK_PAD + 2);
 }
 
 hipError_t launch_fdk(const float *proj, const pmf_cone_t &c, const float *angles, int V,
                       const GridK &g, float *vol, void *ws, hipStream_t s) {
-    float *q = (float *)ws;
-    FdkView *views = (FdkView *)((char *)ws + align256(sizeof(float) * (size_t)c.nu * c.nv * V));
+    char *w = (char *)ws;
+    float4 *qq = (float4 *)w;
+    w += align256(fdk_plane_bytes(c) * V);
+    FdkView *views = (FdkView *)w;
+    w += align256(sizeof(FdkView) * (size_t)V);
+    float *wt = (float *)w;
+    const double tau = (double)c.du * c.sad / c.sdd;
+    const int t0 = fdk_t0(c.nu), K = fdk_taps(c.nu);
     hipError_t e;
+    k_fdk_taps<<<(unsigned)((K * FDK_R + 255) / 256), 256, 0, s>>>(tau, t0, K, wt);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    k_fdk_views<<<(unsigned)((V + 255) / 256), 256, 0, s>>>(angles, V, c.sad, views);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     {
         ProfScope prof_("fdk_filter", s);
-        k_fdk_filter<<<dim3((unsigned)c.nv, (unsigned)V), 256, 0, s>>>(proj, c, q);
+        k_fdk_filter<<<dim3((unsigned)c.nv + 1, (unsigned)V), 64, fdk_filter_lds(c), s>>>(proj, c, wt,
+                                                                                         t0, qq);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    k_fdk_views<<<(unsigned)((V + 255) / 256), 256, 0, s>>>(angles, V, views);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    const int64_t N = grid_size(g);
+    FdkBp p;
+    p.sad = c.sad;
+    p.inv_tu = (float)((double)c.sdd / ((double)c.du * c.sad));
+    p.inv_tv = (float)((double)c.sdd / ((double)c.dv * c.sad));
+    p.cu = (float)(0.5 * (c.nu - 1) - c.off_u + 1.0);
+    p.cv = (float)(0.5 * (c.nv - 1) - c.off_v + 1.0);
+    p.umax = (float)(c.nu + 1);
+    p.vmax = (float)(c.nv + 1);
+    p.wsc = (float)(M_PI / V);
+    p.hz = g.h[2];
+    p.row_bytes = 16u * (unsigned)(c.nu + 2);
+    p.plane_bytes = (int64_t)fdk_plane_bytes(c);
+    p.tx = (g.n[0] + 15) / 16;
+    p.ty = (g.n[1] + 15) / 16;
+    const int64_t nb = (int64_t)p.tx * p.ty * ((g.n[2] + BP_ZC - 1) / BP_ZC);
     {
         ProfScope prof_("fdk_backproject", s);
-        k_fdk_bp<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(q, c, V, views, g, vol);
+        k_fdk_bp<<<(unsigned)nb, 256, 0, s>>>(qq, p, views, V, g, vol);
     }
     return hipGetLastError();
 }

@@ -265,8 +265,10 @@ def test_fdk_rejects_bad_arguments(lib):
     assert lib.pmf_fdk(p, C.byref(cone), p, 0, C.byref(g), p, ws, big, None) == ops.PMF_EINVAL
     assert lib.pmf_fdk(None, C.byref(cone), p, 4, C.byref(g), p, ws, big, None) == ops.PMF_EINVAL
     assert lib.pmf_fdk(p, C.byref(cone), p, 4, C.byref(g), None, ws, big, None) == ops.PMF_EINVAL
-    wide = ops.make_cone(Cone(1000.0, 1500.0, 9000, 4, 0.1, 1.0))
+    wide = ops.make_cone(Cone(1000.0, 1500.0, 4097, 4, 0.1, 1.0))
     assert lib.pmf_fdk(p, C.byref(wide), p, 4, C.byref(g), p, ws, big, None) == ops.PMF_EUNSUPPORTED
+    tall = ops.make_cone(Cone(1000.0, 1500.0, 4096, 40000, 0.01, 0.01))   # 16-byte taps past 2^31
+    assert lib.pmf_fdk(p, C.byref(tall), p, 4, C.byref(g), p, ws, big, None) == ops.PMF_EUNSUPPORTED
     huge = grid(n=(2000, 16, 8), h=(2.0, 2.0, 2.0))            # outside the source circle
     assert lib.pmf_fdk(p, C.byref(cone), p, 4, C.byref(huge), p, ws, big, None) == ops.PMF_EINVAL
     need = lib.pmf_fdk_workspace(C.byref(cone), 4)
