@@ -30,7 +30,7 @@ namespace pmf {
 constexpr int FDK_R = 8;               // outputs per lane per chunk: n = b0 + lane + 64 j
 constexpr int FDK_CH = 64 * FDK_R;     // outputs per chunk
 constexpr int FDK_PAD = 64;            // zeros on each side of the row in LDS
-constexpr int BP_ZC = 8;               // voxels along axis 2 per back-projection thread
+constexpr int BP_ZC = 16;              // voxels along axis 2 per back-projection thread
 
 // First (odd) lag of the tap table and its number of rows.
 static inline int fdk_t0(int nu) { return 1 - 2 * ((nu + 1) / 2); }
@@ -146,7 +146,7 @@ struct FdkBp {
 // numbered so that each XCD gets a contiguous slab along axis 2 (one band of
 // detector rows in every view).  Threads past the grid edge compute on
 // clamped positions and store nothing.
-__global__ __launch_bounds__(256) void k_fdk_bp(const float4 *__restrict__ qq, FdkBp p,
+__global__ __launch_bounds__(256, 8) void k_fdk_bp(const float4 *__restrict__ qq, FdkBp p,
                                                 const FdkView *__restrict__ views, int V, GridK g,
                                                 float *__restrict__ vol) {
     const int b = xcd_block(blockIdx.x, gridDim.x);
