@@ -212,6 +212,20 @@ size_t pmf_fdk_workspace(const pmf_cone_t *cone, int V);
 int pmf_fdk(const float *proj, const pmf_cone_t *cone, const float *angles, int V,
             const pmf_grid_t *grid, float *vol, void *ws, size_t ws_bytes, void *stream);
 
+/* Grid-based sampling of a (FDK) volume into the initial reference Gaussians
+ * (Sec. 2.3.2: sampled points keep their positions and the volume's
+ * intensities as densities).  M = m[0] m[1] m[2] points on the lattice that
+ * evenly fills the volume box: point (k0, k1, k2) at box_lo + (k + 1/2)
+ * box_len / m per axis, axis 2 fastest; its density is the trilinear value
+ * of vol there (the interpolation of pmf_warp); scale = `scale` on every
+ * axis, quaternion (1, 0, 0, 0).  vol on grid (device, read); outputs
+ * (device, written): mean [M][3], scale_out [M][3], quat [M][4], value
+ * [M][1] -- a pmf_gauss_t with c = 1.  Errors: PMF_EINVAL for null
+ * pointers, a bad grid, m[a] outside [1, n[a]] or scale not > 0.  No
+ * workspace. */
+int pmf_grid_init(const float *vol, const pmf_grid_t *grid, const int m[3], float scale,
+                  float *mean, float *scale_out, float *quat, float *value, void *stream);
+
 /* ------------------------------------------------- Stage 1 rasterizer
  * X-ray Gaussian splatting (Sec. 2.2, Eq. 7-9): per view each Gaussian of g
  * (c must be 1: its density rho) is mapped by the local affine approximation

@@ -25,6 +25,13 @@ SAD / SDD):
 Readings of what the paper leaves open ("a quick FDK reconstruction"): the
 plain Ram-Lak kernel without apodisation, linear interpolation, full-scan
 weighting 1/2, no short-scan (Parker) weights.
+
+``grid_init`` is the grid-based sampling that seeds the reference Gaussians
+from the FDK image (Sec. 2.3.2): lattice points keep their positions and the
+image's intensities as densities.  Readings: the lattice evenly fills the
+volume box (m_a points per axis at box_lo + (k + 1/2) box_len / m_a), the
+intensity is the trilinear value of the image at the point, the initial
+rotation is the identity and the scale is the caller's.
 """
 from __future__ import annotations
 
@@ -128,3 +135,20 @@ def ball_projections(center, radius: float, rho: float, cone, angles) -> np.ndar
         dist2 = (w * w).sum() - proj_len ** 2
         out[v] = 2.0 * rho * np.sqrt(np.clip(radius * radius - dist2, 0.0, None))
     return out
+
+
+def grid_init(vol, grid, m, scale: float):
+    """Initial Gaussians from the lattice m = (m0, m1, m2) over the volume box
+    (axis 2 fastest): mean [M][3], scale [M][3], quat [M][4], value [M][1]."""
+    from oracle import sample_points
+    axes = []
+    for a in range(3):
+        L = grid.n[a] * grid.h[a]
+        lo = grid.center[a] - 0.5 * L
+        axes.append(lo + (np.arange(m[a]) + 0.5) * L / m[a])
+    P = np.stack(np.meshgrid(*axes, indexing="ij"), -1).reshape(-1, 3)
+    M = P.shape[0]
+    val = sample_points(vol, grid, P)
+    quat = np.zeros((M, 4))
+    quat[:, 0] = 1.0
+    return P, np.full((M, 3), float(scale)), quat, val.reshape(M, 1)

@@ -325,6 +325,26 @@ int pmf_fdk(const float *proj, const pmf_cone_t *cone, const float *angles, int 
                       "fdk");
 }
 
+int pmf_grid_init(const float *vol, const pmf_grid_t *grid, const int m[3], float scale,
+                  float *mean, float *scale_out, float *quat, float *value, void *stream) {
+    PMF_CHECK(check_grid(grid, "grid"));
+    if (!m) return fail(PMF_EINVAL, "grid_init: null m");
+    int64_t M = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (m[a] < 1 || m[a] > grid->n[a])
+            return fail(PMF_EINVAL, "grid_init: m[%d] = %d outside [1, n[%d] = %d]", a, m[a], a,
+                        grid->n[a]);
+        M *= m[a];
+    }
+    if (!finite_pos(scale)) return fail(PMF_EINVAL, "grid_init: scale must be > 0");
+    if (!vol || !mean || !scale_out || !quat || !value)
+        return fail(PMF_EINVAL, "grid_init: null pointer");
+    (void)M;
+    return hip_status(launch_grid_init(vol, make_grid(*grid), m, scale, mean, scale_out, quat,
+                                       value, as_stream(stream)),
+                      "grid_init");
+}
+
 // ------------------------------------------------------ Stage 1 rasterizer
 static int check_rast(const pmf_gauss_t *gs, const pmf_cone_t *c, const float *angles, int V,
                       float k, const char *what) {

@@ -249,4 +249,40 @@ hipError_t launch_fdk(const float *proj, const pmf_cone_t &c, const float *angle
     return hipGetLastError();
 }
 
+// Grid-based sampling of the FDK volume into initial Gaussians (Sec.
+// 2.3.2): a lattice of m0 x m1 x m2 points evenly filling the volume box
+// (point k at box_lo + (k + 1/2) box_len / m per axis, axis 2 fastest); each
+// point keeps its position and the volume's trilinear value there as its
+// density; isotropic scale s, identity rotation.
+__global__ void k_grid_init(const float *__restrict__ vol, GridK g, int m0, int m1, int m2,
+                            float s, float *__restrict__ mean, float *__restrict__ scale,
+                            float *__restrict__ quat, float *__restrict__ value) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)m0 * m1 * m2) return;
+    const int k2 = (int)(k % m2), k1 = (int)((k / m2) % m1), k0 = (int)(k / ((int64_t)m2 * m1));
+    const int kk[3] = {k0, k1, k2}, mm[3] = {m0, m1, m2};
+    float u[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        // voxel-unit coordinate of the point (voxel 0's centre at 0)
+        const double ua = ((double)kk[a] + 0.5) * g.n[a] / mm[a] - 0.5;
+        u[a] = (float)ua;
+        mean[3 * k + a] = (float)(g.c0d[a] + ua * g.hd[a]);
+        scale[3 * k + a] = s;
+    }
+    quat[4 * k + 0] = 1.0f;
+    quat[4 * k + 1] = 0.0f;
+    quat[4 * k + 2] = 0.0f;
+    quat[4 * k + 3] = 0.0f;
+    value[k] = sample_u(vol, g.n, u[0], u[1], u[2]);
+}
+
+hipError_t launch_grid_init(const float *vol, const GridK &g, const int m[3], float s,
+                            float *mean, float *scale, float *quat, float *value, hipStream_t st) {
+    const int64_t M = (int64_t)m[0] * m[1] * m[2];
+    k_grid_init<<<(unsigned)((M + 255) / 256), 256, 0, st>>>(vol, g, m[0], m[1], m[2], s, mean,
+                                                              scale, quat, value);
+    return hipGetLastError();
+}
+
 }  // namespace pmf

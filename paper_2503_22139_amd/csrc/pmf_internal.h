@@ -330,6 +330,8 @@ hipError_t launch_project_bwd(const float *g_proj, const GridK &g, const ConeK &
 size_t fdk_workspace(const pmf_cone_t &c, int V);
 hipError_t launch_fdk(const float *proj, const pmf_cone_t &c, const float *angles, int V,
                       const GridK &g, float *vol, void *ws, hipStream_t s);
+hipError_t launch_grid_init(const float *vol, const GridK &g, const int m[3], float s,
+                            float *mean, float *scale, float *quat, float *value, hipStream_t st);
 size_t rasterize_workspace(int64_t m, const pmf_cone_t &c, int V);
 hipError_t launch_rasterize(const pmf_gauss_t &gs, const pmf_cone_t &c, const float *angles,
                             int V, float k, float *proj, void *ws, hipStream_t s);

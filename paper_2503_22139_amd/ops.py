@@ -92,6 +92,8 @@ _SIGS = {
     "pmf_accumulate": ([_P, _P, C.c_int64, _P], C.c_int),
     "pmf_fdk_workspace": ([C.POINTER(PmfCone), C.c_int], _SZ),
     "pmf_fdk": ([_P, C.POINTER(PmfCone), _P, C.c_int, C.POINTER(PmfGrid), _P, _P, _SZ, _P], C.c_int),
+    "pmf_grid_init": ([_P, C.POINTER(PmfGrid), C.POINTER(C.c_int), C.c_float, _P, _P, _P, _P, _P],
+                      C.c_int),
     "pmf_rasterize_workspace": ([C.c_int64, C.POINTER(PmfCone), C.c_int], _SZ),
     "pmf_rasterize": ([C.POINTER(PmfGauss), C.POINTER(PmfCone), _P, C.c_int, C.c_float, _P, _P,
                        _SZ, _P], C.c_int),
@@ -340,6 +342,32 @@ def pmf_fdk(proj, cone: Cone, angles, grid: Grid, out=None):
     _check(lib().pmf_fdk(_ptr(proj), C.byref(c), _ptr(angles), V, C.byref(g), _ptr(out),
                          C.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
     return out
+
+
+def grid_init_lattice(grid: Grid, M: int):
+    """Lattice counts (m0, m1, m2) with about M points at equal spacing delta
+    in mm over the volume box, and delta: delta = (box volume / M)^(1/3),
+    m_a = round(box_len_a / delta) clamped to [1, n_a]."""
+    L = [grid.n[a] * grid.h[a] for a in range(3)]
+    delta = (L[0] * L[1] * L[2] / float(M)) ** (1.0 / 3.0)
+    m = tuple(int(min(max(1, round(L[a] / delta)), grid.n[a])) for a in range(3))
+    return m, delta
+
+
+def pmf_grid_init(vol, grid: Grid, m, scale: float):
+    """Initial Gaussians sampled from vol on an m0 x m1 x m2 lattice (Sec.
+    2.3.2): (mean [M][3], scale [M][3], quat [M][4], value [M][1])."""
+    M = int(m[0]) * int(m[1]) * int(m[2])
+    dev = vol.device
+    mean = torch.empty((M, 3), device=dev, dtype=torch.float32)
+    sc = torch.empty((M, 3), device=dev, dtype=torch.float32)
+    quat = torch.empty((M, 4), device=dev, dtype=torch.float32)
+    val = torch.empty((M, 1), device=dev, dtype=torch.float32)
+    g = make_grid(grid)
+    mm = (C.c_int * 3)(*[int(x) for x in m])
+    _check(lib().pmf_grid_init(_ptr(vol), C.byref(g), mm, float(scale), _ptr(mean), _ptr(sc),
+                               _ptr(quat), _ptr(val), _stream()))
+    return mean, sc, quat, val
 
 
 def pmf_rasterize(mean, scale, quat, value, cone: Cone, angles, trunc_k: float = 3.0, out=None):

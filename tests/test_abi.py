@@ -274,3 +274,15 @@ def test_fdk_rejects_bad_arguments(lib):
     need = lib.pmf_fdk_workspace(C.byref(cone), 4)
     assert need > 0
     assert lib.pmf_fdk(p, C.byref(cone), p, 4, C.byref(g), p, ws, need - 1, None) == ops.PMF_EWORKSPACE
+
+
+def test_grid_init_rejects_bad_arguments(lib):
+    p = C.c_void_p(256)
+    g = grid(n=(16, 16, 8), h=(2.0, 2.0, 2.0))
+    m = lambda *a: (C.c_int * 3)(*a)
+    assert lib.pmf_grid_init(p, C.byref(g), m(4, 4, 9), 1.0, p, p, p, p, None) == ops.PMF_EINVAL
+    assert lib.pmf_grid_init(p, C.byref(g), m(0, 4, 4), 1.0, p, p, p, p, None) == ops.PMF_EINVAL
+    assert lib.pmf_grid_init(p, C.byref(g), m(4, 4, 4), 0.0, p, p, p, p, None) == ops.PMF_EINVAL
+    assert lib.pmf_grid_init(p, C.byref(g), m(4, 4, 4), 1.0, p, None, p, p, None) == ops.PMF_EINVAL
+    assert lib.pmf_grid_init(None, C.byref(g), m(4, 4, 4), 1.0, p, p, p, p, None) == ops.PMF_EINVAL
+    assert ops.grid_init_lattice(Grid((256, 256, 128), (1.5, 1.5, 2.0)), 50_000)[0] == (42, 42, 28)

@@ -1,8 +1,8 @@
 """FDK initialisation (cosine weight, Ram-Lak row filter, voxel-driven
-back-projection) through the C ABI against the FP64 oracle: analytic ball
-phantoms on small grids with pixel offsets and ragged sizes, and the
-benchmark geometry (512 x 384 detector, 256 x 256 x 128 grid) at sampled
-voxels.  Inputs are seeded and synthetic; expected values come from the
+back-projection) and the grid-based sampling of its image into Gaussians,
+through the C ABI against the FP64 oracle: analytic ball phantoms on small
+grids with pixel offsets and ragged sizes, and the benchmark geometry
+(512 x 384 detector, 256 x 256 x 128 grid) at sampled voxels.  Inputs are seeded and synthetic; expected values come from the
 oracle only."""
 import numpy as np
 import pytest
@@ -88,4 +88,40 @@ def test_fdk_benchmark_geometry_sampled():
     want = fdk.fdk(p, cone, ang, grid, points=pts)
     r = rel(got[idx[:, 0], idx[:, 1], idx[:, 2]], want)
     print("fdk full-size sampled", r, flush=True)
+    assert r < VOL_TOL, r
+
+
+@pytest.mark.parametrize("case", ["ragged", "full"])
+def test_grid_init_matches_oracle(case):
+    """Grid-based sampling of a volume into Gaussians: positions, densities
+    (trilinear), scales and rotations against the oracle."""
+    grid = Grid((23, 17, 12), (1.5, 2.0, 2.5), (2.0, -3.0, 1.0))
+    vol = np.random.default_rng(5).uniform(0.0, 0.05, grid.n).astype(np.float32)
+    m = (7, 5, 4) if case == "ragged" else grid.n
+    got = [N(t) for t in ops.pmf_grid_init(T(vol), grid, m, 1.25)]
+    want = fdk.grid_init(vol, grid, m, 1.25)
+    assert np.abs(got[0] - want[0]).max() < 1e-5
+    assert np.all(got[1] == 1.25) and np.all(got[2] == want[2])
+    r = rel(got[3], want[3])
+    print("grid_init", case, r, flush=True)
+    assert r < VOL_TOL, r
+
+
+def test_fdk_then_grid_init_at_benchmark_size():
+    """FDK of the 512 x 384 detector onto 256 x 256 x 128, then the ~50k-point
+    lattice of the XCAT setting (M = 50,000): every density against the
+    oracle's sampling of the same FDK volume."""
+    w = synth.c2()
+    cone, grid = w.cone, w.grid
+    V = 24
+    ang = (2 * np.pi * np.arange(V) / V).astype(np.float32)
+    p = phantom(cone, ang)
+    vol = ops.pmf_fdk(T(p), cone, T(ang), grid)
+    m, delta = ops.grid_init_lattice(grid, 50_000)
+    got = [N(t) for t in ops.pmf_grid_init(vol, grid, m, delta / np.sqrt(2 * np.pi))]
+    want = fdk.grid_init(N(vol), grid, m, delta / np.sqrt(2 * np.pi))
+    assert got[0].shape[0] == int(np.prod(m)) and abs(got[0].shape[0] - 50_000) < 2_500
+    assert np.abs(got[0] - want[0]).max() < 1e-4
+    r = rel(got[3], want[3])
+    print("grid_init benchmark size", m, r, flush=True)
     assert r < VOL_TOL, r
