@@ -43,11 +43,11 @@ static inline int fdk_taps(int nu) {
 // 64j -- the weight of input m for output n when n - m = d.  Uniform per
 // loop step of the filter, so the filter reads eight of them with one
 // scalar load.
-__global__ void k_fdk_taps(double tau, int t0, int K, float *__restrict__ wt) {
+__global__ void k_fdk_taps(double tau, int t0, int K, double *__restrict__ wt) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= K * FDK_R) return;
     const double d = (double)t0 + 2.0 * (i / FDK_R) + 64.0 * (i % FDK_R);
-    wt[i] = (float)(-1.0 / (M_PI * M_PI * tau * d * d));
+    wt[i] = -1.0 / (M_PI * M_PI * tau * d * d);
 }
 
 // One wave per (detector row i, view v): cosine-weighted row into LDS (zero
@@ -55,11 +55,15 @@ __global__ void k_fdk_taps(double tau, int t0, int K, float *__restrict__ wt) {
 // wt(n - m) p~[m] with each lane owning the outputs b0 + lane + 64 j (the
 // lag n - m = t + 64 j then depends on the loop counter t and j only), then
 // the row's taps written into the quads of padded rows i + 1 (top pair) and
-// i (bottom pair).  Block row nv writes the plane's zero border rows.
+// i (bottom pair).  Block row nv writes the plane's zero border rows.  The
+// row and the sums are double: for smooth rows on fine pixels q is a small
+// difference of the centre tap and the long odd-lag sum (they cancel exactly
+// on a constant row), and float sums of ~nu/2 terms lose its low digits.
+// On gfx950 a double FMA issues at the rate of an unpacked float one.
 __global__ __launch_bounds__(64) void k_fdk_filter(const float *__restrict__ proj, pmf_cone_t c,
-                                                   const float *__restrict__ wt, int t0,
+                                                   const double *__restrict__ wt, int t0,
                                                    float4 *__restrict__ qq) {
-    extern __shared__ float lds[];
+    extern __shared__ double lds[];
     const int nu = c.nu, nv = c.nv, lane = threadIdx.x;
     const int i = blockIdx.x, v = blockIdx.y;
     const int P = nu + 2;
@@ -73,16 +77,16 @@ __global__ __launch_bounds__(64) void k_fdk_filter(const float *__restrict__ pro
         }
         return;
     }
-    float *const row = lds;                          // row[m + FDK_PAD], m in [-64, nu + 64)
-    float *const out = lds + nu + 2 * FDK_PAD;       // out[n + 1] = q[n], out[0] = out[nu + 1] = 0
+    double *const row = lds;                         // row[m + FDK_PAD], m in [-64, nu + 64)
+    float *const out = (float *)(lds + nu + 2 * FDK_PAD);   // out[n + 1] = q[n], out[0] = out[nu + 1] = 0
     const int64_t base = ((int64_t)v * nv + i) * nu;
     const double b = ((double)i - 0.5 * (nv - 1) + c.off_v) * c.dv;
     const double sdd = c.sdd, sb = sdd * sdd + b * b;
     for (int m = lane - FDK_PAD; m < nu + FDK_PAD; m += 64) {
-        float x = 0.0f;
+        double x = 0.0;
         if (m >= 0 && m < nu) {
             const double a = ((double)m - 0.5 * (nu - 1) + c.off_u) * c.du;
-            x = (float)((double)proj[base + m] * sdd / sqrt(sb + a * a));
+            x = (double)proj[base + m] * sdd / sqrt(sb + a * a);
         }
         row[m + FDK_PAD] = x;
     }
@@ -91,24 +95,24 @@ __global__ __launch_bounds__(64) void k_fdk_filter(const float *__restrict__ pro
         out[nu + 1] = 0.0f;
     }
     __syncthreads();
-    const float c0 = (float)((double)c.sdd / (4.0 * (double)c.du * c.sad));
+    const double c0 = (double)c.sdd / (4.0 * (double)c.du * c.sad);
     for (int b0 = 0; b0 < nu; b0 += FDK_CH) {
-        float acc[FDK_R];
+        double acc[FDK_R];
 #pragma unroll
-        for (int j = 0; j < FDK_R; ++j) acc[j] = 0.0f;
+        for (int j = 0; j < FDK_R; ++j) acc[j] = 0.0;
         const int ts = (b0 - nu + 1) | 1;            // first odd lag with an input on the row
-        const float *wk = wt + ((ts - t0) >> 1) * FDK_R;
-        const float *xr = row + FDK_PAD + b0 + lane - ts;
+        const double *wk = wt + ((ts - t0) >> 1) * FDK_R;
+        const double *xr = row + FDK_PAD + b0 + lane - ts;
 #pragma unroll 4
         for (int t = ts; t <= b0 + 63; t += 2, wk += FDK_R, xr -= 2) {
-            const float x = *xr;
+            const double x = *xr;
 #pragma unroll
-            for (int j = 0; j < FDK_R; ++j) acc[j] = fmaf(wk[j], x, acc[j]);
+            for (int j = 0; j < FDK_R; ++j) acc[j] = fma(wk[j], x, acc[j]);
         }
 #pragma unroll
         for (int j = 0; j < FDK_R; ++j) {
             const int n = b0 + lane + 64 * j;
-            if (n < nu) out[n + 1] = fmaf(c0, row[FDK_PAD + n], acc[j]);
+            if (n < nu) out[n + 1] = (float)fma(c0, row[FDK_PAD + n], acc[j]);
         }
     }
     __syncthreads();
@@ -199,11 +203,11 @@ static size_t fdk_plane_bytes(const pmf_cone_t &c) {
 
 size_t fdk_workspace(const pmf_cone_t &c, int V) {
     return align256(fdk_plane_bytes(c) * V) + align256(sizeof(FdkView) * (size_t)V) +
-           align256(sizeof(float) * FDK_R * (size_t)fdk_taps(c.nu));
+           align256(sizeof(double) * FDK_R * (size_t)fdk_taps(c.nu));
 }
 
 size_t fdk_filter_lds(const pmf_cone_t &c) {
-    return sizeof(float) * (size_t)(2 * c.nu + 2 * FDK_PAD + 2);
+    return sizeof(double) * (size_t)(c.nu + 2 * FDK_PAD) + sizeof(float) * (size_t)(c.nu + 2);
 }
 
 hipError_t launch_fdk(const float *proj, const pmf_cone_t &c, const float *angles, int V,
@@ -213,7 +217,7 @@ hipError_t launch_fdk(const float *proj, const pmf_cone_t &c, const float *angle
     w += align256(fdk_plane_bytes(c) * V);
     FdkView *views = (FdkView *)w;
     w += align256(sizeof(FdkView) * (size_t)V);
-    float *wt = (float *)w;
+    double *wt = (double *)w;
     const double tau = (double)c.du * c.sad / c.sdd;
     const int t0 = fdk_t0(c.nu), K = fdk_taps(c.nu);
     hipError_t e;

@@ -125,3 +125,34 @@ def test_fdk_then_grid_init_at_benchmark_size():
     r = rel(got[3], want[3])
     print("grid_init benchmark size", m, r, flush=True)
     assert r < VOL_TOL, r
+
+
+@pytest.mark.parametrize("case", ["one_view", "tiny_detector", "max_row"])
+def test_fdk_edge_cases(case):
+    """A single view, a 5 x 3 detector (rows shorter than a wave) on the
+    smallest grid, and the longest supported row (4096 pixels)."""
+    if case == "one_view":
+        cone, V, grid = Cone(1000.0, 1500.0, 64, 40, 1.6, 1.6), 1, Grid((20, 18, 10), (2.0, 2.0, 2.0))
+        ang = np.array([0.4], np.float32)
+    elif case == "tiny_detector":
+        cone, V, grid = Cone(1000.0, 1500.0, 5, 3, 8.0, 8.0, off_u=0.3), 7, Grid((2, 2, 2), (4.0, 4.0, 4.0))
+        ang = (2 * np.pi * np.arange(V) / V).astype(np.float32)
+    else:
+        cone, V, grid = Cone(1000.0, 1500.0, 4096, 4, 0.05, 1.0), 3, Grid((24, 24, 2), (2.0, 2.0, 0.5))
+        ang = (2 * np.pi * np.arange(V) / V).astype(np.float32)
+    p = synth.projection_like(13, V, cone.nv, cone.nu)
+    got = N(ops.pmf_fdk(T(p), cone, T(ang), grid))
+    want = fdk.fdk(p, cone, ang, grid)
+    r = rel(got, want)
+    print("fdk edge", case, r, flush=True)
+    assert r < VOL_TOL, r
+
+
+def test_grid_init_single_point_axes():
+    grid = Grid((9, 4, 6), (1.0, 2.0, 3.0), (0.5, 0.0, -1.0))
+    vol = np.random.default_rng(6).uniform(0.0, 1.0, grid.n).astype(np.float32)
+    m = (1, 4, 1)
+    got = [N(t) for t in ops.pmf_grid_init(T(vol), grid, m, 0.5)]
+    want = fdk.grid_init(vol, grid, m, 0.5)
+    assert np.abs(got[0] - want[0]).max() < 1e-5
+    assert rel(got[3], want[3]) < VOL_TOL
