@@ -215,12 +215,38 @@ __device__ __forceinline__ void splat_box(const GaussK &p, const GridK &g, float
     }
 }
 
+// z range [za, zb] of column (ix, iy) that the truncation ellipsoid can
+// reach: the roots of the quadratic in d2, widened by one voxel on each side
+// and clipped to [lo2, hi2]; false when the column's quadratic stays clearly
+// above k2.  Untruncated sets take the whole range.
+__device__ __forceinline__ bool col_range(const GaussK &p, const GridK &g, float k2, bool untrunc,
+                                          float d0, float d1, int lo2, int hi2, int &za,
+                                          int &zb) {
+    za = lo2;
+    zb = hi2;
+    if (untrunc) return true;
+    // quad(d0, d1, d2) = a22 d2^2 + 2 bh d2 + cq
+    const float bh = fmaf(p.a02, d0, p.a12 * d1);
+    const float cq = fmaf(p.a00 * d0, d0, fmaf(2.0f * p.a01 * d0, d1, p.a11 * d1 * d1));
+    float disc = fmaf(bh, bh, -p.a22 * (cq - k2));
+    const float tol = 1e-4f * (fmaf(bh, bh, p.a22 * (fabsf(cq) + k2)));
+    if (disc < -tol) return false;
+    disc = fmaxf(disc, 0.0f);
+    const float r = sqrtf(disc), inv_a = 1.0f / p.a22;
+    // d2 range -> voxel index range: iz = (mu2 + d2 - c0_2) / h2
+    const float inv_h2 = g.inv_h[2];
+    const float zc = (p.mu[2] - g.c0[2]) * inv_h2;
+    const float t_lo = zc + (-bh - r) * inv_a * inv_h2;
+    const float t_hi = zc + (-bh + r) * inv_a * inv_h2;
+    za = max(za, (int)floorf(t_lo) - 1);
+    zb = min(zb, (int)ceilf(t_hi) + 1);
+    return true;
+}
+
 // The same voxels as splat_box, visited by (x, y) column: each lane takes a
-// column and walks only the z range where the ellipsoid can be, from the
-// roots of the quadratic in d2 widened by one voxel on each side; every voxel
-// visited is still tested with quad() exactly as above, so the voxels added
-// and their order within a column are unchanged.  Columns whose quadratic
-// stays clearly above k2 are skipped.  Untruncated sets walk the whole box.
+// column and walks only its col_range; every voxel visited is still tested
+// with quad() exactly as above, so the voxels added and their order within a
+// column are unchanged.
 template <typename Add>
 __device__ __forceinline__ void splat_cols(const GaussK &p, const GridK &g, float k2, int lo0,
                                            int lo1, int lo2, int hi0, int hi1, int hi2, Add add) {
@@ -228,30 +254,14 @@ __device__ __forceinline__ void splat_cols(const GaussK &p, const GridK &g, floa
     const int ny = hi1 - lo1 + 1;
     const int ncol = (hi0 - lo0 + 1) * ny;
     const bool untrunc = isinf(k2);
-    const float inv_h2 = g.inv_h[2];
     for (int c0 = 0; c0 < ncol; c0 += 64) {
         const int col = c0 + lane;
         if (col >= ncol) continue;
         const int ix = lo0 + col / ny, iy = lo1 + col % ny;
         const float d0 = fmaf((float)ix, g.h[0], g.c0[0]) - p.mu[0];
         const float d1 = fmaf((float)iy, g.h[1], g.c0[1]) - p.mu[1];
-        int za = lo2, zb = hi2;
-        if (!untrunc) {
-            // quad(d0, d1, d2) = a22 d2^2 + 2 bh d2 + cq
-            const float bh = fmaf(p.a02, d0, p.a12 * d1);
-            const float cq = fmaf(p.a00 * d0, d0, fmaf(2.0f * p.a01 * d0, d1, p.a11 * d1 * d1));
-            float disc = fmaf(bh, bh, -p.a22 * (cq - k2));
-            const float tol = 1e-4f * (fmaf(bh, bh, p.a22 * (fabsf(cq) + k2)));
-            if (disc < -tol) continue;
-            disc = fmaxf(disc, 0.0f);
-            const float r = sqrtf(disc), inv_a = 1.0f / p.a22;
-            // d2 range -> voxel index range: iz = (mu2 + d2 - c0_2) / h2
-            const float zc = (p.mu[2] - g.c0[2]) * inv_h2;
-            const float t_lo = zc + (-bh - r) * inv_a * inv_h2;
-            const float t_hi = zc + (-bh + r) * inv_a * inv_h2;
-            za = max(za, (int)floorf(t_lo) - 1);
-            zb = min(zb, (int)ceilf(t_hi) + 1);
-        }
+        int za, zb;
+        if (!col_range(p, g, k2, untrunc, d0, d1, lo2, hi2, za, zb)) continue;
         for (int iz = za; iz <= zb; ++iz) {
             const float d2 = fmaf((float)iz, g.h[2], g.c0[2]) - p.mu[2];
             const float mm = quad(p, d0, d1, d2);
@@ -454,13 +464,16 @@ hipError_t launch_voxelize(const pmf_gauss_t &gs, const GridK &g, float k, float
 // ------------------------------------------------------------- backward
 constexpr int MAXC = 16;
 
+// CT > 0: the channel count at compile time (the loads of a voxel's channels
+// issue together); CT = 0: any C up to MAXC.
+template <int CT>
 __global__ __launch_bounds__(256) void k_vox_bwd(pmf_gauss_t gs, GridK g, float k,
                                                  const float *__restrict__ g_vol,
                                                  pmf_gauss_grad_t gr) {
     const int64_t gi = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (gi >= gs.m) return;
     const int lane = threadIdx.x & 63;
-    const int C = gs.c;
+    const int C = CT > 0 ? CT : gs.c;
     GaussFull G;
     gauss_full(gs.mean, gs.scale, gs.quat, gi, k, g, G);
     GaussK p;
@@ -482,37 +495,59 @@ __global__ __launch_bounds__(256) void k_vox_bwd(pmf_gauss_t gs, GridK g, float 
     float gm0 = 0, gm1 = 0, gm2 = 0;
     float M00 = 0, M01 = 0, M02 = 0, M11 = 0, M12 = 0, M22 = 0;
     const int64_t N = grid_size(g);
+    // Column walk of splat_cols with the same voxels in the same order per
+    // lane; every voxel of the column range is loaded (the range lies in the
+    // grid) and voxels outside the ellipsoid add exact zeros, so the loop has
+    // no branch and the loads of successive voxels overlap.
     if (G.lo[0] <= G.hi[0] && G.lo[1] <= G.hi[1] && G.lo[2] <= G.hi[2]) {
-        splat_cols(p, g, k2, G.lo[0], G.lo[1], G.lo[2], G.hi[0], G.hi[1], G.hi[2],
-                  [&](int ix, int iy, int iz, float ev) {
-                      const int64_t j = ((int64_t)ix * g.n[1] + iy) * g.n[2] + iz;
-                      float Gj = 0.0f;
+        const int ny = G.hi[1] - G.lo[1] + 1;
+        const int ncol = (G.hi[0] - G.lo[0] + 1) * ny;
+        const bool untrunc = isinf(k2);
+        for (int c0 = 0; c0 < ncol; c0 += 64) {
+            const int col = c0 + lane;
+            if (col >= ncol) continue;
+            const int ix = G.lo[0] + col / ny, iy = G.lo[1] + col % ny;
+            const float d0 = fmaf((float)ix, g.h[0], g.c0[0]) - p.mu[0];
+            const float d1 = fmaf((float)iy, g.h[1], g.c0[1]) - p.mu[1];
+            int za, zb;
+            if (!col_range(p, g, k2, untrunc, d0, d1, G.lo[2], G.hi[2], za, zb)) continue;
+            const float *gcol = g_vol + ((int64_t)ix * g.n[1] + iy) * g.n[2];
+            constexpr int UNR = CT == 1 ? 4 : 2;     // voxels whose loads overlap
+#pragma unroll UNR
+            for (int iz = za; iz <= zb; ++iz) {
+                float gl[MAXC];
 #pragma unroll
-                      for (int c = 0; c < MAXC; ++c) {
-                          if (c < C) {
-                              const float gc = g_vol[c * N + j];
-                              gv[c] = fmaf(gc, ev, gv[c]);
-                              Gj = fmaf(val[c], gc, Gj);
-                          }
-                      }
-                      const float t = Gj * ev;
-                      const float d0 = fmaf((float)ix, g.h[0], g.c0[0]) - p.mu[0];
-                      const float d1 = fmaf((float)iy, g.h[1], g.c0[1]) - p.mu[1];
-                      const float d2 = fmaf((float)iz, g.h[2], g.c0[2]) - p.mu[2];
-                      const float A0 = fmaf(p.a00, d0, fmaf(p.a01, d1, p.a02 * d2));
-                      const float A1 = fmaf(p.a01, d0, fmaf(p.a11, d1, p.a12 * d2));
-                      const float A2 = fmaf(p.a02, d0, fmaf(p.a12, d1, p.a22 * d2));
-                      gm0 = fmaf(t, A0, gm0);
-                      gm1 = fmaf(t, A1, gm1);
-                      gm2 = fmaf(t, A2, gm2);
-                      const float ht = -0.5f * t;
-                      M00 = fmaf(ht * d0, d0, M00);
-                      M01 = fmaf(ht * d0, d1, M01);
-                      M02 = fmaf(ht * d0, d2, M02);
-                      M11 = fmaf(ht * d1, d1, M11);
-                      M12 = fmaf(ht * d1, d2, M12);
-                      M22 = fmaf(ht * d2, d2, M22);
-                  });
+                for (int c = 0; c < MAXC; ++c)
+                    if (c < C) gl[c] = gcol[c * N + iz];
+                const float d2 = fmaf((float)iz, g.h[2], g.c0[2]) - p.mu[2];
+                const float mm = quad(p, d0, d1, d2);
+                const bool in = mm <= k2;
+                const float ev = in ? __expf(-0.5f * mm) : 0.0f;
+                float Gj = 0.0f;
+#pragma unroll
+                for (int c = 0; c < MAXC; ++c) {
+                    if (c < C) {
+                        const float gc = in ? gl[c] : 0.0f;
+                        gv[c] = fmaf(gc, ev, gv[c]);
+                        Gj = fmaf(val[c], gc, Gj);
+                    }
+                }
+                const float t = Gj * ev;
+                const float A0 = fmaf(p.a00, d0, fmaf(p.a01, d1, p.a02 * d2));
+                const float A1 = fmaf(p.a01, d0, fmaf(p.a11, d1, p.a12 * d2));
+                const float A2 = fmaf(p.a02, d0, fmaf(p.a12, d1, p.a22 * d2));
+                gm0 = fmaf(t, A0, gm0);
+                gm1 = fmaf(t, A1, gm1);
+                gm2 = fmaf(t, A2, gm2);
+                const float ht = -0.5f * t;
+                M00 = fmaf(ht * d0, d0, M00);
+                M01 = fmaf(ht * d0, d1, M01);
+                M02 = fmaf(ht * d0, d2, M02);
+                M11 = fmaf(ht * d1, d1, M11);
+                M12 = fmaf(ht * d1, d2, M12);
+                M22 = fmaf(ht * d2, d2, M22);
+            }
+        }
     }
 #pragma unroll
     for (int c = 0; c < MAXC; ++c)
@@ -564,7 +599,15 @@ hipError_t launch_voxelize_bwd(const pmf_gauss_t &gs, const GridK &g, float k, c
     if (gs.m <= 0) return hipSuccess;
     {
         ProfScope prof_("voxelize_bwd", s);
-        k_vox_bwd<<<(unsigned)((gs.m + 3) / 4), 256, 0, s>>>(gs, g, k, g_vol, gr);
+        const unsigned nb = (unsigned)((gs.m + 3) / 4);
+        if (gs.c == 1)
+            k_vox_bwd<1><<<nb, 256, 0, s>>>(gs, g, k, g_vol, gr);
+        else if (gs.c == 3)
+            k_vox_bwd<3><<<nb, 256, 0, s>>>(gs, g, k, g_vol, gr);
+        else if (gs.c == 9)
+            k_vox_bwd<9><<<nb, 256, 0, s>>>(gs, g, k, g_vol, gr);
+        else
+            k_vox_bwd<0><<<nb, 256, 0, s>>>(gs, g, k, g_vol, gr);
     }
     return hipGetLastError();
 }

@@ -108,13 +108,21 @@ def test_voxelize_c2_full_size():
     assert rel(got, want) < VOL_TOL, rel(got, want)
 
 
-@pytest.mark.parametrize("case", ["c1", "small_mbc", "fd32_untruncated"])
+@pytest.mark.parametrize("case", ["c1", "small_mbc", "signed_c3", "signed_c9", "fd32_untruncated"])
 def test_voxelize_backward(case):
+    """One channel (c1, untruncated fd32), six (the small MBC level: the
+    kernel's generic channel count) and three and nine signed channels (the
+    MBC bases with B = 1 and B = 3)."""
     say("voxelize_bwd", case)
     if case == "c1":
         w = synth.c1(); gs, grid, k = w.ref, w.grid, 3.0
     elif case == "small_mbc":
         w = synth.small_motion(); gs, grid, k = w.mbc[1], w.levels[1], 3.0
+    elif case in ("signed_c3", "signed_c9"):
+        grid = Grid((30, 26, 22), (2.0, 2.5, 3.0), (1.0, -2.0, 0.5))
+        gs = synth.gaussians(np.random.default_rng(17), 400, grid, c=3 if case == "signed_c3" else 9,
+                             value_sigma=1.0)
+        k = 3.0
     else:
         w = synth.fd32(); gs, grid, k = w.ref, w.grid, math.inf
     gv = synth.random_normal(3, (gs.c,) + tuple(grid.n))
