@@ -102,6 +102,11 @@ __device__ __forceinline__ float quad(const GaussK &p, float d0, float d1, float
 }
 
 // ---------------------------------------------------------------- binning
+// Tile counters and cursors sit one per 128-byte line: the binning's atomics
+// are device-scope and contend per line, and a packed array puts every
+// tile's atomics on a few dozen lines.
+constexpr int CNT_STRIDE = 32;
+
 __global__ __launch_bounds__(256) void k_vox_prep(pmf_gauss_t gs, GridK g, float k, int T0,
                                                   int T1, int T2, int nt1, int nt2, int maxtiles,
                                                   GaussK *__restrict__ rec,
@@ -139,11 +144,13 @@ __global__ __launch_bounds__(256) void k_vox_prep(pmf_gauss_t gs, GridK g, float
     }
     for (int a = t0a; a <= t0b; ++a)
         for (int b = t1a; b <= t1b; ++b)
-            for (int c = t2a; c <= t2b; ++c) atomicAdd(&tile_count[(a * nt1 + b) * nt2 + c], 1);
+            for (int c = t2a; c <= t2b; ++c)
+                atomicAdd(&tile_count[((a * nt1 + b) * nt2 + c) * CNT_STRIDE], 1);
 }
 
-// Exclusive scan of n counts by one workgroup of 1024 threads: off[0..n],
-// and cursor[] = off[] for the fill pass.
+// Exclusive scan of n counts (CNT_STRIDE apart) by one workgroup of 1024
+// threads: off[0..n] (dense), and the cursors (CNT_STRIDE apart) = off[] for
+// the fill pass.
 __global__ __launch_bounds__(1024) void k_scan(const int32_t *__restrict__ cnt, int64_t n,
                                                int32_t *__restrict__ off,
                                                int32_t *__restrict__ cursor) {
@@ -152,7 +159,7 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t *__restrict__ cnt, 
     const int64_t b = threadIdx.x * per;
     const int64_t e = b + per < n ? b + per : n;
     int32_t s = 0;
-    for (int64_t i = b; i < e; ++i) s += cnt[i];
+    for (int64_t i = b; i < e; ++i) s += cnt[i * CNT_STRIDE];
     part[threadIdx.x] = s;
     __syncthreads();
     for (int o = 1; o < 1024; o <<= 1) {
@@ -164,8 +171,8 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t *__restrict__ cnt, 
     int32_t run = part[threadIdx.x] - s;
     for (int64_t i = b; i < e; ++i) {
         off[i] = run;
-        cursor[i] = run;
-        run += cnt[i];
+        cursor[i * CNT_STRIDE] = run;
+        run += cnt[i * CNT_STRIDE];
     }
     if (threadIdx.x == 1023) off[n] = part[1023];
 }
@@ -186,7 +193,7 @@ __global__ __launch_bounds__(256) void k_vox_fill(int64_t m, const GaussK *__res
     for (int a = t0a; a <= t0b; ++a)
         for (int b = t1a; b <= t1b; ++b)
             for (int c = t2a; c <= t2b; ++c)
-                list[atomicAdd(&cursor[(a * nt1 + b) * nt2 + c], 1)] = (int32_t)i;
+                list[atomicAdd(&cursor[((a * nt1 + b) * nt2 + c) * CNT_STRIDE], 1)] = (int32_t)i;
 }
 
 // ------------------------------------------------------------ tile splat
@@ -276,16 +283,25 @@ __device__ __forceinline__ void splat_cols(const GaussK &p, const GridK &g, floa
 // channel the scale is 2^30 / S with S = sum of |value| over the tile's
 // Gaussians, which bounds every voxel's sum since each Gaussian adds
 // value * e (e <= 1) at most once per voxel.
+constexpr int VT_CHUNK = 128;      // Gaussians staged in LDS at a time (one per thread)
+
+// STAGE: the tile's Gaussians go through LDS VT_CHUNK at a time (one-channel
+// sets, ~250 Gaussians per 16^3 tile); otherwise each wave reads its
+// Gaussians directly (the many-channel MBC sets have ~16 per tile, where the
+// barriers and the LDS cost more than they save).
+template <bool STAGE>
 __global__ __launch_bounds__(256) void k_vox_tile(const GaussK *__restrict__ rec,
                                                   const float *__restrict__ value, int C, GridK g,
                                                   float k2, int T0, int T1, int T2, int nt1,
                                                   int nt2, const int32_t *__restrict__ off,
                                                   const int32_t *__restrict__ list,
                                                   float *__restrict__ vol) {
-    extern __shared__ int acc[];
+    extern __shared__ int acc[];          // C tile planes, then VT_CHUNK x C staged values
     __shared__ float cs[4][16];
     __shared__ float scale[16];
+    __shared__ GaussK gsh[STAGE ? VT_CHUNK : 1];
     const int tvox = T0 * T1 * T2;
+    float *const vsh = (float *)(acc + C * tvox);
     for (int i = threadIdx.x; i < C * tvox; i += blockDim.x) acc[i] = 0;
     const int t = blockIdx.x;
     const int tz = t % nt2, ty = (t / nt2) % nt1, tx = t / (nt2 * nt1);
@@ -310,19 +326,46 @@ __global__ __launch_bounds__(256) void k_vox_tile(const GaussK *__restrict__ rec
                         (cs[2][threadIdx.x] + cs[3][threadIdx.x]);
         scale[threadIdx.x] = S > 0.0f ? 1073741824.0f / (S * 1.0001f) : 0.0f;
     }
-    __syncthreads();
-    for (int e = beg + wave; e < end; e += nw) {
-        const int gi = __builtin_amdgcn_readfirstlane(list[e]);
-        const GaussK p = rec[gi];
-        const int lo0 = max(p.lo0, b0), lo1 = max(p.lo1, b1), lo2 = max(p.lo2, b2);
-        const int hi0 = min(p.hi0, e0), hi1 = min(p.hi1, e1), hi2 = min(p.hi2, e2);
-        if (lo0 > hi0 || lo1 > hi1 || lo2 > hi2) continue;
-        const float *vv = value + (int64_t)gi * C;
-        splat_cols(p, g, k2, lo0, lo1, lo2, hi0, hi1, hi2, [&](int ix, int iy, int iz, float ev) {
-            const int li = ((ix - b0) * T1 + (iy - b1)) * T2 + (iz - b2);
-            for (int c = 0; c < C; ++c)
-                atomicAdd(&acc[c * tvox + li], __float2int_rn(vv[c] * scale[c] * ev));
-        });
+    // Staged: each thread fetches one record and its values, so a wave does
+    // not wait for two dependent global reads per Gaussian; the integer sums
+    // do not depend on the order.
+    if constexpr (!STAGE) {
+        __syncthreads();
+        for (int e = beg + wave; e < end; e += nw) {
+            const int gi = __builtin_amdgcn_readfirstlane(list[e]);
+            const GaussK p = rec[gi];
+            const int lo0 = max(p.lo0, b0), lo1 = max(p.lo1, b1), lo2 = max(p.lo2, b2);
+            const int hi0 = min(p.hi0, e0), hi1 = min(p.hi1, e1), hi2 = min(p.hi2, e2);
+            if (lo0 > hi0 || lo1 > hi1 || lo2 > hi2) continue;
+            const float *vv = value + (int64_t)gi * C;
+            splat_cols(p, g, k2, lo0, lo1, lo2, hi0, hi1, hi2, [&](int ix, int iy, int iz, float ev) {
+                const int li = ((ix - b0) * T1 + (iy - b1)) * T2 + (iz - b2);
+                for (int c = 0; c < C; ++c)
+                    atomicAdd(&acc[c * tvox + li], __float2int_rn(vv[c] * scale[c] * ev));
+            });
+        }
+    }
+    for (int cb = beg; STAGE && cb < end; cb += VT_CHUNK) {
+        const int n = min(VT_CHUNK, end - cb);
+        __syncthreads();
+        if ((int)threadIdx.x < n) {
+            const int gi = list[cb + threadIdx.x];
+            gsh[threadIdx.x] = rec[gi];
+            for (int c = 0; c < C; ++c) vsh[threadIdx.x * C + c] = value[(int64_t)gi * C + c];
+        }
+        __syncthreads();
+        for (int e = wave; e < n; e += nw) {
+            GaussK p = gsh[e];
+            const int lo0 = max(p.lo0, b0), lo1 = max(p.lo1, b1), lo2 = max(p.lo2, b2);
+            const int hi0 = min(p.hi0, e0), hi1 = min(p.hi1, e1), hi2 = min(p.hi2, e2);
+            if (lo0 > hi0 || lo1 > hi1 || lo2 > hi2) continue;
+            const float *vv = vsh + e * C;
+            splat_cols(p, g, k2, lo0, lo1, lo2, hi0, hi1, hi2, [&](int ix, int iy, int iz, float ev) {
+                const int li = ((ix - b0) * T1 + (iy - b1)) * T2 + (iz - b2);
+                for (int c = 0; c < C; ++c)
+                    atomicAdd(&acc[c * tvox + li], __float2int_rn(vv[c] * scale[c] * ev));
+            });
+        }
     }
     __syncthreads();
     const int64_t N = grid_size(g);
@@ -388,9 +431,9 @@ VoxPlan vox_plan(int64_t m, int c, const GridK &g) {
 size_t vox_workspace(const VoxPlan &p, int64_t m) {
     size_t s = 0;
     s += align256(sizeof(GaussK) * (size_t)(m > 0 ? m : 1));  // records
-    s += align256(sizeof(int32_t) * (size_t)p.ntiles);        // counts
-    s += align256(sizeof(int32_t) * (size_t)(p.ntiles + 1));  // offsets
-    s += align256(sizeof(int32_t) * (size_t)p.ntiles);        // cursors
+    s += align256(sizeof(int32_t) * CNT_STRIDE * (size_t)p.ntiles);   // counts
+    s += align256(sizeof(int32_t) * (size_t)(p.ntiles + 1));          // offsets
+    s += align256(sizeof(int32_t) * CNT_STRIDE * (size_t)p.ntiles);   // cursors
     s += align256(sizeof(int32_t) * (size_t)(p.cap > 0 ? p.cap : 1));  // list
     s += align256(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));  // large list
     s += align256(sizeof(int32_t));                            // large count
@@ -404,11 +447,11 @@ hipError_t launch_voxelize(const pmf_gauss_t &gs, const GridK &g, float k, float
     GaussK *rec = (GaussK *)w;
     w += align256(sizeof(GaussK) * (size_t)(m > 0 ? m : 1));
     int32_t *cnt = (int32_t *)w;
-    w += align256(sizeof(int32_t) * (size_t)p.ntiles);
+    w += align256(sizeof(int32_t) * CNT_STRIDE * (size_t)p.ntiles);
     int32_t *off = (int32_t *)w;
     w += align256(sizeof(int32_t) * (size_t)(p.ntiles + 1));
     int32_t *cur = (int32_t *)w;
-    w += align256(sizeof(int32_t) * (size_t)p.ntiles);
+    w += align256(sizeof(int32_t) * CNT_STRIDE * (size_t)p.ntiles);
     int32_t *list = (int32_t *)w;
     w += align256(sizeof(int32_t) * (size_t)(p.cap > 0 ? p.cap : 1));
     int32_t *large = (int32_t *)w;
@@ -416,7 +459,7 @@ hipError_t launch_voxelize(const pmf_gauss_t &gs, const GridK &g, float k, float
     int32_t *nlarge = (int32_t *)w;
 
     const float k2 = isinf(k) ? INFINITY : k * k;
-    hipError_t e = launch_fill_i32(cnt, p.ntiles, 0, s);
+    hipError_t e = launch_fill_i32(cnt, CNT_STRIDE * p.ntiles, 0, s);
     if (e != hipSuccess) return e;
     e = launch_fill_i32(nlarge, 1, 0, s);
     if (e != hipSuccess) return e;
@@ -442,11 +485,17 @@ hipError_t launch_voxelize(const pmf_gauss_t &gs, const GridK &g, float k, float
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    const size_t lds = sizeof(float) * (size_t)gs.c * p.T[0] * p.T[1] * p.T[2];
+    const bool stage = gs.c == 1;
+    const size_t lds =
+        sizeof(float) * (size_t)gs.c * (p.T[0] * p.T[1] * p.T[2] + (stage ? VT_CHUNK : 0));
     {
         ProfScope prof_("voxelize_tile", s);
-        k_vox_tile<<<(unsigned)p.ntiles, 256, lds, s>>>(rec, gs.value, gs.c, g, k2, p.T[0], p.T[1],
-                                                        p.T[2], p.nt[1], p.nt[2], off, list, vol);
+        if (stage)
+            k_vox_tile<true><<<(unsigned)p.ntiles, 256, lds, s>>>(
+                rec, gs.value, gs.c, g, k2, p.T[0], p.T[1], p.T[2], p.nt[1], p.nt[2], off, list, vol);
+        else
+            k_vox_tile<false><<<(unsigned)p.ntiles, 256, lds, s>>>(
+                rec, gs.value, gs.c, g, k2, p.T[0], p.T[1], p.T[2], p.nt[1], p.nt[2], off, list, vol);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (m > 0) {
