@@ -30,6 +30,9 @@ namespace pmf {
 constexpr int RS_T = 16;                // tile edge (pixels)
 constexpr int RS_THREADS = RS_T * RS_T;
 constexpr int RS_TMAX = 16;             // tiles per Gaussian on the tile path
+// Tile counters and cursors one per 128-byte line: the binning's device-scope
+// atomics contend per line.
+constexpr int RS_CSTRIDE = 32;
 
 // 2-D splat of one (view, Gaussian): centre, conic (Sigma^-1 = [[a, b], [b, c]]),
 // amplitude, and its tile rectangle (empty when lo > hi).
@@ -162,12 +165,14 @@ __global__ __launch_bounds__(256) void k_splat_prep(const float *__restrict__ me
         large[atomicAdd(nlarge, 1)] = (int)i;
         return;
     }
-    int *cv = counts + (int64_t)v * G.tiles_u * G.tiles_v;
+    int *cv = counts + (int64_t)v * G.tiles_u * G.tiles_v * RS_CSTRIDE;
     for (int ty = P.tv0; ty <= P.tv1; ++ty)
-        for (int tx = P.tu0; tx <= P.tu1; ++tx) atomicAdd(&cv[ty * G.tiles_u + tx], 1);
+        for (int tx = P.tu0; tx <= P.tu1; ++tx)
+            atomicAdd(&cv[(ty * G.tiles_u + tx) * RS_CSTRIDE], 1);
 }
 
-// Exclusive prefix sum of n counts (one workgroup, chunks of 1024).
+// Exclusive prefix sum of n counts (RS_CSTRIDE apart; one workgroup, chunks
+// of 1024) into dense offsets.
 __global__ __launch_bounds__(1024) void k_rast_scan(const int *__restrict__ counts, int64_t n,
                                                     int *__restrict__ offsets) {
     __shared__ int buf[1024];
@@ -176,7 +181,7 @@ __global__ __launch_bounds__(1024) void k_rast_scan(const int *__restrict__ coun
     __syncthreads();
     for (int64_t b = 0; b < n; b += 1024) {
         const int64_t i = b + threadIdx.x;
-        const int x = i < n ? counts[i] : 0;
+        const int x = i < n ? counts[i * RS_CSTRIDE] : 0;
         buf[threadIdx.x] = x;
         __syncthreads();
         for (int o = 1; o < 1024; o <<= 1) {
@@ -208,7 +213,7 @@ __global__ __launch_bounds__(256) void k_splat_fill(const SplatP *__restrict__ s
     for (int ty = P.tv0; ty <= P.tv1; ++ty)
         for (int tx = P.tu0; tx <= P.tu1; ++tx) {
             const int64_t tix = (int64_t)v * T + ty * G.tiles_u + tx;
-            list[offsets[tix] + atomicAdd(&cursor[tix], 1)] = (int)i;
+            list[offsets[tix] + atomicAdd(&cursor[tix * RS_CSTRIDE], 1)] = (int)i;
         }
 }
 
@@ -529,8 +534,8 @@ RastWs rast_ws(void *base, int64_t m, const RastGeo &G, int V) {
         return r;
     };
     w.sp = (SplatP *)take(sizeof(SplatP) * (size_t)mv);
-    w.counts = (int *)take(sizeof(int) * (size_t)T);
-    w.cursor = (int *)take(sizeof(int) * (size_t)T);
+    w.counts = (int *)take(sizeof(int) * RS_CSTRIDE * (size_t)T);
+    w.cursor = (int *)take(sizeof(int) * RS_CSTRIDE * (size_t)T);
     w.offsets = (int *)take(sizeof(int) * (size_t)(T + 1));
     w.list = (int *)take(sizeof(int) * (size_t)mv * RS_TMAX);
     w.large = (int *)take(sizeof(int) * (size_t)mv);
@@ -550,8 +555,8 @@ static hipError_t rast_bin(const pmf_gauss_t &gs, const RastGeo &G, const float 
     const int64_t T = (int64_t)G.tiles_u * G.tiles_v * V;
     const int64_t mv = gs.m * V;
     hipError_t e;
-    if ((e = launch_fill_i32(w.counts, T, 0, s)) != hipSuccess) return e;
-    if ((e = launch_fill_i32(w.cursor, T, 0, s)) != hipSuccess) return e;
+    if ((e = launch_fill_i32(w.counts, RS_CSTRIDE * T, 0, s)) != hipSuccess) return e;
+    if ((e = launch_fill_i32(w.cursor, RS_CSTRIDE * T, 0, s)) != hipSuccess) return e;
     if ((e = launch_fill_i32(w.nlarge, 1, 0, s)) != hipSuccess) return e;
     {
         ProfScope prof_("rasterize_bin", s);
