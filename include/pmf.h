@@ -241,7 +241,9 @@ int pmf_grid_init(const float *vol, const pmf_grid_t *grid, const int m[3], floa
  * depends on scheduling (results vary in the last bits between runs).
  * pmf_rasterize_bwd overwrites grad (shapes of g) with the gradients of
  * sum(g_proj * proj), summed over the V views in order (the mask is not
- * differentiated).  Errors: PMF_EINVAL for null pointers, c != 1, V < 1,
+ * differentiated); its sums run in a fixed order (the gradients repeat bit
+ * for bit).  The workspace holds about 570 bytes per (Gaussian, view):
+ * per-splat records, tile lists and per-tile partial gradients.  Errors: PMF_EINVAL for null pointers, c != 1, V < 1,
  * trunc_k <= 0 or a bad cone (0 < SAD < SDD, du, dv > 0, finite offsets);
  * PMF_EUNSUPPORTED for m * V >= 2^27 or detectors wider than 65536;
  * PMF_EWORKSPACE if the workspace from pmf_rasterize_workspace() is missing

@@ -198,11 +198,15 @@ __global__ __launch_bounds__(1024) void k_rast_scan(const int *__restrict__ coun
     if (threadIdx.x == 0) offsets[n] = carry;
 }
 
+// Also records, per (view, Gaussian), the list position of each of its tiles
+// in (row, column) order (gslot), so that the adjoint can sum a Gaussian's
+// per-tile partials in a fixed order.
 __global__ __launch_bounds__(256) void k_splat_fill(const SplatP *__restrict__ sp, int64_t m,
                                                     int V, RastGeo G,
                                                     const int *__restrict__ offsets,
                                                     int *__restrict__ cursor,
-                                                    int *__restrict__ list) {
+                                                    int *__restrict__ list,
+                                                    int *__restrict__ gslot) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m * V) return;
     const SplatP P = sp[i];
@@ -210,10 +214,13 @@ __global__ __launch_bounds__(256) void k_splat_fill(const SplatP *__restrict__ s
     if ((P.tu1 - P.tu0 + 1) * (P.tv1 - P.tv0 + 1) > RS_TMAX) return;
     const int v = (int)(i / m);
     const int64_t T = (int64_t)G.tiles_u * G.tiles_v;
+    int k = 0;
     for (int ty = P.tv0; ty <= P.tv1; ++ty)
         for (int tx = P.tu0; tx <= P.tu1; ++tx) {
             const int64_t tix = (int64_t)v * T + ty * G.tiles_u + tx;
-            list[offsets[tix] + atomicAdd(&cursor[tix * RS_CSTRIDE], 1)] = (int)i;
+            const int slot = offsets[tix] + atomicAdd(&cursor[tix * RS_CSTRIDE], 1);
+            list[slot] = (int)i;
+            gslot[i * RS_TMAX + k++] = slot;
         }
 }
 
@@ -294,13 +301,20 @@ __device__ __forceinline__ void splat_grad(const SplatP &P, float x, float y, fl
     out[5] = -0.5f * gre * dv * dv;
 }
 
+// Per tile: each wave reduces its 64 pixels' six splat gradients per
+// Gaussian with DPP into its LDS slot (zeros when no pixel of the wave is
+// inside the ellipse); the four slots are added in a fixed order and written
+// to part[list entry] -- no atomics.
+constexpr int RB_CHUNK = 128;     // Gaussians per LDS chunk in the adjoint
+
 __global__ __launch_bounds__(RS_THREADS) void k_splat_bwd(const SplatP *__restrict__ sp, RastGeo G,
                                                          const int *__restrict__ offsets,
                                                          const int *__restrict__ list,
                                                          const float *__restrict__ g_proj,
-                                                         float *__restrict__ acc6) {
-    __shared__ SplatP sh[RS_THREADS];
-    __shared__ int sid[RS_THREADS];
+                                                         float *__restrict__ part) {
+    __shared__ SplatP sh[RB_CHUNK];
+    __shared__ float red[RS_THREADS / 64][RB_CHUNK][6];
+    const int wave = threadIdx.x >> 6;
     const int64_t T = (int64_t)G.tiles_u * G.tiles_v;
     const int64_t tix = blockIdx.x;
     const int v = (int)(tix / T), t = (int)(tix - (int64_t)v * T);
@@ -311,28 +325,57 @@ __global__ __launch_bounds__(RS_THREADS) void k_splat_bwd(const SplatP *__restri
     const float k2 = G.k * G.k;
     const int lane = threadIdx.x & 63;
     const int b = offsets[tix], e = offsets[tix + 1];
-    for (int c0 = b; c0 < e; c0 += RS_THREADS) {
-        const int n = min(RS_THREADS, e - c0);
-        if ((int)threadIdx.x < n) {
-            const int id = list[c0 + threadIdx.x];
-            sid[threadIdx.x] = id;
-            sh[threadIdx.x] = sp[id];
-        }
+    for (int c0 = b; c0 < e; c0 += RB_CHUNK) {
+        const int n = min(RB_CHUNK, e - c0);
+        if ((int)threadIdx.x < n) sh[threadIdx.x] = sp[list[c0 + threadIdx.x]];
         __syncthreads();
         for (int j = 0; j < n; ++j) {
             float o[6];
             splat_grad(sh[j], (float)x, (float)y, k2, gp, o);
-            if (__ballot(o[0] != 0.0f) == 0) continue;          // wave-uniform
+            if (__ballot(o[0] != 0.0f) == 0) {                  // wave-uniform
+                if (lane == 63) {
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) red[wave][j][q] = 0.0f;
+                }
+                continue;
+            }
 #pragma unroll
             for (int q = 0; q < 6; ++q) o[q] = wave_sum_lane63(o[q]);
             if (lane == 63) {
-                float *dst = acc6 + (int64_t)sid[j] * 6;
 #pragma unroll
-                for (int q = 0; q < 6; ++q) atomicAdd(dst + q, o[q]);
+                for (int q = 0; q < 6; ++q) red[wave][j][q] = o[q];
             }
         }
         __syncthreads();
+        for (int i = threadIdx.x; i < n * 6; i += RS_THREADS) {
+            const int j = i / 6, q = i - 6 * j;
+            part[(int64_t)c0 * 6 + i] = (red[0][j][q] + red[1][j][q]) + (red[2][j][q] + red[3][j][q]);
+        }
+        __syncthreads();
     }
+}
+
+// acc6 of every tile-path (view, Gaussian): the sum of its per-tile partials
+// in tile order (0 for splats that reach no pixel); large-list splats are
+// left to k_splat_large_bwd.
+__global__ __launch_bounds__(256) void k_splat_gather(const SplatP *__restrict__ sp, int64_t mv,
+                                                      const int *__restrict__ gslot,
+                                                      const float *__restrict__ part,
+                                                      float *__restrict__ acc6) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= mv) return;
+    const SplatP P = sp[i];
+    int area = 0;
+    if (P.tu0 <= P.tu1 && P.tv0 <= P.tv1) area = (P.tu1 - P.tu0 + 1) * (P.tv1 - P.tv0 + 1);
+    if (area > RS_TMAX) return;
+    float o[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    for (int k = 0; k < area; ++k) {
+        const float *pk = part + (int64_t)gslot[i * RS_TMAX + k] * 6;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) o[q] += pk[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) acc6[i * 6 + q] = o[q];
 }
 
 // Large-list Gaussians: one workgroup sums its box's contributions (they
@@ -517,8 +560,8 @@ static RastGeo rast_geo(const pmf_cone_t &c, float k) {
 namespace {
 struct RastWs {
     SplatP *sp;
-    int *counts, *cursor, *offsets, *list, *large, *nlarge;
-    float *acc6;
+    int *counts, *cursor, *offsets, *list, *large, *nlarge, *gslot;
+    float *acc6, *part;
     size_t total;
 };
 
@@ -541,6 +584,8 @@ RastWs rast_ws(void *base, int64_t m, const RastGeo &G, int V) {
     w.large = (int *)take(sizeof(int) * (size_t)mv);
     w.nlarge = (int *)take(sizeof(int));
     w.acc6 = (float *)take(sizeof(float) * 6 * (size_t)mv);
+    w.gslot = (int *)take(sizeof(int) * (size_t)mv * RS_TMAX);
+    w.part = (float *)take(sizeof(float) * 6 * (size_t)mv * RS_TMAX);
     w.total = off;
     return w;
 }
@@ -567,7 +612,7 @@ static hipError_t rast_bin(const pmf_gauss_t &gs, const RastGeo &G, const float 
         k_rast_scan<<<1, 1024, 0, s>>>(w.counts, T, w.offsets);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         k_splat_fill<<<(unsigned)((mv + 255) / 256), 256, 0, s>>>(w.sp, gs.m, V, G, w.offsets,
-                                                                  w.cursor, w.list);
+                                                                  w.cursor, w.list, w.gslot);
     }
     return hipGetLastError();
 }
@@ -595,12 +640,17 @@ hipError_t launch_rasterize_bwd(const pmf_gauss_t &gs, const pmf_cone_t &c, cons
     const RastWs w = rast_ws(ws, gs.m, G, V);
     hipError_t e = rast_bin(gs, G, angles, V, w, s);
     if (e != hipSuccess) return e;
-    if ((e = launch_fill(w.acc6, 6 * gs.m * V, 0.0f, s)) != hipSuccess) return e;
     const int64_t T = (int64_t)G.tiles_u * G.tiles_v * V;
+    const int64_t mv = gs.m * V;
     {
         ProfScope prof_("rasterize_bwd", s);
-        k_splat_bwd<<<(unsigned)T, RS_THREADS, 0, s>>>(w.sp, G, w.offsets, w.list, g_proj, w.acc6);
+        k_splat_bwd<<<(unsigned)T, RS_THREADS, 0, s>>>(w.sp, G, w.offsets, w.list, g_proj, w.part);
         if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (mv > 0) {
+            k_splat_gather<<<(unsigned)((mv + 255) / 256), 256, 0, s>>>(w.sp, mv, w.gslot, w.part,
+                                                                        w.acc6);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
         k_splat_large_bwd<<<1024, 256, 0, s>>>(w.sp, gs.m, G, w.large, w.nlarge, g_proj, w.acc6);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         k_splat_chain<<<(unsigned)((gs.m + 255) / 256), 256, 0, s>>>(

@@ -158,3 +158,16 @@ def test_stage1_step_matches_oracle():
         r = rel(N(g[name]), gw[name])
         say("stage1 grad", name, r)
         assert r < GRAD_TOL, (name, r)
+
+
+def test_gradients_repeat_bit_for_bit():
+    """The adjoint sums in a fixed order: two calls give identical bits."""
+    gs = gaussian_set(9, 3000, 30.0, 0.3, 6.0)
+    cone = Cone(1000.0, 1500.0, 128, 96, 0.9, 0.9, off_u=0.1)
+    ang = np.array([0.2, 2.9])
+    gp = np.random.default_rng(10).normal(size=(2, cone.nv, cone.nu)).astype(np.float32)
+    _, a = run(gs, cone, ang, 3.0, gp)
+    a = [N(t) for t in a]
+    _, b = run(gs, cone, ang, 3.0, gp)
+    for x, y in zip(a, [N(t) for t in b]):
+        assert np.array_equal(x, y)
