@@ -188,31 +188,44 @@ __global__ __launch_bounds__(256) void k_adj_line(Shape4 in_s, int ax, int nc, f
     int next = 0;           // first output not yet written
     int cur = -1;           // cell of the pending pair (cur, cur + 1)
     float a0 = 0.0f, a1 = 0.0f;
-    for (int j = 0; j < nf; ++j) {
-        int i;
-        float f;
-        if (!axis_cell(fmaf((float)j, scale, off), nc, i, f)) continue;
-        if (i != cur) {
-            // cells below i are complete: write them (zeros for cells no value reached)
-            if (cur >= 0) {
-                out[obase + (int64_t)cur * ost] = a0;
-                next = cur + 1;
-                a0 = (cur + 1 == i) ? a1 : 0.0f;
-                if (cur + 1 < i) {
-                    out[obase + (int64_t)(cur + 1) * ost] = a1;
-                    next = cur + 2;
-                }
-            } else {
-                a0 = 0.0f;
-            }
-            for (; next < i; ++next) out[obase + (int64_t)next * ost] = 0.0f;
-            a1 = 0.0f;
-            cur = i;
+    // The line's values are fetched ADJ_U at a time ahead of the walk (whose
+    // branches would otherwise leave one load in flight per wave).
+    constexpr int ADJ_U = 8;
+    for (int j0 = 0; j0 < nf; j0 += ADJ_U) {
+        float xs[ADJ_U];
+#pragma unroll
+        for (int u = 0; u < ADJ_U; ++u) {
+            const int64_t jj = min(j0 + u, nf - 1);     // past the end: in range, unused
+            xs[u] = in ? in[cbase + ibase + jj * ist] : adj_src(src, c, ibase + jj * ist);
         }
-        const float x = in ? in[cbase + ibase + (int64_t)j * ist]
-                           : adj_src(src, c, ibase + (int64_t)j * ist);
-        a0 = fmaf(1.0f - f, x, a0);
-        a1 = fmaf(f, x, a1);
+#pragma unroll
+        for (int u = 0; u < ADJ_U; ++u) {
+            const int j = j0 + u;
+            if (j >= nf) break;
+            int i;
+            float f;
+            if (!axis_cell(fmaf((float)j, scale, off), nc, i, f)) continue;
+            if (i != cur) {
+                // cells below i are complete: write them (zeros for cells no value reached)
+                if (cur >= 0) {
+                    out[obase + (int64_t)cur * ost] = a0;
+                    next = cur + 1;
+                    a0 = (cur + 1 == i) ? a1 : 0.0f;
+                    if (cur + 1 < i) {
+                        out[obase + (int64_t)(cur + 1) * ost] = a1;
+                        next = cur + 2;
+                    }
+                } else {
+                    a0 = 0.0f;
+                }
+                for (; next < i; ++next) out[obase + (int64_t)next * ost] = 0.0f;
+                a1 = 0.0f;
+                cur = i;
+            }
+            const float x = xs[u];
+            a0 = fmaf(1.0f - f, x, a0);
+            a1 = fmaf(f, x, a1);
+        }
     }
     if (cur >= 0) {
         out[obase + (int64_t)cur * ost] = a0;
