@@ -114,6 +114,45 @@ __device__ __forceinline__ float wave_sum_lane63(float v) {
     v += dpp_mov<0x143, 0xc>(v);        // row_bcast:31 into rows 2, 3
     return v;
 }
+
+// Reduce-scatter of 32 per-lane values over the 64 lanes of a wave: returns
+// the total over all lanes of value 16*b3 + 8*b2 + 4*b1 + 2*b0 + b4 (b_k =
+// bit k of the lane; the same total in lanes L and L+32).  Each step pairs
+// lanes that hold the same set of partial sums, keeps half of the set and
+// adds the partner's copy of that half: 16 + 8 + 4 + 2 + 1 + 1 additions
+// instead of 32 separate six-step reductions.
+__device__ __forceinline__ float wave_reduce_scatter32(const float (&x)[32], int lane) {
+    const bool h3 = lane & 8, h2 = lane & 4, h1 = lane & 2, h0 = lane & 1, h4 = lane & 16;
+    float a[16], b[8], c[4], d[2];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {     // partner: row_mirror (lane ^ 15 within 16)
+        const float keep = h3 ? x[16 + j] : x[j], send = h3 ? x[j] : x[16 + j];
+        a[j] = keep + dpp_mov<0x140>(send);
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {      // partner: row_half_mirror (lane ^ 7 within 8)
+        const float keep = h2 ? a[8 + j] : a[j], send = h2 ? a[j] : a[8 + j];
+        b[j] = keep + dpp_mov<0x141>(send);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {      // partner: lane ^ 2
+        const float keep = h1 ? b[4 + j] : b[j], send = h1 ? b[j] : b[4 + j];
+        c[j] = keep + dpp_mov<0x4E>(send);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {      // partner: lane ^ 1
+        const float keep = h0 ? c[2 + j] : c[j], send = h0 ? c[j] : c[2 + j];
+        d[j] = keep + dpp_mov<0xB1>(send);
+    }
+    const float keep = h4 ? d[1] : d[0], send = h4 ? d[0] : d[1];
+    const float e = keep + __shfl_xor(send, 16, 64);
+    return e + __shfl_xor(e, 32, 64);
+}
+
+__device__ __forceinline__ int scatter32_index(int lane) {
+    return 16 * ((lane >> 3) & 1) + 8 * ((lane >> 2) & 1) + 4 * ((lane >> 1) & 1) +
+           2 * (lane & 1) + ((lane >> 4) & 1);
+}
 #endif
 
 // ------------------------------------------------------ ragged launches

@@ -302,9 +302,9 @@ __device__ __forceinline__ void splat_grad(const SplatP &P, float x, float y, fl
 }
 
 // Per tile: each wave reduces its 64 pixels' six splat gradients per
-// Gaussian with DPP into its LDS slot (zeros when no pixel of the wave is
-// inside the ellipse); the four slots are added in a fixed order and written
-// to part[list entry] -- no atomics.
+// Gaussian into its LDS slot (zeros when no pixel of the wave is inside any
+// of the five ellipses reduced together); the four slots are added in a
+// fixed order and written to part[list entry] -- no atomics.
 constexpr int RB_CHUNK = 128;     // Gaussians per LDS chunk in the adjoint
 
 __global__ __launch_bounds__(RS_THREADS) void k_splat_bwd(const SplatP *__restrict__ sp, RastGeo G,
@@ -329,22 +329,26 @@ __global__ __launch_bounds__(RS_THREADS) void k_splat_bwd(const SplatP *__restri
         const int n = min(RB_CHUNK, e - c0);
         if ((int)threadIdx.x < n) sh[threadIdx.x] = sp[list[c0 + threadIdx.x]];
         __syncthreads();
-        for (int j = 0; j < n; ++j) {
-            float o[6];
-            splat_grad(sh[j], (float)x, (float)y, k2, gp, o);
-            if (__ballot(o[0] != 0.0f) == 0) {                  // wave-uniform
-                if (lane == 63) {
+        // five Gaussians at a time: their 30 wave sums come from one 32-value
+        // reduce-scatter (~33 additions instead of 30 six-step reductions)
+        for (int j0 = 0; j0 < n; j0 += 5) {
+            float xv[32];
+            bool any = false;
 #pragma unroll
-                    for (int q = 0; q < 6; ++q) red[wave][j][q] = 0.0f;
-                }
-                continue;
+            for (int jj = 0; jj < 5; ++jj) {
+                float o[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+                if (j0 + jj < n) splat_grad(sh[j0 + jj], (float)x, (float)y, k2, gp, o);
+                any = any || o[0] != 0.0f;
+#pragma unroll
+                for (int q = 0; q < 6; ++q) xv[q * 5 + jj] = o[q];
             }
-#pragma unroll
-            for (int q = 0; q < 6; ++q) o[q] = wave_sum_lane63(o[q]);
-            if (lane == 63) {
-#pragma unroll
-                for (int q = 0; q < 6; ++q) red[wave][j][q] = o[q];
-            }
+            xv[30] = 0.0f;
+            xv[31] = 0.0f;
+            const int idx = scatter32_index(lane);
+            float r = 0.0f;
+            if (__ballot(any) != 0) r = wave_reduce_scatter32(xv, lane);   // wave-uniform
+            const int jj = idx % 5, q = idx / 5;
+            if (lane < 32 && idx < 30 && j0 + jj < n) red[wave][j0 + jj][q] = r;
         }
         __syncthreads();
         for (int i = threadIdx.x; i < n * 6; i += RS_THREADS) {
