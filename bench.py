@@ -342,7 +342,7 @@ def main():
                     help="time the eager batched steps instead of graph replays (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(views would shard across GPUs with one all-reduce of the parameter "
               "gradients; not implemented). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)

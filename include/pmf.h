@@ -52,7 +52,7 @@ typedef enum {
     PMF_EINVAL = -1,       /* invalid argument (null pointer, bad size or geometry) */
     PMF_EHIP = -2,         /* a HIP runtime call or kernel launch failed */
     PMF_EWORKSPACE = -3,   /* workspace missing or smaller than the query returned */
-    PMF_EUNSUPPORTED = -4  /* valid but outside what this build supports (e.g. C > 16) */
+    PMF_EUNSUPPORTED = -4  /* valid but outside what this library supports (e.g. C > 16) */
 } pmf_status;
 
 /* Voxel grid.  n: voxels per axis; h: spacing (mm); center: world position of
