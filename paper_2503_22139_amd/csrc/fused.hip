@@ -123,35 +123,6 @@ __global__ __launch_bounds__(256) void k_combine_warp(CWTab t) {
     combine_warp_voxel<L, B, PAIRED>(cj.ref, cj.g, cj.lv, cj.coeff, cj.V, cj.warped, j);
 }
 
-// The same for 16 values: the total of value 8*b3 + 4*b2 + 2*b1 + b0 (in
-// every lane whose low four bits give that index).
-__device__ __forceinline__ float wave_reduce_scatter16(const float (&x)[16], int lane) {
-    const bool h3 = lane & 8, h2 = lane & 4, h1 = lane & 2, h0 = lane & 1;
-    float b[8], c[4], d[2];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {      // partner: row_mirror (lane ^ 15 within 16)
-        const float keep = h3 ? x[8 + j] : x[j], send = h3 ? x[j] : x[8 + j];
-        b[j] = keep + dpp_mov<0x140>(send);
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {      // partner: row_half_mirror (lane ^ 7 within 8)
-        const float keep = h2 ? b[4 + j] : b[j], send = h2 ? b[j] : b[4 + j];
-        c[j] = keep + dpp_mov<0x141>(send);
-    }
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {      // partner: lane ^ 2
-        const float keep = h1 ? c[2 + j] : c[j], send = h1 ? c[j] : c[2 + j];
-        d[j] = keep + dpp_mov<0x4E>(send);
-    }
-    const float keep = h0 ? d[1] : d[0], send = h0 ? d[0] : d[1];
-    float e = keep + dpp_mov<0xB1>(send);  // partner: lane ^ 1
-    e += __shfl_xor(e, 16, 64);
-    return e + __shfl_xor(e, 32, 64);
-}
-
-__device__ __forceinline__ int scatter16_index(int lane) {
-    return 8 * ((lane >> 3) & 1) + 4 * ((lane >> 2) & 1) + 2 * ((lane >> 1) & 1) + (lane & 1);
-}
 
 
 // Brick of the adjoint pass: 8x8x8 voxels, one per thread; LDS box with a
