@@ -94,6 +94,25 @@ __device__ __forceinline__ void gauss_full(const float *__restrict__ mean,
     }
 }
 
+// Cheap test that Gaussian i's voxel box is empty without building it: the
+// ellipsoid's half-extent on any axis is at most k max(s), and the box adds
+// one voxel on each side (one more of margin here).  False when unsure
+// (untruncated sets, NaN parameters), so callers then build the box.
+__device__ __forceinline__ bool far_from_grid(const float *__restrict__ mean,
+                                              const float *__restrict__ scale, int64_t i, float k,
+                                              const GridK &g) {
+    if (isinf(k)) return false;
+    const float smax = fmaxf(fmaxf(fabsf(scale[3 * i]), fabsf(scale[3 * i + 1])),
+                             fabsf(scale[3 * i + 2]));
+    const float ext = 1.001f * k * smax;
+    bool far = false;
+    for (int a = 0; a < 3; ++a) {
+        const float d = mean[3 * i + a] - g.c0[a];
+        far = far || d + ext < -3.0f * g.h[a] || d - ext > (float)(g.n[a] + 2) * g.h[a];
+    }
+    return far;
+}
+
 __device__ __forceinline__ float quad(const GaussK &p, float d0, float d1, float d2) {
     const float t0 = fmaf(p.a00, d0, fmaf(p.a01, d1, p.a02 * d2));
     const float t1 = fmaf(p.a01, d0, fmaf(p.a11, d1, p.a12 * d2));
@@ -115,6 +134,12 @@ __global__ __launch_bounds__(256) void k_vox_prep(pmf_gauss_t gs, GridK g, float
                                                   int32_t *__restrict__ nlarge) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= gs.m) return;
+    if (far_from_grid(gs.mean, gs.scale, i, k, g)) {
+        GaussK r = {};
+        r.lo0 = r.lo1 = r.lo2 = 1;            // empty box: no tile, no voxel
+        rec[i] = r;
+        return;
+    }
     GaussFull G;
     gauss_full(gs.mean, gs.scale, gs.quat, i, k, g, G);
     GaussK r;
@@ -417,6 +442,20 @@ VoxPlan vox_plan(int64_t m, int c, const GridK &g) {
     } else {
         T[0] = 8; T[1] = 8; T[2] = 8;
     }
+    // small grids (a TV sub-volume): halve the longest tile edge, down to 8,
+    // until there are at least 256 tiles to spread over the CUs
+    auto ntiles_of = [&](const int *t) {
+        int64_t n = 1;
+        for (int a = 0; a < 3; ++a) n *= (g.n[a] + t[a] - 1) / t[a];
+        return n;
+    };
+    while (ntiles_of(T) < 256) {
+        int a = 0;
+        for (int b = 1; b < 3; ++b)
+            if (T[b] > T[a]) a = b;
+        if (T[a] <= 8) break;
+        T[a] /= 2;
+    }
     p.ntiles = 1;
     for (int a = 0; a < 3; ++a) {
         p.T[a] = T[a];
@@ -523,6 +562,17 @@ __global__ __launch_bounds__(256) void k_vox_bwd(pmf_gauss_t gs, GridK g, float 
     if (gi >= gs.m) return;
     const int lane = threadIdx.x & 63;
     const int C = CT > 0 ? CT : gs.c;
+    if (far_from_grid(gs.mean, gs.scale, gi, k, g)) {     // wave-uniform: no voxel, zero gradients
+        if (lane == 63) {
+            for (int c = 0; c < C; ++c) gr.value[gi * C + c] = 0.0f;
+            for (int a = 0; a < 3; ++a) {
+                gr.mean[3 * gi + a] = 0.0f;
+                gr.scale[3 * gi + a] = 0.0f;
+            }
+            for (int c = 0; c < 4; ++c) gr.quat[4 * gi + c] = 0.0f;
+        }
+        return;
+    }
     GaussFull G;
     gauss_full(gs.mean, gs.scale, gs.quat, gi, k, g, G);
     GaussK p;
