@@ -254,6 +254,17 @@ int pmf_rasterize(const pmf_gauss_t *g, const pmf_cone_t *cone, const float *ang
 int pmf_rasterize_bwd(const pmf_gauss_t *g, const pmf_cone_t *cone, const float *angles, int V,
                       float trunc_k, const float *g_proj, const pmf_gauss_grad_t *grad, void *ws,
                       size_t ws_bytes, void *stream);
+/* pmf_rasterize_bwd without its own binning: ws must be the workspace that a
+ * pmf_rasterize call with the same g (unchanged), cone, angles, V and
+ * trunc_k filled, on the same stream, with nothing else written to it since
+ * (the splat records, tile lists and list positions are reused, as a
+ * training step's forward and adjoint share them).  Same results, errors and
+ * workspace size as pmf_rasterize_bwd; a workspace from anything else gives
+ * wrong gradients (unchecked). */
+int pmf_rasterize_bwd_binned(const pmf_gauss_t *g, const pmf_cone_t *cone, const float *angles,
+                             int V, float trunc_k, const float *g_proj,
+                             const pmf_gauss_grad_t *grad, void *ws, size_t ws_bytes,
+                             void *stream);
 
 /* ------------------------------------------------- Stage 2/3 loss terms
  * The loss terms that surround the motion path in Stages 2 and 3 (Sec.

@@ -384,9 +384,9 @@ int pmf_rasterize(const pmf_gauss_t *gs, const pmf_cone_t *cone, const float *an
                       "rasterize");
 }
 
-int pmf_rasterize_bwd(const pmf_gauss_t *gs, const pmf_cone_t *cone, const float *angles, int V,
-                      float trunc_k, const float *g_proj, const pmf_gauss_grad_t *grad, void *ws,
-                      size_t ws_bytes, void *stream) {
+static int rasterize_bwd(const pmf_gauss_t *gs, const pmf_cone_t *cone, const float *angles, int V,
+                         float trunc_k, const float *g_proj, const pmf_gauss_grad_t *grad,
+                         void *ws, size_t ws_bytes, void *stream, bool rebin) {
     PMF_CHECK(check_rast(gs, cone, angles, V, trunc_k, "rasterize_bwd"));
     if (!grad) return fail(PMF_EINVAL, "rasterize_bwd: null gradient struct");
     if (gs->m == 0) return ok();
@@ -394,8 +394,21 @@ int pmf_rasterize_bwd(const pmf_gauss_t *gs, const pmf_cone_t *cone, const float
         return fail(PMF_EINVAL, "rasterize_bwd: null array");
     PMF_CHECK(check_ws(ws, ws_bytes, rasterize_workspace(gs->m, *cone, V)));
     return hip_status(launch_rasterize_bwd(*gs, *cone, angles, V, trunc_k, g_proj, *grad, ws,
-                                           as_stream(stream)),
+                                           as_stream(stream), rebin),
                       "rasterize_bwd");
+}
+
+int pmf_rasterize_bwd(const pmf_gauss_t *gs, const pmf_cone_t *cone, const float *angles, int V,
+                      float trunc_k, const float *g_proj, const pmf_gauss_grad_t *grad, void *ws,
+                      size_t ws_bytes, void *stream) {
+    return rasterize_bwd(gs, cone, angles, V, trunc_k, g_proj, grad, ws, ws_bytes, stream, true);
+}
+
+int pmf_rasterize_bwd_binned(const pmf_gauss_t *gs, const pmf_cone_t *cone, const float *angles,
+                             int V, float trunc_k, const float *g_proj,
+                             const pmf_gauss_grad_t *grad, void *ws, size_t ws_bytes,
+                             void *stream) {
+    return rasterize_bwd(gs, cone, angles, V, trunc_k, g_proj, grad, ws, ws_bytes, stream, false);
 }
 
 // ------------------------------------------------------ Stage 2/3 loss terms

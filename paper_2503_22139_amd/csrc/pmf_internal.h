@@ -406,7 +406,7 @@ hipError_t launch_rasterize(const pmf_gauss_t &gs, const pmf_cone_t &c, const fl
                             int V, float k, float *proj, void *ws, hipStream_t s);
 hipError_t launch_rasterize_bwd(const pmf_gauss_t &gs, const pmf_cone_t &c, const float *angles,
                                 int V, float k, const float *g_proj, const pmf_gauss_grad_t &gg,
-                                void *ws, hipStream_t s);
+                                void *ws, hipStream_t s, bool rebin = true);
 size_t l1_dssim_workspace(int nu, int nv, int V);
 hipError_t launch_l1_dssim(const float *proj, const float *target, int nu, int nv, int V,
                            float lam, float *loss, float *g, void *ws, hipStream_t s);

@@ -637,12 +637,14 @@ hipError_t launch_rasterize(const pmf_gauss_t &gs, const pmf_cone_t &c, const fl
     return hipGetLastError();
 }
 
+// rebin = false: ws already holds the binning of a pmf_rasterize call on the
+// same inputs (splat records, tile lists, list positions), which is reused.
 hipError_t launch_rasterize_bwd(const pmf_gauss_t &gs, const pmf_cone_t &c, const float *angles,
                                 int V, float k, const float *g_proj, const pmf_gauss_grad_t &gg,
-                                void *ws, hipStream_t s) {
+                                void *ws, hipStream_t s, bool rebin) {
     const RastGeo G = rast_geo(c, k);
     const RastWs w = rast_ws(ws, gs.m, G, V);
-    hipError_t e = rast_bin(gs, G, angles, V, w, s);
+    hipError_t e = rebin ? rast_bin(gs, G, angles, V, w, s) : hipSuccess;
     if (e != hipSuccess) return e;
     const int64_t T = (int64_t)G.tiles_u * G.tiles_v * V;
     const int64_t mv = gs.m * V;

@@ -203,10 +203,16 @@ class Stage1Model:
         """target [1][nv][nu], angle [1] (device); returns ({"proj", "tv"}
         device scalars, {"mean", "scale", "quat", "value"} gradients)."""
         g = self.ref
-        proj = ops.pmf_rasterize(g.mean, g.scale, g.quat, g.value, self.cone, angle, self.k)
+        V = angle.numel()
+        if getattr(self, "_rws_key", None) != (g.mean.shape[0], V):
+            self._rws = ops.rasterize_workspace(g.mean.shape[0], self.cone, V, self.device)
+            self._rws_key = (g.mean.shape[0], V)
+        # the adjoint reuses the forward's binning in the step's own workspace
+        proj = ops.pmf_rasterize(g.mean, g.scale, g.quat, g.value, self.cone, angle, self.k,
+                                 ws=self._rws)
         l_proj, g_proj = ops.pmf_l1_dssim_loss(proj, target, lam_ssim)
         grads = ops.pmf_rasterize_bwd(g.mean, g.scale, g.quat, g.value, self.cone, angle, self.k,
-                                      g_proj)
+                                      g_proj, ws=self._rws, binned=True)
         sg = sub_grid(self.grid, corner, D)
         sub = ops.pmf_voxelize(g.mean, g.scale, g.quat, g.value, sg, self.k)
         g_sub = torch.zeros_like(sub)

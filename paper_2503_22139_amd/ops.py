@@ -99,6 +99,8 @@ _SIGS = {
                        _SZ, _P], C.c_int),
     "pmf_rasterize_bwd": ([C.POINTER(PmfGauss), C.POINTER(PmfCone), _P, C.c_int, C.c_float, _P,
                            C.POINTER(PmfGaussGrad), _P, _SZ, _P], C.c_int),
+    "pmf_rasterize_bwd_binned": ([C.POINTER(PmfGauss), C.POINTER(PmfCone), _P, C.c_int, C.c_float, _P,
+                           C.POINTER(PmfGaussGrad), _P, _SZ, _P], C.c_int),
     "pmf_l1_dssim_loss_workspace": ([C.c_int, C.c_int, C.c_int], _SZ),
     "pmf_l1_dssim_loss": ([_P, _P, C.c_int, C.c_int, C.c_int, C.c_float, _P, _P, _P, _SZ, _P],
                           C.c_int),
@@ -370,31 +372,48 @@ def pmf_grid_init(vol, grid: Grid, m, scale: float):
     return mean, sc, quat, val
 
 
-def pmf_rasterize(mean, scale, quat, value, cone: Cone, angles, trunc_k: float = 3.0, out=None):
-    """X-ray Gaussian splatting (Eq. 9) of V views: [V][nv][nu]."""
+def rasterize_workspace(m: int, cone: Cone, V: int, device) -> torch.Tensor:
+    """A workspace of its own for a pmf_rasterize / pmf_rasterize_bwd(binned=True) pair."""
+    c = make_cone(cone)
+    return torch.empty(max(int(lib().pmf_rasterize_workspace(m, C.byref(c), V)), 256),
+                       dtype=torch.uint8, device=device)
+
+
+def pmf_rasterize(mean, scale, quat, value, cone: Cone, angles, trunc_k: float = 3.0, out=None,
+                  ws=None):
+    """X-ray Gaussian splatting (Eq. 9) of V views: [V][nv][nu].  ws: an own
+    workspace (rasterize_workspace) that a following
+    pmf_rasterize_bwd(..., ws=ws, binned=True) reuses."""
     V = angles.numel()
     if out is None:
         out = torch.empty((V, cone.nv, cone.nu), device=mean.device, dtype=torch.float32)
     c = make_cone(cone)
     gs = _gauss(mean, scale, quat, value)
-    ws = workspace(lib().pmf_rasterize_workspace(mean.shape[0], C.byref(c), V), mean.device)
+    if ws is None:
+        ws = workspace(lib().pmf_rasterize_workspace(mean.shape[0], C.byref(c), V), mean.device)
     _check(lib().pmf_rasterize(C.byref(gs), C.byref(c), _ptr(angles), V, float(trunc_k), _ptr(out),
                                C.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
     return out
 
 
-def pmf_rasterize_bwd(mean, scale, quat, value, cone: Cone, angles, trunc_k: float, g_proj):
-    """Gradients of sum(g_proj * rasterize) w.r.t. (mean, scale, quat, value)."""
+def pmf_rasterize_bwd(mean, scale, quat, value, cone: Cone, angles, trunc_k: float, g_proj,
+                      ws=None, binned: bool = False):
+    """Gradients of sum(g_proj * rasterize) w.r.t. (mean, scale, quat, value).
+    binned=True reuses the binning that pmf_rasterize left in ws (same
+    inputs, nothing written to ws since)."""
     V = angles.numel()
     gm, gsc, gq, gv = (torch.empty_like(mean), torch.empty_like(scale), torch.empty_like(quat),
                        torch.empty_like(value))
     c = make_cone(cone)
     gs = _gauss(mean, scale, quat, value)
     gr = PmfGaussGrad(_ptr(gm), _ptr(gsc), _ptr(gq), _ptr(gv))
-    ws = workspace(lib().pmf_rasterize_workspace(mean.shape[0], C.byref(c), V), mean.device)
-    _check(lib().pmf_rasterize_bwd(C.byref(gs), C.byref(c), _ptr(angles), V, float(trunc_k),
-                                   _ptr(g_proj.contiguous()), C.byref(gr),
-                                   C.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    if binned and ws is None:
+        raise ValueError("binned=True needs the workspace of the forward call")
+    if ws is None:
+        ws = workspace(lib().pmf_rasterize_workspace(mean.shape[0], C.byref(c), V), mean.device)
+    fn = lib().pmf_rasterize_bwd_binned if binned else lib().pmf_rasterize_bwd
+    _check(fn(C.byref(gs), C.byref(c), _ptr(angles), V, float(trunc_k), _ptr(g_proj.contiguous()),
+              C.byref(gr), C.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
     return gm, gsc, gq, gv
 
 

@@ -171,3 +171,19 @@ def test_gradients_repeat_bit_for_bit():
     _, b = run(gs, cone, ang, 3.0, gp)
     for x, y in zip(a, [N(t) for t in b]):
         assert np.array_equal(x, y)
+
+
+def test_binned_adjoint_reuses_the_forward_binning():
+    """pmf_rasterize_bwd_binned on the forward's workspace gives the same bits
+    as the adjoint that bins again (its sums do not depend on list order)."""
+    gs = gaussian_set(11, 2000, 30.0, 0.3, 8.0)
+    cone = Cone(1000.0, 1500.0, 112, 80, 0.9, 0.9, off_v=0.2)
+    ang = T(np.array([0.4, 3.3]))
+    gp = T(np.random.default_rng(12).normal(size=(2, cone.nv, cone.nu)))
+    t = [T(a) for a in (gs.mean, gs.scale, gs.quat, gs.value)]
+    ws = ops.rasterize_workspace(gs.mean.shape[0], cone, 2, "cuda")
+    ops.pmf_rasterize(*t, cone, ang, 3.0, ws=ws)
+    a = ops.pmf_rasterize_bwd(*t, cone, ang, 3.0, gp, ws=ws, binned=True)
+    b = ops.pmf_rasterize_bwd(*t, cone, ang, 3.0, gp)
+    for x, y in zip(a, b):
+        assert np.array_equal(N(x), N(y))
