@@ -252,6 +252,9 @@ def test_rasterize_rejects_bad_arguments(lib):
     assert lib.pmf_rasterize_bwd(C.byref(gs1), C.byref(cone), p, 2, 3.0, p, None, ws, big, None) == ops.PMF_EINVAL
     assert lib.pmf_rasterize_bwd(C.byref(gs1), C.byref(cone), p, 2, 3.0, None, C.byref(gg), ws, big, None) == ops.PMF_EINVAL
     assert lib.pmf_rasterize_bwd(C.byref(gs1), C.byref(cone), p, 2, 3.0, p, C.byref(gg), ws, need - 1, None) == ops.PMF_EWORKSPACE
+    assert lib.pmf_rasterize_bwd_binned(C.byref(gs3), C.byref(cone), p, 2, 3.0, p, C.byref(gg), ws, big, None) == ops.PMF_EINVAL
+    assert lib.pmf_rasterize_bwd_binned(C.byref(gs1), C.byref(cone), p, 2, 3.0, None, C.byref(gg), ws, big, None) == ops.PMF_EINVAL
+    assert lib.pmf_rasterize_bwd_binned(C.byref(gs1), C.byref(cone), p, 2, 3.0, p, C.byref(gg), ws, need - 1, None) == ops.PMF_EWORKSPACE
     huge = ops.PmfGauss(p, p, p, p, 1 << 26, 1)
     assert lib.pmf_rasterize(C.byref(huge), C.byref(cone), p, 4, 3.0, p, ws, big, None) == ops.PMF_EUNSUPPORTED
 
