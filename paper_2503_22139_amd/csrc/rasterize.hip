@@ -305,7 +305,8 @@ __device__ __forceinline__ void splat_grad(const SplatP &P, float x, float y, fl
 // Gaussian into its LDS slot (zeros when no pixel of the wave is inside any
 // of the five ellipses reduced together); the four slots are added in a
 // fixed order and written to part[list entry] -- no atomics.
-constexpr int RB_CHUNK = 128;     // Gaussians per LDS chunk in the adjoint
+constexpr int RB_CHUNK = 64;      // Gaussians per LDS chunk in the adjoint
+constexpr int RB_SPLIT = 8;       // workgroups sharing one tile's list in the adjoint
 
 __global__ __launch_bounds__(RS_THREADS) void k_splat_bwd(const SplatP *__restrict__ sp, RastGeo G,
                                                          const int *__restrict__ offsets,
@@ -325,7 +326,9 @@ __global__ __launch_bounds__(RS_THREADS) void k_splat_bwd(const SplatP *__restri
     const float k2 = G.k * G.k;
     const int lane = threadIdx.x & 63;
     const int b = offsets[tix], e = offsets[tix + 1];
-    for (int c0 = b; c0 < e; c0 += RB_CHUNK) {
+    // the tile's list is dealt over gridDim.y workgroups chunk by chunk (each
+    // entry has its own partial, so they need no reduction)
+    for (int c0 = b + (int)blockIdx.y * RB_CHUNK; c0 < e; c0 += (int)gridDim.y * RB_CHUNK) {
         const int n = min(RB_CHUNK, e - c0);
         if ((int)threadIdx.x < n) sh[threadIdx.x] = sp[list[c0 + threadIdx.x]];
         __syncthreads();
@@ -650,7 +653,8 @@ hipError_t launch_rasterize_bwd(const pmf_gauss_t &gs, const pmf_cone_t &c, cons
     const int64_t mv = gs.m * V;
     {
         ProfScope prof_("rasterize_bwd", s);
-        k_splat_bwd<<<(unsigned)T, RS_THREADS, 0, s>>>(w.sp, G, w.offsets, w.list, g_proj, w.part);
+        k_splat_bwd<<<dim3((unsigned)T, RB_SPLIT), RS_THREADS, 0, s>>>(w.sp, G, w.offsets, w.list,
+                                                                      g_proj, w.part);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (mv > 0) {
             k_splat_gather<<<(unsigned)((mv + 255) / 256), 256, 0, s>>>(w.sp, mv, w.gslot, w.part,
