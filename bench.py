@@ -225,6 +225,9 @@ def extras(steps: int):
         i = next(it1)
         return s1.step(tgt1, angs[i], cs[i])
     ms1 = _timed(stage1, steps)
+    gs1 = GraphStep(s1, tgt1, step=lambda t: s1.step(t, angs[0], cs[0]))
+    ms1_g = _timed(gs1.step, steps)
+    del gs1
     _drain_profile()
     ops.pmf_profile(True)
     s1.step(tgt1, angs[0], cs[0])
@@ -236,10 +239,13 @@ def extras(steps: int):
         tot, cnt = ops.pmf_profile_read(k)
         k1[k] = tot
     out["stage1_step"] = {
-        "ms": ms1, "iterations_per_s": 1e3 / ms1, "gaussians": w2.ref.m, "kernels_ms": k1,
+        "ms": ms1, "iterations_per_s": 1e3 / ms1, "graph_ms": ms1_g, "gaussians": w2.ref.m,
+        "kernels_ms": k1,
         "what": "Stage 1 iteration: rasterizer (Eq. 9) fwd+bwd at one random view, L1 + 0.25 "
-                "D-SSIM, 0.05 TV of a random 32^3 sub-volume voxelized from the Gaussians; eager"}
-    print(f"[bench] stage1_step {ms1:.2f} ms (kernels {k1})", file=sys.stderr, flush=True)
+                "D-SSIM, 0.05 TV of a random 32^3 sub-volume voxelized from the Gaussians; eager "
+                "(graph_ms: replayed from a HIP graph with one view and block)"}
+    print(f"[bench] stage1_step {ms1:.2f} ms (graph, one view and block: {ms1_g:.2f}; kernels {k1})",
+          file=sys.stderr, flush=True)
     del s1, tgt1
     torch.cuda.empty_cache()
     # FDK initialisation (Sec. 2.3.2): the full 660-view scan of the 512 x 384
