@@ -18,6 +18,8 @@
 //     summed in block order.
 #include <math.h>
 
+#include <algorithm>
+
 #include "pmf_internal.h"
 
 namespace pmf {
@@ -154,7 +156,7 @@ struct GOut {
 // displacements that leave the halo fall back to global atomics.  dL/dw of
 // each view is reduced over a wave, written to that wave's LDS slot, and the
 // slots are summed over the waves in a fixed order into the brick's partials
-// (reduced over bricks by k_reduce_coeff_blocks), so it is deterministic.
+// (reduced over bricks by k_reduce_coeff_parts / _final), so it is deterministic.
 struct WCK {
     const float *ref;       // y-paired when paired (see k_pair_volume)
     int paired;
@@ -405,19 +407,32 @@ __global__ __launch_bounds__(256) void k_gather_boxes(const float *__restrict__ 
     g_ref[j] += s;
 }
 
-// g_coeff[v0 + v][...] = sum over bricks of the per-brick partials: one
-// workgroup per output entry, fixed-order tree (deterministic).
-__global__ __launch_bounds__(256) void k_reduce_coeff_blocks(const float *__restrict__ partial,
-                                                             int nblk, int V, int NC,
-                                                             float *__restrict__ g_coeff) {
-    const int t = blockIdx.x;
+// g_coeff[v0 + v][...] = sum over bricks of the per-brick partials
+// ([brick][v][c], vnc = views x channels per brick), in two fixed-order
+// stages: P contiguous brick ranges summed for every output with coalesced
+// reads, then the P range sums of each output in a fixed tree.
+__global__ __launch_bounds__(256) void k_reduce_coeff_parts(const float *__restrict__ partial,
+                                                            int nblk, int vnc, int P,
+                                                            float *__restrict__ part2) {
+    const int p = blockIdx.y, o = blockIdx.x * 256 + threadIdx.x;
+    if (o >= vnc) return;
+    const int b0 = (int)((int64_t)nblk * p / P), b1 = (int)((int64_t)nblk * (p + 1) / P);
     float s = 0.0f;
-    for (int i = threadIdx.x; i < nblk; i += blockDim.x) s += partial[(int64_t)i * V * NC + t];
+    for (int i = b0; i < b1; ++i) s += partial[(int64_t)i * vnc + o];
+    part2[(int64_t)p * vnc + o] = s;
+}
+
+// one workgroup per output: its P (<= 256) range sums, one per thread, in a
+// fixed tree
+__global__ __launch_bounds__(256) void k_reduce_coeff_final(const float *__restrict__ part2, int P,
+                                                            int vnc, float *__restrict__ g_coeff) {
     __shared__ float red[4];
+    const int o = blockIdx.x;
+    float s = (int)threadIdx.x < P ? part2[(int64_t)threadIdx.x * vnc + o] : 0.0f;
     s = wave_sum_lane63(s);
     if ((threadIdx.x & 63) == 63) red[threadIdx.x >> 6] = s;
     __syncthreads();
-    if (threadIdx.x == 0) g_coeff[t] = (red[0] + red[1]) + (red[2] + red[3]);
+    if (threadIdx.x == 0) g_coeff[o] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // The warped volumes go to the workspace in the y-paired layout when the
@@ -683,9 +698,17 @@ hipError_t launch_warp_project_bwd_jobs(const WPBJob *jobs, int n, hipStream_t s
             }
             if ((e = hipGetLastError()) != hipSuccess) return e;
             {
+                // the staged boxes are consumed: their buffer holds the range sums
                 ProfScope prof_("coeff_reduce", s);
-                k_reduce_coeff_blocks<<<(unsigned)(vcs[q] * NC), 256, 0, s>>>(
-                    b.partial, b.lay.nbrick, vcs[q], NC, j.g_coeff + (int64_t)v0 * NC);
+                const int vnc = vcs[q] * NC, nbk = b.lay.nbrick;
+                const int64_t fit = (int64_t)nbk * HB3 / vnc;
+                const int P = (int)std::max<int64_t>(1, std::min<int64_t>({256, nbk, fit}));
+                const unsigned gx = (unsigned)((vnc + 255) / 256);
+                k_reduce_coeff_parts<<<dim3(gx, (unsigned)P), 256, 0, s>>>(b.partial, nbk, vnc, P,
+                                                                          b.stage);
+                if ((e = hipGetLastError()) != hipSuccess) return e;
+                k_reduce_coeff_final<<<(unsigned)vnc, 256, 0, s>>>(b.stage, P, vnc,
+                                                                   j.g_coeff + (int64_t)v0 * NC);
             }
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
