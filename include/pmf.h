@@ -206,8 +206,8 @@ int pmf_l2_loss(const float *proj, const float *target, int64_t npix, int V, flo
  * (the volume must lie inside the source circle); PMF_EUNSUPPORTED for rows
  * longer than 4096 pixels, more than 65535 rows or (nu + 2)(nv + 2) >=
  * 2^27; PMF_EWORKSPACE if the workspace from pmf_fdk_workspace() is missing
- * or short.  The workspace holds the filtered views as zero-bordered planes
- * of 2 x 2 bilinear taps, 16 (nu + 2)(nv + 2) bytes per view. */
+ * or short.  The workspace holds mainly the filtered views, as zero-bordered
+ * planes of 2 x 2 bilinear taps: 16 (nu + 2)(nv + 2) bytes per view. */
 size_t pmf_fdk_workspace(const pmf_cone_t *cone, int V);
 int pmf_fdk(const float *proj, const pmf_cone_t *cone, const float *angles, int V,
             const pmf_grid_t *grid, float *vol, void *ws, size_t ws_bytes, void *stream);
