@@ -18,9 +18,11 @@
 // to a per-view list handled one Gaussian per workgroup), then one workgroup
 // per tile: Gaussians staged in LDS, one pixel per thread.  Adjoint: the same
 // binning; per tile each wave reduces its pixels' contributions to the six
-// 2-D parameters (amplitude, centre, conic) of a Gaussian and adds them with
-// one atomic each; per (view, Gaussian) the chain rule back to (p, s, q, rho)
-// in double, summed over views in order.
+// 2-D parameters (amplitude, centre, conic) of a Gaussian, and the tile
+// writes the sum of its waves (fixed order) to a partial per list entry; a
+// gather pass then sums each Gaussian's partials in tile order (no atomics),
+// and per (view, Gaussian) the chain rule goes back to (p, s, q, rho) in
+// double, summed over views in order.
 #include <math.h>
 
 #include "pmf_internal.h"

@@ -110,3 +110,79 @@ def test_grid_init_scale_preserves_the_mean_density():
     f = oracle.voxelize(GaussSet(mean, sc, quat, val), grid, float("inf")).reshape(grid.n)
     inner = f[12:28, 12:28, 12:28]
     assert abs(inner.mean() - rho) < 0.01 * rho, inner.mean()
+
+
+# ------------------------------------------------ the two FDK weights, wide fan
+
+WIDE = dict(sad=80.0, sdd=120.0)
+
+
+def test_backprojection_weight_closed_form():
+    """With q = 1 on every pixel (a detector large enough that every point
+    projects inside) the back-projection is (1/2) sum_views dtheta (SAD/U)^2
+    = pi * mean over views of (SAD/U)^2, U the point's distance from the
+    source along the central ray: computed here from the source position
+    alone.  Short SAD, so the weight ranges over a factor of ~5."""
+    cone = Cone(WIDE["sad"], WIDE["sdd"], 801, 61, 1.0, 1.0)
+    V = 37
+    ang = 2 * np.pi * np.arange(V) / V + 0.1
+    pts = np.array([[0.0, 0.0, 0.0], [30.0, -12.0, 4.0], [-25.0, 20.0, -6.0], [5.0, 38.0, 0.0]])
+    f = fdk.backproject(np.ones((V, cone.nv, cone.nu)), cone, ang, None, points=pts)
+    want = np.zeros(len(pts))
+    for th in ang:
+        src = cone.sad * np.array([math.cos(th), math.sin(th), 0.0])
+        axis = -src / np.linalg.norm(src)               # central ray direction
+        U = (pts - src) @ axis
+        want += (cone.sad / U) ** 2
+    want *= math.pi / V
+    assert np.allclose(f, want, rtol=1e-12, atol=0)
+    assert want.max() / want.min() > 1.3
+
+
+def test_filter_cosine_weight_impulse():
+    """An impulse at a far off-axis pixel is filtered into the Ram-Lak
+    kernel along its row, times tau and the cosine of the pixel's ray with
+    the central ray (SDD over the source-pixel distance, from the pixel's
+    position in space); here that cosine is ~0.74."""
+    cone = Cone(WIDE["sad"], WIDE["sdd"], 41, 9, 6.0, 6.0)
+    iu, iv = 38, 8
+    p = np.zeros((1, cone.nv, cone.nu))
+    p[0, iv, iu] = 1.0
+    q = fdk.filter_rows(p, cone)
+    src = np.array([cone.sad, 0.0, 0.0])
+    pix = np.array([-(cone.sdd - cone.sad), (iu - 0.5 * (cone.nu - 1)) * cone.du,
+                    (iv - 0.5 * (cone.nv - 1)) * cone.dv])
+    cos_ray = cone.sdd / np.linalg.norm(pix - src)
+    tau = cone.du * cone.sad / cone.sdd
+    h = fdk.ramlak(cone.nu, tau)
+    want = tau * cos_ray * h[np.arange(cone.nu) - iu + cone.nu - 1]
+    assert np.allclose(q[0, iv], want, rtol=1e-13, atol=0)
+    assert np.all(q[0, :iv] == 0) and cos_ray < 0.75
+
+
+def test_wide_fan_ball_density_in_mid_plane():
+    """FDK is exact in the mid-plane of a full circular scan (there it is
+    fan-beam filtered back-projection) as long as no view truncates the
+    object.  A ball 40 mm off the axis with a source only 80 mm from it: the
+    ball's rays make fan angles up to ~32 degrees (cosine weights down to
+    ~0.85) and (SAD/U)^2 averages ~1.5 at its centre, so dropping or
+    misplacing either weight moves the density by far more than 5%.  The
+    detector (+-135 mm at SDD, a 59 mm field of view) holds the ball (50 mm
+    from the axis at most) in every view.  The mid-plane density inside the
+    ball is pinned to 0.5%."""
+    cone = Cone(WIDE["sad"], WIDE["sdd"], 675, 3, 0.4, 0.4)
+    V = 360
+    ang = 2 * np.pi * np.arange(V) / V
+    c, r, rho = np.array([40.0, 0.0, 0.0]), 10.0, 0.02
+    p = fdk.ball_projections(c, r, rho, cone, ang)
+    rng = np.random.default_rng(5)
+    phi = rng.uniform(0, 2 * np.pi, 40)
+    rad = 8.0 * np.sqrt(rng.uniform(0, 1, 40))
+    pts = np.stack([c[0] + rad * np.cos(phi), c[1] + rad * np.sin(phi), np.zeros(40)], 1)
+    f = fdk.fdk(p, cone, ang, None, points=pts)
+    assert np.all(np.abs(f - rho) < 0.005 * rho), (f.min() / rho, f.max() / rho)
+    # the weights at the ball's centre are far from one
+    U = cone.sad - (c[0] * np.cos(ang) + c[1] * np.sin(ang))
+    assert np.mean((cone.sad / U) ** 2) > 1.3
+    lat = -c[0] * np.sin(ang) + c[1] * np.cos(ang)
+    assert np.min(np.cos(np.arctan(np.abs(lat) / U))) < 0.9

@@ -450,6 +450,42 @@ def test_project_linear_and_shared_stride():
     assert np.array_equal(stacked, pa)
 
 
+def test_project_rays_equals_project_at_every_pixel():
+    """The selected-ray projector (used for sampled checks of large cases)
+    gives every pixel of the full projector, bit for bit: a ragged,
+    off-centre anisotropic grid with pixel offsets, a shared volume and one
+    volume per view, the rays listed in a shuffled order."""
+    rng = np.random.default_rng(28)
+    grid = Grid((11, 9, 7), (2.0, 1.5, 2.5), (3.0, -2.0, 1.0))
+    cone = Cone(1000.0, 1500.0, 13, 8, 3.0, 2.5, off_u=0.3, off_v=-0.6)
+    ang = [0.3, 1.9, 4.4]
+    vols = rng.normal(size=(3,) + grid.n)
+    for vol, shared in ((vols[0], True), (vols, False)):
+        full = oracle.project(vol, grid, cone, ang, shared=shared)
+        v, iv, iu = np.meshgrid(np.arange(3), np.arange(cone.nv), np.arange(cone.nu), indexing="ij")
+        rays = np.stack([v.ravel(), iu.ravel(), iv.ravel()], 1)
+        order = rng.permutation(rays.shape[0])
+        got = oracle.project_rays(vol, grid, cone, ang, rays[order], shared=shared)
+        want = full[rays[order, 0], rays[order, 2], rays[order, 1]]
+        assert np.array_equal(got, want)
+        assert np.abs(want).max() > 0
+
+
+def test_voxelize_points_equals_voxelize():
+    """The brute-force voxelizer at selected voxels (every Gaussian tested)
+    equals the box-walking voxelizer at those voxels: truncated and
+    untruncated, three signed channels, a ragged off-centre grid."""
+    rng = np.random.default_rng(29)
+    grid = Grid((13, 10, 9), (1.5, 2.0, 1.0), (-1.0, 2.0, 0.5))
+    gs = synth.gaussians(rng, 40, grid, c=3, value_sigma=1.0)
+    idx = rng.choice(grid.size, size=300, replace=False)
+    for k in (3.0, math.inf):
+        want = oracle.voxelize(gs, grid, k).reshape(3, -1)[:, idx].T
+        got = oracle.voxelize_points(gs, grid, k, idx)
+        assert np.max(np.abs(got - want)) <= 1e-14 * max(1.0, np.abs(want).max())
+        assert np.abs(want).max() > 0
+
+
 def test_l2_loss_and_gradient():
     rng = np.random.default_rng(28)
     p = rng.normal(size=(3, 4, 5))
