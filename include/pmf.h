@@ -15,7 +15,8 @@
  *  - Every float pointer is a DEVICE pointer to contiguous float32 data owned
  *    by the caller, unless the comment says "host".  The library never
  *    allocates, frees or retains memory: scratch space is a caller-provided
- *    device buffer whose size the matching *_workspace() query returns.
+ *    device buffer whose size the matching *_workspace() query returns (the
+ *    one exception, pmf_tv_loss_noalloc, uses a small static device array).
  *  - Every call enqueues work on `stream` (a hipStream_t; NULL = the legacy
  *    default stream) and returns without waiting.  Host-side argument checks
  *    run first; on failure nothing is enqueued.
@@ -314,6 +315,22 @@ int pmf_tv_loss(const float *vol, const pmf_grid_t *grid, const int32_t *corner,
  * the gradients of the bases from the motion path.  Errors: PMF_EINVAL for
  * L or C < 1, null pointers or bad grids, PMF_EUNSUPPORTED for L > 4;
  * PMF_EWORKSPACE as above (pmf_mbc_normality_loss_workspace()). */
+/* pmf_tv_loss for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments, checks, results (bit for bit) and accumulation into g_vol,
+ * without a workspace.  Its per-block partial sums live in a static device
+ * array of the library, one per GPU (32 KiB, held until the process ends),
+ * sized for D <= PMF_TV_NOALLOC_MAX_D: a larger D returns PMF_EUNSUPPORTED
+ * before anything is enqueued.  The call allocates nothing (no hipMalloc, no
+ * library allocation); the first call on a device looks up that device's
+ * copy of the array.  Every partial is written before it is read, so nothing
+ * carries over between calls, but all calls on one GPU share the array:
+ * calls that may overlap on one GPU (different streams, or threads without
+ * ordering) race and must be serialised by the caller. */
+#define PMF_TV_NOALLOC_MAX_D 128
+int pmf_tv_loss_noalloc(const float *vol, const pmf_grid_t *grid, const int32_t *corner, int D,
+                        float weight, float *loss, float *g_vol, void *stream);
+
 size_t pmf_mbc_normality_loss_workspace(int L, int C);
 int pmf_mbc_normality_loss(int L, int C, const float *const *bases, const pmf_grid_t *lvl,
                            float weight, float *loss, float *const *g_bases, void *ws,

@@ -453,6 +453,28 @@ int pmf_tv_loss(const float *vol, const pmf_grid_t *grid, const int32_t *corner,
                       "tv_loss");
 }
 
+int pmf_tv_loss_noalloc(const float *vol, const pmf_grid_t *grid, const int32_t *corner, int D,
+                        float weight, float *loss, float *g_vol, void *stream) {
+    PMF_CHECK(check_grid(grid, "grid"));
+    if (!corner) return fail(PMF_EINVAL, "tv_loss_noalloc: null corner");
+    if (D < 1) return fail(PMF_EINVAL, "tv_loss_noalloc: D must be >= 1");
+    if (D > PMF_TV_NOALLOC_MAX_D)
+        return fail(PMF_EUNSUPPORTED,
+                    "tv_loss_noalloc: D = %d exceeds the static scratch's maximum %d (use "
+                    "pmf_tv_loss with a workspace)",
+                    D, PMF_TV_NOALLOC_MAX_D);
+    for (int a = 0; a < 3; ++a)
+        if (corner[a] < 0 || (int64_t)corner[a] + D > grid->n[a])
+            return fail(PMF_EINVAL, "tv_loss_noalloc: block [%d, %d) outside axis %d of size %d",
+                        corner[a], corner[a] + D, a, grid->n[a]);
+    if (!std::isfinite(weight)) return fail(PMF_EINVAL, "tv_loss_noalloc: weight must be finite");
+    if (!vol || !loss) return fail(PMF_EINVAL, "tv_loss_noalloc: null pointer");
+    const int c[3] = {corner[0], corner[1], corner[2]};
+    return hip_status(launch_tv_noalloc(vol, make_grid(*grid), c, D, weight, loss, g_vol,
+                                        as_stream(stream)),
+                      "tv_loss_noalloc");
+}
+
 size_t pmf_mbc_normality_loss_workspace(int L, int C) {
     if (L < 1 || C < 1) return 0;
     return normality_workspace(L, C);

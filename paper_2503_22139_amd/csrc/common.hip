@@ -19,7 +19,7 @@ static std::mutex g_prof_mu;
 static std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> g_prof;
 
 ProfScope::ProfScope(const char *n, hipStream_t s) : name(n), stream(s), on(false) {
-    if (!g_prof_on.load(std::memory_order_relaxed)) return;
+    if (!n || !g_prof_on.load(std::memory_order_relaxed)) return;   // no name: never recorded
     if (hipEventCreate(&start) != hipSuccess) return;
     if (hipEventCreate(&stop) != hipSuccess) {
         (void)hipEventDestroy(start);

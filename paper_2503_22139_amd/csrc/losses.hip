@@ -13,6 +13,7 @@
 // fixed-order tree, so results are deterministic.
 #include <algorithm>
 #include <math.h>
+#include <mutex>
 
 #include "pmf_internal.h"
 
@@ -315,13 +316,15 @@ static int tv_blocks(int D) { return (int)(((int64_t)D * D * D + TV_THREADS - 1)
 
 size_t tv_workspace(int D) { return align256(sizeof(float) * (size_t)tv_blocks(D)); }
 
-hipError_t launch_tv(const float *vol, const GridK &gk, const int corner[3], int D, float weight,
-                     float *loss, float *g, void *ws, hipStream_t s) {
+// The two launches of the TV term; every partial is written by its block
+// before k_sum_scaled reads it, so the buffer needs no clearing.
+static hipError_t tv_launches(const float *vol, const GridK &gk, const int corner[3], int D,
+                              float weight, float *loss, float *g, float *partial, bool prof,
+                              hipStream_t s) {
     const int nb = tv_blocks(D);
     const float scale = weight / ((float)D * (float)D * (float)D);
-    float *partial = (float *)ws;
     {
-        ProfScope prof_("tv", s);
+        ProfScope prof_(prof ? "tv" : nullptr, s);
         k_tv<<<(unsigned)nb, TV_THREADS, 0, s>>>(vol, gk.n[1], gk.n[2], corner[0], corner[1],
                                                  corner[2], D, scale, g, partial);
     }
@@ -329,6 +332,52 @@ hipError_t launch_tv(const float *vol, const GridK &gk, const int corner[3], int
     if (e != hipSuccess) return e;
     k_sum_scaled<<<1, 64, 0, s>>>(partial, nb, scale, loss);
     return hipGetLastError();
+}
+
+hipError_t launch_tv(const float *vol, const GridK &gk, const int corner[3], int D, float weight,
+                     float *loss, float *g, void *ws, hipStream_t s) {
+    return tv_launches(vol, gk, corner, D, weight, loss, g, (float *)ws, true, s);
+}
+
+// Scratch of the allocation-free TV call: the per-block partial sums for
+// blocks up to TV_NOALLOC_MAX_D^3 voxels, one copy per device for the life of
+// the process.  Host code never passes `scratch` itself (on the host it names
+// a stand-in, not device memory): tv_scratch_ptr looks up each device's
+// address once and kernels receive that.
+static __device__ __align__(256) float scratch[(TV_NOALLOC_MAX_D * TV_NOALLOC_MAX_D *
+                                                    TV_NOALLOC_MAX_D + TV_THREADS - 1) /
+                                                   TV_THREADS];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static float *g_scratch_ptr[MAX_DEVICES];
+
+// Device address of `scratch` on the current device, resolved on the first
+// call made with that device current.
+static hipError_t tv_scratch_ptr(float **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = (float *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+hipError_t launch_tv_noalloc(const float *vol, const GridK &gk, const int corner[3], int D,
+                             float weight, float *loss, float *g, hipStream_t s) {
+    if (D < 1 || D > TV_NOALLOC_MAX_D) return hipErrorInvalidValue;
+    float *partial = nullptr;
+    hipError_t e = tv_scratch_ptr(&partial);
+    if (e != hipSuccess) return e;
+    return tv_launches(vol, gk, corner, D, weight, loss, g, partial, false, s);
 }
 
 // ------------------------------------------------------- MBC normality (Eq. 13)

@@ -417,6 +417,11 @@ hipError_t launch_l1_dssim(const float *proj, const float *target, int nu, int n
 size_t tv_workspace(int D);
 hipError_t launch_tv(const float *vol, const GridK &g, const int corner[3], int D, float weight,
                      float *loss, float *g_vol, void *ws, hipStream_t s);
+// pmf_tv_loss without a workspace: the partial sums live in a static device
+// array sized for D <= TV_NOALLOC_MAX_D (hipErrorInvalidValue beyond).
+constexpr int TV_NOALLOC_MAX_D = PMF_TV_NOALLOC_MAX_D;
+hipError_t launch_tv_noalloc(const float *vol, const GridK &g, const int corner[3], int D,
+                             float weight, float *loss, float *g_vol, hipStream_t s);
 size_t normality_workspace(int L, int C);
 hipError_t launch_normality(int L, int C, const float *const *bases, const GridK *lg,
                             float weight, float *loss, float *const *g, void *ws, hipStream_t s);

@@ -107,6 +107,8 @@ _SIGS = {
     "pmf_tv_loss_workspace": ([C.c_int], _SZ),
     "pmf_tv_loss": ([_P, C.POINTER(PmfGrid), C.POINTER(C.c_int32), C.c_int, C.c_float, _P, _P, _P,
                      _SZ, _P], C.c_int),
+    "pmf_tv_loss_noalloc": ([_P, C.POINTER(PmfGrid), C.POINTER(C.c_int32), C.c_int, C.c_float, _P,
+                             _P, _P], C.c_int),
     "pmf_mbc_normality_loss_workspace": ([C.c_int, C.c_int], _SZ),
     "pmf_mbc_normality_loss": ([C.c_int, C.c_int, _P, C.POINTER(PmfGrid), C.c_float, _P, _P, _P,
                                 _SZ, _P], C.c_int),
@@ -428,6 +430,21 @@ def pmf_l1_dssim_loss(proj, target, lambda_ssim: float = 0.25, want_grad: bool =
                                    _ptr(loss), _ptr(g), C.c_void_p(ws.data_ptr()), ws.numel(),
                                    _stream()))
     return loss, g
+
+
+def pmf_tv_loss_noalloc(vol, grid: Grid, corner, D: int, weight: float, g_vol=None, loss=None):
+    """pmf_tv_loss without a workspace (the library's static scratch; D <=
+    TV_NOALLOC_MAX_D).  loss: an optional preallocated device scalar."""
+    if loss is None:
+        loss = torch.empty((), device=vol.device, dtype=torch.float32)
+    g = make_grid(grid)
+    c = (C.c_int32 * 3)(*[int(x) for x in corner])
+    _check(lib().pmf_tv_loss_noalloc(_ptr(vol), C.byref(g), c, int(D), float(weight), _ptr(loss),
+                                     _ptr(g_vol), _stream()))
+    return loss
+
+
+TV_NOALLOC_MAX_D = 128
 
 
 def pmf_tv_loss(vol, grid: Grid, corner, D: int, weight: float, g_vol=None):

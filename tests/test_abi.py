@@ -36,6 +36,12 @@ def test_exports_every_declared_function(lib):
     assert set(names) == set(ops.exported_symbols())
 
 
+def test_noalloc_limit_matches_header():
+    src = open(os.path.join(ROOT, "include", "pmf.h")).read()
+    m = re.search(r"#define PMF_TV_NOALLOC_MAX_D (\d+)", src)
+    assert m and int(m.group(1)) == ops.TV_NOALLOC_MAX_D
+
+
 def test_version(lib):
     assert lib.pmf_version() == 100
 
@@ -216,6 +222,16 @@ def test_loss_terms_reject_bad_arguments(lib):
     assert lib.pmf_tv_loss(None, C.byref(g), c, 4, 0.05, p, p, ws, big, None) == ops.PMF_EINVAL
     assert lib.pmf_tv_loss(p, C.byref(g), c, 4, float("inf"), p, p, ws, big, None) == ops.PMF_EINVAL
     assert lib.pmf_tv_loss(p, C.byref(g), c, 4, 0.05, p, p, ws, 0, None) == ops.PMF_EWORKSPACE
+    # the allocation-free TV call: same checks, and blocks beyond its static scratch
+    assert lib.pmf_tv_loss_noalloc(p, C.byref(g), c, 9, 0.05, p, p, None) == ops.PMF_EINVAL
+    assert lib.pmf_tv_loss_noalloc(p, C.byref(g), c, 0, 0.05, p, p, None) == ops.PMF_EINVAL
+    assert lib.pmf_tv_loss_noalloc(p, C.byref(g), None, 4, 0.05, p, p, None) == ops.PMF_EINVAL
+    assert lib.pmf_tv_loss_noalloc(None, C.byref(g), c, 4, 0.05, p, p, None) == ops.PMF_EINVAL
+    assert lib.pmf_tv_loss_noalloc(p, C.byref(g), c, 4, float("nan"), p, p, None) == ops.PMF_EINVAL
+    gbig = grid(n=(200, 200, 200))
+    D = ops.TV_NOALLOC_MAX_D + 1
+    assert lib.pmf_tv_loss_noalloc(p, C.byref(gbig), c, D, 0.05, p, p, None) == ops.PMF_EUNSUPPORTED
+    assert "maximum" in err(lib)
     # normality: L, C, null pointers, L > 4
     lv = (ops.PmfGrid * 2)(grid(n=(4, 4, 4)), grid(n=(8, 8, 8)))
     bp = (C.c_void_p * 2)(256, 256)
