@@ -163,9 +163,16 @@ int pmf_warp(const float *ref, const pmf_grid_t *grid, const float *dvf, int V, 
  *   g_ref = sum_v S_v^T g_out[v]   (trilinear weights at x_j + dvf),  [N]
  *   g_dvf[v][a][j] = g_out[v][j] dS/dy_a(ref, x_j + dvf[v][:, j]),    [V][3][N]
  * dS/dy_a is the derivative of the trilinear interpolant inside the
- * voxel-centre hull and 0 on the half-voxel rim and outside. */
+ * voxel-centre hull and 0 on the half-voxel rim and outside; the cell of a
+ * point is decided by its displacement, so a point on a cell face takes the
+ * side its displacement puts it on (none: the cell that starts at its voxel).
+ * g_ref is summed in 64-bit fixed point (each term exact to 2^-40 of the
+ * largest |g_out|), so it repeats bit for bit.  Needs the workspace from
+ * pmf_warp_bwd_workspace() (8 bytes per voxel). */
+size_t pmf_warp_bwd_workspace(const pmf_grid_t *grid);
 int pmf_warp_bwd(const float *ref, const pmf_grid_t *grid, const float *dvf, int V,
-                 const float *g_out, float *g_ref, float *g_dvf, void *stream);
+                 const float *g_out, float *g_ref, float *g_dvf, void *ws, size_t ws_bytes,
+                 void *stream);
 
 /* --------------------------------------------------- projection (Eq. 6)
  * DRRs of V views: proj[v][iv][iu] = delta * sum_s S(vol_v, o + t_s d),
@@ -238,8 +245,9 @@ int pmf_grid_init(const float *vol, const pmf_grid_t *grid, const int m[3], floa
  * [V][nv][nu] (overwritten) is the sum of these at its centre, each cut to
  * its ellipse (x - mu)^T Sigma^-1 (x - mu) <= trunc_k^2 (INFINITY: uncut;
  * every Gaussian then covers the whole detector).  Gaussians not in front of
- * the source are skipped.  Pixel sums are float additions in an order that
- * depends on scheduling (results vary in the last bits between runs).
+ * the source are skipped.  Pixel sums are 32-bit fixed point with a per-tile
+ * scale (each term exact to 2^-31 of the sum of the amplitudes that reach the
+ * tile), so images repeat bit for bit.
  * pmf_rasterize_bwd overwrites grad (shapes of g) with the gradients of
  * sum(g_proj * proj), summed over the V views in order (the mask is not
  * differentiated); its sums run in a fixed order (the gradients repeat bit
@@ -341,6 +349,10 @@ int pmf_mbc_normality_loss(int L, int C, const float *const *bases, const pmf_gr
  * that run the steps one view at a time. */
 int pmf_accumulate(float *dst, const float *src, int64_t n, void *stream);
 
+/* dst[i] = value for i < n, by a fill kernel (never a memset node, so it may
+ * be recorded into a graph): buffers that gradients accumulate into. */
+int pmf_fill(float *dst, int64_t n, float value, void *stream);
+
 /* ---------------------------------------------------------- profiling
  * Per-kernel GPU time for measurement.  While enabled, every kernel launch
  * of the library is bracketed by two HIP events recorded on the stream it
@@ -391,6 +403,46 @@ int pmf_autotune_project(const float *vol, const pmf_grid_t *grid, const pmf_con
                          const float *angles, int V, float *proj, const float *g_proj,
                          float *g_vol, void *ws, size_t ws_bytes, int reps, float *ms,
                          void *stream);
+
+/* Autotuner with a persistent cache of the chosen shapes: as
+ * pmf_autotune_project, but first looks up cache_path (a text file of
+ * "key<TAB>tile<TAB>brick" lines, key = the device's architecture, name and
+ * compute-unit count, the grid, the cone geometry and V).  A hit sets both
+ * knobs without timing anything (*cached = 1; ms is not written); a miss
+ * times every candidate as pmf_autotune_project does and appends the choice
+ * (*cached = 0).  cache_path NULL: no cache.  cached may be NULL.  Errors as
+ * pmf_autotune_project, plus PMF_EINVAL if the cache cannot be written (the
+ * tuned choice is then still set).  The views' cost is independent, so one
+ * entry serves any draw of V views of the same scan geometry. */
+int pmf_autotune(const char *cache_path, const float *vol, const pmf_grid_t *grid,
+                 const pmf_cone_t *cone, const float *angles, int V, float *proj,
+                 const float *g_proj, float *g_vol, void *ws, size_t ws_bytes, int reps, float *ms,
+                 int *cached, void *stream);
+
+/* ------------------------------------------------------- graph capture
+ * A training step is a fixed sequence of launches over fixed buffers, so it
+ * can be recorded once and replayed (the batched, many-view form of Sec. 4's
+ * parallel DRRs, without a launch per kernel).  pmf_graph_capture records
+ * everything record(user, stream) enqueues on `stream` (a non-null stream;
+ * work forked to other streams must join it again before record returns)
+ * into a HIP graph and instantiates it.  record returns PMF_OK or an error,
+ * which pmf_graph_capture passes on (nothing is kept).  The recorded calls
+ * must not allocate device memory: every buffer, workspace included, must
+ * exist before capture and outlive the graph; a replay reads and writes the
+ * same device addresses, so new inputs are copied into those buffers between
+ * replays.  Profiling (pmf_profile) is off during the recording.  Library
+ * calls clear memory with fill kernels, never with memset nodes; a recording
+ * that holds a memset node is refused (PMF_EUNSUPPORTED).  pmf_graph_replay
+ * launches the graph on `stream` (stream-ordered, returns at once);
+ * pmf_graph_kernel_count gives the number of kernel nodes (-1 for NULL);
+ * pmf_graph_destroy frees it (NULL: nothing to do).  A graph may be replayed
+ * on one stream at a time. */
+typedef struct pmf_graph pmf_graph_t;
+typedef int (*pmf_record_fn)(void *user, void *stream);
+int pmf_graph_capture(void *stream, pmf_record_fn record, void *user, pmf_graph_t **graph);
+int pmf_graph_replay(const pmf_graph_t *graph, void *stream);
+int64_t pmf_graph_kernel_count(const pmf_graph_t *graph);
+int pmf_graph_destroy(pmf_graph_t *graph);
 
 /* ----------------------------------------- batched motion path (fused)
  * All V views of the motion path in one pass over the bases:

@@ -107,6 +107,22 @@ def voxelize_bwd(gs, grid, k: float, g_vol) -> Dict[str, np.ndarray]:
     return g
 
 
+def voxelize_band(gs, grid, k: float, band: float):
+    """Eq. 5 split by the mask margin (see oracle_voxelize_band): returns
+    (inner, edge, amb, absum), each [c][n0][n1][n2]; inner + edge is
+    voxelize(gs, grid, k)."""
+    mean, scale, quat, value = _d(gs.mean), _d(gs.scale), _d(gs.quat), _d(gs.value)
+    m, c = value.shape
+    n, h, ct = _grid(grid)
+    shape = (c,) + tuple(int(v) for v in grid.n)
+    out = [np.zeros(shape) for _ in range(4)]
+    rc = lib().oracle_voxelize_band(_p(mean), _p(scale), _p(quat), _p(value), C.c_long(m),
+                                    C.c_int(c), _p(n), _p(h), _p(ct), C.c_double(k),
+                                    C.c_double(band), *[_p(o) for o in out])
+    assert rc == 0
+    return tuple(out)
+
+
 def voxelize_points(gs, grid, k: float, flat_idx) -> np.ndarray:
     mean, scale, quat, value = _d(gs.mean), _d(gs.scale), _d(gs.quat), _d(gs.value)
     m, c = value.shape

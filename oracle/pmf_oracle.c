@@ -271,6 +271,63 @@ int oracle_voxelize(const double *mean, const double *scale, const double *quat,
     return 0;
 }
 
+/* Eq. 5 split by the margin of each pair's mask test, for checks of the
+ * binning where several results are correct: a pair whose m lies within
+ * `band` of k^2 may fall either side of the mask under float rounding.
+ *   inner[c][j] = sum over m <= k^2 - band of value e
+ *   edge[c][j]  = sum over k^2 - band < m <= k^2 of value e
+ *                 (inner + edge is Eq. 5 itself)
+ *   amb[c][j]   = sum over |m - k^2| <= band of |value| e
+ *   absum[c][j] = sum over m <= k^2 + band of |value| e
+ * Same loop and voxel order as oracle_voxelize. */
+int oracle_voxelize_band(const double *mean, const double *scale, const double *quat,
+                         const double *value, long m, int nc, const int *n, const double *h,
+                         const double *ctr, double k, double band, double *inner, double *edge,
+                         double *amb, double *absum) {
+    ogrid g = make_grid(n, h, ctr);
+    long N = gsize(&g);
+    ogauss *G = (ogauss *)malloc(sizeof(ogauss) * (size_t)(m > 0 ? m : 1));
+    if (!G) return -1;
+    /* the search box must hold the widened ellipsoid m <= k^2 + band */
+    const double kw = isinf(k) ? k : sqrt(k * k + band);
+    for (long i = 0; i < m; ++i) gauss_setup(mean + 3 * i, scale + 3 * i, quat + 4 * i, kw, &G[i]);
+    const size_t bytes = sizeof(double) * (size_t)N * (size_t)nc;
+    memset(inner, 0, bytes);
+    memset(edge, 0, bytes);
+    memset(amb, 0, bytes);
+    memset(absum, 0, bytes);
+    const double k2 = isinf(k) ? INFINITY : k * k;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long ix = 0; ix < g.n[0]; ++ix) {
+        for (long gi = 0; gi < m; ++gi) {
+            const ogauss *P = &G[gi];
+            long lo[3], hi[3];
+            for (int a = 0; a < 3; ++a) gauss_range(P, &g, a, &lo[a], &hi[a]);
+            if (ix < lo[0] || ix > hi[0]) continue;
+            for (long iy = lo[1]; iy <= hi[1]; ++iy)
+                for (long iz = lo[2]; iz <= hi[2]; ++iz) {
+                    double x[3], d[3];
+                    voxel_centre(&g, ix, iy, iz, x);
+                    for (int a = 0; a < 3; ++a) d[a] = x[a] - P->mu[a];
+                    const double mm = quad_form(P->A, d);
+                    if (!(mm <= k2 + band)) continue;
+                    const double e = exp(-0.5 * mm);
+                    const long j = (ix * g.n[1] + iy) * (long)g.n[2] + iz;
+                    for (int c = 0; c < nc; ++c) {
+                        const double v = value[gi * nc + c];
+                        const long q = (long)c * N + j;
+                        absum[q] += fabs(v) * e;
+                        if (mm <= k2 - band) inner[q] += v * e;
+                        else if (mm <= k2) edge[q] += v * e;
+                        if (fabs(mm - k2) <= band) amb[q] += fabs(v) * e;
+                    }
+                }
+        }
+    }
+    free(G);
+    return 0;
+}
+
 /* Gradient of a scalar loss L through Eq. 5, given g_vol = dL/dvol [c][N].
  * With the truncation mask held fixed, for Gaussian i and each in-mask voxel j
  * (e = exp(-m/2), G_j = sum_c value[i][c] g_vol[c][j], d_j = x_j - mu):

@@ -7,7 +7,10 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <string.h>
+
 #include <string>
+#include <vector>
 
 #include <cmath>
 
@@ -146,6 +149,53 @@ hipStream_t as_stream(void *s) { return (hipStream_t)s; }
         if (r_ != PMF_OK) return r_; \
     } while (0)
 
+// ------------------------------------------- autotuner with a shape cache
+namespace {
+// Cache key: the device (architecture, name, compute units) and every input
+// of the projection's cost (grid, geometry, views).
+std::string autotune_key(const pmf_grid_t *g, const pmf_cone_t *c, int V) {
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    std::string dname = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        dname = std::string(prop.gcnArchName) + "/" + prop.name + "/" +
+                std::to_string(prop.multiProcessorCount);
+    for (char &ch : dname)
+        if (ch == '\t' || ch == '\n' || ch == ' ') ch = '_';
+    char buf[512];
+    snprintf(buf, sizeof buf,
+             "%s n=%d,%d,%d h=%.9g,%.9g,%.9g cone=%d,%d,%.9g,%.9g,%.9g,%.9g,%.9g,%.9g,%.9g V=%d",
+             dname.c_str(), g->n[0], g->n[1], g->n[2], (double)g->h[0], (double)g->h[1],
+             (double)g->h[2], c->nu, c->nv, (double)c->du, (double)c->dv, (double)c->sad,
+             (double)c->sdd, (double)c->off_u, (double)c->off_v, (double)c->step, V);
+    return buf;
+}
+
+// The last entry for key in the cache file: "key\ttile\tbrick" lines.
+bool autotune_lookup(const char *path, const std::string &key, int &tile, int &brick) {
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    bool found = false;
+    char line[1024];
+    while (fgets(line, sizeof line, f)) {
+        char *t1 = strchr(line, '\t');
+        if (!t1) continue;
+        *t1 = '\0';
+        if (key != line) continue;
+        int a = -1, b = -1;
+        if (sscanf(t1 + 1, "%d\t%d", &a, &b) == 2 && a >= 0 &&
+            a < tune_candidates(KNOB_PROJECT_TILE) && b >= 0 &&
+            b < tune_candidates(KNOB_BACKPROJECT_BRICK)) {
+            tile = a;
+            brick = b;
+            found = true;
+        }
+    }
+    fclose(f);
+    return found;
+}
+}  // namespace
+
 extern "C" {
 
 int pmf_version(void) { return PMF_VERSION; }
@@ -240,13 +290,20 @@ int pmf_warp(const float *ref, const pmf_grid_t *grid, const float *dvf, int V, 
     return hip_status(launch_warp(ref, g, dvf, V, out, as_stream(stream)), "warp");
 }
 
+size_t pmf_warp_bwd_workspace(const pmf_grid_t *grid) {
+    if (!grid || grid->n[0] < 1 || grid->n[1] < 1 || grid->n[2] < 1) return 0;
+    return warp_bwd_workspace(make_grid(*grid));
+}
+
 int pmf_warp_bwd(const float *ref, const pmf_grid_t *grid, const float *dvf, int V,
-                 const float *g_out, float *g_ref, float *g_dvf, void *stream) {
+                 const float *g_out, float *g_ref, float *g_dvf, void *ws, size_t ws_bytes,
+                 void *stream) {
     PMF_CHECK(check_grid(grid, "grid"));
     if (V < 1) return fail(PMF_EINVAL, "warp_bwd: V must be >= 1");
     if (!ref || !dvf || !g_out || !g_ref || !g_dvf) return fail(PMF_EINVAL, "warp_bwd: null pointer");
     GridK g = make_grid(*grid);
-    return hip_status(launch_warp_bwd(ref, g, dvf, V, g_out, g_ref, g_dvf, as_stream(stream)),
+    PMF_CHECK(check_ws(ws, ws_bytes, warp_bwd_workspace(g)));
+    return hip_status(launch_warp_bwd(ref, g, dvf, V, g_out, g_ref, g_dvf, ws, as_stream(stream)),
                       "warp_bwd");
 }
 
@@ -508,6 +565,12 @@ int pmf_accumulate(float *dst, const float *src, int64_t n, void *stream) {
     return hip_status(launch_accumulate(dst, src, n, as_stream(stream)), "accumulate");
 }
 
+int pmf_fill(float *dst, int64_t n, float value, void *stream) {
+    if (n < 0) return fail(PMF_EINVAL, "fill: n < 0");
+    if (n > 0 && !dst) return fail(PMF_EINVAL, "fill: null pointer");
+    return hip_status(launch_fill(dst, n, value, as_stream(stream)), "fill");
+}
+
 // --------------------------------------------------------------- profiling
 int pmf_profile(int enable) { return profile_enable(enable); }
 
@@ -591,6 +654,117 @@ int pmf_autotune_project(const float *vol, const pmf_grid_t *grid, const pmf_con
         return hip_status(e, "autotune_project");
     }
     return ok();
+}
+
+// ------------------------------------------- autotuner with a shape cache
+
+int pmf_autotune(const char *cache_path, const float *vol, const pmf_grid_t *grid,
+                 const pmf_cone_t *cone, const float *angles, int V, float *proj,
+                 const float *g_proj, float *g_vol, void *ws, size_t ws_bytes, int reps, float *ms,
+                 int *cached, void *stream) {
+    PMF_CHECK(check_grid(grid, "grid"));
+    PMF_CHECK(check_cone(cone, grid));
+    if (V < 1) return fail(PMF_EINVAL, "autotune: V must be >= 1");
+    if (reps < 1) return fail(PMF_EINVAL, "autotune: reps must be >= 1");
+    if (!vol || !angles || !proj || !g_proj || !g_vol)
+        return fail(PMF_EINVAL, "autotune: null pointer");
+    PMF_CHECK(check_ws(ws, ws_bytes, project_bwd_workspace(*cone, V)));
+    if (cached) *cached = 0;
+    std::string key;
+    if (cache_path) {
+        key = autotune_key(grid, cone, V);
+        int tile = -1, brick = -1;
+        if (autotune_lookup(cache_path, key, tile, brick)) {
+            tune_set(KNOB_PROJECT_TILE, tile);
+            tune_set(KNOB_BACKPROJECT_BRICK, brick);
+            if (cached) *cached = 1;
+            return ok();
+        }
+    }
+    const int rc = pmf_autotune_project(vol, grid, cone, angles, V, proj, g_proj, g_vol, ws,
+                                        ws_bytes, reps, ms, stream);
+    if (rc != PMF_OK || !cache_path) return rc;
+    FILE *f = fopen(cache_path, "a");
+    if (!f) return fail(PMF_EINVAL, "autotune: cannot append to the cache %s", cache_path);
+    const int w = fprintf(f, "%s\t%d\t%d\n", key.c_str(), tune_get(KNOB_PROJECT_TILE),
+                          tune_get(KNOB_BACKPROJECT_BRICK));
+    if (fclose(f) != 0 || w < 0)
+        return fail(PMF_EINVAL, "autotune: cannot write the cache %s", cache_path);
+    return ok();
+}
+
+// ------------------------------------------------------------ graph capture
+struct pmf_graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    int64_t nodes, kernels;
+};
+
+int pmf_graph_capture(void *stream, pmf_record_fn record, void *user, pmf_graph_t **graph) {
+    if (!graph) return fail(PMF_EINVAL, "graph_capture: null output");
+    *graph = nullptr;
+    if (!stream)
+        return fail(PMF_EINVAL, "graph_capture: the legacy default stream cannot be captured");
+    if (!record) return fail(PMF_EINVAL, "graph_capture: null record function");
+    hipStream_t s = as_stream(stream);
+    // profiling events would become graph nodes: off while recording
+    const int was_prof = profile_enable(0);
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        profile_enable(was_prof);
+        return hip_status(e, "graph_capture: begin");
+    }
+    const int rc = record(user, stream);
+    const std::string rec_err = rc != PMF_OK ? g_err : std::string();
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(s, &g);
+    profile_enable(was_prof);
+    if (rc != PMF_OK || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        if (rc != PMF_OK) return fail(rc, "graph_capture: recording failed: %s", rec_err.c_str());
+        return hip_status(e, "graph_capture: end");
+    }
+    size_t n = 0;
+    e = hipGraphGetNodes(g, nullptr, &n);
+    std::vector<hipGraphNode_t> nodes(n);
+    if (e == hipSuccess && n) e = hipGraphGetNodes(g, nodes.data(), &n);
+    int64_t kernels = 0;
+    for (size_t i = 0; i < n && e == hipSuccess; ++i) {
+        hipGraphNodeType t;
+        e = hipGraphNodeGetType(nodes[i], &t);
+        if (e != hipSuccess) break;
+        if (t == hipGraphNodeTypeMemset) {
+            (void)hipGraphDestroy(g);
+            return fail(PMF_EUNSUPPORTED, "graph_capture: the recorded work holds a memset node");
+        }
+        if (t == hipGraphNodeTypeKernel) ++kernels;
+    }
+    hipGraphExec_t x = nullptr;
+    if (e == hipSuccess) e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_status(e, "graph_capture: instantiate");
+    }
+    *graph = new pmf_graph{g, x, (int64_t)n, kernels};
+    return ok();
+}
+
+int pmf_graph_replay(const pmf_graph_t *graph, void *stream) {
+    if (!graph) return fail(PMF_EINVAL, "graph_replay: null graph");
+    return hip_status(hipGraphLaunch(graph->exec, as_stream(stream)), "graph_replay");
+}
+
+int64_t pmf_graph_kernel_count(const pmf_graph_t *graph) {
+    return graph ? graph->kernels : -1;
+}
+
+int pmf_graph_destroy(pmf_graph_t *graph) {
+    if (!graph) return ok();
+    hipError_t e = hipGraphExecDestroy(graph->exec);
+    const hipError_t e2 = hipGraphDestroy(graph->graph);
+    if (e == hipSuccess) e = e2;
+    delete graph;
+    return hip_status(e, "graph_destroy");
 }
 
 // ------------------------------------------------------ fused motion path

@@ -175,6 +175,43 @@ __global__ void k_accumulate(float *__restrict__ dst, const float *__restrict__ 
     for (; i < n; i += stride) dst[i] += src[i];
 }
 
+// out = max |x| over n floats, as the bits of a non-negative float (which
+// order like unsigned integers); *out must hold 0 beforehand.
+__global__ __launch_bounds__(256) void k_absmax(const float *__restrict__ x, int64_t n,
+                                                uint32_t *__restrict__ out) {
+    float m = 0.0f;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        m = fmaxf(m, fabsf(x[i]));
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0 && m > 0.0f) atomicMax(out, __float_as_uint(m));
+}
+
+// out[0] = max of in[0..n) (float bits of non-negative floats), one block.
+__global__ __launch_bounds__(256) void k_max_u32(const uint32_t *__restrict__ in, int n,
+                                                 uint32_t *__restrict__ out) {
+    __shared__ uint32_t red[4];
+    uint32_t m = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) m = max(m, in[i]);
+    for (int o = 32; o > 0; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) out[0] = max(max(red[0], red[1]), max(red[2], red[3]));
+}
+
+// dst[i] = (float) fix[i] / fix_scale(*mx)  (+ dst[i] when add)
+__global__ __launch_bounds__(256) void k_fix_to_float(const long long *__restrict__ fix, int64_t n,
+                                                      const uint32_t *__restrict__ mx, int add,
+                                                      float *__restrict__ dst) {
+    const double sc = fix_scale(*mx);
+    const double inv = sc > 0.0 ? 1.0 / sc : 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float v = (float)((double)fix[i] * inv);
+        dst[i] = add ? dst[i] + v : v;
+    }
+}
+
 static unsigned fill_blocks(int64_t n) {
     int64_t b = (n + 255) / 256;
     if (b > 8192) b = 8192;
@@ -205,6 +242,31 @@ hipError_t launch_fill_pair_u32(uint32_t *p, int64_t n, uint32_t a, uint32_t b, 
     {
         ProfScope prof_("fill", s);
         k_fill_pair_u32<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, n, a, b);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_absmax(const float *x, int64_t n, uint32_t *out, hipStream_t s) {
+    hipError_t e = launch_fill_i32((int32_t *)out, 1, 0, s);
+    if (e != hipSuccess || n <= 0) return e;
+    {
+        ProfScope prof_("absmax", s);
+        k_absmax<<<fill_blocks(n) < 1024 ? fill_blocks(n) : 1024, 256, 0, s>>>(x, n, out);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_max_u32(const uint32_t *in, int n, uint32_t *out, hipStream_t s) {
+    k_max_u32<<<1, 256, 0, s>>>(in, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fix_to_float(const long long *fix, int64_t n, const uint32_t *mx, bool add,
+                               float *dst, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    {
+        ProfScope prof_("fix_to_float", s);
+        k_fix_to_float<<<fill_blocks(n), 256, 0, s>>>(fix, n, mx, add ? 1 : 0, dst);
     }
     return hipGetLastError();
 }

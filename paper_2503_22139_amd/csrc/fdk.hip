@@ -78,7 +78,9 @@ __global__ __launch_bounds__(64) void k_fdk_filter(const float *__restrict__ pro
         return;
     }
     double *const row = lds;                         // row[m + FDK_PAD], m in [-64, nu + 64)
-    float *const out = (float *)(lds + nu + 2 * FDK_PAD);   // out[n + 1] = q[n], out[0] = out[nu + 1] = 0
+    // out[n + 1] = q[n]; out[0] = out[nu + 1] = out[nu + 2] = 0 (the last
+    // quad column pairs the border tap nu + 1 with the one beyond it)
+    float *const out = (float *)(lds + nu + 2 * FDK_PAD);
     const int64_t base = ((int64_t)v * nv + i) * nu;
     const double b = ((double)i - 0.5 * (nv - 1) + c.off_v) * c.dv;
     const double sdd = c.sdd, sb = sdd * sdd + b * b;
@@ -93,6 +95,7 @@ __global__ __launch_bounds__(64) void k_fdk_filter(const float *__restrict__ pro
     if (lane == 0) {
         out[0] = 0.0f;
         out[nu + 1] = 0.0f;
+        out[nu + 2] = 0.0f;
     }
     __syncthreads();
     const double c0 = (double)c.sdd / (4.0 * (double)c.du * c.sad);
@@ -207,7 +210,7 @@ size_t fdk_workspace(const pmf_cone_t &c, int V) {
 }
 
 size_t fdk_filter_lds(const pmf_cone_t &c) {
-    return sizeof(double) * (size_t)(c.nu + 2 * FDK_PAD) + sizeof(float) * (size_t)(c.nu + 2);
+    return sizeof(double) * (size_t)(c.nu + 2 * FDK_PAD) + sizeof(float) * (size_t)(c.nu + 3);
 }
 
 hipError_t launch_fdk(const float *proj, const pmf_cone_t &c, const float *angles, int V,

@@ -8,9 +8,10 @@
 // Adjoint: the back-projection of every view's residual (brick owner, LDS),
 // then one pass over the voxels that, for every view, recomputes the DVF,
 // takes the warp adjoint and the Eq. 3 adjoint in registers:
-//   - g_ref: added into an LDS copy of the brick plus a halo, flushed once
-//     for all views (global atomics only for the halo and for the rare
-//     displacement that leaves the halo);
+//   - g_ref: added into an LDS copy of the brick plus a halo in fixed point,
+//     staged per brick and gathered in a fixed order; the rare displacement
+//     that leaves the halo adds into a 64-bit fixed-point copy of g_ref with
+//     integer atomics, so the sums do not depend on their order;
 //   - dL/dE: sum over views of coeff * g_dvf, per voxel in registers; stored
 //     directly for a level on the output grid, otherwise handed to the
 //     separable upsampling transpose;
@@ -42,14 +43,16 @@ struct CWTab {
 };
 
 // Trilinear read of a y-paired volume (element (i, j, k) holds V[i][j][k] and
-// V[i][j+1][k]): two 16-byte loads, the same blend in the same order as
-// sample_u, 0 outside the box.
-__device__ __forceinline__ float sample_u_paired(const float *__restrict__ vp, const int n[3],
-                                                 float u0, float u1, float u2) {
+// V[i][j+1][k]) at voxel (x0, x1, x2) displaced by (t0, t1, t2) voxels: two
+// 16-byte loads, the same cell, blend and order as sample_disp, 0 outside the
+// box.
+__device__ __forceinline__ float sample_disp_paired(const float *__restrict__ vp, const int n[3],
+                                                    int x0, int x1, int x2, float t0, float t1,
+                                                    float t2) {
     int i0, i1, i2;
     float f0, f1, f2;
-    if (!axis_cell(u0, n[0], i0, f0) || !axis_cell(u1, n[1], i1, f1) ||
-        !axis_cell(u2, n[2], i2, f2))
+    if (!disp_cell(x0, t0, n[0], i0, f0) || !disp_cell(x1, t1, n[1], i1, f1) ||
+        !disp_cell(x2, t2, n[2], i2, f2))
         return 0.0f;
     const float *pa = vp + 2 * ((i0 * n[1] + i1) * n[2] + i2);
     const float *pd = pa + 2 * n[1] * n[2];
@@ -99,10 +102,11 @@ __device__ __forceinline__ void combine_warp_voxel(const float *__restrict__ ref
                 for (int b = 0; b < B; ++b) t = fmaf(cv[(l * B + b) * 3 + k], sv[l][b][k], t);
             d[k] = t;
         }
-        const float u0 = fmaf(d[0], g.inv_h[0], (float)ix), u1 = fmaf(d[1], g.inv_h[1], (float)iy),
-                    u2 = fmaf(d[2], g.inv_h[2], (float)iz);
+        // the sample point in voxel units is (ix, iy, iz) + d / h
+        const float t0 = d[0] * g.inv_h[0], t1 = d[1] * g.inv_h[1], t2 = d[2] * g.inv_h[2];
         // with PAIRED, ref is the y-paired copy of the reference volume
-        const float val = PAIRED ? sample_u_paired(ref, g.n, u0, u1, u2) : sample_u(ref, g.n, u0, u1, u2);
+        const float val = PAIRED ? sample_disp_paired(ref, g.n, ix, iy, iz, t0, t1, t2)
+                                 : sample_disp(ref, g.n, ix, iy, iz, t0, t1, t2);
         if (PAIRED) {
             // y-paired layout: this voxel is the first of its own pair and the
             // second of the pair that starts one row below
@@ -153,7 +157,9 @@ struct GOut {
 // so the two 32-bit sums keep about 48 bits; each round is folded into a
 // float box.
 // The float box is staged per brick and summed by k_gather_boxes;
-// displacements that leave the halo fall back to global atomics.  dL/dw of
+// displacements that leave the halo add into a 64-bit fixed-point volume
+// (fix_add, scale from the largest |dL/dI_v| of all views), which the last
+// k_gather_boxes folds in.  dL/dw of
 // each view is reduced over a wave, written to that wave's LDS slot, and the
 // slots are summed over the waves in a fixed order into the brick's partials
 // (reduced over bricks by k_reduce_coeff_parts / _final), so it is deterministic.
@@ -166,7 +172,8 @@ struct WCK {
     int V;                  // views in this chunk
     const float *g_I;
     const unsigned *vmax;
-    float *g_ref;
+    const unsigned *vmax_all;   // largest |dL/dI_v| over every view of the scan
+    long long *fix;             // [N] 64-bit fixed point for the halo overflow
     float *stage;
     GOut gout;
     int accumulate;
@@ -184,8 +191,9 @@ template <int L, int B>
 __device__ __forceinline__ void warp_combine_bwd_brick(
     const float *__restrict__ ref, int paired, const GridK &g, const LevelsK &lv,
     const float *__restrict__ coeff, int V, const float *__restrict__ g_I,
-    const unsigned *__restrict__ vmax, float *__restrict__ g_ref, float *__restrict__ stage,
-    const GOut &gout, int accumulate, int nb1, int nb2, float *__restrict__ partial, int blk) {
+    const unsigned *__restrict__ vmax, const unsigned *__restrict__ vmax_all,
+    long long *__restrict__ fix, float *__restrict__ stage, const GOut &gout, int accumulate,
+    int nb1, int nb2, float *__restrict__ partial, int blk) {
     constexpr int NC = L * B * 3;
     extern __shared__ float smem[];
     int *ibox = (int *)smem;              // HB^3 fixed point, high words
@@ -220,6 +228,7 @@ __device__ __forceinline__ void warp_combine_bwd_brick(
     __syncthreads();
 
     const int lane = t & 63, wave = t >> 6;
+    const double fscale = fix_scale(*vmax_all);
     for (int r0 = 0; r0 < V; r0 += FLUSH) {
         const int r1 = min(V, r0 + FLUSH);
         float M = 0.0f;
@@ -241,13 +250,12 @@ __device__ __forceinline__ void warp_combine_bwd_brick(
                             acc = fmaf(cv[(l * B + b) * 3 + k], sv[l][b][k], acc);
                     d[k] = acc;
                 }
-                const float u0 = fmaf(d[0], g.inv_h[0], (float)vx);
-                const float u1 = fmaf(d[1], g.inv_h[1], (float)vy);
-                const float u2 = fmaf(d[2], g.inv_h[2], (float)vz);
+                const float t0 = d[0] * g.inv_h[0], t1 = d[1] * g.inv_h[1],
+                            t2 = d[2] * g.inv_h[2];
                 int i0, i1, i2;
                 float f0, f1, f2;
-                if (!axis_cell(u0, g.n[0], i0, f0) || !axis_cell(u1, g.n[1], i1, f1) ||
-                    !axis_cell(u2, g.n[2], i2, f2))
+                if (!disp_cell(vx, t0, g.n[0], i0, f0) || !disp_cell(vy, t1, g.n[1], i1, f1) ||
+                    !disp_cell(vz, t2, g.n[2], i2, f2))
                     break;
                 const float go = g_I[(int64_t)v * N + jj];
                 if (go == 0.0f) break;
@@ -273,9 +281,9 @@ __device__ __forceinline__ void warp_combine_bwd_brick(
                 const float e00 = lerp1(c000, c010, f1), e01 = lerp1(c001, c011, f1);
                 const float e10 = lerp1(c100, c110, f1), e11 = lerp1(c101, c111, f1);
                 const float ddz = lerp1(e01, e11, f0) - lerp1(e00, e10, f0);
-                gD[0] = go * ddx * g.inv_h[0] * axis_free(u0, g.n[0]);
-                gD[1] = go * ddy * g.inv_h[1] * axis_free(u1, g.n[1]);
-                gD[2] = go * ddz * g.inv_h[2] * axis_free(u2, g.n[2]);
+                gD[0] = go * ddx * g.inv_h[0] * disp_free(vx, t0, g.n[0]);
+                gD[1] = go * ddy * g.inv_h[1] * disp_free(vy, t1, g.n[1]);
+                gD[2] = go * ddz * g.inv_h[2] * disp_free(vz, t2, g.n[2]);
                 const int l0 = i0 - (B0 - HALO), l1 = i1 - (B1 - HALO), l2 = i2 - (B2 - HALO);
                 const bool inbox = l0 >= 0 && l0 + 1 < HB && l1 >= 0 && l1 + 1 < HB && l2 >= 0 &&
                                    l2 + 1 < HB;
@@ -305,8 +313,8 @@ __device__ __forceinline__ void warp_combine_bwd_brick(
                         for (int b = 0; b < 2; ++b)
 #pragma unroll
                             for (int c = 0; c < 2; ++c)
-                                unsafeAtomicAdd(&g_ref[base + a * s0 + b * s1 + c],
-                                                go * w0[a] * w1[b] * w2[c]);
+                                fix_add(&fix[base + a * s0 + b * s1 + c],
+                                        (double)(go * w0[a] * w1[b] * w2[c]), fscale);
                 }
             } while (false);
             // dL/dE: per voxel over views; dL/dw[v]: per-lane products,
@@ -377,14 +385,17 @@ __global__ __launch_bounds__(WB_THREADS) void k_warp_combine_bwd(WCTab t) {
     const int item = job_item(t, job, (int)blockIdx.x);
     if (item >= wj.items) return;
     warp_combine_bwd_brick<L, B>(wj.ref, wj.paired, wj.g, wj.lv, wj.coeff, wj.V, wj.g_I, wj.vmax,
-                                 wj.g_ref, wj.stage, wj.gout, wj.accumulate, wj.nb1, wj.nb2,
-                                 wj.partial, item);
+                                 wj.vmax_all, wj.fix, wj.stage, wj.gout, wj.accumulate, wj.nb1,
+                                 wj.nb2, wj.partial, item);
 }
 
 // g_ref[p] += sum of the staged boxes that cover voxel p (at most 2 bricks
-// per axis), in a fixed order.
+// per axis), in a fixed order, plus (when fix is given: the last chunk of
+// views) the 64-bit fixed-point halo overflow.
 __global__ __launch_bounds__(256) void k_gather_boxes(const float *__restrict__ stage, GridK g,
                                                       int nb0, int nb1, int nb2,
+                                                      const long long *__restrict__ fix,
+                                                      const unsigned *__restrict__ vmax_all,
                                                       float *__restrict__ g_ref) {
     const int64_t N = grid_size(g);
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -404,6 +415,10 @@ __global__ __launch_bounds__(256) void k_gather_boxes(const float *__restrict__ 
                           l2 = p2 - (b2 * FB - HALO);
                 s += stage[((int64_t)(b0 * nb1 + b1) * nb2 + b2) * HB3 + (l0 * HB + l1) * HB + l2];
             }
+    if (fix) {
+        const double sc = fix_scale(*vmax_all);
+        if (sc > 0.0) s += (float)((double)fix[j] / sc);
+    }
     g_ref[j] += s;
 }
 
@@ -522,7 +537,7 @@ hipError_t launch_warp_project(const float *ref, const GridK &g, const LevelsK &
 }
 
 struct BwdLayout {
-    size_t gI, rays, gbuf, partial, stage, vmax, pref, adj, total;
+    size_t gI, rays, gbuf, partial, stage, vmax, fix, pref, adj, total;
     int nbrick, nb[3];
 };
 
@@ -550,10 +565,11 @@ static BwdLayout bwd_layout(const LevelsK &lv, const GridK *lvl_grids, int V, co
     b.gbuf = align256(sizeof(float) * (size_t)N * 3 * lv.B * (size_t)ncoarse);
     b.partial = align256(sizeof(float) * (size_t)b.nbrick * vc * lv.L * lv.B * 3);
     b.stage = align256(sizeof(float) * (size_t)b.nbrick * HB3);
-    b.vmax = align256(sizeof(unsigned) * (size_t)V);
+    b.vmax = align256(sizeof(unsigned) * ((size_t)V + 1));    // per view, then over all views
+    b.fix = align256(sizeof(long long) * (size_t)N);
     b.pref = use_paired(g) ? align256(sizeof(float) * 2 * (size_t)N) : 0;
     b.adj = adj;
-    b.total = b.gI + b.rays + b.gbuf + b.partial + b.stage + b.vmax + b.pref + b.adj;
+    b.total = b.gI + b.rays + b.gbuf + b.partial + b.stage + b.vmax + b.fix + b.pref + b.adj;
     return b;
 }
 
@@ -569,7 +585,8 @@ struct BwdScan {
     float *gI, *gbuf, *partial, *stage;
     float2 *pref;           // y-paired reference volume, or null
     void *rays, *adjws;
-    unsigned *vmax;
+    unsigned *vmax;         // [V + 1]: per view, then the largest
+    long long *fix;         // [N]
     GOut gout;
     const float *staged[MAXL];
 };
@@ -590,6 +607,8 @@ BwdScan bwd_scan(const WPBJob &j) {
     w += b.lay.stage;
     b.vmax = (unsigned *)w;
     w += b.lay.vmax;
+    b.fix = (long long *)w;
+    w += b.lay.fix;
     b.pref = b.lay.pref ? (float2 *)w : nullptr;
     w += b.lay.pref;
     b.adjws = w;
@@ -636,6 +655,9 @@ hipError_t launch_warp_project_bwd_jobs(const WPBJob *jobs, int n, hipStream_t s
     for (int k = 0; k < n; ++k) {
         const WPBJob &j = jobs[k];
         if ((e = launch_fill(j.g_ref, grid_size(j.g), 0.0f, s)) != hipSuccess) return e;
+        if ((e = launch_max_u32(sc[k].vmax, j.V, sc[k].vmax + j.V, s)) != hipSuccess) return e;
+        if ((e = launch_fill_i32((int32_t *)sc[k].fix, 2 * grid_size(j.g), 0, s)) != hipSuccess)
+            return e;
         if (sc[k].pref) {
             const int64_t N = grid_size(j.g);
             {
@@ -663,7 +685,8 @@ hipError_t launch_warp_project_bwd_jobs(const WPBJob *jobs, int n, hipStream_t s
             w.V = vc;
             w.g_I = sc[k].gI + (int64_t)v0 * N;
             w.vmax = sc[k].vmax + v0;
-            w.g_ref = j.g_ref;
+            w.vmax_all = sc[k].vmax + j.V;
+            w.fix = sc[k].fix;
             w.stage = sc[k].stage;
             w.gout = sc[k].gout;
             w.accumulate = v0 > 0;
@@ -693,8 +716,10 @@ hipError_t launch_warp_project_bwd_jobs(const WPBJob *jobs, int n, hipStream_t s
             const int64_t N = grid_size(j.g);
             {
                 ProfScope prof_("gather_boxes", s);
+                const bool last = j.V - v0 <= VCH;     // this scan's last chunk of views
                 k_gather_boxes<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(
-                    b.stage, j.g, b.lay.nb[0], b.lay.nb[1], b.lay.nb[2], j.g_ref);
+                    b.stage, j.g, b.lay.nb[0], b.lay.nb[1], b.lay.nb[2], last ? b.fix : nullptr,
+                    b.vmax + j.V, j.g_ref);
             }
             if ((e = hipGetLastError()) != hipSuccess) return e;
             {

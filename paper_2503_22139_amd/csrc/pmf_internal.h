@@ -56,6 +56,24 @@ struct alignas(16) RayK {
 
 // --------------------------------------------------------- device helpers
 #ifdef __HIPCC__
+// 64-bit fixed point for scatters that cannot stay in LDS: with M the largest
+// magnitude of any single contribution (bits of a non-negative float), each
+// contribution x becomes llrint(x 2^40 / M), so it is exact to 2^-40 M and
+// integer sums are independent of the order of the additions (results are
+// bit-reproducible); a sum overflows only beyond 2^23 contributions of size
+// M into one entry.
+__host__ __device__ inline double fix_scale(uint32_t max_bits) {
+    union {
+        uint32_t u;
+        float f;
+    } c;
+    c.u = max_bits;
+    return c.f > 0.0f ? 1099511627776.0 / (double)c.f : 0.0;
+}
+__device__ __forceinline__ void fix_add(long long *dst, double x, double scale) {
+    atomicAdd((unsigned long long *)dst, (unsigned long long)__double2ll_rn(x * scale));
+}
+
 // Trilinear coordinate on one axis: false if u is beyond the half-voxel rim
 // (or NaN); otherwise the clamped cell index i in [0, n-2] and fraction f.
 __device__ __forceinline__ bool axis_cell(float u, int n, int &i, float &f) {
@@ -68,10 +86,34 @@ __device__ __forceinline__ bool axis_cell(float u, int n, int &i, float &f) {
     return true;
 }
 
-// Derivative switch: the interpolant moves with u only strictly inside the
-// voxel-centre hull.
-__device__ __forceinline__ float axis_free(float u, int n) {
-    return (u > 0.0f && u < (float)(n - 1)) ? 1.0f : 0.0f;
+// The same decision for the point idx + t on one axis (voxel units), idx a
+// voxel index and t a displacement in voxels: the cell and fraction that
+// axis_cell(idx + t) gives in exact arithmetic, decided from t alone.  The
+// comparisons are exact (idx + 1/2 and n - 1 - idx are exact floats) and
+// floor(t) is exact, so a point near a cell face takes the side its
+// displacement puts it on; only t itself is rounded, at its own ulp rather
+// than at the ulp of idx + t (up to 1.5e-5 voxel on a 256-voxel axis).
+__device__ __forceinline__ bool disp_cell(int idx, float t, int n, int &i, float &f) {
+    const float fi = (float)idx;
+    if (!(t >= -0.5f - fi && t <= (float)n - 0.5f - fi)) return false;
+    if (t <= -fi) {                     // on the rim below the first centre
+        i = 0;
+        f = 0.0f;
+    } else if (t >= (float)(n - 1) - fi) {   // on the rim above the last centre
+        i = n - 2;
+        f = 1.0f;
+    } else {
+        const float fl = floorf(t);
+        i = idx + (int)fl;
+        f = t - fl;
+    }
+    return true;
+}
+
+// Derivative switch of disp_cell's point: strictly inside the voxel-centre hull.
+__device__ __forceinline__ float disp_free(int idx, float t, int n) {
+    const float fi = (float)idx;
+    return (t > -fi && t < (float)(n - 1) - fi) ? 1.0f : 0.0f;
 }
 
 __device__ __forceinline__ float lerp1(float a, float b, float t) { return fmaf(t, b - a, a); }
@@ -91,6 +133,30 @@ __device__ __forceinline__ float sample_u(const float *__restrict__ vol, const i
     float c10 = lerp1(p[s0], p[s0 + 1], f2);
     float c11 = lerp1(p[s0 + s1], p[s0 + s1 + 1], f2);
     return lerp1(lerp1(c00, c01, f1), lerp1(c10, c11, f1), f0);
+}
+
+// Trilinear read at the point (i0 + t0, i1 + t1, i2 + t2): voxel indices
+// plus displacements in voxels (see disp_cell); 0 outside the box.
+__device__ __forceinline__ float sample_disp(const float *__restrict__ vol, const int n[3], int i0,
+                                             int i1, int i2, float t0, float t1, float t2) {
+    int c0, c1, c2;
+    float f0, f1, f2;
+    if (!disp_cell(i0, t0, n[0], c0, f0) || !disp_cell(i1, t1, n[1], c1, f1) ||
+        !disp_cell(i2, t2, n[2], c2, f2))
+        return 0.0f;
+    const int s1 = n[2], s0 = n[1] * n[2];
+    const float *p = vol + ((c0 * n[1] + c1) * n[2] + c2);
+    float c00 = lerp1(p[0], p[1], f2);
+    float c01 = lerp1(p[s1], p[s1 + 1], f2);
+    float c10 = lerp1(p[s0], p[s0 + 1], f2);
+    float c11 = lerp1(p[s0 + s1], p[s0 + s1 + 1], f2);
+    return lerp1(lerp1(c00, c01, f1), lerp1(c10, c11, f1), f0);
+}
+
+// Largest value over the 64 lanes (every lane receives it).
+__device__ __forceinline__ float wave_max(float v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
 }
 
 __device__ __forceinline__ float warp_sum(float v) {
@@ -331,6 +397,13 @@ hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 // p[2i] = a, p[2i+1] = b for i < n
 hipError_t launch_fill_pair_u32(uint32_t *p, int64_t n, uint32_t a, uint32_t b, hipStream_t s);
 hipError_t launch_accumulate(float *dst, const float *src, int64_t n, hipStream_t s);
+// *out = bits of max |x[i]| over n floats (out is cleared first)
+hipError_t launch_absmax(const float *x, int64_t n, uint32_t *out, hipStream_t s);
+// out[0] = max of n unsigned words (float bits of non-negative floats)
+hipError_t launch_max_u32(const uint32_t *in, int n, uint32_t *out, hipStream_t s);
+// dst = fix / fix_scale(*mx) (add: dst += ...)
+hipError_t launch_fix_to_float(const long long *fix, int64_t n, const uint32_t *mx, bool add,
+                               float *dst, hipStream_t s);
 
 // voxelize
 struct VoxPlan {
@@ -364,8 +437,10 @@ size_t upsample_adjoint_workspace(int C, const GridK &lvl_grid, const GridK &out
 // warp
 hipError_t launch_warp(const float *ref, const GridK &g, const float *dvf, int V, float *out,
                        hipStream_t s);
+size_t warp_bwd_workspace(const GridK &g);
 hipError_t launch_warp_bwd(const float *ref, const GridK &g, const float *dvf, int V,
-                           const float *g_out, float *g_ref, float *g_dvf, hipStream_t s);
+                           const float *g_out, float *g_ref, float *g_dvf, void *ws,
+                           hipStream_t s);
 
 // projection
 struct ProjJob {            // one scan's forward projection

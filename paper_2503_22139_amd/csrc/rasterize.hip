@@ -15,8 +15,9 @@
 //
 // Forward: per-(view, Gaussian) set-up in double, tile binning (16 x 16-pixel
 // tiles; a Gaussian whose truncation box covers more than RS_TMAX tiles goes
-// to a per-view list handled one Gaussian per workgroup), then one workgroup
-// per tile: Gaussians staged in LDS, one pixel per thread.  Adjoint: the same
+// to a list of large splats), then one workgroup per tile: Gaussians staged
+// in LDS, one pixel per thread, summed in fixed point (bit-reproducible),
+// the large splats that reach the tile after its list.  Adjoint: the same
 // binning; per tile each wave reduces its pixels' contributions to the six
 // 2-D parameters (amplitude, centre, conic) of a Gaussian, and the tile
 // writes the sum of its waves (fixed order) to a partial per list entry; a
@@ -237,55 +238,78 @@ __device__ __forceinline__ float splat_at(const SplatP &P, float x, float y, flo
 }
 
 // ------------------------------------------------------------------ forward
-__global__ __launch_bounds__(RS_THREADS) void k_splat_fwd(const SplatP *__restrict__ sp, RastGeo G,
+// One workgroup per (view, tile), one pixel per thread.  Each pixel sums its
+// splats in 32-bit fixed point with the tile's scale 2^30 / S, S = (number of
+// splats reaching the tile: its list and the view's large Gaussians) x (their
+// largest |amplitude|), so every pixel's sum stays below 2^30: neither the
+// integer sums nor S depend on the order in which the binning's atomics
+// filled the list, so the images repeat bit for bit.  The large Gaussians (no tile entries) are walked by
+// every tile they reach, after its list.
+__global__ __launch_bounds__(RS_THREADS) void k_splat_fwd(const SplatP *__restrict__ sp, int64_t m,
+                                                         RastGeo G,
                                                          const int *__restrict__ offsets,
                                                          const int *__restrict__ list,
+                                                         const int *__restrict__ large,
+                                                         const int *__restrict__ nlarge,
                                                          float *__restrict__ proj) {
     __shared__ SplatP sh[RS_THREADS];
+    __shared__ float red[RS_THREADS / 64];
+    __shared__ int cnt[RS_THREADS / 64];
     const int64_t T = (int64_t)G.tiles_u * G.tiles_v;
     const int64_t tix = blockIdx.x;
     const int v = (int)(tix / T), t = (int)(tix - (int64_t)v * T);
-    const int x = (t % G.tiles_u) * RS_T + (threadIdx.x % RS_T);
-    const int y = (t / G.tiles_u) * RS_T + (threadIdx.x / RS_T);
+    const int tx = t % G.tiles_u, ty = t / G.tiles_u;
+    const int x = tx * RS_T + (threadIdx.x % RS_T);
+    const int y = ty * RS_T + (threadIdx.x / RS_T);
     const float k2 = G.k * G.k;
     const int b = offsets[tix], e = offsets[tix + 1];
-    float acc = 0.0f;
+    const int nl = *nlarge;
+    auto reaches = [&](const SplatP &P) {
+        return P.tu0 <= tx && tx <= P.tu1 && P.tv0 <= ty && ty <= P.tv1;
+    };
+    // S = (splats reaching the tile) x (their largest |amplitude|): an
+    // order-independent bound of every pixel's sum
+    float mx = 0.0f;
+    int nh = 0;
+    for (int q = b + (int)threadIdx.x; q < e; q += RS_THREADS) mx = fmaxf(mx, fabsf(sp[list[q]].rho));
+    for (int q = (int)threadIdx.x; q < nl; q += RS_THREADS) {
+        const int64_t i = large[q];
+        if (i / m == v && reaches(sp[i])) {
+            mx = fmaxf(mx, fabsf(sp[i].rho));
+            ++nh;
+        }
+    }
+    mx = wave_max(mx);
+    for (int o = 32; o > 0; o >>= 1) nh += __shfl_xor(nh, o, 64);
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6] = mx;
+        cnt[threadIdx.x >> 6] = nh;
+    }
+    __syncthreads();
+    const float S = (float)((e - b) + cnt[0] + cnt[1] + cnt[2] + cnt[3]) *
+                    fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    const float scale = S > 0.0f ? 1073741824.0f / (S * 1.0001f) : 0.0f;
+    int acc = 0;
     for (int c0 = b; c0 < e; c0 += RS_THREADS) {
         const int n = min(RS_THREADS, e - c0);
         if ((int)threadIdx.x < n) sh[threadIdx.x] = sp[list[c0 + threadIdx.x]];
         __syncthreads();
         for (int j = 0; j < n; ++j) {
             float du, dv, ex;
-            acc += splat_at(sh[j], (float)x, (float)y, k2, du, dv, ex);
+            acc += __float2int_rn(splat_at(sh[j], (float)x, (float)y, k2, du, dv, ex) * scale);
         }
         __syncthreads();
     }
-    if (x < G.nu && y < G.nv) proj[((int64_t)v * G.nv + y) * G.nu + x] = acc;
-}
-
-// Gaussians of the per-view large list: one workgroup per Gaussian adds it
-// to every pixel of its box (after the tile pass has written the images).
-__global__ __launch_bounds__(256) void k_splat_large_fwd(const SplatP *__restrict__ sp, int64_t m,
-                                                         RastGeo G, const int *__restrict__ large,
-                                                         const int *__restrict__ nlarge,
-                                                         float *__restrict__ proj) {
-    const float k2 = G.k * G.k;
-    const int n = *nlarge;
-    for (int li = blockIdx.x; li < n; li += gridDim.x) {
-        const int64_t i = large[li];
+    for (int q = 0; q < nl; ++q) {
+        const int64_t i = large[q];
+        if (i / m != v) continue;
         const SplatP P = sp[i];
-        const int v = (int)(i / m);
-        const int u0 = P.tu0 * RS_T, u1 = min((P.tu1 + 1) * RS_T, G.nu);
-        const int v0 = P.tv0 * RS_T, v1 = min((P.tv1 + 1) * RS_T, G.nv);
-        const int w = u1 - u0;
-        const int64_t npx = (int64_t)w * (v1 - v0);
-        for (int64_t p = threadIdx.x; p < npx; p += blockDim.x) {
-            const int x = u0 + (int)(p % w), y = v0 + (int)(p / w);
-            float du, dv, e;
-            const float val = splat_at(P, (float)x, (float)y, k2, du, dv, e);
-            if (val != 0.0f) atomicAdd(&proj[((int64_t)v * G.nv + y) * G.nu + x], val);
-        }
+        if (!reaches(P)) continue;
+        float du, dv, ex;
+        acc += __float2int_rn(splat_at(P, (float)x, (float)y, k2, du, dv, ex) * scale);
     }
+    if (x < G.nu && y < G.nv)
+        proj[((int64_t)v * G.nv + y) * G.nu + x] = scale > 0.0f ? (float)acc / scale : 0.0f;
 }
 
 // ------------------------------------------------------------------ adjoint
@@ -635,9 +659,8 @@ hipError_t launch_rasterize(const pmf_gauss_t &gs, const pmf_cone_t &c, const fl
     const int64_t T = (int64_t)G.tiles_u * G.tiles_v * V;
     {
         ProfScope prof_("rasterize", s);
-        k_splat_fwd<<<(unsigned)T, RS_THREADS, 0, s>>>(w.sp, G, w.offsets, w.list, proj);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        k_splat_large_fwd<<<1024, 256, 0, s>>>(w.sp, gs.m, G, w.large, w.nlarge, proj);
+        k_splat_fwd<<<(unsigned)T, RS_THREADS, 0, s>>>(w.sp, gs.m, G, w.offsets, w.list, w.large,
+                                                        w.nlarge, proj);
     }
     return hipGetLastError();
 }

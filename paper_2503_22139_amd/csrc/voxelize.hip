@@ -4,11 +4,13 @@
 // ellipsoid is bounded by a box of voxels; Gaussians are binned into the
 // tiles their box overlaps (count, scan, fill).  One workgroup owns a tile:
 // its waves take the tile's Gaussians one at a time (parameters wave-uniform,
-// held in scalar registers), evaluate them over box-and-tile in 4x4x4 voxel
-// chunks and add into an LDS copy of the tile; the tile is then stored once
-// with plain coalesced writes -- no global atomics.  Gaussians whose box
-// spans more tiles than the bin capacity (e.g. untruncated ones) go to a
-// separate list that is splatted with global atomics after the tiles.
+// held in scalar registers), evaluate them over box-and-tile column by column
+// and add into an LDS copy of the tile in fixed point; the tile is then
+// stored once with plain coalesced writes -- no global atomics.  Gaussians
+// whose box spans more tiles than the bin capacity (e.g. untruncated ones) go
+// to a separate list in ascending order, which every tile walks after its own
+// list, adding in float per voxel in that order; neither sum depends on the
+// order in which the binning's atomics filled the tile lists.
 //
 // Backward: Gaussian owner.  One wave per Gaussian walks the same voxel box,
 // accumulates the per-Gaussian sums in registers and reduces them across the
@@ -130,10 +132,10 @@ __global__ __launch_bounds__(256) void k_vox_prep(pmf_gauss_t gs, GridK g, float
                                                   int T1, int T2, int nt1, int nt2, int maxtiles,
                                                   GaussK *__restrict__ rec,
                                                   int32_t *__restrict__ tile_count,
-                                                  int32_t *__restrict__ large,
-                                                  int32_t *__restrict__ nlarge) {
+                                                  int32_t *__restrict__ is_large) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= gs.m) return;
+    is_large[i] = 0;
     if (far_from_grid(gs.mean, gs.scale, i, k, g)) {
         GaussK r = {};
         r.lo0 = r.lo1 = r.lo2 = 1;            // empty box: no tile, no voxel
@@ -164,7 +166,7 @@ __global__ __launch_bounds__(256) void k_vox_prep(pmf_gauss_t gs, GridK g, float
     const int t2a = G.lo[2] / T2, t2b = G.hi[2] / T2;
     const int64_t cnt = (int64_t)(t0b - t0a + 1) * (t1b - t1a + 1) * (t2b - t2a + 1);
     if (cnt > maxtiles) {
-        large[atomicAdd(nlarge, 1)] = (int32_t)i;
+        is_large[i] = 1;
         return;
     }
     for (int a = t0a; a <= t0b; ++a)
@@ -202,6 +204,31 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t *__restrict__ cnt, 
     if (threadIdx.x == 1023) off[n] = part[1023];
 }
 
+// The large Gaussians in ascending index order (so that every tile adds
+// them in one fixed order): one workgroup, each thread a contiguous chunk.
+__global__ __launch_bounds__(1024) void k_large_compact(const int32_t *__restrict__ is_large,
+                                                        int64_t m, int32_t *__restrict__ large,
+                                                        int32_t *__restrict__ nlarge) {
+    __shared__ int32_t part[1024];
+    const int64_t per = (m + 1023) / 1024;
+    const int64_t b = threadIdx.x * per;
+    const int64_t e = b + per < m ? b + per : m;
+    int32_t s = 0;
+    for (int64_t i = b; i < e; ++i) s += is_large[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int32_t t = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0;
+        __syncthreads();
+        part[threadIdx.x] += t;
+        __syncthreads();
+    }
+    int32_t pos = part[threadIdx.x] - s;
+    for (int64_t i = b; i < e; ++i)
+        if (is_large[i]) large[pos++] = (int32_t)i;
+    if (threadIdx.x == 1023) *nlarge = part[1023];
+}
+
 __global__ __launch_bounds__(256) void k_vox_fill(int64_t m, const GaussK *__restrict__ rec,
                                                   int T0, int T1, int T2, int nt1, int nt2,
                                                   int maxtiles, int32_t *__restrict__ cursor,
@@ -222,31 +249,6 @@ __global__ __launch_bounds__(256) void k_vox_fill(int64_t m, const GaussK *__res
 }
 
 // ------------------------------------------------------------ tile splat
-// Evaluate Gaussian `gi` over the voxel box [lo, hi] (inclusive) in 4x4x4
-// chunks; call add(local index fn) for each in-mask voxel.
-template <typename Add>
-__device__ __forceinline__ void splat_box(const GaussK &p, const GridK &g, float k2, int lo0,
-                                          int lo1, int lo2, int hi0, int hi1, int hi2, Add add) {
-    const int lane = threadIdx.x & 63;
-    const int lx = lane >> 4, ly = (lane >> 2) & 3, lz = lane & 3;
-    for (int cx = lo0; cx <= hi0; cx += 4) {
-        const int ix = cx + lx;
-        const float d0 = fmaf((float)ix, g.h[0], g.c0[0]) - p.mu[0];
-        for (int cy = lo1; cy <= hi1; cy += 4) {
-            const int iy = cy + ly;
-            const float d1 = fmaf((float)iy, g.h[1], g.c0[1]) - p.mu[1];
-            for (int cz = lo2; cz <= hi2; cz += 4) {
-                const int iz = cz + lz;
-                if (ix > hi0 || iy > hi1 || iz > hi2) continue;
-                const float d2 = fmaf((float)iz, g.h[2], g.c0[2]) - p.mu[2];
-                const float mm = quad(p, d0, d1, d2);
-                if (!(mm <= k2)) continue;
-                add(ix, iy, iz, __expf(-0.5f * mm));
-            }
-        }
-    }
-}
-
 // z range [za, zb] of column (ix, iy) that the truncation ellipsoid can
 // reach: the roots of the quadratic in d2, widened by one voxel on each side
 // and clipped to [lo2, hi2]; false when the column's quadratic stays clearly
@@ -275,10 +277,10 @@ __device__ __forceinline__ bool col_range(const GaussK &p, const GridK &g, float
     return true;
 }
 
-// The same voxels as splat_box, visited by (x, y) column: each lane takes a
-// column and walks only its col_range; every voxel visited is still tested
-// with quad() exactly as above, so the voxels added and their order within a
-// column are unchanged.
+// Evaluate a Gaussian over the voxel box [lo, hi] (inclusive) by (x, y)
+// column: each lane takes a column and walks only its col_range, testing
+// every voxel it visits with quad(); add(ix, iy, iz, e) for each in-mask
+// voxel.
 template <typename Add>
 __device__ __forceinline__ void splat_cols(const GaussK &p, const GridK &g, float k2, int lo0,
                                            int lo1, int lo2, int hi0, int hi1, int hi2, Add add) {
@@ -304,10 +306,11 @@ __device__ __forceinline__ void splat_cols(const GaussK &p, const GridK &g, floa
 }
 
 // One workgroup per tile.  Accumulation is in 32-bit fixed point with
-// integer LDS atomics (float LDS atomics are far slower on gfx950): per
-// channel the scale is 2^30 / S with S = sum of |value| over the tile's
-// Gaussians, which bounds every voxel's sum since each Gaussian adds
-// value * e (e <= 1) at most once per voxel.
+// integer LDS atomics, so the sums do not depend on their order: per channel
+// the scale is 2^30 / S with S = (Gaussians reaching the tile) x (their
+// largest |value|), which bounds every voxel's sum since each Gaussian adds
+// value * e (e <= 1) at most once per voxel, and is itself independent of
+// the list's order.
 constexpr int VT_CHUNK = 128;      // Gaussians staged in LDS at a time (one per thread)
 
 // STAGE: the tile's Gaussians go through LDS VT_CHUNK at a time (one-channel
@@ -320,6 +323,8 @@ __global__ __launch_bounds__(256) void k_vox_tile(const GaussK *__restrict__ rec
                                                   float k2, int T0, int T1, int T2, int nt1,
                                                   int nt2, const int32_t *__restrict__ off,
                                                   const int32_t *__restrict__ list,
+                                                  const int32_t *__restrict__ large,
+                                                  const int32_t *__restrict__ nlarge,
                                                   float *__restrict__ vol) {
     extern __shared__ int acc[];          // C tile planes, then VT_CHUNK x C staged values
     __shared__ float cs[4][16];
@@ -337,18 +342,23 @@ __global__ __launch_bounds__(256) void k_vox_tile(const GaussK *__restrict__ rec
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int nw = blockDim.x >> 6;
-    // per-channel bound S
+    const int nl = *nlarge;
+    // per-channel bound S = (the tile's list length) x (the list's largest
+    // |value|): every voxel's sum stays below it, and unlike a float sum of
+    // the |values| it does not depend on the order the binning's atomics gave
+    // the list, so neither does the scale (results repeat bit for bit)
     for (int c = 0; c < C; ++c) {
-        float sc = 0.0f;
+        float mx = 0.0f;
         for (int e = beg + (int)threadIdx.x; e < end; e += blockDim.x)
-            sc += fabsf(value[(int64_t)list[e] * C + c]);
-        sc = wave_sum_lane63(sc);
-        if (lane == 63) cs[wave][c] = sc;
+            mx = fmaxf(mx, fabsf(value[(int64_t)list[e] * C + c]));
+        mx = wave_max(mx);
+        if (lane == 0) cs[wave][c] = mx;
     }
     __syncthreads();
     if (threadIdx.x < (unsigned)C) {
-        const float S = (cs[0][threadIdx.x] + cs[1][threadIdx.x]) +
-                        (cs[2][threadIdx.x] + cs[3][threadIdx.x]);
+        const float mx = fmaxf(fmaxf(cs[0][threadIdx.x], cs[1][threadIdx.x]),
+                               fmaxf(cs[2][threadIdx.x], cs[3][threadIdx.x]));
+        const float S = (float)(end - beg) * mx;
         scale[threadIdx.x] = S > 0.0f ? 1073741824.0f / (S * 1.0001f) : 0.0f;
     }
     // Staged: each thread fetches one record and its values, so a wave does
@@ -393,40 +403,45 @@ __global__ __launch_bounds__(256) void k_vox_tile(const GaussK *__restrict__ rec
         }
     }
     __syncthreads();
+    // fixed point -> float, in place
+    float *const accf = (float *)acc;
+    for (int i = threadIdx.x; i < C * tvox; i += blockDim.x) {
+        const float sc = scale[i / tvox];
+        accf[i] = sc > 0.0f ? (float)acc[i] / sc : 0.0f;
+    }
+    // Gaussians too large for the bins (e.g. untruncated sets): each thread
+    // owns voxels of the tile and adds them in float, in the list's ascending
+    // order (a fixed order: the results repeat bit for bit)
+    if (nl > 0) {
+        __syncthreads();
+        for (int li = threadIdx.x; li < tvox; li += blockDim.x) {
+            const int ix = b0 + li / (T1 * T2), iy = b1 + (li / T2) % T1, iz = b2 + li % T2;
+            if (ix > e0 || iy > e1 || iz > e2) continue;
+            const float d0g = fmaf((float)ix, g.h[0], g.c0[0]);
+            const float d1g = fmaf((float)iy, g.h[1], g.c0[1]);
+            const float d2g = fmaf((float)iz, g.h[2], g.c0[2]);
+            for (int e = 0; e < nl; ++e) {
+                const int gi = __builtin_amdgcn_readfirstlane(large[e]);
+                const GaussK p = rec[gi];
+                if (ix < p.lo0 || ix > p.hi0 || iy < p.lo1 || iy > p.hi1 || iz < p.lo2 ||
+                    iz > p.hi2)
+                    continue;
+                const float mm = quad(p, d0g - p.mu[0], d1g - p.mu[1], d2g - p.mu[2]);
+                if (!(mm <= k2)) continue;
+                const float ev = __expf(-0.5f * mm);
+                const float *vv = value + (int64_t)gi * C;
+                for (int c = 0; c < C; ++c) accf[c * tvox + li] += vv[c] * ev;
+            }
+        }
+    }
+    __syncthreads();
     const int64_t N = grid_size(g);
     for (int i = threadIdx.x; i < C * tvox; i += blockDim.x) {
         const int c = i / tvox, li = i % tvox;
         const int z = li % T2, y = (li / T2) % T1, x = li / (T2 * T1);
         const int gx = b0 + x, gy = b1 + y, gz = b2 + z;
-        if (gx < g.n[0] && gy < g.n[1] && gz < g.n[2]) {
-            const float sc = scale[c];
-            vol[(int64_t)c * N + ((int64_t)gx * g.n[1] + gy) * g.n[2] + gz] =
-                sc > 0.0f ? (float)acc[i] / sc : 0.0f;
-        }
-    }
-}
-
-// Gaussians too large for the bins: one wave each, global atomics.
-__global__ __launch_bounds__(256) void k_vox_large(const GaussK *__restrict__ rec,
-                                                   const float *__restrict__ value, int C,
-                                                   GridK g, float k2,
-                                                   const int32_t *__restrict__ large,
-                                                   const int32_t *__restrict__ nlarge,
-                                                   float *__restrict__ vol) {
-    const int64_t N = grid_size(g);
-    const int nl = *nlarge;
-    const int gw = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const int nwaves = gridDim.x * (blockDim.x >> 6);
-    for (int e = __builtin_amdgcn_readfirstlane(gw); e < nl; e += nwaves) {
-        const int gi = __builtin_amdgcn_readfirstlane(large[e]);
-        const GaussK p = rec[gi];
-        if (p.lo0 > p.hi0 || p.lo1 > p.hi1 || p.lo2 > p.hi2) continue;
-        const float *vv = value + (int64_t)gi * C;
-        splat_cols(p, g, k2, p.lo0, p.lo1, p.lo2, p.hi0, p.hi1, p.hi2,
-                  [&](int ix, int iy, int iz, float ev) {
-                      const int64_t j = ((int64_t)ix * g.n[1] + iy) * g.n[2] + iz;
-                      for (int c = 0; c < C; ++c) unsafeAtomicAdd(&vol[c * N + j], vv[c] * ev);
-                  });
+        if (gx < g.n[0] && gy < g.n[1] && gz < g.n[2])
+            vol[(int64_t)c * N + ((int64_t)gx * g.n[1] + gy) * g.n[2] + gz] = accf[i];
     }
 }
 
@@ -476,6 +491,7 @@ size_t vox_workspace(const VoxPlan &p, int64_t m) {
     s += align256(sizeof(int32_t) * (size_t)(p.cap > 0 ? p.cap : 1));  // list
     s += align256(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));  // large list
     s += align256(sizeof(int32_t));                            // large count
+    s += align256(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));  // large flags
     return s;
 }
 
@@ -496,6 +512,8 @@ hipError_t launch_voxelize(const pmf_gauss_t &gs, const GridK &g, float k, float
     int32_t *large = (int32_t *)w;
     w += align256(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
     int32_t *nlarge = (int32_t *)w;
+    w += align256(sizeof(int32_t));
+    int32_t *is_large = (int32_t *)w;
 
     const float k2 = isinf(k) ? INFINITY : k * k;
     hipError_t e = launch_fill_i32(cnt, CNT_STRIDE * p.ntiles, 0, s);
@@ -506,8 +524,10 @@ hipError_t launch_voxelize(const pmf_gauss_t &gs, const GridK &g, float k, float
         {
             ProfScope prof_("voxelize_prep", s);
             k_vox_prep<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(
-                gs, g, k, p.T[0], p.T[1], p.T[2], p.nt[1], p.nt[2], p.maxtiles, rec, cnt, large, nlarge);
+                gs, g, k, p.T[0], p.T[1], p.T[2], p.nt[1], p.nt[2], p.maxtiles, rec, cnt, is_large);
         }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        k_large_compact<<<1, 1024, 0, s>>>(is_large, m, large, nlarge);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     {
@@ -531,22 +551,14 @@ hipError_t launch_voxelize(const pmf_gauss_t &gs, const GridK &g, float k, float
         ProfScope prof_("voxelize_tile", s);
         if (stage)
             k_vox_tile<true><<<(unsigned)p.ntiles, 256, lds, s>>>(
-                rec, gs.value, gs.c, g, k2, p.T[0], p.T[1], p.T[2], p.nt[1], p.nt[2], off, list, vol);
+                rec, gs.value, gs.c, g, k2, p.T[0], p.T[1], p.T[2], p.nt[1], p.nt[2], off, list,
+                large, nlarge, vol);
         else
             k_vox_tile<false><<<(unsigned)p.ntiles, 256, lds, s>>>(
-                rec, gs.value, gs.c, g, k2, p.T[0], p.T[1], p.T[2], p.nt[1], p.nt[2], off, list, vol);
+                rec, gs.value, gs.c, g, k2, p.T[0], p.T[1], p.T[2], p.nt[1], p.nt[2], off, list,
+                large, nlarge, vol);
     }
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (m > 0) {
-        int64_t nb = (m + 3) / 4;
-        if (nb > 2048) nb = 2048;
-        {
-            ProfScope prof_("voxelize_large", s);
-            k_vox_large<<<(unsigned)nb, 256, 0, s>>>(rec, gs.value, gs.c, g, k2, large, nlarge, vol);
-        }
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
-    return hipSuccess;
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------- backward

@@ -1,9 +1,11 @@
 // warp.hip -- the motion-compensated warp of Eq. 2 and its adjoint.
 //
 // One thread per voxel of the output grid; the sample point x_j + d is taken
-// in voxel units as u_a = i_a + d_a / h_a.  The adjoint writes g_dvf directly
-// (one owner per entry) and scatters g_ref onto the 8 corners of each
-// sample with global atomics.
+// in voxel units as i_a + t_a, t_a = d_a / h_a, its cell decided from t_a
+// (disp_cell).  The adjoint writes g_dvf directly (one owner per entry) and
+// scatters g_ref onto the 8 corners of each sample in 64-bit fixed point
+// (fix_add, scale from the largest |g_out|), so g_ref does not depend on the
+// order of the additions; a last pass converts it to float.
 #include "pmf_internal.h"
 
 namespace pmf {
@@ -19,17 +21,17 @@ __global__ __launch_bounds__(256) void k_warp(const float *__restrict__ ref, Gri
     const int ix = (int)(j / ((int64_t)g.n[2] * g.n[1]));
     for (int v = 0; v < V; ++v) {
         const float *d = dvf + (int64_t)v * 3 * N;
-        const float u0 = fmaf(d[j], g.inv_h[0], (float)ix);
-        const float u1 = fmaf(d[N + j], g.inv_h[1], (float)iy);
-        const float u2 = fmaf(d[2 * N + j], g.inv_h[2], (float)iz);
-        out[(int64_t)v * N + j] = sample_u(ref, g.n, u0, u1, u2);
+        const float t0 = d[j] * g.inv_h[0], t1 = d[N + j] * g.inv_h[1],
+                    t2 = d[2 * N + j] * g.inv_h[2];
+        out[(int64_t)v * N + j] = sample_disp(ref, g.n, ix, iy, iz, t0, t1, t2);
     }
 }
 
 __global__ __launch_bounds__(256) void k_warp_bwd(const float *__restrict__ ref, GridK g,
                                                   const float *__restrict__ dvf, int V,
                                                   const float *__restrict__ g_out,
-                                                  float *__restrict__ g_ref,
+                                                  const uint32_t *__restrict__ gmax,
+                                                  long long *__restrict__ fix,
                                                   float *__restrict__ g_dvf) {
     const int64_t N = grid_size(g);
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -38,17 +40,17 @@ __global__ __launch_bounds__(256) void k_warp_bwd(const float *__restrict__ ref,
     const int iy = (int)((j / g.n[2]) % g.n[1]);
     const int ix = (int)(j / ((int64_t)g.n[2] * g.n[1]));
     const int s1 = g.n[2], s0 = g.n[1] * g.n[2];
+    const double fscale = fix_scale(*gmax);
     for (int v = 0; v < V; ++v) {
         const float *d = dvf + (int64_t)v * 3 * N;
-        const float u0 = fmaf(d[j], g.inv_h[0], (float)ix);
-        const float u1 = fmaf(d[N + j], g.inv_h[1], (float)iy);
-        const float u2 = fmaf(d[2 * N + j], g.inv_h[2], (float)iz);
+        const float t0 = d[j] * g.inv_h[0], t1 = d[N + j] * g.inv_h[1],
+                    t2 = d[2 * N + j] * g.inv_h[2];
         const float go = g_out[(int64_t)v * N + j];
         float *gd = g_dvf + (int64_t)v * 3 * N;
         int i0, i1, i2;
         float f0, f1, f2;
-        if (!axis_cell(u0, g.n[0], i0, f0) || !axis_cell(u1, g.n[1], i1, f1) ||
-            !axis_cell(u2, g.n[2], i2, f2)) {
+        if (!disp_cell(ix, t0, g.n[0], i0, f0) || !disp_cell(iy, t1, g.n[1], i1, f1) ||
+            !disp_cell(iz, t2, g.n[2], i2, f2)) {
             gd[j] = 0.0f;
             gd[N + j] = 0.0f;
             gd[2 * N + j] = 0.0f;
@@ -66,9 +68,9 @@ __global__ __launch_bounds__(256) void k_warp_bwd(const float *__restrict__ ref,
         const float b00 = lerp1(c000, c010, f1), b01 = lerp1(c001, c011, f1);
         const float b10 = lerp1(c100, c110, f1), b11 = lerp1(c101, c111, f1);
         const float dz = lerp1(b01, b11, f0) - lerp1(b00, b10, f0);
-        gd[j] = go * dx * g.inv_h[0] * axis_free(u0, g.n[0]);
-        gd[N + j] = go * dy * g.inv_h[1] * axis_free(u1, g.n[1]);
-        gd[2 * N + j] = go * dz * g.inv_h[2] * axis_free(u2, g.n[2]);
+        gd[j] = go * dx * g.inv_h[0] * disp_free(ix, t0, g.n[0]);
+        gd[N + j] = go * dy * g.inv_h[1] * disp_free(iy, t1, g.n[1]);
+        gd[2 * N + j] = go * dz * g.inv_h[2] * disp_free(iz, t2, g.n[2]);
         if (go == 0.0f) continue;
         const float w0[2] = {1.0f - f0, f0}, w1[2] = {1.0f - f1, f1}, w2[2] = {1.0f - f2, f2};
 #pragma unroll
@@ -77,7 +79,8 @@ __global__ __launch_bounds__(256) void k_warp_bwd(const float *__restrict__ ref,
             for (int b = 0; b < 2; ++b)
 #pragma unroll
                 for (int c = 0; c < 2; ++c)
-                    unsafeAtomicAdd(&g_ref[base + a * s0 + b * s1 + c], go * w0[a] * w1[b] * w2[c]);
+                    fix_add(&fix[base + a * s0 + b * s1 + c], (double)(go * w0[a] * w1[b] * w2[c]),
+                            fscale);
     }
 }
 
@@ -91,16 +94,27 @@ hipError_t launch_warp(const float *ref, const GridK &g, const float *dvf, int V
     return hipGetLastError();
 }
 
+// Workspace: the 64-bit fixed-point g_ref, then the largest |g_out|.
+size_t warp_bwd_workspace(const GridK &g) {
+    return align256(sizeof(long long) * (size_t)grid_size(g)) + align256(sizeof(uint32_t));
+}
+
 hipError_t launch_warp_bwd(const float *ref, const GridK &g, const float *dvf, int V,
-                           const float *g_out, float *g_ref, float *g_dvf, hipStream_t s) {
+                           const float *g_out, float *g_ref, float *g_dvf, void *ws,
+                           hipStream_t s) {
     const int64_t N = grid_size(g);
-    hipError_t e = launch_fill(g_ref, N, 0.0f, s);
+    long long *fix = (long long *)ws;
+    uint32_t *gmax = (uint32_t *)((char *)ws + align256(sizeof(long long) * (size_t)N));
+    hipError_t e = launch_fill_i32((int32_t *)fix, 2 * N, 0, s);
     if (e != hipSuccess) return e;
+    if ((e = launch_absmax(g_out, N * V, gmax, s)) != hipSuccess) return e;
     {
         ProfScope prof_("warp_bwd", s);
-        k_warp_bwd<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(ref, g, dvf, V, g_out, g_ref, g_dvf);
+        k_warp_bwd<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(ref, g, dvf, V, g_out, gmax, fix,
+                                                                g_dvf);
     }
-    return hipGetLastError();
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return launch_fix_to_float(fix, N, gmax, false, g_ref, s);
 }
 
 }  // namespace pmf

@@ -99,7 +99,7 @@ class MotionModel:
     def forward_plain(self, ref=None, bases=None):
         if ref is None:
             ref, bases = self.volumes()
-        proj = torch.empty((self.V, self.cone.nv, self.cone.nu), device=self.device)
+        proj = ops._empty((self.V, self.cone.nv, self.cone.nu), self.device)
         for v in range(self.V):
             dvf = ops.pmf_combine_dvf(bases, self.levels, self.coeff[v:v + 1], self.grid)
             wv = ops.pmf_warp(ref, self.grid, dvf)
@@ -117,7 +117,7 @@ class MotionModel:
     def step_plain(self, target):
         """One iteration, one view at a time (per-view DVFs kept for the backward)."""
         ref, bases = self.volumes()
-        proj = torch.empty((self.V, self.cone.nv, self.cone.nu), device=self.device)
+        proj = ops._empty((self.V, self.cone.nv, self.cone.nu), self.device)
         dvfs = []
         for v in range(self.V):
             dvf = ops.pmf_combine_dvf(bases, self.levels, self.coeff[v:v + 1], self.grid)
@@ -127,7 +127,7 @@ class MotionModel:
             dvfs.append(dvf)
         loss, g_proj = ops.pmf_l2_loss(proj, target)
         g_ref, g_bases = None, None
-        g_coeff = torch.empty_like(self.coeff)
+        g_coeff = ops._empty_like(self.coeff)
         for v in reversed(range(self.V)):
             g_wv = ops.pmf_project_bwd(g_proj[v:v + 1], self.grid, self.cone, self.angles[v:v + 1])
             gr, gd = ops.pmf_warp_bwd(ref, self.grid, dvfs[v], g_wv)
@@ -215,7 +215,7 @@ class Stage1Model:
                                       g_proj, ws=self._rws, binned=True)
         sg = sub_grid(self.grid, corner, D)
         sub = ops.pmf_voxelize(g.mean, g.scale, g.quat, g.value, sg, self.k)
-        g_sub = torch.zeros_like(sub)
+        g_sub = ops.pmf_fill(ops._empty_like(sub), 0.0)
         l_tv = ops.pmf_tv_loss(sub, sg, (0, 0, 0), D, lam_tv, g_vol=g_sub)
         tv = ops.pmf_voxelize_bwd(g.mean, g.scale, g.quat, g.value, sg, self.k, g_sub)
         for a, b in zip(grads, tv):
@@ -277,38 +277,48 @@ def _copy(dst, src):
 
 
 class GraphStep:
-    """A batched iteration captured once into a HIP graph and replayed.
+    """A batched iteration recorded once into a HIP graph by the library
+    (pmf_graph_capture) and replayed (pmf_graph_replay).
 
     ``model`` is a MotionModel (target: one tensor) or a MultiScanModel
-    (targets: one tensor per scan).  Before each replay the new targets, and
+    (targets: one tensor per scan).  One eager warm-up step on the graph's
+    own stream sizes every workspace and allocates the step's outputs in an
+    Arena; the recording then reuses exactly those buffers, so it allocates
+    nothing and every replay writes the same tensors (``self.out``; read them
+    before the next replay).  Before each replay the new targets, and
     optionally new per-view coefficients and angles (the views drawn for this
-    iteration), are copied into the device buffers the graph reads; the loss
-    and gradients live in static tensors owned by the graph (read them before
-    the next replay).  Capture happens after one eager warm-up step so that
-    every workspace is already allocated; the library's kernels clear memory
-    with fill kernels, never with memset nodes.
+    iteration), are copied into the device buffers the graph reads.  The
+    library's kernels clear memory with fill kernels, never memset nodes
+    (pmf_graph_capture refuses a recording with one).
     """
 
     def __init__(self, model, target, step=None):
-        """step(target) is the iteration to capture (model.step_batched by
+        """step(target) is the iteration to record (model.step_batched by
         default, e.g. a closure over model.step_batched_paper)."""
         self.model = model
         self.target = _clone(target)
         fn = model.step_batched if step is None else step
         was = ops.pmf_profile(False)
-        s = torch.cuda.Stream()
-        s.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(s):
-            fn(self.target)                          # warm-up: allocate workspaces
-        torch.cuda.current_stream().wait_stream(s)
-        torch.cuda.synchronize()
-        self.graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(self.graph):
-            self.out = fn(self.target)
-        torch.cuda.synchronize()
-        # the graph holds raw pointers into the scratch buffers: keep them alive
-        self._scratch = dict(ops._ws_cache)
-        ops.pmf_profile(was)
+        try:
+            self.stream = torch.cuda.Stream()
+            self.stream.wait_stream(torch.cuda.current_stream())
+            self.arena = ops.Arena()
+            with torch.cuda.stream(self.stream), ops.use_arena(self.arena):
+                fn(self.target)                      # warm-up: outputs and workspaces
+            self.arena.freeze()
+            self.stream.synchronize()
+            res = {}
+
+            def record():
+                with ops.use_arena(self.arena):
+                    res["out"] = fn(self.target)
+
+            self.graph = ops.Graph(record, self.stream)
+            self.out = res["out"]
+            # the graph holds raw pointers into the scratch buffers: keep them alive
+            self._scratch = dict(ops._ws_cache)
+        finally:
+            ops.pmf_profile(was)
 
     def _models(self):
         return self.model.models if isinstance(self.model, MultiScanModel) else [self.model]
@@ -325,5 +335,8 @@ class GraphStep:
         if angles is not None:
             for m, a in zip(ms, angles if len(ms) > 1 else [angles]):
                 m.angles.copy_(a)
+        cur = torch.cuda.current_stream()
+        self.stream.wait_stream(cur)
         self.graph.replay()
+        cur.wait_stream(self.stream)
         return self.out

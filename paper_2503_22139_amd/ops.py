@@ -6,7 +6,7 @@ pointers are handed to the library together with torch's current stream.
 Nothing is computed in Python: if the library is missing this module raises.
 
 Autograd wrappers (``Voxelize``, ``CombineDVF``, ``Warp``, ``Project``,
-``WarpProject``) call the forward entry point in ``forward`` and the adjoint
+``WarpProject``, ``L2Loss``) call the forward entry point in ``forward`` and the adjoint
 entry point in ``backward``; they save inputs only, never intermediate
 volumes (``WarpProject`` recomputes every view's DVF in its backward).
 """
@@ -81,7 +81,8 @@ _SIGS = {
     "pmf_combine_dvf_bwd": ([C.c_int, C.c_int, _P, C.POINTER(PmfGrid), _P, C.c_int,
                              C.POINTER(PmfGrid), _P, _P, _P, _P, _SZ, _P], C.c_int),
     "pmf_warp": ([_P, C.POINTER(PmfGrid), _P, C.c_int, _P, _P], C.c_int),
-    "pmf_warp_bwd": ([_P, C.POINTER(PmfGrid), _P, C.c_int, _P, _P, _P, _P], C.c_int),
+    "pmf_warp_bwd_workspace": ([C.POINTER(PmfGrid)], _SZ),
+    "pmf_warp_bwd": ([_P, C.POINTER(PmfGrid), _P, C.c_int, _P, _P, _P, _P, _SZ, _P], C.c_int),
     "pmf_project": ([_P, C.c_int64, C.POINTER(PmfGrid), C.POINTER(PmfCone), _P, C.c_int, _P, _P],
                     C.c_int),
     "pmf_project_bwd_workspace": ([C.POINTER(PmfCone), C.c_int], _SZ),
@@ -122,6 +123,13 @@ _SIGS = {
                                    C.c_int),
     "pmf_autotune_project": ([_P, C.POINTER(PmfGrid), C.POINTER(PmfCone), _P, C.c_int, _P, _P, _P,
                               _P, _SZ, C.c_int, C.POINTER(C.c_float), _P], C.c_int),
+    "pmf_autotune": ([C.c_char_p, _P, C.POINTER(PmfGrid), C.POINTER(PmfCone), _P, C.c_int, _P, _P, _P,
+                      _P, _SZ, C.c_int, C.POINTER(C.c_float), C.POINTER(C.c_int), _P], C.c_int),
+    "pmf_graph_capture": ([_P, _P, _P, C.POINTER(C.c_void_p)], C.c_int),
+    "pmf_graph_replay": ([_P, _P], C.c_int),
+    "pmf_graph_kernel_count": ([_P], C.c_int64),
+    "pmf_graph_destroy": ([_P], C.c_int),
+    "pmf_fill": ([_P, C.c_int64, C.c_float, _P], C.c_int),
     "pmf_tune_candidates": ([C.c_int], C.c_int),
     "pmf_tune_get": ([C.c_int], C.c_int),
     "pmf_tune_set": ([C.c_int, C.c_int], C.c_int),
@@ -193,6 +201,72 @@ def _stream():
 _ws_cache = {}
 
 
+class Arena:
+    """The output buffers of a fixed sequence of library calls.
+
+    While an arena is active (``use_arena``), every tensor the binding would
+    allocate for a call's outputs comes from it: the first pass over the
+    sequence allocates them in call order, and after ``freeze()`` each later
+    pass gets the same tensors back in the same order (shapes are checked).
+    A step replayed from a graph thus reads and writes fixed buffers, and
+    recording it allocates nothing."""
+
+    def __init__(self):
+        self.bufs: List[torch.Tensor] = []
+        self.frozen = False
+        self.pos = 0
+
+    def freeze(self):
+        self.frozen = True
+
+    def take(self, shape, device, dtype):
+        shape = tuple(int(x) for x in shape)
+        if not self.frozen:
+            t = torch.empty(shape, device=device, dtype=dtype)
+            self.bufs.append(t)
+            return t
+        if self.pos >= len(self.bufs):
+            raise RuntimeError("arena: more outputs than in the first pass")
+        t = self.bufs[self.pos]
+        if tuple(t.shape) != shape or t.dtype != dtype or t.device != torch.device(device):
+            raise RuntimeError(f"arena: output {self.pos} is {tuple(t.shape)}, asked for {shape}")
+        self.pos += 1
+        return t
+
+
+_arena: Optional[Arena] = None
+
+
+class use_arena:
+    """Context manager: the binding's outputs come from `arena` (from its
+    first buffer on)."""
+
+    def __init__(self, arena: Arena):
+        self.arena = arena
+
+    def __enter__(self):
+        global _arena
+        self.prev = _arena
+        self.arena.pos = 0
+        _arena = self.arena
+        return self.arena
+
+    def __exit__(self, *exc):
+        global _arena
+        _arena = self.prev
+        return False
+
+
+def _empty(shape, device, dtype=torch.float32) -> torch.Tensor:
+    if _arena is not None:
+        return _arena.take(shape, device, dtype)
+    return torch.empty(tuple(shape), device=device, dtype=dtype)
+
+
+def _empty_like(t: torch.Tensor) -> torch.Tensor:
+    return _empty(t.shape, t.device, t.dtype)
+
+
 def workspace(nbytes: int, device) -> torch.Tensor:
     """A reusable device scratch buffer of at least nbytes (grown on demand),
     one per device and stream, so calls on different streams never share it."""
@@ -227,7 +301,7 @@ def pmf_version() -> int:
 def pmf_voxelize(mean, scale, quat, value, grid: Grid, trunc_k: float = 3.0, out=None):
     c = value.shape[1]
     if out is None:
-        out = torch.empty((c,) + tuple(grid.n), device=mean.device, dtype=torch.float32)
+        out = _empty((c,) + tuple(grid.n), mean.device)
     g = make_grid(grid)
     nbytes = lib().pmf_voxelize_workspace(mean.shape[0], c, C.byref(g))
     ws = workspace(nbytes, mean.device)
@@ -238,8 +312,8 @@ def pmf_voxelize(mean, scale, quat, value, grid: Grid, trunc_k: float = 3.0, out
 
 
 def pmf_voxelize_bwd(mean, scale, quat, value, grid: Grid, trunc_k: float, g_vol):
-    gm, gsc, gq, gv = (torch.empty_like(mean), torch.empty_like(scale), torch.empty_like(quat),
-                       torch.empty_like(value))
+    gm, gsc, gq, gv = (_empty_like(mean), _empty_like(scale), _empty_like(quat),
+                       _empty_like(value))
     g = make_grid(grid)
     gs = _gauss(mean, scale, quat, value)
     gr = PmfGaussGrad(_ptr(gm), _ptr(gsc), _ptr(gq), _ptr(gv))
@@ -251,7 +325,7 @@ def pmf_voxelize_bwd(mean, scale, quat, value, grid: Grid, trunc_k: float, g_vol
 def pmf_combine_dvf(bases: Sequence[torch.Tensor], levels: Sequence[Grid], coeff, grid: Grid, out=None):
     V, L, B, _ = coeff.shape
     if out is None:
-        out = torch.empty((V, 3) + tuple(grid.n), device=coeff.device, dtype=torch.float32)
+        out = _empty((V, 3) + tuple(grid.n), coeff.device)
     lv = _levels(levels)
     og = make_grid(grid)
     _check(lib().pmf_combine_dvf(L, B, _ptr_array(bases), lv, _ptr(coeff), V, C.byref(og), _ptr(out),
@@ -263,8 +337,8 @@ def pmf_combine_dvf_bwd(bases, levels, coeff, grid: Grid, g_dvf, g_coeff_out=Non
     V, L, B, _ = coeff.shape
     lv = _levels(levels)
     og = make_grid(grid)
-    g_bases = [torch.empty_like(b) for b in bases]
-    g_coeff = torch.empty_like(coeff) if g_coeff_out is None else g_coeff_out
+    g_bases = [_empty_like(b) for b in bases]
+    g_coeff = _empty_like(coeff) if g_coeff_out is None else g_coeff_out
     nbytes = lib().pmf_combine_dvf_bwd_workspace(L, B, lv, V, C.byref(og))
     ws = workspace(nbytes, coeff.device)
     _check(lib().pmf_combine_dvf_bwd(L, B, _ptr_array(bases), lv, _ptr(coeff), V, C.byref(og),
@@ -276,7 +350,7 @@ def pmf_combine_dvf_bwd(bases, levels, coeff, grid: Grid, g_dvf, g_coeff_out=Non
 def pmf_warp(ref, grid: Grid, dvf, out=None):
     V = dvf.shape[0]
     if out is None:
-        out = torch.empty((V,) + tuple(grid.n), device=ref.device, dtype=torch.float32)
+        out = _empty((V,) + tuple(grid.n), ref.device)
     g = make_grid(grid)
     _check(lib().pmf_warp(_ptr(ref), C.byref(g), _ptr(dvf), V, _ptr(out), _stream()))
     return out
@@ -284,11 +358,13 @@ def pmf_warp(ref, grid: Grid, dvf, out=None):
 
 def pmf_warp_bwd(ref, grid: Grid, dvf, g_out):
     V = dvf.shape[0]
-    g_ref = torch.empty_like(ref)
-    g_dvf = torch.empty_like(dvf)
+    g_ref = _empty_like(ref)
+    g_dvf = _empty_like(dvf)
     g = make_grid(grid)
+    ws = workspace(lib().pmf_warp_bwd_workspace(C.byref(g)), ref.device)
     _check(lib().pmf_warp_bwd(_ptr(ref), C.byref(g), _ptr(dvf), V, _ptr(g_out.contiguous()),
-                              _ptr(g_ref), _ptr(g_dvf), _stream()))
+                              _ptr(g_ref), _ptr(g_dvf), C.c_void_p(ws.data_ptr()), ws.numel(),
+                              _stream()))
     return g_ref, g_dvf
 
 
@@ -299,7 +375,7 @@ def pmf_project(vol, grid: Grid, cone: Cone, angles, shared: Optional[bool] = No
         shared = vol.numel() == N
     stride = 0 if shared else N
     if out is None:
-        out = torch.empty((V, cone.nv, cone.nu), device=vol.device, dtype=torch.float32)
+        out = _empty((V, cone.nv, cone.nu), vol.device)
     g = make_grid(grid)
     cn = make_cone(cone)
     _check(lib().pmf_project(_ptr(vol), stride, C.byref(g), C.byref(cn), _ptr(angles), V, _ptr(out),
@@ -312,7 +388,7 @@ def pmf_project_bwd(g_proj, grid: Grid, cone: Cone, angles, shared: bool = False
     N = grid.size
     if out is None:
         shape = tuple(grid.n) if shared else (V,) + tuple(grid.n)
-        out = torch.empty(shape, device=g_proj.device, dtype=torch.float32)
+        out = _empty(shape, g_proj.device)
     g = make_grid(grid)
     cn = make_cone(cone)
     nbytes = lib().pmf_project_bwd_workspace(C.byref(cn), V)
@@ -326,8 +402,8 @@ def pmf_project_bwd(g_proj, grid: Grid, cone: Cone, angles, shared: bool = False
 def pmf_l2_loss(proj, target, want_grad: bool = True):
     V = proj.shape[0]
     npix = proj[0].numel()
-    loss = torch.empty((), device=proj.device, dtype=torch.float32)
-    g = torch.empty_like(proj) if want_grad else None
+    loss = _empty((), proj.device)
+    g = _empty_like(proj) if want_grad else None
     nbytes = lib().pmf_l2_loss_workspace(npix, V)
     ws = workspace(nbytes, proj.device)
     _check(lib().pmf_l2_loss(_ptr(proj), _ptr(target), npix, V, _ptr(loss), _ptr(g),
@@ -339,7 +415,7 @@ def pmf_fdk(proj, cone: Cone, angles, grid: Grid, out=None):
     """FDK reconstruction of a full-circle scan proj [V][nv][nu] onto grid."""
     V = proj.shape[0]
     if out is None:
-        out = torch.empty(tuple(grid.n), device=proj.device, dtype=torch.float32)
+        out = _empty(tuple(grid.n), proj.device)
     c = make_cone(cone)
     g = make_grid(grid)
     ws = workspace(lib().pmf_fdk_workspace(C.byref(c), V), proj.device)
@@ -363,10 +439,10 @@ def pmf_grid_init(vol, grid: Grid, m, scale: float):
     2.3.2): (mean [M][3], scale [M][3], quat [M][4], value [M][1])."""
     M = int(m[0]) * int(m[1]) * int(m[2])
     dev = vol.device
-    mean = torch.empty((M, 3), device=dev, dtype=torch.float32)
-    sc = torch.empty((M, 3), device=dev, dtype=torch.float32)
-    quat = torch.empty((M, 4), device=dev, dtype=torch.float32)
-    val = torch.empty((M, 1), device=dev, dtype=torch.float32)
+    mean = _empty((M, 3), dev)
+    sc = _empty((M, 3), dev)
+    quat = _empty((M, 4), dev)
+    val = _empty((M, 1), dev)
     g = make_grid(grid)
     mm = (C.c_int * 3)(*[int(x) for x in m])
     _check(lib().pmf_grid_init(_ptr(vol), C.byref(g), mm, float(scale), _ptr(mean), _ptr(sc),
@@ -388,7 +464,7 @@ def pmf_rasterize(mean, scale, quat, value, cone: Cone, angles, trunc_k: float =
     pmf_rasterize_bwd(..., ws=ws, binned=True) reuses."""
     V = angles.numel()
     if out is None:
-        out = torch.empty((V, cone.nv, cone.nu), device=mean.device, dtype=torch.float32)
+        out = _empty((V, cone.nv, cone.nu), mean.device)
     c = make_cone(cone)
     gs = _gauss(mean, scale, quat, value)
     if ws is None:
@@ -404,8 +480,8 @@ def pmf_rasterize_bwd(mean, scale, quat, value, cone: Cone, angles, trunc_k: flo
     binned=True reuses the binning that pmf_rasterize left in ws (same
     inputs, nothing written to ws since)."""
     V = angles.numel()
-    gm, gsc, gq, gv = (torch.empty_like(mean), torch.empty_like(scale), torch.empty_like(quat),
-                       torch.empty_like(value))
+    gm, gsc, gq, gv = (_empty_like(mean), _empty_like(scale), _empty_like(quat),
+                       _empty_like(value))
     c = make_cone(cone)
     gs = _gauss(mean, scale, quat, value)
     gr = PmfGaussGrad(_ptr(gm), _ptr(gsc), _ptr(gq), _ptr(gv))
@@ -422,8 +498,8 @@ def pmf_rasterize_bwd(mean, scale, quat, value, cone: Cone, angles, trunc_k: flo
 def pmf_l1_dssim_loss(proj, target, lambda_ssim: float = 0.25, want_grad: bool = True):
     """L1 + lambda_ssim * D-SSIM of a batch of views (Eq. 10 / 12): (loss, g_proj)."""
     V, nv, nu = proj.shape
-    loss = torch.empty((), device=proj.device, dtype=torch.float32)
-    g = torch.empty_like(proj) if want_grad else None
+    loss = _empty((), proj.device)
+    g = _empty_like(proj) if want_grad else None
     nbytes = lib().pmf_l1_dssim_loss_workspace(nu, nv, V)
     ws = workspace(nbytes, proj.device)
     _check(lib().pmf_l1_dssim_loss(_ptr(proj), _ptr(target), nu, nv, V, float(lambda_ssim),
@@ -436,7 +512,7 @@ def pmf_tv_loss_noalloc(vol, grid: Grid, corner, D: int, weight: float, g_vol=No
     """pmf_tv_loss without a workspace (the library's static scratch; D <=
     TV_NOALLOC_MAX_D).  loss: an optional preallocated device scalar."""
     if loss is None:
-        loss = torch.empty((), device=vol.device, dtype=torch.float32)
+        loss = _empty((), vol.device)
     g = make_grid(grid)
     c = (C.c_int32 * 3)(*[int(x) for x in corner])
     _check(lib().pmf_tv_loss_noalloc(_ptr(vol), C.byref(g), c, int(D), float(weight), _ptr(loss),
@@ -450,7 +526,7 @@ TV_NOALLOC_MAX_D = 128
 def pmf_tv_loss(vol, grid: Grid, corner, D: int, weight: float, g_vol=None):
     """weight * TV of the D^3 block of vol at corner (Eq. 11); adds
     weight * d TV / d vol into g_vol when given.  Returns the loss."""
-    loss = torch.empty((), device=vol.device, dtype=torch.float32)
+    loss = _empty((), vol.device)
     g = make_grid(grid)
     c = (C.c_int32 * 3)(*[int(x) for x in corner])
     nbytes = lib().pmf_tv_loss_workspace(int(D))
@@ -465,7 +541,7 @@ def pmf_mbc_normality_loss(bases, levels, weight: float, g_bases=None):
     adds weight * d loss / d E into g_bases when given.  Returns the loss."""
     L = len(bases)
     Cc = bases[0].shape[0]
-    loss = torch.empty((), device=bases[0].device, dtype=torch.float32)
+    loss = _empty((), bases[0].device)
     lv = _levels(levels)
     nbytes = lib().pmf_mbc_normality_loss_workspace(L, Cc)
     ws = workspace(nbytes, bases[0].device)
@@ -534,8 +610,8 @@ def pmf_autotune_project(vol, grid: Grid, cone: Cone, angles, g_proj, reps: int 
     V = int(angles.numel())
     g = make_grid(grid)
     cn = make_cone(cone)
-    proj = torch.empty((V, cone.nv, cone.nu), device=vol.device, dtype=torch.float32)
-    g_vol = torch.empty_like(vol)
+    proj = _empty((V, cone.nv, cone.nu), vol.device)
+    g_vol = _empty_like(vol)
     nbytes = lib().pmf_project_bwd_workspace(C.byref(cn), V)
     ws = workspace(nbytes, vol.device)
     nt = pmf_tune_candidates(PMF_TUNE_PROJECT_TILE)
@@ -550,10 +626,101 @@ def pmf_autotune_project(vol, grid: Grid, cone: Cone, angles, g_proj, reps: int 
             "backproject_brick_ms": [float(x) for x in ms[nt:]]}
 
 
+def pmf_autotune(cache_path: Optional[str], vol, grid: Grid, cone: Cone, angles, g_proj,
+                 reps: int = 3):
+    """pmf_autotune_project behind the library's shape cache at cache_path
+    (None: no cache).  Returns the chosen shapes, whether they came from the
+    cache, and the candidates' timings when they were measured."""
+    V = int(angles.numel())
+    g = make_grid(grid)
+    cn = make_cone(cone)
+    proj = _empty((V, cone.nv, cone.nu), vol.device)
+    g_vol = _empty_like(vol)
+    nbytes = lib().pmf_project_bwd_workspace(C.byref(cn), V)
+    ws = workspace(nbytes, vol.device)
+    nt = pmf_tune_candidates(PMF_TUNE_PROJECT_TILE)
+    nb = pmf_tune_candidates(PMF_TUNE_BACKPROJECT_BRICK)
+    ms = (C.c_float * (nt + nb))(*([-1.0] * (nt + nb)))
+    hit = C.c_int(0)
+    path = None if cache_path is None else os.fsencode(cache_path)
+    _check(lib().pmf_autotune(path, _ptr(vol), C.byref(g), C.byref(cn), _ptr(angles), V, _ptr(proj),
+                              _ptr(g_proj.contiguous()), _ptr(g_vol), C.c_void_p(ws.data_ptr()),
+                              ws.numel(), reps, ms, C.byref(hit), _stream()))
+    return {"project_tile": pmf_tune_get(PMF_TUNE_PROJECT_TILE),
+            "backproject_brick": pmf_tune_get(PMF_TUNE_BACKPROJECT_BRICK),
+            "cached": bool(hit.value),
+            "project_tile_ms": [float(x) for x in ms[:nt]],
+            "backproject_brick_ms": [float(x) for x in ms[nt:]]}
+
+
+def pmf_fill(dst, value: float):
+    """dst[:] = value, in the library (a fill kernel, never a memset)."""
+    _check(lib().pmf_fill(_ptr(dst), dst.numel(), float(value), _stream()))
+    return dst
+
+
+RECORD_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_void_p)
+
+
+class Graph:
+    """The library calls that ``record()`` makes, captured once by
+    pmf_graph_capture on ``stream`` (a torch stream; the current one by
+    default) and replayed with pmf_graph_replay.  ``record`` runs with that
+    stream current and must not allocate device memory (outputs from an
+    Arena, workspaces sized beforehand): the capture checks torch's
+    allocation counter and refuses a recording that allocated."""
+
+    def __init__(self, record, stream=None):
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        err = []
+
+        def cb(user, sptr):
+            try:
+                with torch.cuda.stream(self.stream):
+                    record()
+                return PMF_OK
+            except Exception as e:          # re-raised once the capture has ended
+                err.append(e)
+                return PMF_EINVAL
+
+        dev = self.stream.device
+        before = torch.cuda.memory_stats(dev).get("allocation.all.allocated", 0)
+        self._fn = RECORD_FN(cb)
+        h = C.c_void_p()
+        rc = lib().pmf_graph_capture(C.c_void_p(self.stream.cuda_stream), self._fn, None,
+                                     C.byref(h))
+        self._h = h if rc == PMF_OK else None
+        if err:
+            raise err[0]
+        _check(rc)
+        after = torch.cuda.memory_stats(dev).get("allocation.all.allocated", 0)
+        if after != before:
+            self.close()
+            raise RuntimeError("the recorded calls allocated device memory")
+
+    def replay(self, stream=None):
+        s = self.stream if stream is None else stream
+        _check(lib().pmf_graph_replay(self._h, C.c_void_p(s.cuda_stream)))
+
+    def kernel_count(self) -> int:
+        return int(lib().pmf_graph_kernel_count(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _check(lib().pmf_graph_destroy(self._h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def pmf_warp_project(ref, grid: Grid, bases, levels, coeff, cone: Cone, angles, out=None):
     V, L, B, _ = coeff.shape
     if out is None:
-        out = torch.empty((V, cone.nv, cone.nu), device=ref.device, dtype=torch.float32)
+        out = _empty((V, cone.nv, cone.nu), ref.device)
     g = make_grid(grid)
     lv = _levels(levels)
     cn = make_cone(cone)
@@ -570,9 +737,9 @@ def pmf_warp_project_bwd(ref, grid: Grid, bases, levels, coeff, cone: Cone, angl
     g = make_grid(grid)
     lv = _levels(levels)
     cn = make_cone(cone)
-    g_ref = torch.empty_like(ref)
-    g_bases = [torch.empty_like(b) for b in bases]
-    g_coeff = torch.empty_like(coeff)
+    g_ref = _empty_like(ref)
+    g_bases = [_empty_like(b) for b in bases]
+    g_coeff = _empty_like(coeff)
     nbytes = lib().pmf_warp_project_bwd_workspace(L, B, lv, V, C.byref(g), C.byref(cn))
     ws = workspace(nbytes, ref.device)
     _check(lib().pmf_warp_project_bwd(_ptr(ref), C.byref(g), L, B, _ptr_array(bases), lv,
@@ -613,8 +780,7 @@ def pmf_warp_project_scans(scans):
     L, B = int(scans[0]["coeff"].shape[1]), int(scans[0]["coeff"].shape[2])
     dev = scans[0]["ref"].device
     for sc in scans:
-        sc["proj"] = torch.empty((sc["coeff"].shape[0], sc["cone"].nv, sc["cone"].nu), device=dev,
-                                 dtype=torch.float32)
+        sc["proj"] = _empty((sc["coeff"].shape[0], sc["cone"].nv, sc["cone"].nu), dev)
     arr = _scan_array(scans)
     nbytes = lib().pmf_warp_project_scans_workspace(L, B, arr, len(scans))
     ws = workspace(nbytes, dev)
@@ -630,9 +796,9 @@ def pmf_warp_project_bwd_scans(scans):
     dev = scans[0]["ref"].device
     for sc in scans:
         sc["g_proj"] = sc["g_proj"].contiguous()
-        sc["g_ref"] = torch.empty_like(sc["ref"])
-        sc["g_bases"] = [torch.empty_like(b) for b in sc["bases"]]
-        sc["g_coeff"] = torch.empty_like(sc["coeff"])
+        sc["g_ref"] = _empty_like(sc["ref"])
+        sc["g_bases"] = [_empty_like(b) for b in sc["bases"]]
+        sc["g_coeff"] = _empty_like(sc["coeff"])
     arr = _scan_array(scans)
     nbytes = lib().pmf_warp_project_bwd_scans_workspace(L, B, arr, len(scans))
     ws = workspace(nbytes, dev)
@@ -708,6 +874,23 @@ class Project(torch.autograd.Function):
         (angles,) = ctx.saved_tensors
         gv = pmf_project_bwd(g.contiguous(), ctx.grid, ctx.cone, angles, shared=ctx.shared)
         return gv.reshape(ctx.shape), None, None, None
+
+
+class L2Loss(torch.autograd.Function):
+    """The L2 projection loss (1/V) sum (proj - target)^2 (pmf_l2_loss); the
+    target gets no gradient.  The gradient pmf_l2_loss writes is scaled by the
+    incoming scalar gradient (autograd glue)."""
+
+    @staticmethod
+    def forward(ctx, proj, target):
+        loss, g = pmf_l2_loss(proj.contiguous(), target.contiguous())
+        ctx.save_for_backward(g)
+        return loss
+
+    @staticmethod
+    def backward(ctx, gl):
+        (g,) = ctx.saved_tensors
+        return g * gl, None
 
 
 class WarpProject(torch.autograd.Function):

@@ -115,7 +115,12 @@ def test_combine_and_warp_reject_bad_arguments(lib):
     assert lib.pmf_combine_dvf(2, 1, bases, lv, p, 0, C.byref(g), p, None) == ops.PMF_EINVAL
     assert lib.pmf_warp(p, C.byref(g), p, 0, p, None) == ops.PMF_EINVAL
     assert lib.pmf_warp(None, C.byref(g), p, 1, p, None) == ops.PMF_EINVAL
-    assert lib.pmf_warp_bwd(p, C.byref(g), p, 1, p, None, p, None) == ops.PMF_EINVAL
+    big = 1 << 40
+    assert lib.pmf_warp_bwd(p, C.byref(g), p, 1, p, None, p, p, big, None) == ops.PMF_EINVAL
+    assert lib.pmf_warp_bwd(p, C.byref(g), p, 0, p, p, p, p, big, None) == ops.PMF_EINVAL
+    need = lib.pmf_warp_bwd_workspace(C.byref(g))
+    assert need >= 8 * 8 * 8 * 8
+    assert lib.pmf_warp_bwd(p, C.byref(g), p, 1, p, p, p, p, need - 1, None) == ops.PMF_EWORKSPACE
     assert lib.pmf_l2_loss(p, p, 0, 1, p, p, p, 1 << 20, None) == ops.PMF_EINVAL
     assert lib.pmf_accumulate(None, p, 5, None) == ops.PMF_EINVAL
     assert lib.pmf_combine_dvf_bwd_workspace(2, 3, lv, 4, C.byref(g)) > 0
@@ -305,3 +310,34 @@ def test_grid_init_rejects_bad_arguments(lib):
     assert lib.pmf_grid_init(p, C.byref(g), m(4, 4, 4), 1.0, p, None, p, p, None) == ops.PMF_EINVAL
     assert lib.pmf_grid_init(None, C.byref(g), m(4, 4, 4), 1.0, p, p, p, p, None) == ops.PMF_EINVAL
     assert ops.grid_init_lattice(Grid((256, 256, 128), (1.5, 1.5, 2.0)), 50_000)[0] == (42, 42, 28)
+
+
+def test_graph_fill_and_autotune_reject_bad_arguments(lib):
+    p = C.c_void_p(16)
+    out = C.c_void_p()
+    rec = ops.RECORD_FN(lambda u, s: 0)
+    # no graph output, legacy default stream, no record function
+    assert lib.pmf_graph_capture(p, rec, None, None) == ops.PMF_EINVAL
+    assert lib.pmf_graph_capture(None, rec, None, C.byref(out)) == ops.PMF_EINVAL
+    assert "default stream" in err(lib)
+    assert lib.pmf_graph_capture(p, None, None, C.byref(out)) == ops.PMF_EINVAL
+    assert out.value is None
+    assert lib.pmf_graph_replay(None, p) == ops.PMF_EINVAL
+    assert lib.pmf_graph_kernel_count(None) == -1
+    assert lib.pmf_graph_destroy(None) == ops.PMF_OK
+    assert lib.pmf_fill(None, 4, 0.0, None) == ops.PMF_EINVAL
+    assert lib.pmf_fill(p, -1, 0.0, None) == ops.PMF_EINVAL
+    g = grid()
+    cn = ops.make_cone(Cone(1000.0, 1500.0, 8, 8, 1.0, 1.0))
+    big = 1 << 40
+    hit = C.c_int(7)
+    ms = (C.c_float * 15)()
+    assert lib.pmf_autotune(b"/nonexistent/x", p, C.byref(g), C.byref(cn), p, 0, p, p, p, p, big,
+                            1, ms, C.byref(hit), None) == ops.PMF_EINVAL
+    assert lib.pmf_autotune(None, p, C.byref(g), C.byref(cn), p, 2, p, p, p, p, big, 0, ms,
+                            C.byref(hit), None) == ops.PMF_EINVAL
+    assert lib.pmf_autotune(None, None, C.byref(g), C.byref(cn), p, 2, p, p, p, p, big, 1, ms,
+                            C.byref(hit), None) == ops.PMF_EINVAL
+    assert lib.pmf_autotune(None, p, C.byref(g), C.byref(cn), p, 2, p, p, p, p, 0, 1, ms,
+                            C.byref(hit), None) == ops.PMF_EWORKSPACE
+    assert hit.value == 7          # rejected before anything was looked up

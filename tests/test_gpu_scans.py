@@ -152,18 +152,18 @@ def test_c5_scans_batched_equals_separate():
     res = mm.step_batched(targets)
     say("c5: separate steps")
     sep = mm.step_separate(targets)
-    # Two runs of the same call differ slightly: a few sums are float atomics
-    # in arrival order, and at this size some voxels warp to within float
-    # rounding of a cell face, where the trilinear derivative jumps, which
-    # turns those last-bit differences into up to ~1e-4 of a coefficient
-    # gradient.  Projections and the loss are compared tightly, the
-    # gradients at the gradient tolerance.
+    # Every sum of the path runs in a fixed order or in integers, and each
+    # item of the ragged launch does the arithmetic of the separate call, so
+    # the two agree to float rounding (in fact bit for bit).
     for k, ((l, g), (ls, gsp)) in enumerate(zip(res, sep)):
         assert abs(float(N(l)) - float(N(ls))) <= 1e-6 * abs(float(N(ls))), k
         r = rel(N(g["coeff"]), N(gsp["coeff"]))
-        say("c5: scan", k, "coeff rel", r)
-        assert r < GRAD_TOL, (k, r)
+        say("c5: scan", k, "coeff rel", r, "equal", np.array_equal(N(g["coeff"]), N(gsp["coeff"])))
+        assert r <= 1e-6, (k, r)
         for name in ("mean", "scale", "quat", "value"):
             r = rel(N(g["ref"][name]), N(gsp["ref"][name]))
             say("c5: scan", k, "ref", name, "rel", r)
-            assert r < GRAD_TOL, (k, name, r)
+            assert r <= 1e-6, (k, name, r)
+            for l_ in range(len(g["mbc"])):
+                r = rel(N(g["mbc"][l_][name]), N(gsp["mbc"][l_][name]))
+                assert r <= 1e-6, (k, "mbc", l_, name, r)

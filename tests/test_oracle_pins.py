@@ -486,6 +486,38 @@ def test_voxelize_points_equals_voxelize():
         assert np.abs(want).max() > 0
 
 
+def test_voxelize_band_matches_bruteforce():
+    """The mask-margin split of Eq. 5 (used to check the GPU binning where
+    pairs on the mask's edge may go either way) against brute force over
+    every pair with scipy's rotation, for a band wide enough that every class
+    holds pairs; inner + edge is the voxelizer itself."""
+    rng = np.random.default_rng(31)
+    grid = Grid((11, 9, 10), (1.0, 1.25, 1.5), (0.4, -0.3, 0.2))
+    gs = synth.gaussians(rng, 30, grid, s_vox=(0.6, 2.0), c=2, value_sigma=1.0)
+    X = np.stack(centres(grid), -1).reshape(-1, 3)
+    k, band = 3.0, 2.5
+    want = [np.zeros((2, X.shape[0])) for _ in range(4)]
+    for i in range(gs.m):
+        q = gs.quat[i].astype(np.float64)
+        R = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()
+        A = np.linalg.inv(R @ np.diag(gs.scale[i].astype(np.float64) ** 2) @ R.T)
+        d = X - gs.mean[i].astype(np.float64)
+        m = np.einsum("pa,ab,pb->p", d, A, d)
+        e = np.exp(-0.5 * m)
+        for c in range(2):
+            v = float(gs.value[i, c])
+            want[0][c] += np.where(m <= k * k - band, v * e, 0.0)
+            want[1][c] += np.where((m > k * k - band) & (m <= k * k), v * e, 0.0)
+            want[2][c] += np.where(np.abs(m - k * k) <= band, abs(v) * e, 0.0)
+            want[3][c] += np.where(m <= k * k + band, abs(v) * e, 0.0)
+    got = [g.reshape(2, -1) for g in oracle.voxelize_band(gs, grid, k, band)]
+    for a, b in zip(got, want):
+        assert np.abs(b).max() > 0
+        assert np.max(np.abs(a - b)) <= 1e-12 * np.abs(b).max()
+    full = oracle.voxelize(gs, grid, k).reshape(2, -1)
+    assert np.max(np.abs(got[0] + got[1] - full)) <= 1e-13 * np.abs(full).max()
+
+
 def test_l2_loss_and_gradient():
     rng = np.random.default_rng(28)
     p = rng.normal(size=(3, 4, 5))
