@@ -186,7 +186,7 @@ int pmf_project(const float *vol, int64_t vol_stride, const pmf_grid_t *grid,
  * g_vol_v = P_v^T g_proj[v].  vol_stride = N writes one volume per view
  * ([V][N]); vol_stride = 0 writes their sum ([N]).
  * Needs the workspace from pmf_project_bwd_workspace(). */
-size_t pmf_project_bwd_workspace(const pmf_cone_t *cone, int V);
+size_t pmf_project_bwd_workspace(const pmf_grid_t *grid, const pmf_cone_t *cone, int V);
 int pmf_project_bwd(const float *g_proj, const pmf_grid_t *grid, const pmf_cone_t *cone,
                     const float *angles, int V, float *g_vol, int64_t vol_stride, void *ws,
                     size_t ws_bytes, void *stream);
@@ -375,11 +375,16 @@ size_t pmf_profile_names(char *buf, size_t len);
  *                              3 = 2x32 in 8x32, 4 = 32x2 in 32x8,
  *                              5 = 1x64 in 4x64 (default), 6 = 2x32 in 4x64,
  *                              7 = 1x64 in 2x128, 8 = 2x32 in 2x128;
- *   PMF_TUNE_BACKPROJECT_BRICK voxel brick of the adjoint projection (axes
- *                              0 x 1 x 2) and the wavefronts sharing it:
- *                              0 = 16x16x16 x 8, 1 = 16x16x16 x 4,
- *                              2 = 32x32x4 x 8, 3 = 32x32x8 x 8,
- *                              4 = 24x24x8 x 8 (default), 5 = 8x8x8 x 4.
+ *   PMF_TUNE_BACKPROJECT_BRICK cell brick of the adjoint projection, L x W x H
+ *                              (L along the horizontal axis a view's rays
+ *                              mostly follow, H along z), 8 wavefronts, with
+ *                              consecutive samples of a ray in one cell
+ *                              summed in registers first unless noted:
+ *                              0 = 48x16x8, 1 = 48x16x8 summing each
+ *                              sample alone, 2 = 32x16x8, 3, 4 (default), 5
+ *                              = 48x16x8 walked in chunks of 2, 8, 4 bricks
+ *                              along z by one workgroup, 6 = 32x16x8 in
+ *                              chunks of 4, 7 = 32x32x8, 8 = 48x24x8.
  * pmf_tune_candidates returns the number of choices of a knob (0 for an
  * unknown knob); pmf_tune_set returns the previous choice or PMF_EINVAL for an
  * unknown knob or a choice out of range; pmf_tune_get returns the current

@@ -323,9 +323,11 @@ int pmf_project(const float *vol, int64_t vol_stride, const pmf_grid_t *grid,
                       "project");
 }
 
-size_t pmf_project_bwd_workspace(const pmf_cone_t *cone, int V) {
-    if (!cone || V < 1 || cone->nu < 1 || cone->nv < 1) return 0;
-    return project_bwd_workspace(*cone, V);
+size_t pmf_project_bwd_workspace(const pmf_grid_t *grid, const pmf_cone_t *cone, int V) {
+    if (!grid || !cone || V < 1 || cone->nu < 1 || cone->nv < 1) return 0;
+    for (int a = 0; a < 3; ++a)
+        if (grid->n[a] < 1) return 0;
+    return project_bwd_workspace(make_grid(*grid), *cone, V);
 }
 
 int pmf_project_bwd(const float *g_proj, const pmf_grid_t *grid, const pmf_cone_t *cone,
@@ -338,7 +340,7 @@ int pmf_project_bwd(const float *g_proj, const pmf_grid_t *grid, const pmf_cone_
     GridK g = make_grid(*grid);
     if (vol_stride != 0 && vol_stride < grid_size(g))
         return fail(PMF_EINVAL, "project_bwd: vol_stride must be 0 or >= N");
-    PMF_CHECK(check_ws(ws, ws_bytes, project_bwd_workspace(*cone, V)));
+    PMF_CHECK(check_ws(ws, ws_bytes, project_bwd_workspace(g, *cone, V)));
     ConeK c = make_cone(*cone, g);
     return hip_status(
         launch_project_bwd(g_proj, g, c, angles, V, g_vol, vol_stride, ws, as_stream(stream)),
@@ -606,8 +608,8 @@ int pmf_autotune_project(const float *vol, const pmf_grid_t *grid, const pmf_con
     if (reps < 1) return fail(PMF_EINVAL, "autotune: reps must be >= 1");
     if (!vol || !angles || !proj || !g_proj || !g_vol)
         return fail(PMF_EINVAL, "autotune: null pointer");
-    PMF_CHECK(check_ws(ws, ws_bytes, project_bwd_workspace(*cone, V)));
     const GridK g = make_grid(*grid);
+    PMF_CHECK(check_ws(ws, ws_bytes, project_bwd_workspace(g, *cone, V)));
     const ConeK c = make_cone(*cone, g);
     const int64_t N = grid_size(g);
     hipStream_t st = as_stream(stream);
@@ -668,7 +670,7 @@ int pmf_autotune(const char *cache_path, const float *vol, const pmf_grid_t *gri
     if (reps < 1) return fail(PMF_EINVAL, "autotune: reps must be >= 1");
     if (!vol || !angles || !proj || !g_proj || !g_vol)
         return fail(PMF_EINVAL, "autotune: null pointer");
-    PMF_CHECK(check_ws(ws, ws_bytes, project_bwd_workspace(*cone, V)));
+    PMF_CHECK(check_ws(ws, ws_bytes, project_bwd_workspace(make_grid(*grid), *cone, V)));
     if (cached) *cached = 0;
     std::string key;
     if (cache_path) {

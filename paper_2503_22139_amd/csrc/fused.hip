@@ -561,7 +561,7 @@ static BwdLayout bwd_layout(const LevelsK &lv, const GridK *lvl_grids, int V, co
     pc.nv = nv;
     const int vc = V < VCH ? V : VCH;
     b.gI = align256(sizeof(float) * (size_t)N * V);
-    b.rays = project_bwd_workspace(pc, V);
+    b.rays = project_bwd_workspace(g, pc, V);
     b.gbuf = align256(sizeof(float) * (size_t)N * 3 * lv.B * (size_t)ncoarse);
     b.partial = align256(sizeof(float) * (size_t)b.nbrick * vc * lv.L * lv.B * 3);
     b.stage = align256(sizeof(float) * (size_t)b.nbrick * HB3);

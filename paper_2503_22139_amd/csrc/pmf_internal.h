@@ -464,11 +464,11 @@ struct BwdJob {             // one scan's back-projection (all jobs per view, or
     int V;
     float *g_vol;
     int64_t stride;         // 0: sum over views into one volume
-    void *ws;               // project_bwd_workspace(c, V) bytes
+    void *ws;               // project_bwd_workspace(g, c, V) bytes
     unsigned *vmax;         // optional [V], zeroed: largest |g_vol| per view (float bits)
 };
 hipError_t launch_project_bwd_jobs(const BwdJob *jobs, int n, hipStream_t s);
-size_t project_bwd_workspace(const pmf_cone_t &c, int V);
+size_t project_bwd_workspace(const GridK &g, const pmf_cone_t &c, int V);
 // vmax (optional, [V] zeroed uint): largest |g_vol| of each view, as float bits
 hipError_t launch_project_bwd(const float *g_proj, const GridK &g, const ConeK &c,
                               const float *angles, int V, float *g_vol, int64_t stride, void *ws,

@@ -14,6 +14,8 @@
 // no sample is lost or counted twice.
 #include <math.h>
 
+#include <algorithm>
+
 #include "pmf_internal.h"
 
 namespace pmf {
@@ -342,8 +344,9 @@ __global__ __launch_bounds__(256) void k_project(ProjTab t) {
     pj.proj[((int64_t)v * c.nv + iv) * c.nu + iu] = (acc0 + acc1) * r.delta;
 }
 
-// Per-ray constants of every view, and per view the two figures that set the
-// back-projection's fixed-point scale: the largest |g_proj * delta| over the
+// Per-ray constants of every view, per view the brick orientation of the
+// back-projection, and per view the two figures that set its fixed-point
+// scale: the largest |g_proj * delta| over the
 // rays, and the smallest step over the rays with at least two samples (a ray
 // with one sample gives any voxel at most one contribution).  The grid is
 // (workgroups per view, V): a workgroup strides over the rays of one view and
@@ -352,12 +355,16 @@ __global__ __launch_bounds__(256) void k_ray_table(GridK g, ConeK c,
                                                    const float *__restrict__ angles,
                                                    const float *__restrict__ g_proj,
                                                    RayK *__restrict__ out,
-                                                   unsigned *__restrict__ stats) {
+                                                   unsigned *__restrict__ stats,
+                                                   int *__restrict__ orient) {
     __shared__ float red[8];
     const int npix = c.nu * c.nv;
     const int v = blockIdx.y;
     const double th = (double)angles[v];
     const double ct = cos(th), st = sin(th);
+    // the back-projection's brick orientation: long edge along axis 1 when
+    // the view's rays run mostly along it
+    if (blockIdx.x == 0 && threadIdx.x == 0) orient[v] = fabs(st) > fabs(ct) ? 1 : 0;
     float m = 0.0f, d = INFINITY;
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += gridDim.x * blockDim.x) {
         const RayK r = ray_setup(g, c, ct, st, p % c.nu, p / c.nu);
@@ -467,12 +474,25 @@ struct BoundK {
     float mag, persp, R, Z, two_hx, two_hy, two_hz, inv_du, inv_dv, diag;
 };
 
-// g_vol (per view, or summed over views when SUM) of one S0 x S1 x S2 brick.
+// The adjoint of the ray march, g_vol_v = P_v^T g_proj, by brick owners.
 //
-// The LDS accumulator spans the brick plus one voxel on every side, so the
-// 8 corners of every owned sample land inside it; the pad is dropped on
-// write-out (it belongs to the neighbouring bricks, which take those
-// samples themselves).
+// Ownership: the cells (i, i+1 per axis) of the grid are split into disjoint
+// bricks of S0 x S1 x S2 cells; a workgroup owns one brick of one view and
+// takes exactly the samples whose cell lies in it, so every sample is
+// scattered once.  Its 8 corner weights land in an LDS box of (S+1) voxels
+// per axis: the brick's own voxels and a one-voxel pad on the high side of
+// each axis, which belongs to the next brick.  Own voxels are stored to
+// g_vol directly.  A workgroup walks a chunk of bricks along axis 2 and
+// carries each brick's axis-2 pad layer in LDS into the next brick (those
+// voxels are contiguous in memory only along axis 2, so staging them would
+// cost a cache line per voxel); the other pads are staged per (view, brick)
+// and a fix-up pass adds them into the voxels they belong to, in a fixed
+// order.
+//
+// Shape: a brick is long (L cells) along the horizontal axis the view's rays
+// mostly follow and W cells across it (H along z), so a ray's run in one
+// brick is long and its set-up (reading its constants, finding the run) is
+// spread over many samples.  Every brick of a view has the same orientation.
 //
 // Work distribution: each wave takes 64 rays of the brick's detector shadow
 // at a time (an 8x8 grid of pixels spread over the shadow rectangle), finds
@@ -482,19 +502,24 @@ struct BoundK {
 // however the run lengths differ, and the lanes of a wave stay in different
 // rays (their LDS atomics seldom hit the same word).
 //
-// Accumulation is in 32-bit fixed point with integer LDS atomics (float LDS
-// atomics run about 30x slower on gfx950).  For each (brick, view) the scale
-// is 2^30 / (kbound * M), where M is the largest |g_proj * delta| among the
+// Accumulation is in 32-bit fixed point with integer LDS atomics, so the
+// sums do not depend on their order.  For each view the scale is
+// 2^30 / (kbound * M), where M is the largest |g_proj * delta| among the
 // view's rays and kbound bounds how many samples can touch one voxel in this
 // view (from the geometry and the smallest step of the rays with two or more
-// samples): every partial sum stays below 2^30 in magnitude, and each
-// contribution is rounded to within 0.5 / scale.  A lane adds consecutive
-// samples that fall in one cell in registers and rounds their sum once.
-// With vmax non-null the largest |g_vol| of each view is also recorded.
+// samples): every sum stays below 2^30 in magnitude, and each contribution
+// is rounded to within 0.5 / scale.  Optionally (MERGE) a lane adds
+// consecutive samples that fall in one cell in registers and rounds their
+// sum once, which saves LDS traffic but not instructions.  The scale is the
+// same in every brick of a view, so a pad and the voxel it belongs to add up
+// as partial sums of one fixed-point sum.  With vmax non-null the largest
+// |g_vol| of each view is recorded (by the fix-up for the voxels it
+// completes).
 
 // One scan's share of a ragged back-projection launch: workgroups
-// [first[k], first[k+1]) belong to scan k, view-major (one view per
-// workgroup) or one per brick when summing over views.
+// [first[k], first[k+1]) belong to scan k, view-major (nbv items per view,
+// the brick count of the orientation with more bricks) or one per brick when
+// summing over views.
 struct BwdK {
     const float *g_proj;
     GridK g;
@@ -502,11 +527,15 @@ struct BwdK {
     const float *angles;
     const RayK *rays;
     const unsigned *stats;
+    const int *orient;      // [V]: 1 when the view's rays run mostly along axis 1
     int V;
     float *g_vol;
     int64_t stride;
-    int nb1, nb2, nbricks;
-    int items;              // nbricks * V, or nbricks when summing over views
+    float *pads;            // [V (or 1)][nbb][NPMAX]: one box per brick
+    int nbb;                // bricks per view (the orientation with more)
+    int zc;                 // bricks per chunk along axis 2 (per-view mode)
+    int nbv;                // work items per view (column chunks, or bricks when summing)
+    int items;              // nbv * V, or nbv when summing over views
     BoundK kb;
     MarchK mk;
     unsigned *vmax;
@@ -517,64 +546,74 @@ struct BwdTab {
     int n;
 };
 
-// S0, S1, S2: brick extents (voxels) per axis; W: wavefronts per workgroup
-// sharing the brick.
-template <int S0, int S1, int S2, bool SUM, int W>
-__global__ __launch_bounds__(64 * W) void k_project_bwd(BwdTab t) {
-    constexpr int P0 = S0 + 2, P1 = S1 + 2, P2 = S2 + 2;   // padded edges
-    constexpr int NP = P0 * P1 * P2;
+// Geometry of one brick: owned cells [clo, chi] per axis, their extent in
+// voxel units [ulo, uhi] and world box [wlo, whi], and whether every owned
+// cell avoids the clamped rim cells.
+struct BrickGeo {
+    int B[3];
+    float clo[3], chi[3], ulo[3], uhi[3];
+    double wlo[3], whi[3];
+    bool interior, cells;
+};
+
+template <int S0, int S1, int S2>
+__device__ __forceinline__ BrickGeo brick_geo(const GridK &g, int b0, int b1, int b2) {
     constexpr int SZ[3] = {S0, S1, S2};
-    constexpr int NT = 64 * W;
-    constexpr int PER = (NP + NT - 1) / NT;     // padded entries per thread
-    __shared__ int acc[NP];
-    __shared__ RunP runs[W][64];
-    __shared__ int ends[W][64];
-    // within each scan, each XCD takes one contiguous range of its (view,
-    // brick) items
-    const int job = job_of(t, (int)blockIdx.x);
-    const BwdK &bj = t.s[job];
-    const int local = job_item(t, job, (int)blockIdx.x);
-    if (local >= bj.items) return;
-    const GridK &g = bj.g;
-    const ConeK &c = bj.c;
+    BrickGeo q;
+    q.B[0] = b0 * S0;
+    q.B[1] = b1 * S1;
+    q.B[2] = b2 * S2;
+    q.interior = true;
+    q.cells = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int lo = q.B[a], hi = min(q.B[a] + SZ[a] - 1, g.n[a] - 2);
+        q.cells = q.cells && lo <= hi;
+        q.clo[a] = (float)lo;
+        q.chi[a] = (float)hi;
+        q.interior = q.interior && lo >= 1 && hi <= g.n[a] - 3;
+        q.ulo[a] = lo == 0 ? -0.5f : (float)lo;
+        q.uhi[a] = hi == g.n[a] - 2 ? (float)g.n[a] - 0.5f : (float)(hi + 1);
+        q.wlo[a] = g.c0d[a] + ((double)q.ulo[a] - 0.5) * g.hd[a];
+        q.whi[a] = g.c0d[a] + ((double)q.uhi[a] + 0.5) * g.hd[a];
+    }
+    return q;
+}
+
+// Fixed-point scale of view v: 2^30 / (kbound M) (see above); 0 when the view
+// has no residual.
+__device__ __forceinline__ float bp_scale(const BwdK &bj, int v, double ct, double st) {
     const BoundK &kb = bj.kb;
+    const float m = __uint_as_float(bj.stats[2 * v]);
+    const float dmin = __uint_as_float(bj.stats[2 * v + 1]);
+    if (!(m > 0.0f)) return 0.0f;
+    // Contributions one voxel can receive in this view: rays through the
+    // detector shadow of its 2x2x2-cell support, times samples of one ray
+    // inside that support (its diagonal over the smallest step, plus one).
+    const float as = fabsf((float)st), ac = fabsf((float)ct);
+    const float lat = kb.two_hx * as + kb.two_hy * ac;    // lateral extent (mm)
+    const float dep = kb.two_hx * ac + kb.two_hy * as;    // depth extent (mm)
+    const float wu = lat * kb.mag + kb.R * kb.persp * dep;
+    const float wv = kb.two_hz * kb.mag + kb.Z * kb.persp * dep;
+    const float nr = (floorf(wu * kb.inv_du) + 1.0f) * (floorf(wv * kb.inv_dv) + 1.0f);
+    const float ns = floorf(kb.diag / dmin) + 1.0f;     // 1 when no ray has two samples
+    const float kbound = nr * ns * 1.0625f + 1.0f;
+    return 1073741824.0f / (kbound * m);                // 2^30 / (kbound M)
+}
+
+// Scatter every owned sample of view v into the LDS box acc (fixed point,
+// scale `scale`) of the brick q.  Waves work independently; the caller
+// synchronises the workgroup before and after.
+template <int S0, int S1, int S2, int NW, bool MERGE>
+__device__ __forceinline__ void bp_scatter(const BwdK &bj, const BrickGeo &q, int v, double ct,
+                                           double st, float scale, int *__restrict__ acc,
+                                           RunP (*__restrict__ runs)[64],
+                                           int (*__restrict__ ends)[64]) {
+    constexpr int P1 = S1 + 1, P2 = S2 + 1;
+    const ConeK &c = bj.c;
     const MarchK &mk = bj.mk;
     const float *__restrict__ g_proj = bj.g_proj;
     const RayK *__restrict__ rays = bj.rays;
-    const int V = bj.V;
-    const int nb1 = bj.nb1, nb2 = bj.nb2;
-    const int view = SUM ? 0 : local / bj.nbricks;
-    const int bid = SUM ? local : local - view * bj.nbricks;
-    const int b2 = bid % nb2, b1 = (bid / nb2) % nb1, b0 = bid / (nb2 * nb1);
-    const int B[3] = {b0 * S0, b1 * S1, b2 * S2};
-
-    // owned cells [clo, chi] and their extent in voxel units [ulo, uhi]
-    float clo[3], chi[3], ulo[3], uhi[3];
-    double wlo[3], whi[3];
-    bool interior = true;       // no owned cell touches the clamped rim cells
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const int lo = max(B[a] - 1, 0), hi = min(B[a] + SZ[a] - 1, g.n[a] - 2);
-        clo[a] = (float)lo;
-        chi[a] = (float)hi;
-        interior = interior && lo >= 1 && hi <= g.n[a] - 3;
-        ulo[a] = lo == 0 ? -0.5f : (float)lo;
-        uhi[a] = hi == g.n[a] - 2 ? (float)g.n[a] - 0.5f : (float)(hi + 1);
-        wlo[a] = g.c0d[a] + ((double)ulo[a] - 0.5) * g.hd[a];
-        whi[a] = g.c0d[a] + ((double)uhi[a] + 0.5) * g.hd[a];
-    }
-    // byte offset in acc of cell (c0, c1, c2): c0*K0 + c1*K1 + c2*4 + KC,
-    // exact in float (every term is an integer below 2^24)
-    const float K0 = 4.0f * P1 * P2, K1 = 4.0f * P2;
-    const float KC =
-        -4.0f * ((float)(B[0] - 1) * P1 * P2 + (float)(B[1] - 1) * P2 + (float)(B[2] - 1));
-    float sum[SUM ? PER : 1];   // per-thread float accumulation over views (strided entries)
-#pragma unroll
-    for (int k = 0; k < (SUM ? PER : 1); ++k) sum[k] = 0.0f;
-    float last_inv = 0.0f;      // per-view mode: 1/scale of the one view
-
-    const int vb = SUM ? 0 : view;
-    const int ve = SUM ? V : view + 1;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wave
     const int lx = lane & 7, ly = lane >> 3;
@@ -587,252 +626,484 @@ __global__ __launch_bounds__(64 * W) void k_project_bwd(BwdTab t) {
         nm2[a] = mk.nm2[a];
         asm volatile("" : "+s"(nm1[a]), "+s"(nm2[a]));
     }
+    const bool interior = q.interior;
+    // byte offset in acc of cell (c0, c1, c2): c0*K0 + c1*K1 + c2*4 + KC,
+    // exact in float (every term is an integer below 2^24)
+    const float K0 = 4.0f * P1 * P2, K1 = 4.0f * P2;
+    const float KC = -4.0f * ((float)q.B[0] * P1 * P2 + (float)q.B[1] * P2 + (float)q.B[2]);
+    int u0, u1, v0, v1;
+    shadow_rect(c, ct, st, q.wlo, q.whi, u0, u1, v0, v1);   // uniform across the block
+    if (u1 < u0 || v1 < v0) return;
+    // The 64 lanes of a wave take an 8x8 grid of pixels spread over the
+    // rectangle (strides gu, gv); the waves sweep the gu*gv offsets.  Rays
+    // that far apart keep the lanes' LDS atomics on unrelated words.
+    const int gu = (u1 - u0 + 8) / 8, gv = (v1 - v0 + 8) / 8;
+    const int nph = gu * gv;
     RunP *const wr = runs[wave];
     int *const we = ends[wave];
-    for (int v = vb; v < ve; ++v) {
-        const double th = (double)bj.angles[v];
-        const double ct = cos(th), st = sin(th);
-        int u0, u1, v0, v1;
-        shadow_rect(c, ct, st, wlo, whi, u0, u1, v0, v1);   // uniform across the block
-        if (u1 < u0 || v1 < v0) continue;
-        // The 64 lanes of a wave take an 8x8 grid of pixels spread over the
-        // rectangle (strides gu, gv); the waves sweep the gu*gv offsets.  Rays
-        // that far apart keep the lanes' LDS atomics on unrelated words.
-        const int gu = (u1 - u0 + 8) / 8, gv = (v1 - v0 + 8) / 8;
-        const int nph = gu * gv;
-        const float m = __uint_as_float(bj.stats[2 * v]);
-        const float dmin = __uint_as_float(bj.stats[2 * v + 1]);
-        if (!(m > 0.0f)) continue;
-        for (int i = threadIdx.x; i < NP; i += NT) acc[i] = 0;
-        __syncthreads();
-        // Contributions one voxel can receive in this view: rays through the
-        // detector shadow of its 2x2x2-cell support, times samples of one ray
-        // inside that support (its diagonal over the smallest step, plus one).
-        const float as = fabsf((float)st), ac = fabsf((float)ct);
-        const float lat = kb.two_hx * as + kb.two_hy * ac;    // lateral extent (mm)
-        const float dep = kb.two_hx * ac + kb.two_hy * as;    // depth extent (mm)
-        const float wu = lat * kb.mag + kb.R * kb.persp * dep;
-        const float wv = kb.two_hz * kb.mag + kb.Z * kb.persp * dep;
-        const float nr = (floorf(wu * kb.inv_du) + 1.0f) * (floorf(wv * kb.inv_dv) + 1.0f);
-        const float ns = floorf(kb.diag / dmin) + 1.0f;     // 1 when no ray has two samples
-        const float kbound = nr * ns * 1.0625f + 1.0f;
-        const float scale = 1073741824.0f / (kbound * m);   // 2^30 / (kbound M)
-        // pass 2: scatter every owned sample's 8 weights
-        for (int ph = wave; ph < nph; ph += W) {             // uniform per wave
-            const int iu = u0 + lx * gu + ph % gu, iv = v0 + ly * gv + ph / gu;
-            int s0 = 0, len = 0;
-            RayK r;
-            float gp = 0.0f;
-            if (iu <= u1 && iv <= v1) {
-                const int64_t pix = ((int64_t)v * c.nv + iv) * c.nu + iu;
-                r = rays[pix];
-                gp = g_proj[pix] * r.delta * scale;
-                if (r.n > 0 && gp != 0.0f) {
-                    float smin = 0.0f, smax = (float)(r.n - 1);
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        if (r.su[a] != 0.0f) {
-                            // an estimate only: the run is made exact below
-                            const float inv = __builtin_amdgcn_rcpf(r.su[a]);
-                            const float ta = (ulo[a] - r.bu[a]) * inv, tb = (uhi[a] - r.bu[a]) * inv;
-                            smin = fmaxf(smin, fminf(ta, tb));
-                            smax = fminf(smax, fmaxf(ta, tb));
-                        } else if (r.bu[a] < ulo[a] - 1.0f || r.bu[a] > uhi[a] + 1.0f) {
-                            smax = -10.0f;
-                        }
-                    }
-                    if (smin <= smax + 2.0f) {
-                        // The owned samples form one run of s: every axis's cell
-                        // index is monotone in s and the owned cells form a box.
-                        // The estimate puts the run at [ceil(smin), ceil(smax) - 1]
-                        // up to rounding far below one sample; start one sample
-                        // outside each end and move to the exact ends.
-                        // (in an interior brick the clamps cannot change the
-                        // answer: owned cells lie in [1, n-3] on every axis)
-                        auto cell = [&](float x, int a) {
-                            if (interior) return floorf(x);
-                            float fi, fr;
-                            ray_cell(x, nm1[a], nm2[a], fi, fr);
-                            return fi;
-                        };
-                        auto owned = [&](int si) {
-                            const float sf = (float)si;
-                            float fi = cell(fmaf(sf, r.su[0], r.bu[0]), 0);
-                            bool o = fi >= clo[0] && fi <= chi[0];
-                            fi = cell(fmaf(sf, r.su[1], r.bu[1]), 1);
-                            o = o && fi >= clo[1] && fi <= chi[1];
-                            fi = cell(fmaf(sf, r.su[2], r.bu[2]), 2);
-                            return o && fi >= clo[2] && fi <= chi[2];
-                        };
-                        const int last = r.n - 1;
-                        s0 = min(max(0, (int)ceilf(smin) - 1), last);
-                        int s1 = min(max(0, (int)ceilf(smax)), last);
-                        bool found;
-                        if (owned(s0)) {
-                            while (s0 > 0 && owned(s0 - 1)) --s0;
-                            found = true;
-                        } else {
-                            ++s0;
-                            while (s0 <= s1 && !owned(s0)) ++s0;
-                            found = s0 <= s1;
-                        }
-                        if (found) {
-                            s1 = max(s1, s0);
-                            if (owned(s1)) {
-                                while (s1 < last && owned(s1 + 1)) ++s1;
-                            } else {
-                                --s1;
-                                while (s1 > s0 && !owned(s1)) --s1;
-                            }
-                            len = s1 - s0 + 1;
-                        }
-                    }
-                }
-            }
-            // flatten the wave's runs: item q in [start, start + len) is
-            // sample q - start + s0 of this lane's ray
-            const int incl = wave_incl_sum(len);
-            const int T = __builtin_amdgcn_readlane(incl, 63);
-            if (T == 0) continue;
-            {
-                RunP rp;
+    for (int ph = wave; ph < nph; ph += NW) {            // uniform per wave
+        const int iu = u0 + lx * gu + ph % gu, iv = v0 + ly * gv + ph / gu;
+        int s0 = 0, len = 0;
+        RayK r;
+        float gp = 0.0f;
+        if (iu <= u1 && iv <= v1) {
+            const int64_t pix = ((int64_t)v * c.nv + iv) * c.nu + iu;
+            r = rays[pix];
+            gp = g_proj[pix] * r.delta * scale;
+            if (r.n > 0 && gp != 0.0f) {
+                float smin = 0.0f, smax = (float)(r.n - 1);
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    rp.bu[a] = r.bu[a];
-                    rp.su[a] = r.su[a];
-                }
-                rp.gp = gp;
-                rp.off = s0 - (incl - len);
-                if (len > 0) wr[lane] = rp;
-                we[lane] = incl;
-            }
-            wave_lds_sync();
-            // Lane j takes items [j K, j K + K): every lane does a sample per
-            // step however the run lengths differ.
-            const int K = (T + 63) >> 6;
-            int q = lane * K;
-            const int qe = min(q + K, T);
-            // first ray of the slice: the smallest r with end_r > q (binary
-            // lifting)
-            int ri = 0;
-#pragma unroll
-            for (int step = 32; step > 0; step >>= 1)
-                if (we[ri + step - 1] <= q) ri += step;
-            int rend = we[ri];
-            RunP rp = wr[ri];
-            lds_wait();
-            // Sample s of ray rp: its cell's LDS byte offset and the 8 corner
-            // weights.
-            auto sample = [&](float sf, int &off, float e[8]) {
-                const float x0 = fmaf(sf, rp.su[0], rp.bu[0]);
-                const float x1 = fmaf(sf, rp.su[1], rp.bu[1]);
-                const float x2 = fmaf(sf, rp.su[2], rp.bu[2]);
-                float c0f, c1f, c2f, f0, f1, f2;
-                if (interior) {
-                    c0f = floorf(x0);
-                    c1f = floorf(x1);
-                    c2f = floorf(x2);
-                    f0 = x0 - c0f;
-                    f1 = x1 - c1f;
-                    f2 = x2 - c2f;
-                } else {
-                    ray_cell(x0, nm1[0], nm2[0], c0f, f0);
-                    ray_cell(x1, nm1[1], nm2[1], c1f, f1);
-                    ray_cell(x2, nm1[2], nm2[2], c2f, f2);
-                }
-                off = (int)fmaf(c0f, K0, fmaf(c1f, K1, fmaf(c2f, 4.0f, KC)));
-                const float w = rp.gp;
-                const float wx1 = w * f0, wx0 = w - wx1;
-                const float a01 = wx0 * f1, a00 = wx0 - a01;
-                const float a11 = wx1 * f1, a10 = wx1 - a11;
-                const float e001 = a00 * f2, e011 = a01 * f2;
-                const float e101 = a10 * f2, e111 = a11 * f2;
-                e[0] = a00 - e001;
-                e[1] = e001;
-                e[2] = a01 - e011;
-                e[3] = e011;
-                e[4] = a10 - e101;
-                e[5] = e101;
-                e[6] = a11 - e111;
-                e[7] = e111;
-            };
-            if (q < qe) {
-                // Consecutive samples in one cell add up in registers; the
-                // cell's 8 corners go to LDS when the lane moves on.
-                int cur_off;
-                float cw[8];
-                float sf = (float)(q + rp.off);
-                sample(sf, cur_off, cw);
-                auto flush = [&]() {
-                    char *qb = (char *)acc + cur_off;
-                    atomicAdd((int *)qb, round_int(cw[0]));
-                    atomicAdd((int *)(qb + 4), round_int(cw[1]));
-                    atomicAdd((int *)(qb + 4 * P2), round_int(cw[2]));
-                    atomicAdd((int *)(qb + 4 * P2 + 4), round_int(cw[3]));
-                    atomicAdd((int *)(qb + 4 * P1 * P2), round_int(cw[4]));
-                    atomicAdd((int *)(qb + 4 * P1 * P2 + 4), round_int(cw[5]));
-                    atomicAdd((int *)(qb + 4 * P1 * P2 + 4 * P2), round_int(cw[6]));
-                    atomicAdd((int *)(qb + 4 * P1 * P2 + 4 * P2 + 4), round_int(cw[7]));
-                };
-                for (++q; q < qe; ++q) {
-                    sf += 1.0f;                 // exact: sample indices are small integers
-                    if (q >= rend) {
-                        do {
-                            rend = we[++ri];
-                        } while (q >= rend);
-                        rp = wr[ri];
-                        lds_wait();
-                        sf = (float)(q + rp.off);
+                    if (r.su[a] != 0.0f) {
+                        // an estimate only: the run is made exact below
+                        const float inv = __builtin_amdgcn_rcpf(r.su[a]);
+                        const float ta = (q.ulo[a] - r.bu[a]) * inv, tb = (q.uhi[a] - r.bu[a]) * inv;
+                        smin = fmaxf(smin, fminf(ta, tb));
+                        smax = fminf(smax, fmaxf(ta, tb));
+                    } else if (r.bu[a] < q.ulo[a] - 1.0f || r.bu[a] > q.uhi[a] + 1.0f) {
+                        smax = -10.0f;
                     }
-                    int off;
-                    float e[8];
-                    sample(sf, off, e);
-                    // a restart is a multiply by 0, so both cases share one fma
-                    const bool moved = off != cur_off;
-                    const float keep = moved ? 0.0f : 1.0f;
-                    if (moved) flush();
-                    cur_off = off;
-#pragma unroll
-                    for (int k = 0; k < 8; ++k) fma_in_place(cw[k], keep, e[k]);
                 }
-                flush();
+                if (smin <= smax + 2.0f) {
+                    // The owned samples form one run of s: every axis's cell
+                    // index is monotone in s and the owned cells form a box.
+                    // The estimate puts the run at [ceil(smin), ceil(smax) - 1]
+                    // up to rounding far below one sample; start one sample
+                    // outside each end and move to the exact ends.
+                    // (in an interior brick the clamps cannot change the
+                    // answer: owned cells lie in [1, n-3] on every axis)
+                    auto cell = [&](float x, int a) {
+                        if (interior) return floorf(x);
+                        float fi, fr;
+                        ray_cell(x, nm1[a], nm2[a], fi, fr);
+                        return fi;
+                    };
+                    auto owned = [&](int si) {
+                        const float sf = (float)si;
+                        float fi = cell(fmaf(sf, r.su[0], r.bu[0]), 0);
+                        bool o = fi >= q.clo[0] && fi <= q.chi[0];
+                        fi = cell(fmaf(sf, r.su[1], r.bu[1]), 1);
+                        o = o && fi >= q.clo[1] && fi <= q.chi[1];
+                        fi = cell(fmaf(sf, r.su[2], r.bu[2]), 2);
+                        return o && fi >= q.clo[2] && fi <= q.chi[2];
+                    };
+                    const int last = r.n - 1;
+                    s0 = min(max(0, (int)ceilf(smin) - 1), last);
+                    int s1 = min(max(0, (int)ceilf(smax)), last);
+                    bool found;
+                    if (owned(s0)) {
+                        while (s0 > 0 && owned(s0 - 1)) --s0;
+                        found = true;
+                    } else {
+                        ++s0;
+                        while (s0 <= s1 && !owned(s0)) ++s0;
+                        found = s0 <= s1;
+                    }
+                    if (found) {
+                        s1 = max(s1, s0);
+                        if (owned(s1)) {
+                            while (s1 < last && owned(s1 + 1)) ++s1;
+                        } else {
+                            --s1;
+                            while (s1 > s0 && !owned(s1)) --s1;
+                        }
+                        len = s1 - s0 + 1;
+                    }
+                }
             }
-            wave_lds_sync();
         }
-        __syncthreads();
-        const float inv_scale = 1.0f / scale;
-        if constexpr (SUM) {
+        // flatten the wave's runs: item q in [start, start + len) is
+        // sample q - start + s0 of this lane's ray
+        const int incl = wave_incl_sum(len);
+        const int T = __builtin_amdgcn_readlane(incl, 63);
+        if (T == 0) continue;
+        {
+            RunP rp;
 #pragma unroll
-            for (int k = 0; k < PER; ++k) {
-                const int i = threadIdx.x + NT * k;
-                if (i < NP) sum[k] += (float)acc[i] * inv_scale;
+            for (int a = 0; a < 3; ++a) {
+                rp.bu[a] = r.bu[a];
+                rp.su[a] = r.su[a];
             }
+            rp.gp = gp;
+            rp.off = s0 - (incl - len);
+            if (len > 0) wr[lane] = rp;
+            we[lane] = incl;
+        }
+        wave_lds_sync();
+        // Lane j takes items [j K, j K + K): every lane does a sample per
+        // step however the run lengths differ.
+        const int K = (T + 63) >> 6;
+        int it = lane * K;
+        const int ite = min(it + K, T);
+        // first ray of the slice: the smallest r with end_r > it (binary
+        // lifting)
+        int ri = 0;
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1)
+            if (we[ri + step - 1] <= it) ri += step;
+        int rend = we[ri];
+        RunP rp = wr[ri];
+        lds_wait();
+        // Sample s of ray rp: its cell's LDS byte offset and the 8 corner
+        // weights.
+        auto sample = [&](float sf, int &off, float e[8]) {
+            const float x0 = fmaf(sf, rp.su[0], rp.bu[0]);
+            const float x1 = fmaf(sf, rp.su[1], rp.bu[1]);
+            const float x2 = fmaf(sf, rp.su[2], rp.bu[2]);
+            float c0f, c1f, c2f, f0, f1, f2;
+            if (interior) {
+                c0f = floorf(x0);
+                c1f = floorf(x1);
+                c2f = floorf(x2);
+                f0 = x0 - c0f;
+                f1 = x1 - c1f;
+                f2 = x2 - c2f;
+            } else {
+                ray_cell(x0, nm1[0], nm2[0], c0f, f0);
+                ray_cell(x1, nm1[1], nm2[1], c1f, f1);
+                ray_cell(x2, nm1[2], nm2[2], c2f, f2);
+            }
+            off = (int)fmaf(c0f, K0, fmaf(c1f, K1, fmaf(c2f, 4.0f, KC)));
+            const float w = rp.gp;
+            const float wx1 = w * f0, wx0 = w - wx1;
+            const float a01 = wx0 * f1, a00 = wx0 - a01;
+            const float a11 = wx1 * f1, a10 = wx1 - a11;
+            const float e001 = a00 * f2, e011 = a01 * f2;
+            const float e101 = a10 * f2, e111 = a11 * f2;
+            e[0] = a00 - e001;
+            e[1] = e001;
+            e[2] = a01 - e011;
+            e[3] = e011;
+            e[4] = a10 - e101;
+            e[5] = e101;
+            e[6] = a11 - e111;
+            e[7] = e111;
+        };
+        auto add8 = [&](int off, const float e[8]) {
+            char *qb = (char *)acc + off;
+            atomicAdd((int *)qb, round_int(e[0]));
+            atomicAdd((int *)(qb + 4), round_int(e[1]));
+            atomicAdd((int *)(qb + 4 * P2), round_int(e[2]));
+            atomicAdd((int *)(qb + 4 * P2 + 4), round_int(e[3]));
+            atomicAdd((int *)(qb + 4 * P1 * P2), round_int(e[4]));
+            atomicAdd((int *)(qb + 4 * P1 * P2 + 4), round_int(e[5]));
+            atomicAdd((int *)(qb + 4 * P1 * P2 + 4 * P2), round_int(e[6]));
+            atomicAdd((int *)(qb + 4 * P1 * P2 + 4 * P2 + 4), round_int(e[7]));
+        };
+        if (!MERGE) {
+            // every sample's 8 corners go to LDS at once
+            float sf = (float)(it + rp.off);
+            for (; it < ite; ++it, sf += 1.0f) {
+                if (it >= rend) {
+                    do {
+                        rend = we[++ri];
+                    } while (it >= rend);
+                    rp = wr[ri];
+                    lds_wait();
+                    sf = (float)(it + rp.off);
+                }
+                int off;
+                float e[8];
+                sample(sf, off, e);
+                add8(off, e);
+            }
+        } else if (it < ite) {
+            // Consecutive samples in one cell add up in registers; the
+            // cell's 8 corners go to LDS when the lane moves on.
+            int cur_off;
+            float cw[8];
+            float sf = (float)(it + rp.off);
+            sample(sf, cur_off, cw);
+            for (++it; it < ite; ++it) {
+                sf += 1.0f;                 // exact: sample indices are small integers
+                if (it >= rend) {
+                    do {
+                        rend = we[++ri];
+                    } while (it >= rend);
+                    rp = wr[ri];
+                    lds_wait();
+                    sf = (float)(it + rp.off);
+                }
+                int off;
+                float e[8];
+                sample(sf, off, e);
+                // a restart is a multiply by 0, so both cases share one fma
+                const bool moved = off != cur_off;
+                const float keep = moved ? 0.0f : 1.0f;
+                if (moved) add8(cur_off, cw);
+                cur_off = off;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) fma_in_place(cw[k], keep, e[k]);
+            }
+            add8(cur_off, cw);
+        }
+        wave_lds_sync();
+    }
+}
+
+// Per-view mode: one workgroup walks a chunk of up to ZC bricks along
+// axis 2 of one (b0, b1) column for one view.  The high pad layer of each
+// brick (z = S2 in its box) is the low layer of the next one: it is carried
+// in LDS (integer sums: exact), so only the chunk's last brick stages it.
+// Own voxels go to g_vol, the pads of axes 0 and 1 to the staging box; a
+// voxel on a low face whose lower neighbour stages a pad is completed by the
+// fix-up (which also takes its part of vmax).
+template <int S0, int S1, int S2, int NW, int NPMAX, bool MERGE, int ZC>
+__device__ __forceinline__ void bp_column(const BwdK &bj, int view, int item, int *__restrict__ acc,
+                                          RunP (*__restrict__ runs)[64],
+                                          int (*__restrict__ ends)[64]) {
+    constexpr int P1 = S1 + 1, P2 = S2 + 1;
+    constexpr int NP = (S0 + 1) * P1 * P2;
+    static_assert(NP <= NPMAX, "box larger than the LDS array");
+    constexpr int NT = 64 * NW;
+    const GridK &g = bj.g;
+    const int nb0 = (g.n[0] + S0 - 1) / S0, nb1 = (g.n[1] + S1 - 1) / S1;
+    const int nb2 = (g.n[2] + S2 - 1) / S2;
+    constexpr int zc = ZC;
+    const int nzc = (nb2 + zc - 1) / zc;
+    if (item >= nb0 * nb1 * nzc) return;      // the other orientation has more items
+    const int chunk = item % nzc, col = item / nzc;
+    const int b1 = col % nb1, b0 = col / nb1;
+    const int z0 = chunk * zc, z1 = min(nb2, z0 + zc);
+    const int v = view;
+    const double th = (double)bj.angles[v];
+    const double ct = cos(th), st = sin(th);
+    const float scale = bp_scale(bj, v, ct, st);
+    const float inv_scale = scale > 0.0f ? 1.0f / scale : 0.0f;
+    float *out = bj.g_vol + (int64_t)v * bj.stride;
+    const int lane = threadIdx.x & 63;
+    float mx = 0.0f;
+    for (int i = threadIdx.x; i < NP; i += NT) acc[i] = 0;
+    __syncthreads();
+    for (int b2 = z0; b2 < z1; ++b2) {
+        const BrickGeo q = brick_geo<S0, S1, S2>(g, b0, b1, b2);
+        if (q.cells && scale > 0.0f) bp_scatter<S0, S1, S2, NW, MERGE>(bj, q, v, ct, st, scale, acc, runs, ends);
+        __syncthreads();
+        const bool lastb = b2 + 1 == z1;
+        float *pad = bj.pads + ((int64_t)v * bj.nbb + (b0 * nb1 + b1) * nb2 + b2) * NPMAX;
+#pragma unroll 1
+        for (int i = threadIdx.x; i < NP; i += NT) {
+            const int z = i % P2, y = (i / P2) % P1, x = i / (P1 * P2);
+            const int gx = q.B[0] + x, gy = q.B[1] + y, gz = q.B[2] + z;
+            if (gx >= g.n[0] || gy >= g.n[1] || gz >= g.n[2]) continue;
+            const float val = (float)acc[i] * inv_scale;
+            if (x < S0 && y < S1 && z < S2) {
+                out[((int64_t)gx * g.n[1] + gy) * g.n[2] + gz] = val;
+                const bool fixed = (x == 0 && b0 > 0) || (y == 0 && b1 > 0) ||
+                                   (z == 0 && b2 == z0 && b2 > 0);
+                if (!fixed) mx = fmaxf(mx, fabsf(val));
+            } else if (z < S2 || lastb) {
+                pad[i] = val;
+            }
+        }
+        if (!lastb) {
+            // the z = S2 layer becomes the next brick's z = 0 layer; the rest
+            // is cleared (two phases: the two layers are disjoint)
             __syncthreads();
-        } else {
-            last_inv = inv_scale;
+#pragma unroll 1
+            for (int i = threadIdx.x; i < NP; i += NT)
+                if (i % P2 == 0) acc[i] = acc[i + S2];
+            __syncthreads();
+#pragma unroll 1
+            for (int i = threadIdx.x; i < NP; i += NT)
+                if (i % P2 != 0) acc[i] = 0;
+            __syncthreads();
         }
     }
-    float *out = bj.g_vol + (SUM ? 0 : (int64_t)view * bj.stride);
-    float mx = 0.0f;
+    if (bj.vmax) {
+        for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+        if (lane == 0 && mx > 0.0f) atomicMax(&bj.vmax[v], __float_as_uint(mx));
+    }
+}
+
+// Summed over views: one brick per workgroup (chunks of one brick), every
+// view in order with its own scale, float sums per box entry; all pads are
+// staged.
+template <int S0, int S1, int S2, int NW, int NPMAX, bool MERGE>
+__device__ __forceinline__ void bp_summed(const BwdK &bj, int bid, int *__restrict__ acc,
+                                          RunP (*__restrict__ runs)[64],
+                                          int (*__restrict__ ends)[64]) {
+    constexpr int P1 = S1 + 1, P2 = S2 + 1;
+    constexpr int NP = (S0 + 1) * P1 * P2;
+    static_assert(NP <= NPMAX, "box larger than the LDS array");
+    constexpr int NT = 64 * NW;
+    constexpr int PER = (NP + NT - 1) / NT;
+    const GridK &g = bj.g;
+    const int nb0 = (g.n[0] + S0 - 1) / S0, nb1 = (g.n[1] + S1 - 1) / S1;
+    const int nb2 = (g.n[2] + S2 - 1) / S2;
+    if (bid >= nb0 * nb1 * nb2) return;
+    const int b2 = bid % nb2, b1 = (bid / nb2) % nb1, b0 = bid / (nb2 * nb1);
+    const BrickGeo q = brick_geo<S0, S1, S2>(g, b0, b1, b2);
+    float sum[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) sum[k] = 0.0f;
+    for (int v = 0; v < bj.V; ++v) {
+        const double th = (double)bj.angles[v];
+        const double ct = cos(th), st = sin(th);
+        const float scale = bp_scale(bj, v, ct, st);
+        if (!q.cells || !(scale > 0.0f)) continue;
+        for (int i = threadIdx.x; i < NP; i += NT) acc[i] = 0;
+        __syncthreads();
+        bp_scatter<S0, S1, S2, NW, MERGE>(bj, q, v, ct, st, scale, acc, runs, ends);
+        __syncthreads();
+        const float inv = 1.0f / scale;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int i = threadIdx.x + NT * k;
+            if (i < NP) sum[k] += (float)acc[i] * inv;
+        }
+        __syncthreads();
+    }
+    float *pad = bj.pads + (int64_t)bid * NPMAX;
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const int i = threadIdx.x + NT * k;
         if (i >= NP) continue;
-        const int z = i % P2 - 1, y = (i / P2) % P1 - 1, x = i / (P1 * P2) - 1;
-        if (x < 0 || y < 0 || z < 0 || x >= S0 || y >= S1 || z >= S2) continue;
-        const int gx = B[0] + x, gy = B[1] + y, gz = B[2] + z;
-        if (gx < g.n[0] && gy < g.n[1] && gz < g.n[2]) {
-            float val;
-            if constexpr (SUM) val = sum[k];
-            else val = (float)acc[i] * last_inv;
-            out[((int64_t)gx * g.n[1] + gy) * g.n[2] + gz] = val;
-            mx = fmaxf(mx, fabsf(val));
+        const int z = i % P2, y = (i / P2) % P1, x = i / (P1 * P2);
+        const int gx = q.B[0] + x, gy = q.B[1] + y, gz = q.B[2] + z;
+        if (gx >= g.n[0] || gy >= g.n[1] || gz >= g.n[2]) continue;
+        if (x < S0 && y < S1 && z < S2) bj.g_vol[((int64_t)gx * g.n[1] + gy) * g.n[2] + gz] = sum[k];
+        else pad[i] = sum[k];
+    }
+}
+
+// L x W x H cells per brick (L along the axis the view's rays mostly
+// follow), NW waves per workgroup.
+// (at most 80 VGPRs: six waves per SIMD, the three workgroups per CU that
+// the LDS box allows)
+template <int L, int W, int H, int NW, bool SUM, bool MERGE, int ZC>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(6)))
+void k_project_bwd(BwdTab t) {
+    constexpr int NPMAX = (L + 1) * (W + 1) * (H + 1);
+    __shared__ int acc[NPMAX];
+    __shared__ RunP runs[NW][64];
+    __shared__ int ends[NW][64];
+    // within each scan, each XCD takes one contiguous range of its (view,
+    // column chunk) items
+    const int job = job_of(t, (int)blockIdx.x);
+    const BwdK &bj = t.s[job];
+    const int local = job_item(t, job, (int)blockIdx.x);
+    if (local >= bj.items) return;
+    if constexpr (SUM) {
+        // summed over views: one orientation for all views (the first's)
+        if (bj.orient[0])
+            bp_summed<W, L, H, NW, NPMAX, MERGE>(bj, local, acc, runs, ends);
+        else
+            bp_summed<L, W, H, NW, NPMAX, MERGE>(bj, local, acc, runs, ends);
+    } else {
+        const int view = local / bj.nbv, item = local - view * bj.nbv;
+        if (bj.orient[view])
+            bp_column<W, L, H, NW, NPMAX, MERGE, ZC>(bj, view, item, acc, runs, ends);
+        else
+            bp_column<L, W, H, NW, NPMAX, MERGE, ZC>(bj, view, item, acc, runs, ends);
+    }
+}
+
+// Fix-up of the brick faces: a voxel on the low face of its brick, where the
+// brick below it on that axis staged its pad, gets the pads of the bricks
+// below it, added in a fixed order (neighbour mask 1..7), and its share of
+// vmax.  Axis-2 faces take part only at chunk boundaries (b2 a multiple of
+// zc): inside a chunk the pad was carried.  The face voxels are walked by
+// rows: family a holds the planes p_a = k S_a (k >= 1; family 2 only at chunk
+// boundaries); a row is one line of such a plane along its faster axis, and a
+// voxel that a lower family's plane also holds is left to that family, so
+// each face voxel is completed once.  Blocks stride over one view's rows
+// (one atomic for vmax per block).
+template <int S0, int S1, int S2, int NPMAX>
+__device__ __forceinline__ void bp_fixup(const BwdK &bj, int view, int sum_views, float *red) {
+    constexpr int S[3] = {S0, S1, S2};
+    constexpr int P1 = S1 + 1, P2 = S2 + 1;
+    const GridK &g = bj.g;
+    const int nb[3] = {(g.n[0] + S0 - 1) / S0, (g.n[1] + S1 - 1) / S1, (g.n[2] + S2 - 1) / S2};
+    const int zc = sum_views ? 1 : bj.zc;
+    const int nz = (nb[2] - 1) / zc;        // axis-2 planes at chunk boundaries
+    // work rows: family 0 (axis-0 planes) and family 1 (axis-1 planes) are
+    // lines along axis 2, rows_per lines to a row of work; family 2: per
+    // (p0, p1) line along axis 2 its nz face voxels, taken by neighbouring
+    // lanes, so a wave reads whole lines of memory (the face voxels are S2
+    // floats apart)
+    const int n2 = g.n[2];
+    const int lpr = max(1, (int)blockDim.x / n2);                  // lines per row, families 0-1
+    int zs = 1;
+    while (zs < nz) zs <<= 1;
+    const int lines2 = max(1, (int)blockDim.x / zs);               // lines per row, family 2
+    const int l0 = (nb[0] - 1) * g.n[1], l1 = (nb[1] - 1) * g.n[0];  // lines of families 0, 1
+    const int r0 = (l0 + lpr - 1) / lpr, r1 = (l1 + lpr - 1) / lpr;
+    const int r2 = nz > 0 ? (g.n[0] * g.n[1] + lines2 - 1) / lines2 : 0;
+    float *out = bj.g_vol + (sum_views ? 0 : (int64_t)view * bj.stride);
+    const float *pads = bj.pads + (int64_t)view * bj.nbb * NPMAX;
+    float mx = 0.0f;
+    for (int row = blockIdx.x; row < r0 + r1 + r2; row += gridDim.x) {
+      const int fam = row < r0 ? 0 : (row < r0 + r1 ? 1 : 2);
+      const int span = fam < 2 ? lpr * n2 : lines2 * zs;       // entries of this row
+      for (int e = threadIdx.x; e < span; e += blockDim.x) {
+        int p[3];
+        if (fam < 2) {
+            const int line = (fam == 0 ? row : row - r0) * lpr + e / n2;
+            if (line >= (fam == 0 ? l0 : l1)) continue;
+            p[2] = e - (e / n2) * n2;
+            if (fam == 0) {
+                p[0] = (line / g.n[1] + 1) * S0;
+                p[1] = line - (line / g.n[1]) * g.n[1];
+            } else {
+                p[1] = (line / g.n[0] + 1) * S1;
+                p[0] = line - (line / g.n[0]) * g.n[0];
+            }
+        } else {
+            const int k = e & (zs - 1), line = (row - r0 - r1) * lines2 + e / zs;
+            if (k >= nz || line >= g.n[0] * g.n[1]) continue;
+            p[0] = line / g.n[1];
+            p[1] = line - p[0] * g.n[1];
+            p[2] = (k + 1) * zc * S2;
+        }
+        if (p[0] >= g.n[0] || p[1] >= g.n[1] || p[2] >= g.n[2]) continue;
+        int b[3], l[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            b[a] = p[a] / S[a];                 // constant divisors
+            l[a] = p[a] - b[a] * S[a];
+        }
+        int mask = 0;
+        if (l[0] == 0 && b[0] > 0) mask |= 1;
+        if (l[1] == 0 && b[1] > 0) mask |= 2;
+        if (l[2] == 0 && b[2] > 0 && b[2] % zc == 0) mask |= 4;
+        if (!(mask >> fam & 1) || (mask & ((1 << fam) - 1))) continue;
+        float sum = 0.0f;
+#pragma unroll
+        for (int d = 1; d < 8; ++d) {
+            if ((d & mask) != d) continue;
+            const int q0 = b[0] - (d & 1), q1 = b[1] - ((d >> 1) & 1), q2 = b[2] - ((d >> 2) & 1);
+            const int lq0 = (d & 1) ? S0 : l[0], lq1 = (d & 2) ? S1 : l[1],
+                      lq2 = (d & 4) ? S2 : l[2];
+            const int nbid = (q0 * nb[1] + q1) * nb[2] + q2;
+            sum += pads[(int64_t)nbid * NPMAX + (lq0 * P1 + lq1) * P2 + lq2];
+        }
+        float *o = out + ((int64_t)p[0] * g.n[1] + p[1]) * g.n[2] + p[2];
+        const float val = *o + sum;
+        *o = val;
+        mx = fmaxf(mx, fabsf(val));
+      }
+    }
+    if (bj.vmax && !sum_views) {
+        mx = wave_max(mx);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+            if (mx > 0.0f) atomicMax(&bj.vmax[view], __float_as_uint(mx));
         }
     }
-    if (bj.vmax && !SUM) {
-        for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
-        if (lane == 0 && mx > 0.0f) atomicMax(&bj.vmax[view], __float_as_uint(mx));
-    }
+}
+
+template <int L, int W, int H>
+__global__ __launch_bounds__(256) void k_project_bwd_fixup(BwdK bj, int sum_views) {
+    constexpr int NPMAX = (L + 1) * (W + 1) * (H + 1);
+    __shared__ float red[4];
+    const int view = blockIdx.y;
+    if (bj.orient[view])
+        bp_fixup<W, L, H, NPMAX>(bj, view, sum_views, red);
+    else
+        bp_fixup<L, W, H, NPMAX>(bj, view, sum_views, red);
 }
 
 // Geometry constants of the per-view bound on contributions per voxel
@@ -913,15 +1184,51 @@ hipError_t launch_project(const float *vol, int64_t stride, const GridK &g, cons
     return launch_project_jobs(&j, 1, s);
 }
 
-// Workspace: the per-ray table, then two words of statistics per view.
-size_t project_bwd_workspace(const pmf_cone_t &c, int V) {
-    return align256(sizeof(RayK) * (size_t)c.nu * (size_t)c.nv * (size_t)V) +
-           align256(sizeof(unsigned) * 2 * (size_t)V);
+// Brick shapes of PMF_TUNE_BACKPROJECT_BRICK: L x W x H cells, waves.
+struct BrickShape {
+    int L, W, H, NW;
+};
+static const BrickShape kBricks[] = {{48, 16, 8, 8}, {48, 16, 8, 8}, {32, 16, 8, 8},
+                                     {48, 16, 8, 8}, {48, 16, 8, 8}, {48, 16, 8, 8},
+                                     {32, 16, 8, 8}, {32, 32, 8, 8}, {48, 24, 8, 8}};
+constexpr int NBRICKS = sizeof(kBricks) / sizeof(kBricks[0]);
+
+// Items per view: the brick count of the orientation with more bricks.
+static int bricks_per_view(const GridK &g, int L, int W, int H) {
+    auto cnt = [&](int s0, int s1) {
+        return ((g.n[0] + s0 - 1) / s0) * ((g.n[1] + s1 - 1) / s1) * ((g.n[2] + H - 1) / H);
+    };
+    return std::max(cnt(L, W), cnt(W, L));
 }
 
-template <int S0, int S1, int S2, int W>
+// Work items per view in per-view mode: (b0, b1) columns x chunks, for the
+// orientation with more.
+static int column_items_per_view(const GridK &g, int L, int W, int H, int zc) {
+    const int nz = ((g.n[2] + H - 1) / H + zc - 1) / zc;
+    auto cnt = [&](int s0, int s1) { return ((g.n[0] + s0 - 1) / s0) * ((g.n[1] + s1 - 1) / s1) * nz; };
+    return std::max(cnt(L, W), cnt(W, L));
+}
+
+// Workspace: the per-ray table, two words of statistics and the orientation
+// per view, then the pad boxes (sized for the largest brick shape, so the
+// tuner can switch shapes on one workspace).
+static size_t pad_floats(const GridK &g) {
+    size_t m = 0;
+    for (const BrickShape &b : kBricks)
+        m = std::max(m, (size_t)bricks_per_view(g, b.L, b.W, b.H) * (size_t)(b.L + 1) *
+                            (size_t)(b.W + 1) * (size_t)(b.H + 1));
+    return m;
+}
+
+size_t project_bwd_workspace(const GridK &g, const pmf_cone_t &c, int V) {
+    return align256(sizeof(RayK) * (size_t)c.nu * (size_t)c.nv * (size_t)V) +
+           align256(sizeof(unsigned) * 2 * (size_t)V) + align256(sizeof(int) * (size_t)V) +
+           align256(sizeof(float) * pad_floats(g) * (size_t)V);
+}
+
+template <int L, int W, int H, int NW, bool MERGE, int ZC>
 static hipError_t project_bwd_bricks(const BwdJob *jobs, int n, hipStream_t s) {
-    const int SZ[3] = {S0, S1, S2};
+    constexpr int NPMAX = (L + 1) * (W + 1) * (H + 1);
     const bool sum_views = jobs[0].stride == 0;
     BwdTab t{};
     t.n = n;
@@ -929,10 +1236,14 @@ static hipError_t project_bwd_bricks(const BwdJob *jobs, int n, hipStream_t s) {
     for (int k = 0; k < n; ++k) {
         const BwdJob &j = jobs[k];
         if ((j.stride == 0) != sum_views) return hipErrorInvalidValue;
-        RayK *rays = (RayK *)j.ws;
-        unsigned *stats = (unsigned *)((char *)j.ws +
-                                       align256(sizeof(RayK) * (size_t)j.c.nu * (size_t)j.c.nv *
-                                                (size_t)j.V));
+        char *w = (char *)j.ws;
+        RayK *rays = (RayK *)w;
+        w += align256(sizeof(RayK) * (size_t)j.c.nu * (size_t)j.c.nv * (size_t)j.V);
+        unsigned *stats = (unsigned *)w;
+        w += align256(sizeof(unsigned) * 2 * (size_t)j.V);
+        int *orient = (int *)w;
+        w += align256(sizeof(int) * (size_t)j.V);
+        float *pads = (float *)w;
         // stats[2v] = 0 (max), stats[2v+1] = +inf (min)
         hipError_t e = launch_fill_pair_u32(stats, j.V, 0u, 0x7f800000u, s);
         if (e != hipSuccess) return e;
@@ -940,7 +1251,7 @@ static hipError_t project_bwd_bricks(const BwdJob *jobs, int n, hipStream_t s) {
             ProfScope prof_("ray_table", s);
             const int per_view = (j.c.nu * j.c.nv + 255) / 256;
             dim3 grid((unsigned)(per_view < 64 ? per_view : 64), (unsigned)j.V);
-            k_ray_table<<<grid, 256, 0, s>>>(j.g, j.c, j.angles, j.g_proj, rays, stats);
+            k_ray_table<<<grid, 256, 0, s>>>(j.g, j.c, j.angles, j.g_proj, rays, stats, orient);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
         BwdK &b = t.s[k];
@@ -950,15 +1261,15 @@ static hipError_t project_bwd_bricks(const BwdJob *jobs, int n, hipStream_t s) {
         b.angles = j.angles;
         b.rays = rays;
         b.stats = stats;
+        b.orient = orient;
         b.V = j.V;
         b.g_vol = j.g_vol;
         b.stride = j.stride;
-        int nb[3];
-        for (int a = 0; a < 3; ++a) nb[a] = (j.g.n[a] + SZ[a] - 1) / SZ[a];
-        b.nb1 = nb[1];
-        b.nb2 = nb[2];
-        b.nbricks = nb[0] * nb[1] * nb[2];
-        b.items = b.nbricks * (sum_views ? 1 : j.V);
+        b.pads = pads;
+        b.nbb = bricks_per_view(j.g, L, W, H);
+        b.zc = sum_views ? 1 : ZC;
+        b.nbv = sum_views ? b.nbb : column_items_per_view(j.g, L, W, H, b.zc);
+        b.items = b.nbv * (sum_views ? 1 : j.V);
         b.kb = make_bound(j.g, j.c);
         b.mk = make_march(j.g);
         b.vmax = j.vmax;
@@ -968,22 +1279,40 @@ static hipError_t project_bwd_bricks(const BwdJob *jobs, int n, hipStream_t s) {
     {
         ProfScope prof_("project_bwd", s);
         if (sum_views)
-            k_project_bwd<S0, S1, S2, true, W><<<(unsigned)t.first[n], 64 * W, 0, s>>>(t);
+            k_project_bwd<L, W, H, NW, true, MERGE, 1><<<(unsigned)t.first[n], 64 * NW, 0, s>>>(t);
         else
-            k_project_bwd<S0, S1, S2, false, W><<<(unsigned)t.first[n], 64 * W, 0, s>>>(t);
+            k_project_bwd<L, W, H, NW, false, MERGE, ZC><<<(unsigned)t.first[n], 64 * NW, 0, s>>>(t);
     }
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    for (int k = 0; k < n; ++k) {
+        const int64_t N = grid_size(t.s[k].g);
+        ProfScope prof_("project_bwd_fixup", s);
+        // blocks per view: enough to fill the chip across the views
+        const int V = sum_views ? 1 : t.s[k].V;
+        const int per_view = std::max(1, std::min(256, 2048 / V));
+        (void)N;
+        k_project_bwd_fixup<L, W, H><<<dim3((unsigned)per_view, (unsigned)V), 256, 0, s>>>(
+            t.s[k], sum_views ? 1 : 0);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    (void)NPMAX;
+    return hipSuccess;
 }
 
 hipError_t launch_project_bwd_jobs(const BwdJob *jobs, int n, hipStream_t s) {
     if (n < 1 || n > MAXS) return hipErrorInvalidValue;
+    static_assert(NBRICKS == 9, "tune candidates");
     switch (tune_get(KNOB_BACKPROJECT_BRICK)) {
-        case 1: return project_bwd_bricks<16, 16, 16, 4>(jobs, n, s);
-        case 2: return project_bwd_bricks<32, 32, 4, 8>(jobs, n, s);
-        case 3: return project_bwd_bricks<32, 32, 8, 8>(jobs, n, s);
-        case 4: return project_bwd_bricks<24, 24, 8, 8>(jobs, n, s);
-        case 5: return project_bwd_bricks<8, 8, 8, 4>(jobs, n, s);
-        default: return project_bwd_bricks<16, 16, 16, 8>(jobs, n, s);
+        case 1: return project_bwd_bricks<48, 16, 8, 8, false, 1>(jobs, n, s);
+        case 2: return project_bwd_bricks<32, 16, 8, 8, true, 1>(jobs, n, s);
+        case 3: return project_bwd_bricks<48, 16, 8, 8, true, 2>(jobs, n, s);
+        case 4: return project_bwd_bricks<48, 16, 8, 8, true, 8>(jobs, n, s);
+        case 5: return project_bwd_bricks<48, 16, 8, 8, true, 4>(jobs, n, s);
+        case 6: return project_bwd_bricks<32, 16, 8, 8, true, 4>(jobs, n, s);
+        case 7: return project_bwd_bricks<32, 32, 8, 8, true, 1>(jobs, n, s);
+        case 8: return project_bwd_bricks<48, 24, 8, 8, true, 1>(jobs, n, s);
+        default: return project_bwd_bricks<48, 16, 8, 8, true, 1>(jobs, n, s);
     }
 }
 

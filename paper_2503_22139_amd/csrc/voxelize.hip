@@ -205,16 +205,29 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t *__restrict__ cnt, 
 }
 
 // The large Gaussians in ascending index order (so that every tile adds
-// them in one fixed order): one workgroup, each thread a contiguous chunk.
-__global__ __launch_bounds__(1024) void k_large_compact(const int32_t *__restrict__ is_large,
-                                                        int64_t m, int32_t *__restrict__ large,
-                                                        int32_t *__restrict__ nlarge) {
+// them in one fixed order), by a three-step compaction: per block of 256
+// Gaussians the count of large ones, an exclusive scan of the counts (one
+// workgroup), and per block the positions of its large ones (ballots).
+__global__ __launch_bounds__(256) void k_large_count(const int32_t *__restrict__ is_large,
+                                                     int64_t m, int32_t *__restrict__ blk) {
+    __shared__ int32_t part[4];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool f = i < m && is_large[i];
+    const unsigned long long b = __ballot(f);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = __popcll(b);
+    __syncthreads();
+    if (threadIdx.x == 0) blk[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
+}
+
+// In place: blk[0..n) counts -> exclusive offsets; *total = their sum.
+__global__ __launch_bounds__(1024) void k_scan_counts(int32_t *__restrict__ blk, int n,
+                                                      int32_t *__restrict__ total) {
     __shared__ int32_t part[1024];
-    const int64_t per = (m + 1023) / 1024;
-    const int64_t b = threadIdx.x * per;
-    const int64_t e = b + per < m ? b + per : m;
+    const int per = (n + 1023) / 1024;
+    const int b = threadIdx.x * per;
+    const int e = min(b + per, n);
     int32_t s = 0;
-    for (int64_t i = b; i < e; ++i) s += is_large[i];
+    for (int i = b; i < e; ++i) s += blk[i];
     part[threadIdx.x] = s;
     __syncthreads();
     for (int o = 1; o < 1024; o <<= 1) {
@@ -223,10 +236,29 @@ __global__ __launch_bounds__(1024) void k_large_compact(const int32_t *__restric
         part[threadIdx.x] += t;
         __syncthreads();
     }
-    int32_t pos = part[threadIdx.x] - s;
-    for (int64_t i = b; i < e; ++i)
-        if (is_large[i]) large[pos++] = (int32_t)i;
-    if (threadIdx.x == 1023) *nlarge = part[1023];
+    int32_t run = part[threadIdx.x] - s;
+    for (int i = b; i < e; ++i) {
+        const int32_t c = blk[i];
+        blk[i] = run;
+        run += c;
+    }
+    if (threadIdx.x == 1023) *total = part[1023];
+}
+
+__global__ __launch_bounds__(256) void k_large_fill(const int32_t *__restrict__ is_large,
+                                                    int64_t m, const int32_t *__restrict__ blk,
+                                                    int32_t *__restrict__ large) {
+    __shared__ int32_t part[4];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool f = i < m && is_large[i];
+    const unsigned long long b = __ballot(f);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) part[w] = __popcll(b);
+    __syncthreads();
+    int base = blk[blockIdx.x];
+    for (int k = 0; k < w; ++k) base += part[k];
+    const int below = __popcll(b & ((1ull << lane) - 1ull));
+    if (f) large[base + below] = (int32_t)i;
 }
 
 __global__ __launch_bounds__(256) void k_vox_fill(int64_t m, const GaussK *__restrict__ rec,
@@ -492,6 +524,7 @@ size_t vox_workspace(const VoxPlan &p, int64_t m) {
     s += align256(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));  // large list
     s += align256(sizeof(int32_t));                            // large count
     s += align256(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));  // large flags
+    s += align256(sizeof(int32_t) * (size_t)((m + 255) / 256 + 1));   // per-block counts
     return s;
 }
 
@@ -514,6 +547,8 @@ hipError_t launch_voxelize(const pmf_gauss_t &gs, const GridK &g, float k, float
     int32_t *nlarge = (int32_t *)w;
     w += align256(sizeof(int32_t));
     int32_t *is_large = (int32_t *)w;
+    w += align256(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
+    int32_t *blk = (int32_t *)w;
 
     const float k2 = isinf(k) ? INFINITY : k * k;
     hipError_t e = launch_fill_i32(cnt, CNT_STRIDE * p.ntiles, 0, s);
@@ -527,7 +562,12 @@ hipError_t launch_voxelize(const pmf_gauss_t &gs, const GridK &g, float k, float
                 gs, g, k, p.T[0], p.T[1], p.T[2], p.nt[1], p.nt[2], p.maxtiles, rec, cnt, is_large);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        k_large_compact<<<1, 1024, 0, s>>>(is_large, m, large, nlarge);
+        const int nblk = (int)((m + 255) / 256);
+        k_large_count<<<(unsigned)nblk, 256, 0, s>>>(is_large, m, blk);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        k_scan_counts<<<1, 1024, 0, s>>>(blk, nblk, nlarge);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        k_large_fill<<<(unsigned)nblk, 256, 0, s>>>(is_large, m, blk, large);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     {

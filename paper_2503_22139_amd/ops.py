@@ -85,7 +85,7 @@ _SIGS = {
     "pmf_warp_bwd": ([_P, C.POINTER(PmfGrid), _P, C.c_int, _P, _P, _P, _P, _SZ, _P], C.c_int),
     "pmf_project": ([_P, C.c_int64, C.POINTER(PmfGrid), C.POINTER(PmfCone), _P, C.c_int, _P, _P],
                     C.c_int),
-    "pmf_project_bwd_workspace": ([C.POINTER(PmfCone), C.c_int], _SZ),
+    "pmf_project_bwd_workspace": ([C.POINTER(PmfGrid), C.POINTER(PmfCone), C.c_int], _SZ),
     "pmf_project_bwd": ([_P, C.POINTER(PmfGrid), C.POINTER(PmfCone), _P, C.c_int, _P, C.c_int64,
                          _P, _SZ, _P], C.c_int),
     "pmf_l2_loss_workspace": ([C.c_int64, C.c_int], _SZ),
@@ -391,7 +391,7 @@ def pmf_project_bwd(g_proj, grid: Grid, cone: Cone, angles, shared: bool = False
         out = _empty(shape, g_proj.device)
     g = make_grid(grid)
     cn = make_cone(cone)
-    nbytes = lib().pmf_project_bwd_workspace(C.byref(cn), V)
+    nbytes = lib().pmf_project_bwd_workspace(C.byref(g), C.byref(cn), V)
     ws = workspace(nbytes, g_proj.device)
     _check(lib().pmf_project_bwd(_ptr(g_proj.contiguous()), C.byref(g), C.byref(cn), _ptr(angles), V,
                                  _ptr(out), 0 if shared else N, C.c_void_p(ws.data_ptr()),
@@ -612,7 +612,7 @@ def pmf_autotune_project(vol, grid: Grid, cone: Cone, angles, g_proj, reps: int 
     cn = make_cone(cone)
     proj = _empty((V, cone.nv, cone.nu), vol.device)
     g_vol = _empty_like(vol)
-    nbytes = lib().pmf_project_bwd_workspace(C.byref(cn), V)
+    nbytes = lib().pmf_project_bwd_workspace(C.byref(g), C.byref(cn), V)
     ws = workspace(nbytes, vol.device)
     nt = pmf_tune_candidates(PMF_TUNE_PROJECT_TILE)
     nb = pmf_tune_candidates(PMF_TUNE_BACKPROJECT_BRICK)
@@ -636,7 +636,7 @@ def pmf_autotune(cache_path: Optional[str], vol, grid: Grid, cone: Cone, angles,
     cn = make_cone(cone)
     proj = _empty((V, cone.nv, cone.nu), vol.device)
     g_vol = _empty_like(vol)
-    nbytes = lib().pmf_project_bwd_workspace(C.byref(cn), V)
+    nbytes = lib().pmf_project_bwd_workspace(C.byref(g), C.byref(cn), V)
     ws = workspace(nbytes, vol.device)
     nt = pmf_tune_candidates(PMF_TUNE_PROJECT_TILE)
     nb = pmf_tune_candidates(PMF_TUNE_BACKPROJECT_BRICK)

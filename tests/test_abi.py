@@ -97,7 +97,7 @@ def test_project_rejects_bad_geometry(lib):
     assert lib.pmf_project(p, 0, C.byref(g), C.byref(c), p, 0, p, None) == ops.PMF_EINVAL
     assert lib.pmf_project(p, 5, C.byref(g), C.byref(c), p, 1, p, None) == ops.PMF_EINVAL  # stride < N
     assert lib.pmf_project(None, 0, C.byref(g), C.byref(c), p, 1, p, None) == ops.PMF_EINVAL
-    need = lib.pmf_project_bwd_workspace(C.byref(c), 3)
+    need = lib.pmf_project_bwd_workspace(C.byref(g), C.byref(c), 3)
     assert need >= 3 * 64 * 32
     assert lib.pmf_project_bwd(p, C.byref(g), C.byref(c), p, 3, p, 0, p, need - 1, None) == ops.PMF_EWORKSPACE
 
@@ -130,7 +130,8 @@ def test_workspace_queries_reject_invalid(lib):
     g = grid()
     assert lib.pmf_voxelize_workspace(-1, 1, C.byref(g)) == 0
     assert lib.pmf_voxelize_workspace(10, 1, None) == 0
-    assert lib.pmf_project_bwd_workspace(None, 1) == 0
+    assert lib.pmf_project_bwd_workspace(None, None, 1) == 0
+    assert lib.pmf_project_bwd_workspace(C.byref(g), None, 1) == 0
     c = ops.make_cone(Cone(1000.0, 1500.0, 8, 8, 1.0, 1.0))
     lv = (ops.PmfGrid * 1)(grid())
     assert lib.pmf_warp_project_workspace(1, 1, lv, 2, C.byref(g), C.byref(c)) >= 2 * 512 * 4
@@ -331,7 +332,7 @@ def test_graph_fill_and_autotune_reject_bad_arguments(lib):
     cn = ops.make_cone(Cone(1000.0, 1500.0, 8, 8, 1.0, 1.0))
     big = 1 << 40
     hit = C.c_int(7)
-    ms = (C.c_float * 15)()
+    ms = (C.c_float * 18)()
     assert lib.pmf_autotune(b"/nonexistent/x", p, C.byref(g), C.byref(cn), p, 0, p, p, p, p, big,
                             1, ms, C.byref(hit), None) == ops.PMF_EINVAL
     assert lib.pmf_autotune(None, p, C.byref(g), C.byref(cn), p, 2, p, p, p, p, big, 0, ms,

@@ -540,15 +540,23 @@ def test_launch_shapes_agree_and_autotune():
             p = ops.pmf_project(vol, grid, cone, ang, shared=False)
             ref_p = p.clone() if ref_p is None else ref_p
             assert torch.equal(p, ref_p), k
+        want = np.asarray(oracle.project_bwd(N(gp), grid, cone, angles))
+        want_s = want.sum(0)
+        first = {}
         for k in range(ops.pmf_tune_candidates(ops.PMF_TUNE_BACKPROJECT_BRICK)):
             ops.pmf_tune_set(ops.PMF_TUNE_BACKPROJECT_BRICK, k)
-            b = ops.pmf_project_bwd(gp, grid, cone, ang, shared=False)
-            ref_b = b.clone() if ref_b is None else ref_b
-            assert rel(N(b), N(ref_b)) < 1e-6, k
-            bs = ops.pmf_project_bwd(gp, grid, cone, ang, shared=True)
-            assert rel(N(bs), N(ref_b.sum(0))) < 1e-6, k
-        want = oracle.project_bwd(N(gp), grid, cone, angles)
-        assert rel(N(ref_b).reshape(-1), np.asarray(want).reshape(-1)) < VOL_TOL
+            b = N(ops.pmf_project_bwd(gp, grid, cone, ang, shared=False))
+            bs = N(ops.pmf_project_bwd(gp, grid, cone, ang, shared=True))
+            assert rel(b.reshape(want.shape), want) < VOL_TOL, k
+            assert rel(bs.reshape(want_s.shape), want_s) < VOL_TOL, k
+            # shapes that first sum a ray's consecutive samples in one cell
+            # (all but 1) round per merged group; within each kind the
+            # fixed-point sums repeat up to the float additions at brick faces
+            grp = k == 1
+            if grp not in first:
+                first[grp] = (b, bs)
+            assert rel(b, first[grp][0]) < 1e-6, k
+            assert rel(bs, first[grp][1]) < 1e-6, k
         res = ops.pmf_autotune_project(vol, grid, cone, ang, gp, reps=2)
         say("autotune", res)
         assert 0 <= res["project_tile"] < ops.pmf_tune_candidates(ops.PMF_TUNE_PROJECT_TILE)
