@@ -31,7 +31,15 @@ import numpy as np
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X FP32 vector (published)
-FLOP_PER_SAMPLE = 22           # trilinear sample: 7 lerps x 3 flops + 1 accumulate
+CU_COUNT = 256                 # MI355X compute units
+CLOCK_GHZ = 2.4                # MI355X peak engine clock
+# One trilinear ray-march sample costs about 33 VALU lane operations (ray
+# point, cell index and fractions, eight taps, seven lerps, the accumulate);
+# 22 of them are floating-point arithmetic (7 lerps x 3 + 1 accumulate).  Its
+# transpose in the back-projection does the same work per sample.
+OPS_PER_SAMPLE = 33
+FLOP_PER_SAMPLE = 22
+GATHER_BYTES_PER_SAMPLE = 32   # 8 taps x 4 B
 
 
 def ray_samples(grid, cone, angles) -> np.ndarray:
@@ -64,10 +72,12 @@ def ray_samples(grid, cone, angles) -> np.ndarray:
 PROFILE_COUNTERS = "profiles/motion_fwdbwd_32views_256x256x128_counters.md"
 
 
-def profiled_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (FETCH_SIZE + WRITE_SIZE, calibrated by a plain copy), or None if
-    there is none or the kernel's source file changed since it was taken."""
+def profiled_counters(kernel: str):
+    """Per-launch counters of `kernel` (a library kernel name) from the
+    committed rocprofv3 counter summary: HBM bytes (FETCH_SIZE + WRITE_SIZE,
+    calibrated by a plain copy), SQ_INSTS_VALU, SQ_WAVES, ... as a dict, or
+    None if there is no such line or the kernel's source file changed since
+    the counters were taken (sha256 prefix of the file)."""
     import hashlib
     root = os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(root, PROFILE_COUNTERS)
@@ -75,29 +85,100 @@ def profiled_traffic(kernel: str):
         return None
     best = None
     for line in open(path):
-        m = re.match(r"traffic: kernel=(\S+) grid=(\d+) source=(\S+) sha256=(\S+) hbm_bytes=(\S+)", line.strip())
-        if not m or m.group(1) != kernel:
+        line = line.strip()
+        if not line.startswith("counters: "):
             continue
-        if best is None or int(m.group(2)) > best[0]:
-            best = (int(m.group(2)), m.group(3), m.group(4), float(m.group(5)))
+        kv = dict(f.split("=", 1) for f in line[len("counters: "):].split() if "=" in f)
+        if kv.get("kernel") != kernel:
+            continue
+        if best is None or int(kv["grid"]) > int(best["grid"]):
+            best = kv
     if best is None:
         return None
-    src = os.path.join(root, best[1])
-    if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != best[2]:
+    src = os.path.join(root, best["source"])
+    if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != best["sha256"]:
         return None
-    return best[3]
+    out = {}
+    for k, v in best.items():
+        try:
+            out[k] = float(v)
+        except ValueError:
+            out[k] = v
+    return out
 
 
-def kernel_model(name, w, V, samples):
-    """Algorithmic work of one launch of a kernel in the batched step:
-    (bound, achieved-unit quantity, hbm bytes)."""
-    N = w.grid.size
-    npix = w.cone.nu * w.cone.nv
-    if name in ("project", "project_bwd"):
-        flops = FLOP_PER_SAMPLE * float(samples.sum())
-        byts = 4.0 * (V * N + V * npix)
-        return "alu", flops, byts
-    return None
+def alu_roofline(name, avg_ms, samples):
+    """Roofline entry of a ray-march kernel (project or project_bwd): the
+    33-op sample count against the FP32 vector peak, the 22-FLOP figure beside
+    it, the VALU-issue fraction and lane slots per sample from the committed
+    SQ_INSTS_VALU, the gather rate and the measured HBM traffic."""
+    S = float(samples)
+    t = avg_ms * 1e-3
+    ops_ = OPS_PER_SAMPLE * S
+    c = profiled_counters(name)
+    out = {"kernel": name, "bound": "alu", "achieved": ops_ / t / 1e12, "peak": FP32_VECTOR_PEAK_TFLOPS,
+           "unit": "TFLOP/s", "frac": ops_ / t / 1e12 / FP32_VECTOR_PEAK_TFLOPS,
+           "traffic": c["hbm_bytes"] if c else None, "avg_launch_ms": avg_ms,
+           "samples_per_launch": S, "ops_per_sample": OPS_PER_SAMPLE,
+           "flop22": {"flop_per_sample": FLOP_PER_SAMPLE, "achieved": FLOP_PER_SAMPLE * S / t / 1e12,
+                      "frac": FLOP_PER_SAMPLE * S / t / 1e12 / FP32_VECTOR_PEAK_TFLOPS},
+           "gather": {"bytes_per_launch": GATHER_BYTES_PER_SAMPLE * S,
+                      "achieved": GATHER_BYTES_PER_SAMPLE * S / t / 1e9, "unit": "GB/s"},
+           "valu_issue": None}
+    if c and "valu_insts" in c:
+        # a CU issues at most one wave64 VALU instruction per cycle (four
+        # SIMDs, four cycles each)
+        out["valu_issue"] = {"valu_insts_per_launch": c["valu_insts"],
+                             "frac": c["valu_insts"] / (CU_COUNT * CLOCK_GHZ * 1e9 * t),
+                             "lane_slots_per_sample": 64.0 * c["valu_insts"] / S}
+        if c.get("dur_ns"):
+            out["valu_issue"]["frac_profiled_duration"] = \
+                c["valu_insts"] / (CU_COUNT * CLOCK_GHZ * c["dur_ns"])
+    return out
+
+
+def hbm_phase(byts, ms):
+    return {"algorithmic_bytes": byts, "ms": ms, "achieved": byts / (ms * 1e-3) / 1e9, "unit": "GB/s",
+            "peak": HBM_PEAK_GBS, "frac": byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
+def hbm_phases(m, steps: int):
+    """HBM fractions of the phases that are HBM-bound: the MBC
+    voxelizations, the voxelization adjoints (reference + MBC) and the plain
+    schedule's per-view combine + warp, each timed on its own, serially on
+    one stream."""
+    import torch
+    from paper_2503_22139_amd import ops
+    N = m.grid.size
+    C_l = [int(g.value.shape[1]) for g in m.mbc]
+    n_l = [lg.size for lg in m.levels]
+    basis_bytes = 4.0 * sum(n * c for n, c in zip(n_l, C_l))
+    par = lambda g: 4.0 * g.mean.numel() + 4.0 * g.scale.numel() + 4.0 * g.quat.numel() + 4.0 * g.value.numel()
+
+    def vox_mbc():
+        return [ops.pmf_voxelize(g.mean, g.scale, g.quat, g.value, lg, m.k) for g, lg in zip(m.mbc, m.levels)]
+    ms4 = _timed(vox_mbc, steps)
+    a4 = hbm_phase(basis_bytes + sum(par(g) for g in m.mbc), ms4)
+    ref, bases = m.volumes()
+    g_ref = torch.ones(N, device="cuda") * 1e-3
+    g_b = [torch.full_like(b, 1e-3) for b in bases]
+
+    def vox_bwd():
+        ops.pmf_voxelize_bwd(m.ref.mean, m.ref.scale, m.ref.quat, m.ref.value, m.grid, m.k, g_ref.reshape(1, -1))
+        for g, lg, gb in zip(m.mbc, m.levels, g_b):
+            ops.pmf_voxelize_bwd(g.mean, g.scale, g.quat, g.value, lg, m.k, gb)
+    ms12 = _timed(vox_bwd, steps)
+    a12 = hbm_phase(4.0 * N + basis_bytes + 2 * (par(m.ref) + sum(par(g) for g in m.mbc)), ms12)
+
+    def plain_cw():
+        for v in range(m.V):
+            dvf = ops.pmf_combine_dvf(bases, m.levels, m.coeff[v:v + 1], m.grid)
+            ops.pmf_warp(ref, m.grid, dvf)
+    msp = _timed(plain_cw, max(2, steps // 2))
+    # per view: every basis read, I_ref read, the DVF written and read back,
+    # the warped volume written
+    pcw = hbm_phase(m.V * (basis_bytes + 4.0 * N + 2 * 12.0 * N + 4.0 * N), msp)
+    return {"a4_voxelize_mbc": a4, "a12_voxelize_bwd": a12, "plain_combine_warp": pcw}
 
 
 def _timed(fn, steps: int, warmup: int = 1) -> float:
@@ -293,12 +374,28 @@ def extras(steps: int):
     return out
 
 
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, target, views: int = 2):
-    """FP64 oracle on a bounded sample: the volumes, `views` views' fwd+bwd and
-    the voxelization adjoints; extrapolated linearly to all views."""
+    """FP64 oracle on a bounded sample, on every core the process may use:
+    the benchmark iteration (volumes, `views` views' fwd+bwd and the
+    voxelization adjoints, extrapolated linearly to all views), the C1 and C2
+    forward passes in full, the C3 forward on a few of its views
+    (extrapolated), and C1 forward again on one core."""
     sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
     import oracle
+    from paper_2503_22139_amd import synth
     oracle.build()
+    cores = len(os.sched_getaffinity(0))
+    oracle.set_threads(cores)
     cores = oracle.get_threads()
     t0 = time.perf_counter()
     ref, bases = oracle.forward_volumes(w)
@@ -327,10 +424,46 @@ def cpu_baseline(w, target, views: int = 2):
         oracle.voxelize_bwd(s, g, w.trunc_k, gb)
     t_vb = time.perf_counter() - t2
     t_iter = t_vol + len(w.angles) * t_view + t_vb
+    print(f"[bench] cpu baseline: iteration {t_iter:.1f} s (extrapolated)", file=sys.stderr, flush=True)
+
+    def fwd_proj(wk):
+        vol = oracle.voxelize(wk.ref, wk.grid, wk.trunc_k)[0]
+        return oracle.project(vol, wk.grid, wk.cone, wk.angles)
+
+    c1 = synth.c1()
+    t = time.perf_counter()
+    fwd_proj(c1)
+    t_c1 = time.perf_counter() - t
+    c2 = synth.c2()
+    t = time.perf_counter()
+    fwd_proj(c2)
+    t_c2 = time.perf_counter() - t
+    c3 = synth.c3()
+    n3 = 2
+    t = time.perf_counter()
+    oracle.forward(c3, views=list(range(n3)))
+    t_c3s = time.perf_counter() - t
+    t = time.perf_counter()
+    oracle.forward_volumes(c3)
+    t_c3v = time.perf_counter() - t
+    t_c3 = t_c3v + (t_c3s - t_c3v) * len(c3.angles) / n3
+    oracle.set_threads(1)
+    t = time.perf_counter()
+    fwd_proj(c1)
+    t_c1_1 = time.perf_counter() - t
+    oracle.set_threads(cores)
+    print(f"[bench] cpu baseline: c1 {t_c1:.2f} s, c2 {t_c2:.2f} s, c3 {t_c3:.2f} s, c1 on one core "
+          f"{t_c1_1:.2f} s", file=sys.stderr, flush=True)
     return {"value": 1.0 / t_iter, "unit": "iterations/s", "cores": cores, "kind": "oracle",
+            "cpu_model": _cpu_model(),
             "sample": (f"FP64 oracle: volumes ({t_vol:.2f} s) + {views} of {len(w.angles)} views "
                        f"fwd+bwd ({t_view:.2f} s/view) + voxelization adjoints ({t_vb:.2f} s), "
-                       f"extrapolated linearly to {len(w.angles)} views = {t_iter:.1f} s/iteration")}
+                       f"extrapolated linearly to {len(w.angles)} views = {t_iter:.1f} s/iteration"),
+            "c1_forward_s": t_c1, "c2_forward_s": t_c2,
+            "c3_forward_s": t_c3,
+            "c3_sample": (f"volumes {t_c3v:.2f} s + {n3} of {len(c3.angles)} views, extrapolated "
+                          f"linearly"),
+            "c1_forward_1core_s": t_c1_1}
 
 
 def main():
@@ -344,6 +477,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the other configurations")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
+    ap.add_argument("--tune-cache", default=os.path.join("/tmp", f"pmf_tune_{os.getuid()}.txt"),
+                    help="the autotuner's shape cache ('' for none)")
     ap.add_argument("--no-graph", action="store_true",
                     help="time the eager batched steps instead of graph replays (for counter runs)")
     args = ap.parse_args()
@@ -377,7 +512,7 @@ def main():
         # launch shapes for this geometry, timed on per-view volumes of its size
         vol = torch.from_numpy(synth.random_volume(7, (V,) + tuple(w.grid.n))).cuda()
         gp = torch.from_numpy(synth.random_normal(8, (V, w.cone.nv, w.cone.nu))).cuda()
-        tuned = ops.pmf_autotune_project(vol, w.grid, w.cone, m.angles, gp, reps=2)
+        tuned = ops.pmf_autotune(args.tune_cache or None, vol, w.grid, w.cone, m.angles, gp, reps=2)
         del vol, gp
         torch.cuda.empty_cache()
         print(f"[bench] autotune {tuned}", file=sys.stderr, flush=True)
@@ -436,18 +571,19 @@ def main():
         ms_plain = (time.perf_counter() - t0) / args.plain_steps * 1e3
         print(f"[bench] plain {ms_plain:.2f} ms/step", file=sys.stderr, flush=True)
 
-    samples = ray_samples(w.grid, w.cone, w.angles)
-    dom = max((k for k in kern if kernel_model(k, w, V, samples)), key=lambda k: kern[k]["ms_per_step"])
-    bound, flops, byts = kernel_model(dom, w, V, samples)
-    avg_s = kern[dom]["avg_ms"] * 1e-3
-    achieved = flops / avg_s / 1e12
-    traffic = profiled_traffic(dom)
-    roof = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": traffic,
-            "avg_launch_ms": kern[dom]["avg_ms"], "algorithmic_flop": flops,
-            "hbm": {"achieved": byts / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": byts / avg_s / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes": byts,
-                    "measured_traffic_GBps": (traffic / avg_s / 1e9) if traffic else None}}
+    samples = float(ray_samples(w.grid, w.cone, w.angles).sum())
+    # the dominant kernel of the step and the forward projection beside it
+    march = [k for k in ("project_bwd", "project") if k in kern]
+    dom = max(march, key=lambda k: kern[k]["ms_per_step"])
+    roof = alu_roofline(dom, kern[dom]["avg_ms"], samples)
+    N = w.grid.size
+    byts = 4.0 * (V * N + V * w.cone.nu * w.cone.nv)
+    roof["hbm"] = {"algorithmic_bytes": byts, "achieved": byts / (kern[dom]["avg_ms"] * 1e-3) / 1e9,
+                   "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                   "frac": byts / (kern[dom]["avg_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    others = {k: alu_roofline(k, kern[k]["avg_ms"], samples) for k in march if k != dom}
+    print(f"[bench] hbm phases", file=sys.stderr, flush=True)
+    phases = hbm_phases(m, max(3, min(args.steps, 10)))
 
     out = {
         "metric": "fwd+bwd iterations/s (32 views, 256²×128) batched vs plain; % HBM roofline",
@@ -474,6 +610,8 @@ def main():
         "loss": float(loss),
         "kernels": kern,
         "roofline": roof,
+        "roofline_other": others,
+        "hbm_phases": phases,
     }
     out["tuned"] = tuned
     if not args.no_extras:
