@@ -384,12 +384,15 @@ size_t pmf_profile_names(char *buf, size_t len);
  *                              sample alone, 2 = 32x16x8, 3, 4 (default), 5
  *                              = 48x16x8 walked in chunks of 2, 8, 4 bricks
  *                              along z by one workgroup, 6 = 32x16x8 in
- *                              chunks of 4, 7 = 32x32x8, 8 = 48x24x8.
+ *                              chunks of 4, 7 = 32x32x8, 8 = 48x24x8;
+ *   PMF_TUNE_VOXELIZE_BWD      Gaussians per wavefront in pmf_voxelize_bwd:
+ *                              0 = chosen from the set's size (default),
+ *                              k = 1..7: 2^(k-1).
  * pmf_tune_candidates returns the number of choices of a knob (0 for an
  * unknown knob); pmf_tune_set returns the previous choice or PMF_EINVAL for an
  * unknown knob or a choice out of range; pmf_tune_get returns the current
  * choice.  Not to be changed while another thread launches library work. */
-enum { PMF_TUNE_PROJECT_TILE = 0, PMF_TUNE_BACKPROJECT_BRICK = 1 };
+enum { PMF_TUNE_PROJECT_TILE = 0, PMF_TUNE_BACKPROJECT_BRICK = 1, PMF_TUNE_VOXELIZE_BWD = 2 };
 int pmf_tune_candidates(int knob);
 int pmf_tune_get(int knob);
 int pmf_tune_set(int knob, int choice);

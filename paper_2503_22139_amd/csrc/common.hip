@@ -42,8 +42,8 @@ ProfScope::~ProfScope() {
 int profile_enable(int on) { return g_prof_on.exchange(on ? 1 : 0); }
 
 // ------------------------------------------------------------- launch shapes
-static const int g_tune_count[KNOB_COUNT] = {9, 9};
-static std::atomic<int> g_tune[KNOB_COUNT] = {{5}, {4}};
+static const int g_tune_count[KNOB_COUNT] = {9, 9, 8};
+static std::atomic<int> g_tune[KNOB_COUNT] = {{5}, {4}, {0}};
 
 int tune_candidates(int knob) { return knob >= 0 && knob < KNOB_COUNT ? g_tune_count[knob] : 0; }
 

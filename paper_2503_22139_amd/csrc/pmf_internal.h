@@ -181,6 +181,31 @@ __device__ __forceinline__ float wave_sum_lane63(float v) {
     return v;
 }
 
+// Orders the LDS accesses of one wavefront (a compiler barrier: the hardware
+// performs a wavefront's LDS operations in order).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ int dpp_i(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROW_MASK, 0xf, true);
+}
+
+// Inclusive prefix sum over the 64 lanes (lanes shifted in from outside a
+// row read 0).
+__device__ __forceinline__ int wave_incl_sum(int x) {
+    x += dpp_i<0x111>(x);          // row_shr:1
+    x += dpp_i<0x112>(x);          // row_shr:2
+    x += dpp_i<0x114>(x);          // row_shr:4
+    x += dpp_i<0x118>(x);          // row_shr:8
+    x += dpp_i<0x142, 0xa>(x);     // row_bcast:15 into rows 1, 3
+    x += dpp_i<0x143, 0xc>(x);     // row_bcast:31 into rows 2, 3
+    return x;
+}
+
 // Reduce-scatter of 32 per-lane values over the 64 lanes of a wave: returns
 // the total over all lanes of value 16*b3 + 8*b2 + 4*b1 + 2*b0 + b4 (b_k =
 // bit k of the lane; the same total in lanes L and L+32).  Each step pairs
@@ -385,7 +410,12 @@ size_t profile_names(char *buf, size_t len);
 // ------------------------------------------------------------- launch shapes
 // Process-wide choice of launch shape per tunable kernel (index into that
 // kernel's candidate list); set by pmf_tune_set or the autotuner.
-enum Knob { KNOB_PROJECT_TILE = 0, KNOB_BACKPROJECT_BRICK = 1, KNOB_COUNT = 2 };
+enum Knob {
+    KNOB_PROJECT_TILE = 0,
+    KNOB_BACKPROJECT_BRICK = 1,
+    KNOB_VOXELIZE_BWD = 2,
+    KNOB_COUNT = 3
+};
 int tune_get(int knob);
 int tune_set(int knob, int value);   // returns the previous value, or -1 if out of range
 int tune_candidates(int knob);

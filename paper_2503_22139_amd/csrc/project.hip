@@ -437,31 +437,6 @@ __device__ __forceinline__ void fma_in_place(float &acc, float k, float e) {
 // atomics.
 __device__ __forceinline__ void lds_wait() { __builtin_amdgcn_s_waitcnt(0xc07f); }  // lgkmcnt(0)
 
-// Orders the LDS accesses of one wavefront (a compiler barrier: the hardware
-// performs a wavefront's LDS operations in order).
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-template <int CTRL, int ROW_MASK = 0xf>
-__device__ __forceinline__ int dpp_i(int v) {
-    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROW_MASK, 0xf, true);
-}
-
-// Inclusive prefix sum over the 64 lanes (lanes shifted in from outside a
-// row read 0).
-__device__ __forceinline__ int wave_incl_sum(int x) {
-    x += dpp_i<0x111>(x);          // row_shr:1
-    x += dpp_i<0x112>(x);          // row_shr:2
-    x += dpp_i<0x114>(x);          // row_shr:4
-    x += dpp_i<0x118>(x);          // row_shr:8
-    x += dpp_i<0x142, 0xa>(x);     // row_bcast:15 into rows 1, 3
-    x += dpp_i<0x143, 0xc>(x);     // row_bcast:31 into rows 2, 3
-    return x;
-}
-
 // One ray's owned run, staged in LDS for the lanes that take its samples:
 // item q of the wave's flattened list is sample q + off of the ray.
 struct RunP {

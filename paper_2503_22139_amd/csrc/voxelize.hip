@@ -1,26 +1,31 @@
 // voxelize.hip -- Eq. 5 (Gaussian voxelization) and its gradient.
 //
-// Forward: tile-binned splatting into LDS.  Each Gaussian's truncation
-// ellipsoid is bounded by a box of voxels; Gaussians are binned into the
-// tiles their box overlaps (count, scan, fill).  One workgroup owns a tile:
-// its waves take the tile's Gaussians one at a time (parameters wave-uniform,
-// held in scalar registers), evaluate them over box-and-tile column by column
-// and add into an LDS copy of the tile in fixed point; the tile is then
-// stored once with plain coalesced writes -- no global atomics.  Gaussians
-// whose box spans more tiles than the bin capacity (e.g. untruncated ones) go
-// to a separate list in ascending order, which every tile walks after its own
-// list, adding in float per voxel in that order; neither sum depends on the
-// order in which the binning's atomics filled the tile lists.
+// Forward: tile-binned.  Each Gaussian's truncation ellipsoid is bounded by
+// a box of voxels; Gaussians are binned into the tiles their box overlaps
+// (count, scan, fill).  One workgroup owns a tile.  One-channel sets (the
+// reference, ~150 Gaussians per tile) are splatted: the waves lay the
+// (Gaussian, column) pairs of batches of the tile's Gaussians over their
+// lanes and add into an LDS copy of the tile in fixed point.  Three- and
+// nine-channel sets (the MBC bases, ~10 Gaussians per tile) are gathered:
+// each thread owns a few voxels and keeps their channel sums in registers.
+// Either way the tile is stored once with plain writes -- no global atomics
+// -- and the integer sums do not depend on the order in which the binning's
+// atomics filled the tile lists.  Gaussians whose box spans more tiles than
+// the bin capacity (e.g. untruncated ones) go to a separate list in
+// ascending order, which every tile walks after its own list, adding in
+// float per voxel in that order.
 //
-// Backward: Gaussian owner.  One wave per Gaussian walks the same voxel box,
-// accumulates the per-Gaussian sums in registers and reduces them across the
-// wave; lane 0 applies the chain rule through Sigma = R diag(s^2) R^T and the
-// quaternion normalisation.
+// Backward: Gaussian owner.  A wave takes a batch of Gaussians, walks each
+// one's voxel box, accumulates the per-Gaussian sums in registers and
+// reduces them across the wave; one lane per Gaussian applies the chain rule
+// through Sigma = R diag(s^2) R^T and the quaternion normalisation.
 #include <math.h>
 
 #include "pmf_internal.h"
 
 namespace pmf {
+
+constexpr int MAXC_VOX = 16;     // channels per Gaussian set (voxelize_workspace checks)
 
 struct alignas(16) GaussK {
     float mu[3];
@@ -113,13 +118,6 @@ __device__ __forceinline__ bool far_from_grid(const float *__restrict__ mean,
         far = far || d + ext < -3.0f * g.h[a] || d - ext > (float)(g.n[a] + 2) * g.h[a];
     }
     return far;
-}
-
-__device__ __forceinline__ float quad(const GaussK &p, float d0, float d1, float d2) {
-    const float t0 = fmaf(p.a00, d0, fmaf(p.a01, d1, p.a02 * d2));
-    const float t1 = fmaf(p.a01, d0, fmaf(p.a11, d1, p.a12 * d2));
-    const float t2 = fmaf(p.a02, d0, fmaf(p.a12, d1, p.a22 * d2));
-    return fmaf(d0, t0, fmaf(d1, t1, d2 * t2));
 }
 
 // ---------------------------------------------------------------- binning
@@ -281,60 +279,41 @@ __global__ __launch_bounds__(256) void k_vox_fill(int64_t m, const GaussK *__res
 }
 
 // ------------------------------------------------------------ tile splat
-// z range [za, zb] of column (ix, iy) that the truncation ellipsoid can
-// reach: the roots of the quadratic in d2, widened by one voxel on each side
-// and clipped to [lo2, hi2]; false when the column's quadratic stays clearly
+// On a column (d0, d1 fixed) the quadratic form is m(d2) = a22 d2^2 + b2 d2
+// + cq; the forward and the adjoint evaluate it in this form, so both take
+// the same mask decisions.
+__device__ __forceinline__ void col_coeffs(float a00, float a01, float a02, float a11, float a12,
+                                           float d0, float d1, float &b2, float &cq) {
+    b2 = 2.0f * fmaf(a02, d0, a12 * d1);
+    cq = fmaf(a00 * d0, d0, fmaf(2.0f * a01 * d0, d1, a11 * d1 * d1));
+}
+
+__device__ __forceinline__ float col_quad(float a22, float b2, float cq, float d2) {
+    return fmaf(fmaf(a22, d2, b2), d2, cq);
+}
+
+// z range [za, zb] of a column that the truncation ellipsoid m <= k2 can
+// reach: the roots of m(d2) = k2, widened by one voxel on each side and
+// clipped to [lo2, hi2]; false when the column's quadratic stays clearly
 // above k2.  Untruncated sets take the whole range.
-__device__ __forceinline__ bool col_range(const GaussK &p, const GridK &g, float k2, bool untrunc,
-                                          float d0, float d1, int lo2, int hi2, int &za,
+__device__ __forceinline__ bool col_range(float a22, float b2, float cq, float zc, float inv_h2,
+                                          float k2, bool untrunc, int lo2, int hi2, int &za,
                                           int &zb) {
     za = lo2;
     zb = hi2;
     if (untrunc) return true;
-    // quad(d0, d1, d2) = a22 d2^2 + 2 bh d2 + cq
-    const float bh = fmaf(p.a02, d0, p.a12 * d1);
-    const float cq = fmaf(p.a00 * d0, d0, fmaf(2.0f * p.a01 * d0, d1, p.a11 * d1 * d1));
-    float disc = fmaf(bh, bh, -p.a22 * (cq - k2));
-    const float tol = 1e-4f * (fmaf(bh, bh, p.a22 * (fabsf(cq) + k2)));
+    const float bh = 0.5f * b2;
+    float disc = fmaf(bh, bh, -a22 * (cq - k2));
+    const float tol = 1e-4f * (fmaf(bh, bh, a22 * (fabsf(cq) + k2)));
     if (disc < -tol) return false;
     disc = fmaxf(disc, 0.0f);
-    const float r = sqrtf(disc), inv_a = 1.0f / p.a22;
-    // d2 range -> voxel index range: iz = (mu2 + d2 - c0_2) / h2
-    const float inv_h2 = g.inv_h[2];
-    const float zc = (p.mu[2] - g.c0[2]) * inv_h2;
+    const float r = sqrtf(disc), inv_a = 1.0f / a22;
+    // d2 range -> voxel index range: iz = zc + d2 / h2, zc = (mu2 - c0_2) / h2
     const float t_lo = zc + (-bh - r) * inv_a * inv_h2;
     const float t_hi = zc + (-bh + r) * inv_a * inv_h2;
     za = max(za, (int)floorf(t_lo) - 1);
     zb = min(zb, (int)ceilf(t_hi) + 1);
     return true;
-}
-
-// Evaluate a Gaussian over the voxel box [lo, hi] (inclusive) by (x, y)
-// column: each lane takes a column and walks only its col_range, testing
-// every voxel it visits with quad(); add(ix, iy, iz, e) for each in-mask
-// voxel.
-template <typename Add>
-__device__ __forceinline__ void splat_cols(const GaussK &p, const GridK &g, float k2, int lo0,
-                                           int lo1, int lo2, int hi0, int hi1, int hi2, Add add) {
-    const int lane = threadIdx.x & 63;
-    const int ny = hi1 - lo1 + 1;
-    const int ncol = (hi0 - lo0 + 1) * ny;
-    const bool untrunc = isinf(k2);
-    for (int c0 = 0; c0 < ncol; c0 += 64) {
-        const int col = c0 + lane;
-        if (col >= ncol) continue;
-        const int ix = lo0 + col / ny, iy = lo1 + col % ny;
-        const float d0 = fmaf((float)ix, g.h[0], g.c0[0]) - p.mu[0];
-        const float d1 = fmaf((float)iy, g.h[1], g.c0[1]) - p.mu[1];
-        int za, zb;
-        if (!col_range(p, g, k2, untrunc, d0, d1, lo2, hi2, za, zb)) continue;
-        for (int iz = za; iz <= zb; ++iz) {
-            const float d2 = fmaf((float)iz, g.h[2], g.c0[2]) - p.mu[2];
-            const float mm = quad(p, d0, d1, d2);
-            if (!(mm <= k2)) continue;
-            add(ix, iy, iz, __expf(-0.5f * mm));
-        }
-    }
 }
 
 // One workgroup per tile.  Accumulation is in 32-bit fixed point with
@@ -343,28 +322,43 @@ __device__ __forceinline__ void splat_cols(const GaussK &p, const GridK &g, floa
 // largest |value|), which bounds every voxel's sum since each Gaussian adds
 // value * e (e <= 1) at most once per voxel, and is itself independent of
 // the list's order.
-constexpr int VT_CHUNK = 128;      // Gaussians staged in LDS at a time (one per thread)
+//
+// Work layout: each wave takes batches of up to VB of the tile's Gaussians
+// (lane j < VB reads batch entry j, clips its box to the tile and stages it
+// in LDS), then lays the batch's (Gaussian, column) pairs out over its
+// lanes, 64 at a time: a lane finds its pair by a search over the batch's
+// column offsets, walks the column's z range (col_range: nearly every voxel
+// it visits is inside the ellipsoid) and adds value x e^(-m/2) of each
+// in-mask voxel.  The lanes are spread over the columns of many Gaussians,
+// not one Gaussian's few.
+constexpr int VB = 16;
 
-// STAGE: the tile's Gaussians go through LDS VT_CHUNK at a time (one-channel
-// sets, ~125 Gaussians per 8x16x16 tile); otherwise each wave reads its
-// Gaussians directly (the many-channel MBC sets have ~16 per tile, where the
-// barriers and the LDS cost more than they save).
-template <bool STAGE>
+struct VoxB {                 // one Gaussian of a wave's batch, box clipped to the tile
+    float mu[3];
+    float a00, a01, a02, a11, a12, a22;
+    int lo0, lo1, lo2, hi2, ny, cend;    // its columns are [cend - ncols, cend)
+    int ncols;
+};
+
+template <int T0, int T1, int T2, int CT>
 __global__ __launch_bounds__(256) void k_vox_tile(const GaussK *__restrict__ rec,
-                                                  const float *__restrict__ value, int C, GridK g,
-                                                  float k2, int T0, int T1, int T2, int nt1,
-                                                  int nt2, const int32_t *__restrict__ off,
+                                                  const float *__restrict__ value, int Crt, GridK g,
+                                                  float k2, int nt1, int nt2,
+                                                  const int32_t *__restrict__ off,
                                                   const int32_t *__restrict__ list,
                                                   const int32_t *__restrict__ large,
                                                   const int32_t *__restrict__ nlarge,
                                                   float *__restrict__ vol) {
-    extern __shared__ int acc[];          // C tile planes, then VT_CHUNK x C staged values
-    __shared__ float cs[4][16];
-    __shared__ float scale[16];
-    __shared__ GaussK gsh[STAGE ? VT_CHUNK : 1];
-    const int tvox = T0 * T1 * T2;
-    float *const vsh = (float *)(acc + C * tvox);
-    for (int i = threadIdx.x; i < C * tvox; i += blockDim.x) acc[i] = 0;
+    constexpr int TV = T0 * T1 * T2;
+    constexpr int NW = 4;
+    constexpr int CM = CT > 0 ? CT : MAXC_VOX;
+    const int C = CT > 0 ? CT : Crt;
+    extern __shared__ int acc[];          // C tile planes
+    __shared__ float cs[NW][CM];
+    __shared__ float scale[CM];
+    __shared__ VoxB bt[NW][VB];
+    __shared__ float bv[NW][VB][CM];      // value x scale per batch entry
+    for (int i = threadIdx.x; i < C * TV; i += 256) acc[i] = 0;
     const int t = blockIdx.x;
     const int tz = t % nt2, ty = (t / nt2) % nt1, tx = t / (nt2 * nt1);
     const int b0 = tx * T0, b1 = ty * T1, b2 = tz * T2;
@@ -373,7 +367,6 @@ __global__ __launch_bounds__(256) void k_vox_tile(const GaussK *__restrict__ rec
     const int beg = off[t], end = off[t + 1];
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int nw = blockDim.x >> 6;
     const int nl = *nlarge;
     // per-channel bound S = (the tile's list length) x (the list's largest
     // |value|): every voxel's sum stays below it, and unlike a float sum of
@@ -381,7 +374,7 @@ __global__ __launch_bounds__(256) void k_vox_tile(const GaussK *__restrict__ rec
     // the list, so neither does the scale (results repeat bit for bit)
     for (int c = 0; c < C; ++c) {
         float mx = 0.0f;
-        for (int e = beg + (int)threadIdx.x; e < end; e += blockDim.x)
+        for (int e = beg + (int)threadIdx.x; e < end; e += 256)
             mx = fmaxf(mx, fabsf(value[(int64_t)list[e] * C + c]));
         mx = wave_max(mx);
         if (lane == 0) cs[wave][c] = mx;
@@ -393,52 +386,89 @@ __global__ __launch_bounds__(256) void k_vox_tile(const GaussK *__restrict__ rec
         const float S = (float)(end - beg) * mx;
         scale[threadIdx.x] = S > 0.0f ? 1073741824.0f / (S * 1.0001f) : 0.0f;
     }
-    // Staged: each thread fetches one record and its values, so a wave does
-    // not wait for two dependent global reads per Gaussian; the integer sums
-    // do not depend on the order.
-    if constexpr (!STAGE) {
-        __syncthreads();
-        for (int e = beg + wave; e < end; e += nw) {
-            const int gi = __builtin_amdgcn_readfirstlane(list[e]);
+    __syncthreads();
+    const bool untrunc = isinf(k2);
+    const float inv_h2 = g.inv_h[2];
+    VoxB *const B = bt[wave];
+    for (int eb = beg + wave * VB; eb < end; eb += NW * VB) {     // uniform per wave
+        const int nb = min(VB, end - eb);
+        int ncols = 0;
+        VoxB q;
+        if (lane < nb) {
+            const int gi = list[eb + lane];
             const GaussK p = rec[gi];
             const int lo0 = max(p.lo0, b0), lo1 = max(p.lo1, b1), lo2 = max(p.lo2, b2);
             const int hi0 = min(p.hi0, e0), hi1 = min(p.hi1, e1), hi2 = min(p.hi2, e2);
-            if (lo0 > hi0 || lo1 > hi1 || lo2 > hi2) continue;
+            if (lo0 <= hi0 && lo1 <= hi1 && lo2 <= hi2) ncols = (hi0 - lo0 + 1) * (hi1 - lo1 + 1);
+            for (int a = 0; a < 3; ++a) q.mu[a] = p.mu[a];
+            q.a00 = p.a00;
+            q.a01 = p.a01;
+            q.a02 = p.a02;
+            q.a11 = p.a11;
+            q.a12 = p.a12;
+            q.a22 = p.a22;
+            q.lo0 = lo0;
+            q.lo1 = lo1;
+            q.lo2 = lo2;
+            q.hi2 = hi2;
+            q.ny = hi1 - lo1 + 1;
+            q.ncols = ncols;
             const float *vv = value + (int64_t)gi * C;
-            splat_cols(p, g, k2, lo0, lo1, lo2, hi0, hi1, hi2, [&](int ix, int iy, int iz, float ev) {
-                const int li = ((ix - b0) * T1 + (iy - b1)) * T2 + (iz - b2);
-                for (int c = 0; c < C; ++c)
-                    atomicAdd(&acc[c * tvox + li], __float2int_rn(vv[c] * scale[c] * ev));
-            });
+            for (int c = 0; c < C; ++c) bv[wave][lane][c] = vv[c] * scale[c];
         }
-    }
-    for (int cb = beg; STAGE && cb < end; cb += VT_CHUNK) {
-        const int n = min(VT_CHUNK, end - cb);
-        __syncthreads();
-        if ((int)threadIdx.x < n) {
-            const int gi = list[cb + threadIdx.x];
-            gsh[threadIdx.x] = rec[gi];
-            for (int c = 0; c < C; ++c) vsh[threadIdx.x * C + c] = value[(int64_t)gi * C + c];
+        const int cend = wave_incl_sum(ncols);          // lanes >= nb add 0
+        const int total = __builtin_amdgcn_readlane(cend, VB - 1);
+        if (lane < nb) {
+            q.cend = cend;
+            B[lane] = q;
+        } else if (lane < VB) {          // the search reads every entry's cend
+            B[lane].cend = cend;
+            B[lane].ncols = 0;
         }
-        __syncthreads();
-        for (int e = wave; e < n; e += nw) {
-            GaussK p = gsh[e];
-            const int lo0 = max(p.lo0, b0), lo1 = max(p.lo1, b1), lo2 = max(p.lo2, b2);
-            const int hi0 = min(p.hi0, e0), hi1 = min(p.hi1, e1), hi2 = min(p.hi2, e2);
-            if (lo0 > hi0 || lo1 > hi1 || lo2 > hi2) continue;
-            const float *vv = vsh + e * C;
-            splat_cols(p, g, k2, lo0, lo1, lo2, hi0, hi1, hi2, [&](int ix, int iy, int iz, float ev) {
-                const int li = ((ix - b0) * T1 + (iy - b1)) * T2 + (iz - b2);
-                for (int c = 0; c < C; ++c)
-                    atomicAdd(&acc[c * tvox + li], __float2int_rn(vv[c] * scale[c] * ev));
-            });
+        wave_lds_sync();
+        for (int cb = 0; cb < total; cb += 64) {           // uniform per wave
+            const int qc = cb + lane;
+            if (qc >= total) continue;
+            // batch entry: the smallest j with cend_j > qc
+            int j = 0;
+#pragma unroll
+            for (int step = VB / 2; step > 0; step >>= 1)
+                if (B[j + step - 1].cend <= qc) j += step;
+            const VoxB &q = B[j];
+            const int ql = qc - (q.cend - q.ncols);
+            // column ql of the clipped box, y fastest (exact: ql < 256, ny <= 16)
+            const int cx = (int)(((float)ql + 0.5f) * __builtin_amdgcn_rcpf((float)q.ny));
+            const int ix = q.lo0 + cx, iy = q.lo1 + (ql - cx * q.ny);
+            const float d0 = fmaf((float)ix, g.h[0], g.c0[0]) - q.mu[0];
+            const float d1 = fmaf((float)iy, g.h[1], g.c0[1]) - q.mu[1];
+            float cb2, cq;
+            col_coeffs(q.a00, q.a01, q.a02, q.a11, q.a12, d0, d1, cb2, cq);
+            int za, zb;
+            if (!col_range(q.a22, cb2, cq, (q.mu[2] - g.c0[2]) * inv_h2, inv_h2, k2, untrunc,
+                           q.lo2, q.hi2, za, zb))
+                continue;
+            const float a22 = q.a22, mu2 = q.mu[2];
+            float vs[CM];
+#pragma unroll
+            for (int c = 0; c < CM; ++c) vs[c] = c < C ? bv[wave][j][c] : 0.0f;
+            int li = ((ix - b0) * T1 + (iy - b1)) * T2 + (za - b2);
+            for (int iz = za; iz <= zb; ++iz, ++li) {
+                const float d2 = fmaf((float)iz, g.h[2], g.c0[2]) - mu2;
+                const float mm = col_quad(a22, cb2, cq, d2);
+                if (!(mm <= k2)) continue;
+                const float ev = __expf(-0.5f * mm);
+#pragma unroll
+                for (int c = 0; c < CM; ++c)
+                    if (c < C) atomicAdd(&acc[c * TV + li], __float2int_rn(vs[c] * ev));
+            }
         }
+        wave_lds_sync();
     }
     __syncthreads();
     // fixed point -> float, in place
     float *const accf = (float *)acc;
-    for (int i = threadIdx.x; i < C * tvox; i += blockDim.x) {
-        const float sc = scale[i / tvox];
+    for (int i = threadIdx.x; i < C * TV; i += 256) {
+        const float sc = scale[i / TV];
         accf[i] = sc > 0.0f ? (float)acc[i] / sc : 0.0f;
     }
     // Gaussians too large for the bins (e.g. untruncated sets): each thread
@@ -446,7 +476,7 @@ __global__ __launch_bounds__(256) void k_vox_tile(const GaussK *__restrict__ rec
     // order (a fixed order: the results repeat bit for bit)
     if (nl > 0) {
         __syncthreads();
-        for (int li = threadIdx.x; li < tvox; li += blockDim.x) {
+        for (int li = threadIdx.x; li < TV; li += 256) {
             const int ix = b0 + li / (T1 * T2), iy = b1 + (li / T2) % T1, iz = b2 + li % T2;
             if (ix > e0 || iy > e1 || iz > e2) continue;
             const float d0g = fmaf((float)ix, g.h[0], g.c0[0]);
@@ -458,23 +488,153 @@ __global__ __launch_bounds__(256) void k_vox_tile(const GaussK *__restrict__ rec
                 if (ix < p.lo0 || ix > p.hi0 || iy < p.lo1 || iy > p.hi1 || iz < p.lo2 ||
                     iz > p.hi2)
                     continue;
-                const float mm = quad(p, d0g - p.mu[0], d1g - p.mu[1], d2g - p.mu[2]);
+                float cb2, cq;
+                col_coeffs(p.a00, p.a01, p.a02, p.a11, p.a12, d0g - p.mu[0], d1g - p.mu[1], cb2, cq);
+                const float mm = col_quad(p.a22, cb2, cq, d2g - p.mu[2]);
                 if (!(mm <= k2)) continue;
                 const float ev = __expf(-0.5f * mm);
                 const float *vv = value + (int64_t)gi * C;
-                for (int c = 0; c < C; ++c) accf[c * tvox + li] += vv[c] * ev;
+                for (int c = 0; c < C; ++c) accf[c * TV + li] += vv[c] * ev;
             }
         }
     }
     __syncthreads();
     const int64_t N = grid_size(g);
-    for (int i = threadIdx.x; i < C * tvox; i += blockDim.x) {
-        const int c = i / tvox, li = i % tvox;
+    for (int i = threadIdx.x; i < C * TV; i += 256) {
+        const int c = i / TV, li = i % TV;
         const int z = li % T2, y = (li / T2) % T1, x = li / (T2 * T1);
         const int gx = b0 + x, gy = b1 + y, gz = b2 + z;
         if (gx < g.n[0] && gy < g.n[1] && gz < g.n[2])
             vol[(int64_t)c * N + ((int64_t)gx * g.n[1] + gy) * g.n[2] + gz] = accf[i];
     }
+}
+
+// Multi-channel sets (the MBC bases: few Gaussians per tile, 3 or 9
+// channels): voxel owners.  A thread owns SEG consecutive voxels of one
+// column of the tile and keeps their channel sums in registers, in the same
+// 32-bit fixed point and with the same per-term rounding as k_vox_tile (so
+// the two give the same bits, and the sums do not depend on the order of the
+// tile's list); the tile's Gaussians are staged in LDS a chunk at a time and
+// every thread tests each against its voxels.  No LDS accumulator, no
+// atomics: the kernel holds little LDS and keeps many tiles in flight.
+constexpr int VG_CHUNK = 64;
+
+template <int T0, int T1, int T2, int CT>
+__global__ __launch_bounds__(256) void k_vox_gather(const GaussK *__restrict__ rec,
+                                                    const float *__restrict__ value, GridK g,
+                                                    float k2, int nt1, int nt2,
+                                                    const int32_t *__restrict__ off,
+                                                    const int32_t *__restrict__ list,
+                                                    const int32_t *__restrict__ large,
+                                                    const int32_t *__restrict__ nlarge,
+                                                    float *__restrict__ vol) {
+    constexpr int TV = T0 * T1 * T2;
+    constexpr int SEG = TV / 256;           // voxels per thread (along z)
+    constexpr int NS = T2 / SEG;            // threads per column
+    static_assert(SEG >= 1 && T2 % SEG == 0 && TV % 256 == 0, "tile shape");
+    __shared__ GaussK gsh[VG_CHUNK];
+    __shared__ float gvs[VG_CHUNK][CT];
+    __shared__ float cs[4][CT];
+    __shared__ float scale[CT];
+    const int t = blockIdx.x;
+    const int tz = t % nt2, ty = (t / nt2) % nt1, tx = t / (nt2 * nt1);
+    const int b0 = tx * T0, b1 = ty * T1, b2 = tz * T2;
+    const int e0 = min(b0 + T0, g.n[0]) - 1, e1 = min(b1 + T1, g.n[1]) - 1,
+              e2 = min(b2 + T2, g.n[2]) - 1;
+    const int beg = off[t], end = off[t + 1];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int seg = threadIdx.x % NS, col = threadIdx.x / NS;
+    const int ix = b0 + col / T1, iy = b1 + col % T1, z0 = b2 + seg * SEG;
+    // x range of the wave's columns (a wave-uniform cull of each Gaussian)
+    const int wx0 = b0 + (wave * 64 / NS) / T1, wx1 = b0 + ((wave * 64 + 63) / NS) / T1;
+    for (int c = 0; c < CT; ++c) {
+        float mx = 0.0f;
+        for (int e = beg + (int)threadIdx.x; e < end; e += 256)
+            mx = fmaxf(mx, fabsf(value[(int64_t)list[e] * CT + c]));
+        mx = wave_max(mx);
+        if (lane == 0) cs[wave][c] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x < (unsigned)CT) {
+        const float mx = fmaxf(fmaxf(cs[0][threadIdx.x], cs[1][threadIdx.x]),
+                               fmaxf(cs[2][threadIdx.x], cs[3][threadIdx.x]));
+        const float S = (float)(end - beg) * mx;
+        scale[threadIdx.x] = S > 0.0f ? 1073741824.0f / (S * 1.0001f) : 0.0f;
+    }
+    const float d0g = fmaf((float)ix, g.h[0], g.c0[0]);
+    const float d1g = fmaf((float)iy, g.h[1], g.c0[1]);
+    float d2g[SEG];
+#pragma unroll
+    for (int s = 0; s < SEG; ++s) d2g[s] = fmaf((float)(z0 + s), g.h[2], g.c0[2]);
+    int acc[SEG][CT];
+#pragma unroll
+    for (int s = 0; s < SEG; ++s)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) acc[s][c] = 0;
+    for (int cb = beg; cb < end; cb += VG_CHUNK) {
+        const int n = min(VG_CHUNK, end - cb);
+        __syncthreads();                  // scale ready / previous chunk consumed
+        if ((int)threadIdx.x < n) {
+            const int gi = list[cb + threadIdx.x];
+            gsh[threadIdx.x] = rec[gi];
+            for (int c = 0; c < CT; ++c) gvs[threadIdx.x][c] = value[(int64_t)gi * CT + c] * scale[c];
+        }
+        __syncthreads();
+        for (int e = 0; e < n; ++e) {
+            const GaussK p = gsh[e];
+            if (p.hi0 < wx0 || p.lo0 > wx1 || p.hi1 < b1 || p.lo1 > e1 || p.hi2 < b2 || p.lo2 > e2)
+                continue;                                     // uniform
+            if (ix < p.lo0 || ix > p.hi0 || iy < p.lo1 || iy > p.hi1 || z0 > p.hi2 ||
+                z0 + SEG - 1 < p.lo2)
+                continue;
+            float cb2, cq;
+            col_coeffs(p.a00, p.a01, p.a02, p.a11, p.a12, d0g - p.mu[0], d1g - p.mu[1], cb2, cq);
+#pragma unroll
+            for (int s = 0; s < SEG; ++s) {
+                const float mm = col_quad(p.a22, cb2, cq, d2g[s] - p.mu[2]);
+                if (z0 + s >= p.lo2 && z0 + s <= p.hi2 && mm <= k2) {
+                    const float ev = __expf(-0.5f * mm);
+#pragma unroll
+                    for (int c = 0; c < CT; ++c) acc[s][c] += __float2int_rn(gvs[e][c] * ev);
+                }
+            }
+        }
+    }
+    float out[SEG][CT];
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+        const float sc = scale[c];
+#pragma unroll
+        for (int s = 0; s < SEG; ++s) out[s][c] = sc > 0.0f ? (float)acc[s][c] / sc : 0.0f;
+    }
+    // Gaussians too large for the bins, in float, in the list's ascending
+    // order (as k_vox_tile)
+    const int nl = *nlarge;
+    for (int e = 0; e < nl; ++e) {
+        const int gi = __builtin_amdgcn_readfirstlane(large[e]);
+        const GaussK p = rec[gi];
+        if (ix < p.lo0 || ix > p.hi0 || iy < p.lo1 || iy > p.hi1) continue;
+        float cb2, cq;
+        col_coeffs(p.a00, p.a01, p.a02, p.a11, p.a12, d0g - p.mu[0], d1g - p.mu[1], cb2, cq);
+#pragma unroll
+        for (int s = 0; s < SEG; ++s) {
+            if (z0 + s < p.lo2 || z0 + s > p.hi2) continue;
+            const float mm = col_quad(p.a22, cb2, cq, d2g[s] - p.mu[2]);
+            if (!(mm <= k2)) continue;
+            const float ev = __expf(-0.5f * mm);
+#pragma unroll
+            for (int c = 0; c < CT; ++c) out[s][c] += value[(int64_t)gi * CT + c] * ev;
+        }
+    }
+    if (ix > e0 || iy > e1) return;
+    const int64_t N = grid_size(g);
+    float *const vb = vol + ((int64_t)ix * g.n[1] + iy) * g.n[2];
+#pragma unroll
+    for (int c = 0; c < CT; ++c)
+#pragma unroll
+        for (int s = 0; s < SEG; ++s)
+            if (z0 + s <= e2) vb[(int64_t)c * N + z0 + s] = out[s][c];
 }
 
 VoxPlan vox_plan(int64_t m, int c, const GridK &g) {
@@ -584,142 +744,295 @@ hipError_t launch_voxelize(const pmf_gauss_t &gs, const GridK &g, float k, float
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    const bool stage = gs.c == 1;
-    const size_t lds =
-        sizeof(float) * (size_t)gs.c * (p.T[0] * p.T[1] * p.T[2] + (stage ? VT_CHUNK : 0));
+    const size_t lds = sizeof(float) * (size_t)gs.c * (p.T[0] * p.T[1] * p.T[2]);
     {
         ProfScope prof_("voxelize_tile", s);
-        if (stage)
-            k_vox_tile<true><<<(unsigned)p.ntiles, 256, lds, s>>>(
-                rec, gs.value, gs.c, g, k2, p.T[0], p.T[1], p.T[2], p.nt[1], p.nt[2], off, list,
-                large, nlarge, vol);
-        else
-            k_vox_tile<false><<<(unsigned)p.ntiles, 256, lds, s>>>(
-                rec, gs.value, gs.c, g, k2, p.T[0], p.T[1], p.T[2], p.nt[1], p.nt[2], off, list,
-                large, nlarge, vol);
+        const int sel = (p.T[1] == 16 ? 2 : 0) + (p.T[2] == 16 ? 1 : 0);
+        const int cs = gs.c;
+        // one channel: the LDS splat (many Gaussians per tile); 3 or 9
+        // channels: voxel owners; other channel counts: the LDS splat
+#define VOX_TILE(T1_, T2_, CT_)                                                                   \
+    k_vox_tile<8, T1_, T2_, CT_><<<(unsigned)p.ntiles, 256, lds, s>>>(                           \
+        rec, gs.value, gs.c, g, k2, p.nt[1], p.nt[2], off, list, large, nlarge, vol)
+#define VOX_GATHER(T1_, T2_, CT_)                                                                 \
+    k_vox_gather<8, T1_, T2_, CT_><<<(unsigned)p.ntiles, 256, 0, s>>>(                           \
+        rec, gs.value, g, k2, p.nt[1], p.nt[2], off, list, large, nlarge, vol)
+#define VOX_TILE_C(T1_, T2_)                                                                      \
+    do {                                                                                          \
+        if (cs == 1) VOX_TILE(T1_, T2_, 1);                                                       \
+        else if (cs == 3) VOX_GATHER(T1_, T2_, 3);                                                \
+        else if (cs == 9) VOX_GATHER(T1_, T2_, 9);                                                \
+        else VOX_TILE(T1_, T2_, 0);                                                               \
+    } while (0)
+        switch (sel) {
+            case 3: VOX_TILE_C(16, 16); break;
+            case 2: VOX_TILE_C(16, 8); break;
+            case 1: VOX_TILE_C(8, 16); break;
+            default: VOX_TILE_C(8, 8); break;
+        }
+#undef VOX_TILE_C
+#undef VOX_GATHER
+#undef VOX_TILE
     }
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------- backward
-constexpr int MAXC = 16;
 
-// CT > 0: the channel count at compile time (the loads of a voxel's channels
-// issue together); CT = 0: any C up to MAXC.
-template <int CT>
-__global__ __launch_bounds__(256) void k_vox_bwd(pmf_gauss_t gs, GridK g, float k,
-                                                 const float *__restrict__ g_vol,
-                                                 pmf_gauss_grad_t gr) {
-    const int64_t gi = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (gi >= gs.m) return;
-    const int lane = threadIdx.x & 63;
+// Adjoint, Gaussian owner.  A wave takes `per` consecutive Gaussians; lane
+// j < per builds Gaussian j's geometry and stages what the walk needs in
+// LDS.  The wave then walks each Gaussian's voxel box in turn with the
+// forward's columns (64 columns at a time over the lanes, z along each
+// lane's col_range) and accumulates per lane, with t = e sum_c v_c g_c:
+//   sum e g_c (value gradients),
+//   sum t d    (mean gradient A sum t d),
+//   sum t d d^T (the gradient of the quadratic form),
+// where on a column (d0, d1 fixed) only sum t, sum t d2 and sum t d2^2 are
+// kept per voxel and folded into the others when the lane leaves the
+// column.  The sums are reduced across the wave, and at the end lane j
+// applies the chain rule through Sigma^-1 = R diag(s^-2) R^T and the
+// quaternion normalisation to Gaussian j.
+constexpr int BW_NS = 9;       // sums besides the channels: P0..P2, M00 M01 M02 M11 M12 M22
+
+struct VoxG {                  // one Gaussian of the wave's batch
+    float mu[3];
+    float a00, a01, a02, a11, a12, a22;
+    int lo0, lo1, lo2, hi0, hi1, hi2;
+};
+
+//
+// ZL: the multi-channel layout.  Each voxel then loads C values, and lanes on
+// different columns would touch a cache line per lane per channel; instead
+// the lanes of a wave sit along z (zl lanes per column, 64 / zl columns per
+// step) so each load covers a few lines, and every voxel accumulates its
+// terms directly.
+template <int CT, bool ZL>
+__global__ __launch_bounds__(64) void k_vox_bwd(pmf_gauss_t gs, GridK g, float k, int per,
+                                                const float *__restrict__ g_vol,
+                                                pmf_gauss_grad_t gr) {
+    constexpr int CM = CT > 0 ? CT : MAXC_VOX;
     const int C = CT > 0 ? CT : gs.c;
-    if (far_from_grid(gs.mean, gs.scale, gi, k, g)) {     // wave-uniform: no voxel, zero gradients
-        if (lane == 63) {
-            for (int c = 0; c < C; ++c) gr.value[gi * C + c] = 0.0f;
-            for (int a = 0; a < 3; ++a) {
-                gr.mean[3 * gi + a] = 0.0f;
-                gr.scale[3 * gi + a] = 0.0f;
-            }
-            for (int c = 0; c < 4; ++c) gr.quat[4 * gi + c] = 0.0f;
+    __shared__ VoxG gb[64];
+    __shared__ float gval[64][CM];
+    __shared__ float sums[64][CM + BW_NS];
+    const int lane = threadIdx.x;
+    const int64_t g0 = (int64_t)blockIdx.x * per;
+    const float k2 = isinf(k) ? INFINITY : k * k;
+    const bool untrunc = isinf(k2);
+    // set-up: lane j < per builds Gaussian g0 + j
+    if (lane < per) {
+        const int64_t gi = g0 + lane;
+        VoxG q = {};
+        q.lo0 = q.lo1 = q.lo2 = 1;                  // empty box
+        if (gi < gs.m && !far_from_grid(gs.mean, gs.scale, gi, k, g)) {
+            GaussFull G;
+            gauss_full(gs.mean, gs.scale, gs.quat, gi, k, g, G);
+            for (int a = 0; a < 3; ++a) q.mu[a] = G.mu[a];
+            q.a00 = G.A[0][0];
+            q.a01 = G.A[0][1];
+            q.a02 = G.A[0][2];
+            q.a11 = G.A[1][1];
+            q.a12 = G.A[1][2];
+            q.a22 = G.A[2][2];
+            q.lo0 = G.lo[0];
+            q.lo1 = G.lo[1];
+            q.lo2 = G.lo[2];
+            q.hi0 = G.hi[0];
+            q.hi1 = G.hi[1];
+            q.hi2 = G.hi[2];
+            for (int c = 0; c < C; ++c) gval[lane][c] = gs.value[gi * C + c];
         }
+        gb[lane] = q;
+    }
+    __syncthreads();
+    const int64_t N = grid_size(g);
+    const float inv_h2 = g.inv_h[2];
+    const int nj = (int)min((int64_t)per, gs.m - g0);
+    for (int j = 0; j < nj; ++j) {                  // uniform
+        const VoxG q = gb[j];
+        float gv[CM];
+#pragma unroll
+        for (int c = 0; c < CM; ++c) gv[c] = 0.0f;
+        float P0 = 0, P1 = 0, P2 = 0, M00 = 0, M01 = 0, M02 = 0, M11 = 0, M12 = 0, M22 = 0;
+        if (q.lo0 <= q.hi0 && q.lo1 <= q.hi1 && q.lo2 <= q.hi2) {
+            float val[CM];
+#pragma unroll
+            for (int c = 0; c < CM; ++c) val[c] = c < C ? gval[j][c] : 0.0f;
+            const int ny = q.hi1 - q.lo1 + 1;
+            const int ncol = (q.hi0 - q.lo0 + 1) * ny;
+            const float rny = __builtin_amdgcn_rcpf((float)ny);
+            const float zc = (q.mu[2] - g.c0[2]) * inv_h2;
+            if constexpr (ZL) {
+                const int nz = q.hi2 - q.lo2 + 1;
+                const int zl = nz <= 4 ? 4 : nz <= 8 ? 8 : nz <= 16 ? 16 : nz <= 32 ? 32 : 64;
+                const int cpr = 64 / zl;
+                const int zr = lane & (zl - 1), cl = lane / zl;
+                for (int c0 = 0; c0 < ncol; c0 += cpr) {
+                    const int col = c0 + cl;
+                    if (col >= ncol) continue;
+                    int cx = (int)(((float)col + 0.5f) * rny);
+                    int cy = col - cx * ny;
+                    if (cy < 0) {
+                        --cx;
+                        cy += ny;
+                    } else if (cy >= ny) {
+                        ++cx;
+                        cy -= ny;
+                    }
+                    const int ix = q.lo0 + cx, iy = q.lo1 + cy;
+                    const float d0 = fmaf((float)ix, g.h[0], g.c0[0]) - q.mu[0];
+                    const float d1 = fmaf((float)iy, g.h[1], g.c0[1]) - q.mu[1];
+                    float cb2, cq;
+                    col_coeffs(q.a00, q.a01, q.a02, q.a11, q.a12, d0, d1, cb2, cq);
+                    int za, zb;
+                    if (!col_range(q.a22, cb2, cq, zc, inv_h2, k2, untrunc, q.lo2, q.hi2, za, zb))
+                        continue;
+                    const float *gcol = g_vol + ((int64_t)ix * g.n[1] + iy) * g.n[2];
+                    for (int iz = za + zr; iz <= zb; iz += zl) {
+                        float gl[CM];
+#pragma unroll
+                        for (int c = 0; c < CM; ++c)
+                            if (c < C) gl[c] = gcol[c * N + iz];
+                        const float d2 = fmaf((float)iz, g.h[2], g.c0[2]) - q.mu[2];
+                        const float mm = col_quad(q.a22, cb2, cq, d2);
+                        const float ev = mm <= k2 ? __expf(-0.5f * mm) : 0.0f;
+                        float Gj = 0.0f;
+#pragma unroll
+                        for (int c = 0; c < CM; ++c) {
+                            if (c < C) {
+                                gv[c] = fmaf(gl[c], ev, gv[c]);
+                                Gj = fmaf(val[c], gl[c], Gj);
+                            }
+                        }
+                        const float t = Gj * ev;
+                        const float t0 = t * d0, t1 = t * d1, t2 = t * d2;
+                        P0 += t0;
+                        P1 += t1;
+                        P2 += t2;
+                        M00 = fmaf(t0, d0, M00);
+                        M01 = fmaf(t0, d1, M01);
+                        M02 = fmaf(t0, d2, M02);
+                        M11 = fmaf(t1, d1, M11);
+                        M12 = fmaf(t1, d2, M12);
+                        M22 = fmaf(t2, d2, M22);
+                    }
+                }
+            } else
+            for (int c0 = 0; c0 < ncol; c0 += 64) {
+                const int col = c0 + lane;
+                if (col >= ncol) continue;
+                // col = cx * ny + cy (the float quotient is corrected to exact)
+                int cx = (int)(((float)col + 0.5f) * rny);
+                int cy = col - cx * ny;
+                if (cy < 0) {
+                    --cx;
+                    cy += ny;
+                } else if (cy >= ny) {
+                    ++cx;
+                    cy -= ny;
+                }
+                const int ix = q.lo0 + cx, iy = q.lo1 + cy;
+                const float d0 = fmaf((float)ix, g.h[0], g.c0[0]) - q.mu[0];
+                const float d1 = fmaf((float)iy, g.h[1], g.c0[1]) - q.mu[1];
+                float cb2, cq;
+                col_coeffs(q.a00, q.a01, q.a02, q.a11, q.a12, d0, d1, cb2, cq);
+                int za, zb;
+                if (!col_range(q.a22, cb2, cq, zc, inv_h2, k2, untrunc, q.lo2, q.hi2, za, zb))
+                    continue;
+                const float *gcol = g_vol + ((int64_t)ix * g.n[1] + iy) * g.n[2];
+                float St = 0.0f, Sz = 0.0f, Szz = 0.0f;
+                // every voxel of the range is loaded (the range lies in the
+                // grid); voxels outside the ellipsoid add exact zeros, so the
+                // loop has no branch and successive voxels' loads overlap
+                constexpr int UNR = CT == 1 ? 4 : 1;
+#pragma unroll UNR
+                for (int iz = za; iz <= zb; ++iz) {
+                    float gl[CM];
+#pragma unroll
+                    for (int c = 0; c < CM; ++c)
+                        if (c < C) gl[c] = gcol[c * N + iz];
+                    const float d2 = fmaf((float)iz, g.h[2], g.c0[2]) - q.mu[2];
+                    const float mm = col_quad(q.a22, cb2, cq, d2);
+                    const float ev = mm <= k2 ? __expf(-0.5f * mm) : 0.0f;
+                    float Gj = 0.0f;
+#pragma unroll
+                    for (int c = 0; c < CM; ++c) {
+                        if (c < C) {
+                            gv[c] = fmaf(gl[c], ev, gv[c]);
+                            Gj = fmaf(val[c], gl[c], Gj);
+                        }
+                    }
+                    const float t = Gj * ev;
+                    St += t;
+                    const float td = t * d2;
+                    Sz += td;
+                    Szz = fmaf(td, d2, Szz);
+                }
+                P0 = fmaf(d0, St, P0);
+                P1 = fmaf(d1, St, P1);
+                P2 += Sz;
+                M00 = fmaf(d0 * St, d0, M00);
+                M01 = fmaf(d0 * St, d1, M01);
+                M02 = fmaf(d0, Sz, M02);
+                M11 = fmaf(d1 * St, d1, M11);
+                M12 = fmaf(d1, Sz, M12);
+                M22 += Szz;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < CM; ++c)
+            if (c < C) gv[c] = wave_sum_lane63(gv[c]);
+        P0 = wave_sum_lane63(P0);
+        P1 = wave_sum_lane63(P1);
+        P2 = wave_sum_lane63(P2);
+        M00 = wave_sum_lane63(M00);
+        M01 = wave_sum_lane63(M01);
+        M02 = wave_sum_lane63(M02);
+        M11 = wave_sum_lane63(M11);
+        M12 = wave_sum_lane63(M12);
+        M22 = wave_sum_lane63(M22);
+        if (lane == 63) {
+            float *o = sums[j];
+#pragma unroll
+            for (int c = 0; c < CM; ++c)
+                if (c < C) o[c] = gv[c];
+            o[CM + 0] = P0;
+            o[CM + 1] = P1;
+            o[CM + 2] = P2;
+            o[CM + 3] = M00;
+            o[CM + 4] = M01;
+            o[CM + 5] = M02;
+            o[CM + 6] = M11;
+            o[CM + 7] = M12;
+            o[CM + 8] = M22;
+        }
+    }
+    __syncthreads();
+    // chain rule: lane j for Gaussian g0 + j
+    const int64_t gi = g0 + lane;
+    if (lane >= nj) return;
+    const VoxG q = gb[lane];
+    if (!(q.lo0 <= q.hi0 && q.lo1 <= q.hi1 && q.lo2 <= q.hi2)) {   // no voxel: zero gradients
+        for (int c = 0; c < C; ++c) gr.value[gi * C + c] = 0.0f;
+        for (int a = 0; a < 3; ++a) {
+            gr.mean[3 * gi + a] = 0.0f;
+            gr.scale[3 * gi + a] = 0.0f;
+        }
+        for (int c = 0; c < 4; ++c) gr.quat[4 * gi + c] = 0.0f;
         return;
     }
     GaussFull G;
     gauss_full(gs.mean, gs.scale, gs.quat, gi, k, g, G);
-    GaussK p;
-    for (int a = 0; a < 3; ++a) p.mu[a] = G.mu[a];
-    p.a00 = G.A[0][0];
-    p.a01 = G.A[0][1];
-    p.a02 = G.A[0][2];
-    p.a11 = G.A[1][1];
-    p.a12 = G.A[1][2];
-    p.a22 = G.A[2][2];
-    const float k2 = isinf(k) ? INFINITY : k * k;
-    const float *vv = gs.value + gi * C;
-    float val[MAXC];
-#pragma unroll
-    for (int c = 0; c < MAXC; ++c) val[c] = c < C ? vv[c] : 0.0f;
-    float gv[MAXC];
-#pragma unroll
-    for (int c = 0; c < MAXC; ++c) gv[c] = 0.0f;
-    float gm0 = 0, gm1 = 0, gm2 = 0;
-    float M00 = 0, M01 = 0, M02 = 0, M11 = 0, M12 = 0, M22 = 0;
-    const int64_t N = grid_size(g);
-    // Column walk of splat_cols with the same voxels in the same order per
-    // lane; every voxel of the column range is loaded (the range lies in the
-    // grid) and voxels outside the ellipsoid add exact zeros, so the loop has
-    // no branch and the loads of successive voxels overlap.
-    if (G.lo[0] <= G.hi[0] && G.lo[1] <= G.hi[1] && G.lo[2] <= G.hi[2]) {
-        const int ny = G.hi[1] - G.lo[1] + 1;
-        const int ncol = (G.hi[0] - G.lo[0] + 1) * ny;
-        const bool untrunc = isinf(k2);
-        for (int c0 = 0; c0 < ncol; c0 += 64) {
-            const int col = c0 + lane;
-            if (col >= ncol) continue;
-            const int ix = G.lo[0] + col / ny, iy = G.lo[1] + col % ny;
-            const float d0 = fmaf((float)ix, g.h[0], g.c0[0]) - p.mu[0];
-            const float d1 = fmaf((float)iy, g.h[1], g.c0[1]) - p.mu[1];
-            int za, zb;
-            if (!col_range(p, g, k2, untrunc, d0, d1, G.lo[2], G.hi[2], za, zb)) continue;
-            const float *gcol = g_vol + ((int64_t)ix * g.n[1] + iy) * g.n[2];
-            constexpr int UNR = CT == 1 ? 4 : 2;     // voxels whose loads overlap
-#pragma unroll UNR
-            for (int iz = za; iz <= zb; ++iz) {
-                float gl[MAXC];
-#pragma unroll
-                for (int c = 0; c < MAXC; ++c)
-                    if (c < C) gl[c] = gcol[c * N + iz];
-                const float d2 = fmaf((float)iz, g.h[2], g.c0[2]) - p.mu[2];
-                const float mm = quad(p, d0, d1, d2);
-                const bool in = mm <= k2;
-                const float ev = in ? __expf(-0.5f * mm) : 0.0f;
-                float Gj = 0.0f;
-#pragma unroll
-                for (int c = 0; c < MAXC; ++c) {
-                    if (c < C) {
-                        const float gc = in ? gl[c] : 0.0f;
-                        gv[c] = fmaf(gc, ev, gv[c]);
-                        Gj = fmaf(val[c], gc, Gj);
-                    }
-                }
-                const float t = Gj * ev;
-                const float A0 = fmaf(p.a00, d0, fmaf(p.a01, d1, p.a02 * d2));
-                const float A1 = fmaf(p.a01, d0, fmaf(p.a11, d1, p.a12 * d2));
-                const float A2 = fmaf(p.a02, d0, fmaf(p.a12, d1, p.a22 * d2));
-                gm0 = fmaf(t, A0, gm0);
-                gm1 = fmaf(t, A1, gm1);
-                gm2 = fmaf(t, A2, gm2);
-                const float ht = -0.5f * t;
-                M00 = fmaf(ht * d0, d0, M00);
-                M01 = fmaf(ht * d0, d1, M01);
-                M02 = fmaf(ht * d0, d2, M02);
-                M11 = fmaf(ht * d1, d1, M11);
-                M12 = fmaf(ht * d1, d2, M12);
-                M22 = fmaf(ht * d2, d2, M22);
-            }
-        }
-    }
-#pragma unroll
-    for (int c = 0; c < MAXC; ++c)
-        if (c < C) gv[c] = wave_sum_lane63(gv[c]);
-    gm0 = wave_sum_lane63(gm0);
-    gm1 = wave_sum_lane63(gm1);
-    gm2 = wave_sum_lane63(gm2);
-    M00 = wave_sum_lane63(M00);
-    M01 = wave_sum_lane63(M01);
-    M02 = wave_sum_lane63(M02);
-    M11 = wave_sum_lane63(M11);
-    M12 = wave_sum_lane63(M12);
-    M22 = wave_sum_lane63(M22);
-    if (lane != 63) return;
-#pragma unroll
-    for (int c = 0; c < MAXC; ++c)
-        if (c < C) gr.value[gi * C + c] = gv[c];
-    gr.mean[3 * gi + 0] = gm0;
-    gr.mean[3 * gi + 1] = gm1;
-    gr.mean[3 * gi + 2] = gm2;
-    const float M[3][3] = {{M00, M01, M02}, {M01, M11, M12}, {M02, M12, M22}};
+    const float *o = sums[lane];
+    for (int c = 0; c < C; ++c) gr.value[gi * C + c] = o[c];
+    const float P[3] = {o[CM + 0], o[CM + 1], o[CM + 2]};
+    // mean: d/dmu of -m/2 is A d, so dL/dmu = A sum t d
+    for (int a = 0; a < 3; ++a)
+        gr.mean[3 * gi + a] = G.A[a][0] * P[0] + G.A[a][1] * P[1] + G.A[a][2] * P[2];
+    // d/dA of -m/2 is -d d^T / 2
+    const float M[3][3] = {{-0.5f * o[CM + 3], -0.5f * o[CM + 4], -0.5f * o[CM + 5]},
+                           {-0.5f * o[CM + 4], -0.5f * o[CM + 6], -0.5f * o[CM + 7]},
+                           {-0.5f * o[CM + 5], -0.5f * o[CM + 7], -0.5f * o[CM + 8]}};
     float MR[3][3];
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b)
@@ -750,15 +1063,26 @@ hipError_t launch_voxelize_bwd(const pmf_gauss_t &gs, const GridK &g, float k, c
     if (gs.m <= 0) return hipSuccess;
     {
         ProfScope prof_("voxelize_bwd", s);
-        const unsigned nb = (unsigned)((gs.m + 3) / 4);
-        if (gs.c == 1)
-            k_vox_bwd<1><<<nb, 256, 0, s>>>(gs, g, k, g_vol, gr);
-        else if (gs.c == 3)
-            k_vox_bwd<3><<<nb, 256, 0, s>>>(gs, g, k, g_vol, gr);
-        else if (gs.c == 9)
-            k_vox_bwd<9><<<nb, 256, 0, s>>>(gs, g, k, g_vol, gr);
+        // Gaussians per wave: at least ~12,500 waves (a dozen per SIMD) to
+        // hide the loads' latency, then as many Gaussians per wave as keeps
+        // that (the set-up and the chain rule run lane-parallel over a
+        // wave's Gaussians); measured on 200k one-channel and 1k-16k
+        // nine-channel sets
+        int per = 1;
+        const int choice = tune_get(KNOB_VOXELIZE_BWD);
+        if (choice > 0)
+            per = 1 << (choice - 1);
         else
-            k_vox_bwd<0><<<nb, 256, 0, s>>>(gs, g, k, g_vol, gr);
+            while (per < 64 && gs.m / (2 * per) > 12500) per *= 2;
+        const unsigned nb = (unsigned)((gs.m + per - 1) / per);
+        if (gs.c == 1)
+            k_vox_bwd<1, false><<<nb, 64, 0, s>>>(gs, g, k, per, g_vol, gr);
+        else if (gs.c == 3)
+            k_vox_bwd<3, true><<<nb, 64, 0, s>>>(gs, g, k, per, g_vol, gr);
+        else if (gs.c == 9)
+            k_vox_bwd<9, true><<<nb, 64, 0, s>>>(gs, g, k, per, g_vol, gr);
+        else
+            k_vox_bwd<0, true><<<nb, 64, 0, s>>>(gs, g, k, per, g_vol, gr);
     }
     return hipGetLastError();
 }

@@ -582,6 +582,7 @@ def pmf_profile_read(kernel: str) -> Tuple[float, int]:
 
 PMF_TUNE_PROJECT_TILE = 0
 PMF_TUNE_BACKPROJECT_BRICK = 1
+PMF_TUNE_VOXELIZE_BWD = 2
 
 
 def pmf_tune_candidates(knob: int) -> int:

@@ -143,6 +143,7 @@ def test_tune_knobs(lib):
     n = lib.pmf_tune_candidates(knob)
     assert n >= 2
     assert lib.pmf_tune_candidates(99) == 0
+    assert lib.pmf_tune_candidates(ops.PMF_TUNE_VOXELIZE_BWD) == 8
     prev = lib.pmf_tune_get(knob)
     assert 0 <= prev < n
     assert lib.pmf_tune_set(knob, n - 1) == prev

@@ -316,6 +316,35 @@ def test_rasterizer_and_untruncated_voxelization_repeat_bit_for_bit():
     assert np.array_equal(a, b)
 
 
+def test_voxelize_adjoint_batch_choices_agree_bit_for_bit():
+    """Every PMF_TUNE_VOXELIZE_BWD choice (1 to 64 Gaussians per wavefront)
+    gives the same bits: a Gaussian's sums are laid over the lanes and
+    reduced the same way whatever batch it sits in.  One-channel column
+    walk, nine-channel z-along-lanes walk (a set size that leaves the last
+    batch ragged), each against the oracle too."""
+    w = synth.small_motion()
+    rng = np.random.default_rng(21)
+    cases = [(w.ref, w.grid), (synth.gaussians(rng, 203, w.levels[2], c=9, value_sigma=1.0), w.levels[2])]
+    knob = ops.PMF_TUNE_VOXELIZE_BWD
+    prev = ops.pmf_tune_get(knob)
+    try:
+        for gs, grid in cases:
+            gv = synth.random_normal(31, (gs.c,) + tuple(grid.n))
+            want = oracle.voxelize_bwd(gs, grid, 3.0, gv)
+            outs = []
+            for choice in range(ops.pmf_tune_candidates(knob)):
+                ops.pmf_tune_set(knob, choice)
+                outs.append([N(t) for t in ops.pmf_voxelize_bwd(
+                    T(gs.mean), T(gs.scale), T(gs.quat), T(gs.value), grid, 3.0, T(gv))])
+            for o in outs[1:]:
+                for x, y in zip(outs[0], o):
+                    assert np.array_equal(x, y), gs.c
+            for name, g in zip(("mean", "scale", "quat", "value"), outs[0]):
+                assert rel(g, want[name]) < GRAD_TOL, (gs.c, name)
+    finally:
+        ops.pmf_tune_set(knob, prev)
+
+
 # ---------------------------------------------- graphs and the tuner cache
 
 def test_graph_capture_through_the_abi():
