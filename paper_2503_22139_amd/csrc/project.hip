@@ -856,34 +856,60 @@ __device__ __forceinline__ void bp_column(const BwdK &bj, int view, int item, in
         __syncthreads();
         const bool lastb = b2 + 1 == z1;
         float *pad = bj.pads + ((int64_t)v * bj.nbb + (b0 * nb1 + b1) * nb2 + b2) * NPMAX;
+        // Row owners: a thread takes one (x, y) row of the box (P2 entries
+        // along z), stores it, and then carries its z = S2 entry to z = 0
+        // and clears the rest for the next brick (its own row only, so no
+        // other thread's reads are in the way).
+        const bool zfix = b2 == z0 && b2 > 0;     // the z = 0 layer is completed by the fix-up
+        const bool full_z = q.B[2] + S2 <= g.n[2] && (g.n[2] & 3) == 0;
 #pragma unroll 1
-        for (int i = threadIdx.x; i < NP; i += NT) {
-            const int z = i % P2, y = (i / P2) % P1, x = i / (P1 * P2);
-            const int gx = q.B[0] + x, gy = q.B[1] + y, gz = q.B[2] + z;
-            if (gx >= g.n[0] || gy >= g.n[1] || gz >= g.n[2]) continue;
-            const float val = (float)acc[i] * inv_scale;
-            if (x < S0 && y < S1 && z < S2) {
-                out[((int64_t)gx * g.n[1] + gy) * g.n[2] + gz] = val;
-                const bool fixed = (x == 0 && b0 > 0) || (y == 0 && b1 > 0) ||
-                                   (z == 0 && b2 == z0 && b2 > 0);
-                if (!fixed) mx = fmaxf(mx, fabsf(val));
-            } else if (z < S2 || lastb) {
-                pad[i] = val;
+        for (int r = threadIdx.x; r < (S0 + 1) * P1; r += NT) {
+            const int x = r / P1, y = r - x * P1;
+            const int gx = q.B[0] + x, gy = q.B[1] + y;
+            int *row = acc + r * P2;
+            int raw[P2];
+#pragma unroll
+            for (int z = 0; z < P2; ++z) raw[z] = row[z];
+            if (gx < g.n[0] && gy < g.n[1]) {
+                float val[P2];
+#pragma unroll
+                for (int z = 0; z < P2; ++z) val[z] = (float)raw[z] * inv_scale;
+                float *orow = out + ((int64_t)gx * g.n[1] + gy) * g.n[2] + q.B[2];
+                if (x < S0 && y < S1) {
+                    if constexpr (S2 % 4 == 0) {
+                        if (full_z && ((uintptr_t)orow & 15) == 0) {
+#pragma unroll
+                            for (int z = 0; z < S2; z += 4)
+                                *(float4 *)(orow + z) = make_float4(val[z], val[z + 1], val[z + 2], val[z + 3]);
+                        } else {
+#pragma unroll
+                            for (int z = 0; z < S2; ++z)
+                                if (q.B[2] + z < g.n[2]) orow[z] = val[z];
+                        }
+                    } else {
+#pragma unroll
+                        for (int z = 0; z < S2; ++z)
+                            if (q.B[2] + z < g.n[2]) orow[z] = val[z];
+                    }
+                    if (!((x == 0 && b0 > 0) || (y == 0 && b1 > 0))) {
+#pragma unroll
+                        for (int z = 0; z < S2; ++z)
+                            if (q.B[2] + z < g.n[2] && !(z == 0 && zfix)) mx = fmaxf(mx, fabsf(val[z]));
+                    }
+                    if (lastb && q.B[2] + S2 < g.n[2]) pad[r * P2 + S2] = val[S2];
+                } else {
+#pragma unroll
+                    for (int z = 0; z < P2; ++z)
+                        if (q.B[2] + z < g.n[2] && (z < S2 || lastb)) pad[r * P2 + z] = val[z];
+                }
+            }
+            if (!lastb) {
+                row[0] = raw[S2];
+#pragma unroll
+                for (int z = 1; z < P2; ++z) row[z] = 0;
             }
         }
-        if (!lastb) {
-            // the z = S2 layer becomes the next brick's z = 0 layer; the rest
-            // is cleared (two phases: the two layers are disjoint)
-            __syncthreads();
-#pragma unroll 1
-            for (int i = threadIdx.x; i < NP; i += NT)
-                if (i % P2 == 0) acc[i] = acc[i + S2];
-            __syncthreads();
-#pragma unroll 1
-            for (int i = threadIdx.x; i < NP; i += NT)
-                if (i % P2 != 0) acc[i] = 0;
-            __syncthreads();
-        }
+        __syncthreads();
     }
     if (bj.vmax) {
         for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
