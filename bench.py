@@ -369,8 +369,32 @@ def extras(steps: int):
     out["b1_step"] = {"ms": ms, "iterations_per_s": 1e3 / ms,
                       "what": "benchmark workload with B = 1 (9 coefficients per view)"}
     print(f"[bench] b1_step {ms:.2f} ms", file=sys.stderr, flush=True)
-    del gs, mb
+    del gs, mb, tb
     torch.cuda.empty_cache()
+    # large motion: the benchmark workload with the MBC values scaled up, so
+    # that many displacements leave the warp adjoint's 3-voxel LDS halo (its
+    # overflow goes to a 64-bit fixed-point volume)
+    lm = {}
+    for scale in (1.0, 4.0):
+        wl = synth.headline()
+        for st in wl.mbc:
+            st.value = (st.value * np.float32(scale)).astype(np.float32)
+        ml = MotionModel(wl)
+        ref, bases = ml.volumes()
+        dvf = ops.pmf_combine_dvf(bases, ml.levels, ml.coeff[:1], ml.grid).reshape(3, -1)
+        h = torch.tensor(wl.grid.h, device="cuda", dtype=torch.float32).reshape(3, 1)
+        vox = (dvf.abs() / h).amax(0)
+        tl = torch.from_numpy(synth.random_volume(96, (len(wl.angles), wl.cone.nv, wl.cone.nu),
+                                                  0.0, 20.0)).cuda()
+        gl = GraphStep(ml, tl)
+        ms = _timed(gl.step, steps)
+        lm[f"x{scale:g}"] = {"ms": ms, "max_disp_mm": float(dvf.abs().max()),
+                             "frac_voxels_beyond_halo_view0": float((vox > 3.0).float().mean())}
+        del gl, ml, tl, ref, bases, dvf
+        torch.cuda.empty_cache()
+    out["large_motion_step"] = dict(lm, what="benchmark workload with MBC values x1 and x4; "
+                                    "displacement statistics of view 0")
+    print(f"[bench] large_motion_step {lm}", file=sys.stderr, flush=True)
     return out
 
 
