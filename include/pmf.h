@@ -384,7 +384,9 @@ size_t pmf_profile_names(char *buf, size_t len);
  *                              sample alone, 2 = 32x16x8, 3, 4 (default), 5
  *                              = 48x16x8 walked in chunks of 2, 8, 4 bricks
  *                              along z by one workgroup, 6 = 32x16x8 in
- *                              chunks of 4, 7 = 32x32x8, 8 = 48x24x8;
+ *                              chunks of 4, 7 = 32x32x8, 8 = 48x24x8 (a
+ *                              launch of few views takes shorter chunks, so
+ *                              that it still fills the chip);
  *   PMF_TUNE_VOXELIZE_BWD      Gaussians per wavefront in pmf_voxelize_bwd:
  *                              0 = chosen from the set's size (default),
  *                              k = 1..7: 2^(k-1).

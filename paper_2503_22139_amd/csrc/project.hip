@@ -1301,16 +1301,30 @@ static hipError_t project_bwd_bricks(const BwdJob *jobs, int n, hipStream_t s) {
     return hipSuccess;
 }
 
+// A chunked walk needs enough workgroups to fill the chip (a few per CU):
+// a launch with few views (the plain schedule's one) takes shorter chunks,
+// halving them until the column-chunk items reach 1536.
+template <int L, int W, int H, int NW, bool MERGE, int ZC>
+static hipError_t project_bwd_chunked(const BwdJob *jobs, int n, hipStream_t s) {
+    if constexpr (ZC > 1) {
+        int64_t items = 0;
+        for (int k = 0; k < n; ++k) items += (int64_t)jobs[k].V * column_items_per_view(jobs[k].g, L, W, H, ZC);
+        if (jobs[0].stride != 0 && items < 1536)
+            return project_bwd_chunked<L, W, H, NW, MERGE, ZC / 2>(jobs, n, s);
+    }
+    return project_bwd_bricks<L, W, H, NW, MERGE, ZC>(jobs, n, s);
+}
+
 hipError_t launch_project_bwd_jobs(const BwdJob *jobs, int n, hipStream_t s) {
     if (n < 1 || n > MAXS) return hipErrorInvalidValue;
     static_assert(NBRICKS == 9, "tune candidates");
     switch (tune_get(KNOB_BACKPROJECT_BRICK)) {
         case 1: return project_bwd_bricks<48, 16, 8, 8, false, 1>(jobs, n, s);
         case 2: return project_bwd_bricks<32, 16, 8, 8, true, 1>(jobs, n, s);
-        case 3: return project_bwd_bricks<48, 16, 8, 8, true, 2>(jobs, n, s);
-        case 4: return project_bwd_bricks<48, 16, 8, 8, true, 8>(jobs, n, s);
-        case 5: return project_bwd_bricks<48, 16, 8, 8, true, 4>(jobs, n, s);
-        case 6: return project_bwd_bricks<32, 16, 8, 8, true, 4>(jobs, n, s);
+        case 3: return project_bwd_chunked<48, 16, 8, 8, true, 2>(jobs, n, s);
+        case 4: return project_bwd_chunked<48, 16, 8, 8, true, 8>(jobs, n, s);
+        case 5: return project_bwd_chunked<48, 16, 8, 8, true, 4>(jobs, n, s);
+        case 6: return project_bwd_chunked<32, 16, 8, 8, true, 4>(jobs, n, s);
         case 7: return project_bwd_bricks<32, 32, 8, 8, true, 1>(jobs, n, s);
         case 8: return project_bwd_bricks<48, 24, 8, 8, true, 1>(jobs, n, s);
         default: return project_bwd_bricks<48, 16, 8, 8, true, 1>(jobs, n, s);
