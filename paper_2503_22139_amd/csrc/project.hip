@@ -968,12 +968,21 @@ __device__ __forceinline__ void bp_summed(const BwdK &bj, int bid, int *__restri
     }
 }
 
+// Waves per SIMD that the LDS of one workgroup (box + run staging) allows
+// on a 160 KB CU, at most six: the register budget is set to match, so the
+// compiler does not trade occupancy the LDS cannot use for registers.
+constexpr int bwd_waves_per_simd(int L, int W, int H, int NW) {
+    const int bytes = 4 * (L + 1) * (W + 1) * (H + 1) + NW * 64 * (int)(sizeof(RunP) + sizeof(int));
+    const int wg = (160 * 1024) / bytes;
+    const int w = wg * NW / 4;
+    return w < 1 ? 1 : w > 6 ? 6 : w;
+}
+
 // L x W x H cells per brick (L along the axis the view's rays mostly
 // follow), NW waves per workgroup.
-// (at most 80 VGPRs: six waves per SIMD, the three workgroups per CU that
-// the LDS box allows)
 template <int L, int W, int H, int NW, bool SUM, bool MERGE, int ZC>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(6)))
+__global__ __launch_bounds__(64 * NW)
+__attribute__((amdgpu_waves_per_eu(bwd_waves_per_simd(L, W, H, NW))))
 void k_project_bwd(BwdTab t) {
     constexpr int NPMAX = (L + 1) * (W + 1) * (H + 1);
     __shared__ int acc[NPMAX];
