@@ -457,9 +457,12 @@ int pmf_graph_destroy(pmf_graph_t *graph);
 /* ----------------------------------------- batched motion path (fused)
  * All V views of the motion path in one pass over the bases:
  *   proj[v] = P_v( warp(ref, combine(bases, coeff[v])) )
- * The DVFs are never written to memory; the warped volumes of all views live
- * in the workspace.  Arguments as in the calls above.
- * Needs the workspace from pmf_warp_project_workspace(). */
+ * i.e. the DVF of Eq. 3 from the MBC bases (Sec. 2.3.1) and the view's
+ * coefficients, the pull-back warp of Eq. 2, and the line integrals of
+ * Eq. 6, for every sampled view of a training iteration (Sec. 2.3.2).  The
+ * DVFs are never written to memory; the warped volumes of all views live in
+ * the workspace.  Arguments as in the calls above.  Needs the workspace from
+ * pmf_warp_project_workspace(). */
 size_t pmf_warp_project_workspace(int L, int B, const pmf_grid_t *lvl, int V,
                                     const pmf_grid_t *grid, const pmf_cone_t *cone);
 int pmf_warp_project(const float *ref, const pmf_grid_t *grid, int L, int B,
@@ -467,10 +470,14 @@ int pmf_warp_project(const float *ref, const pmf_grid_t *grid, int L, int B,
                        int V, const pmf_cone_t *cone, const float *angles, float *proj,
                        void *ws, size_t ws_bytes, void *stream);
 
-/* Adjoint of pmf_warp_project given g_proj [V][nv][nu]: writes g_ref [N],
- * g_bases (HOST array of L device pointers, [3B][N_l] each) and g_coeff
- * [V][L][B][3].  Recomputes every view's DVF instead of storing it.
- * Needs the workspace from pmf_warp_project_bwd_workspace(). */
+/* Adjoint of pmf_warp_project given g_proj [V][nv][nu] (the exact
+ * transpose of the discrete Eq. 6, Eq. 2 and Eq. 3 chain, which the
+ * training's gradient step through the forward model needs): writes g_ref
+ * [N], g_bases (HOST array of L device pointers, [3B][N_l] each) and g_coeff
+ * [V][L][B][3].  Recomputes every view's DVF instead of storing it; the
+ * sums do not depend on scheduling (fixed point and fixed orders), so a call
+ * repeats bit for bit.  Needs the workspace from
+ * pmf_warp_project_bwd_workspace(). */
 size_t pmf_warp_project_bwd_workspace(int L, int B, const pmf_grid_t *lvl, int V,
                                         const pmf_grid_t *grid, const pmf_cone_t *cone);
 int pmf_warp_project_bwd(const float *ref, const pmf_grid_t *grid, int L, int B,
