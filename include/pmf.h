@@ -377,16 +377,18 @@ size_t pmf_profile_names(char *buf, size_t len);
  *                              7 = 1x64 in 2x128, 8 = 2x32 in 2x128;
  *   PMF_TUNE_BACKPROJECT_BRICK cell brick of the adjoint projection, L x W x H
  *                              (L along the horizontal axis a view's rays
- *                              mostly follow, H along z), 8 wavefronts, with
+ *                              mostly follow, H along z), 8 wavefronts unless
+ *                              noted, with
  *                              consecutive samples of a ray in one cell
  *                              summed in registers first unless noted:
  *                              0 = 48x16x8, 1 = 48x16x8 summing each
  *                              sample alone, 2 = 32x16x8, 3, 4 (default), 5
  *                              = 48x16x8 walked in chunks of 2, 8, 4 bricks
  *                              along z by one workgroup, 6 = 32x16x8 in
- *                              chunks of 4, 7 = 32x32x8, 8 = 48x24x8 (a
- *                              launch of few views takes shorter chunks, so
- *                              that it still fills the chip);
+ *                              chunks of 4, 7 = 64x16x8 and 8 = 80x16x8
+ *                              with 12 wavefronts, in chunks of 8 (a launch
+ *                              of few views takes shorter chunks, so that
+ *                              it still fills the chip);
  *   PMF_TUNE_VOXELIZE_BWD      Gaussians per wavefront in pmf_voxelize_bwd:
  *                              0 = chosen from the set's size (default),
  *                              k = 1..7: 2^(k-1).

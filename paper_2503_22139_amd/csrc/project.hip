@@ -1200,7 +1200,7 @@ struct BrickShape {
 };
 static const BrickShape kBricks[] = {{48, 16, 8, 8}, {48, 16, 8, 8}, {32, 16, 8, 8},
                                      {48, 16, 8, 8}, {48, 16, 8, 8}, {48, 16, 8, 8},
-                                     {32, 16, 8, 8}, {32, 32, 8, 8}, {48, 24, 8, 8}};
+                                     {32, 16, 8, 8}, {64, 16, 8, 12}, {80, 16, 8, 12}};
 constexpr int NBRICKS = sizeof(kBricks) / sizeof(kBricks[0]);
 
 // Items per view: the brick count of the orientation with more bricks.
@@ -1334,8 +1334,8 @@ hipError_t launch_project_bwd_jobs(const BwdJob *jobs, int n, hipStream_t s) {
         case 4: return project_bwd_chunked<48, 16, 8, 8, true, 8>(jobs, n, s);
         case 5: return project_bwd_chunked<48, 16, 8, 8, true, 4>(jobs, n, s);
         case 6: return project_bwd_chunked<32, 16, 8, 8, true, 4>(jobs, n, s);
-        case 7: return project_bwd_bricks<32, 32, 8, 8, true, 1>(jobs, n, s);
-        case 8: return project_bwd_bricks<48, 24, 8, 8, true, 1>(jobs, n, s);
+        case 7: return project_bwd_chunked<64, 16, 8, 12, true, 8>(jobs, n, s);
+        case 8: return project_bwd_chunked<80, 16, 8, 12, true, 8>(jobs, n, s);
         default: return project_bwd_bricks<48, 16, 8, 8, true, 1>(jobs, n, s);
     }
 }
