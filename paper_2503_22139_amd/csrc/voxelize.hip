@@ -548,12 +548,21 @@ __global__ __launch_bounds__(256) void k_vox_gather(const GaussK *__restrict__ r
     const int ix = b0 + col / T1, iy = b1 + col % T1, z0 = b2 + seg * SEG;
     // x range of the wave's columns (a wave-uniform cull of each Gaussian)
     const int wx0 = b0 + (wave * 64 / NS) / T1, wx1 = b0 + ((wave * 64 + 63) / NS) / T1;
-    for (int c = 0; c < CT; ++c) {
-        float mx = 0.0f;
-        for (int e = beg + (int)threadIdx.x; e < end; e += 256)
-            mx = fmaxf(mx, fabsf(value[(int64_t)list[e] * CT + c]));
-        mx = wave_max(mx);
-        if (lane == 0) cs[wave][c] = mx;
+    {
+        // one pass over the list: each entry's channels load together
+        float mx[CT];
+#pragma unroll
+        for (int c = 0; c < CT; ++c) mx[c] = 0.0f;
+        for (int e = beg + (int)threadIdx.x; e < end; e += 256) {
+            const float *vv = value + (int64_t)list[e] * CT;
+#pragma unroll
+            for (int c = 0; c < CT; ++c) mx[c] = fmaxf(mx[c], fabsf(vv[c]));
+        }
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            const float m = wave_max(mx[c]);
+            if (lane == 0) cs[wave][c] = m;
+        }
     }
     __syncthreads();
     if (threadIdx.x < (unsigned)CT) {
