@@ -1,17 +1,19 @@
 // project.hip -- cone-beam line integrals (Eq. 6) and their exact adjoint.
 //
-// Forward: one thread per ray (16x16-pixel tiles per workgroup so that the
-// 64 rays of a wave sample neighbouring voxels), midpoint rule in voxel
-// units with sample s at u = fma(s, su, bu).
+// Forward: one thread per ray (a wave's 64 rays form a tunable pixel tile so
+// that they sample neighbouring voxels), midpoint rule in voxel units with
+// sample s at u = fma(s, su, bu).
 //
-// Adjoint: voxel-brick owner, no global atomics.  A workgroup owns a brick of
-// the output volume, accumulates in LDS, and visits every ray whose samples
-// can touch the brick: the rays through the detector rectangle that bounds
-// the brick region's shadow.  A sample contributes to the 8 voxels of its
-// cell (i, i+1 per axis), so the brick takes exactly the samples whose cell
-// index lies in [B0-1, B0+S-1] on every axis; each ray's sample positions
-// come from one per-ray table, so every brick sees bit-identical samples and
-// no sample is lost or counted twice.
+// Adjoint: cell-brick owners, no global atomics.  The cells of the grid are
+// split into disjoint bricks; a workgroup owns one brick of one view, visits
+// every ray of the detector rectangle that bounds the brick's shadow, takes
+// exactly the samples whose cell lies in the brick and adds their 8 corner
+// weights into an LDS box (the brick's voxels plus a one-voxel pad on the
+// high side of each axis) in fixed point.  Each ray's sample positions come
+// from one per-ray table, so every brick sees bit-identical samples and no
+// sample is lost or counted twice.  Own voxels are stored directly; pads are
+// carried to the next brick of a z-chunk or staged, and a fix-up pass adds
+// the staged pads into the voxels they belong to in a fixed order.
 #include <math.h>
 
 #include <algorithm>
