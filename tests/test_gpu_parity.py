@@ -191,6 +191,48 @@ def test_project_backward(case):
     assert rel(got_s, want_s) < VOL_TOL, rel(got_s, want_s)
 
 
+def test_project_degenerate_cases():
+    """Edge cases of Eq. 6 and its adjoint against the oracle: the smallest
+    grid (2 voxels per axis) seen by a 5x3 detector whose outer rays miss
+    it; a view whose detector is shifted off the volume (every ray misses:
+    zero projections, zero adjoint); a residual on a single pixel; an all-zero
+    residual (the back-projection's fixed-point scale is then 0)."""
+    grid = Grid((2, 2, 2), (3.0, 2.5, 2.0), (0.4, -0.3, 0.2))
+    cone = Cone(400.0, 700.0, 5, 3, 2.6, 2.2, off_u=0.3, off_v=-0.2, step=0.0)
+    ang = np.asarray([0.1, 1.3, 2.9], np.float32)
+    V = len(ang)
+    vol = synth.random_volume(41, (V,) + grid.n, 0.5, 1.5)
+    want = oracle.project(vol, grid, cone, ang, shared=False)
+    got = N(ops.pmf_project(T(vol), grid, cone, T(ang), shared=False))
+    assert np.any(want == 0.0) and np.any(want > 0.0)
+    assert rel(got, want) < VOL_TOL, rel(got, want)
+    gp = synth.random_normal(42, (V, cone.nv, cone.nu))
+    want_b = oracle.project_bwd(gp, grid, cone, ang, shared=False)
+    got_b = N(ops.pmf_project_bwd(T(gp), grid, cone, T(ang), shared=False))
+    assert rel(got_b, want_b) < VOL_TOL, rel(got_b, want_b)
+    # detector shifted far off the volume: every ray misses
+    far = Cone(1000.0, 1500.0, 16, 12, 0.8, 0.8, off_u=400.0, step=0.0)
+    g2 = Grid((12, 10, 8), (1.5, 1.5, 2.0))
+    v2 = synth.random_volume(43, (1,) + g2.n)
+    a2 = np.asarray([0.4], np.float32)
+    assert np.all(oracle.project(v2, g2, far, a2, shared=False) == 0.0)
+    assert np.all(N(ops.pmf_project(T(v2), g2, far, T(a2), shared=False)) == 0.0)
+    gp2 = synth.random_normal(44, (1, far.nv, far.nu))
+    assert np.all(N(ops.pmf_project_bwd(T(gp2), g2, far, T(a2), shared=False)) == 0.0)
+    # one pixel's residual, and none at all
+    c3 = Cone(1000.0, 1500.0, 24, 20, 1.6, 1.6, step=0.0)
+    a3 = np.asarray([0.7, 2.2], np.float32)
+    one = np.zeros((2, c3.nv, c3.nu), np.float32)
+    one[1, 9, 13] = 2.5
+    want_1 = oracle.project_bwd(one, g2, c3, a3, shared=False)
+    got_1 = N(ops.pmf_project_bwd(T(one), g2, c3, T(a3), shared=False))
+    assert np.abs(want_1).max() > 0.0
+    assert rel(got_1, want_1) < VOL_TOL, rel(got_1, want_1)
+    zero = np.zeros_like(one)
+    assert np.all(N(ops.pmf_project_bwd(T(zero), g2, c3, T(a3), shared=False)) == 0.0)
+    assert np.all(N(ops.pmf_project_bwd(T(zero), g2, c3, T(a3), shared=True)) == 0.0)
+
+
 def test_project_adjoint_identity_fp32():
     vol, grid, cone, ang = _proj_case("aniso")
     V = len(ang)
