@@ -419,18 +419,29 @@ def test_headline_full_size_sampled():
         assert rel(N(grads_b["ref"][name]), N(grads_p["ref"][name])) < 1e-4, name
     say("headline: adjoint identity in ref")
     ref_g, bases_g = m.volumes()
-    x = T(synth.random_normal(25, w.grid.n))
-    y = T(synth.random_normal(26, (V, w.cone.nv, w.cone.nu)))
-    px = ops.pmf_warp_project(x, w.grid, bases_g, w.levels, m.coeff, w.cone, m.angles)
-    gx, _, _ = ops.pmf_warp_project_bwd(ref_g, w.grid, bases_g, w.levels, m.coeff, w.cone, m.angles, y)
-    lhs = float(torch.sum(px.double() * y.double()))
-    rhs = float(torch.sum(x.double() * gx.double()))
-    # The back-projection accumulates in 32-bit fixed point: each term is
-    # rounded to within 2^-31 * (bound on terms per voxel) * max|y * delta|,
-    # about 1e-7 of the largest term here; with random-sign y and x the
-    # identity's relative error is then of order 1e-5, not the 1e-7 of
-    # float rounding, so the bar is the volume tolerance.
-    assert abs(lhs - rhs) / abs(lhs) < VOL_TOL, (lhs, rhs)
+
+    def identity(x, y):
+        px = ops.pmf_warp_project(x, w.grid, bases_g, w.levels, m.coeff, w.cone, m.angles)
+        gx, _, _ = ops.pmf_warp_project_bwd(ref_g, w.grid, bases_g, w.levels, m.coeff, w.cone,
+                                            m.angles, y)
+        lhs = float(torch.sum(px.double() * y.double()))
+        rhs = float(torch.sum(x.double() * gx.double()))
+        norm = float(torch.linalg.vector_norm(px.double()) * torch.linalg.vector_norm(y.double()))
+        return lhs, rhs, norm
+    # nonnegative x and y: the inner product is a sum of nonnegative terms
+    # (no cancellation), so its relative error is that of the terms: float
+    # rounding and the back-projection's fixed point (each term rounded to
+    # within 2^-31 * kbound * max|y * delta|, ~1e-7 of the largest)
+    lhs, rhs, _ = identity(T(synth.random_volume(25, w.grid.n)),
+                           T(synth.random_volume(26, (V, w.cone.nv, w.cone.nu))))
+    say("headline: adjoint identity rel (nonnegative inputs)", abs(lhs - rhs) / abs(lhs))
+    assert abs(lhs - rhs) / abs(lhs) < 1e-5, (lhs, rhs)
+    # signed inputs: the inner product cancels, so the error is measured
+    # against the Cauchy-Schwarz bound |<Px, y>| <= |Px| |y|
+    lhs, rhs, norm = identity(T(synth.random_normal(27, w.grid.n)),
+                              T(synth.random_normal(28, (V, w.cone.nv, w.cone.nu))))
+    say("headline: adjoint identity (signed inputs), |lhs-rhs| / (|Px||y|)", abs(lhs - rhs) / norm)
+    assert abs(lhs - rhs) / norm < 1e-6, (lhs, rhs, norm)
 
 
 def _near_faces(w, dvf, dabs):
