@@ -821,9 +821,12 @@ __global__ __launch_bounds__(64) void k_vox_bwd(pmf_gauss_t gs, GridK g, float k
                                                 pmf_gauss_grad_t gr) {
     constexpr int CM = CT > 0 ? CT : MAXC_VOX;
     const int C = CT > 0 ? CT : gs.c;
-    __shared__ VoxG gb[64];
-    __shared__ float gval[64][CM];
-    __shared__ float sums[64][CM + BW_NS];
+    // LDS for the wave's `per` Gaussians only (a one-Gaussian batch leaves
+    // room for many waves per CU): records, values, reduced sums
+    extern __shared__ float4 bwd_smem[];
+    VoxG *const gb = (VoxG *)bwd_smem;
+    float(*const gval)[CM] = (float(*)[CM])(gb + per);
+    float(*const sums)[CM + BW_NS] = (float(*)[CM + BW_NS])(gval + per);
     const int lane = threadIdx.x;
     const int64_t g0 = (int64_t)blockIdx.x * per;
     const float k2 = isinf(k) ? INFINITY : k * k;
@@ -1084,14 +1087,16 @@ hipError_t launch_voxelize_bwd(const pmf_gauss_t &gs, const GridK &g, float k, c
         else
             while (per < 64 && gs.m / (2 * per) > 12500) per *= 2;
         const unsigned nb = (unsigned)((gs.m + per - 1) / per);
+        const int cm = gs.c == 1 || gs.c == 3 || gs.c == 9 ? gs.c : MAXC_VOX;
+        const size_t lds = (size_t)per * (sizeof(VoxG) + sizeof(float) * (2 * cm + BW_NS));
         if (gs.c == 1)
-            k_vox_bwd<1, false><<<nb, 64, 0, s>>>(gs, g, k, per, g_vol, gr);
+            k_vox_bwd<1, false><<<nb, 64, lds, s>>>(gs, g, k, per, g_vol, gr);
         else if (gs.c == 3)
-            k_vox_bwd<3, true><<<nb, 64, 0, s>>>(gs, g, k, per, g_vol, gr);
+            k_vox_bwd<3, true><<<nb, 64, lds, s>>>(gs, g, k, per, g_vol, gr);
         else if (gs.c == 9)
-            k_vox_bwd<9, true><<<nb, 64, 0, s>>>(gs, g, k, per, g_vol, gr);
+            k_vox_bwd<9, true><<<nb, 64, lds, s>>>(gs, g, k, per, g_vol, gr);
         else
-            k_vox_bwd<0, true><<<nb, 64, 0, s>>>(gs, g, k, per, g_vol, gr);
+            k_vox_bwd<0, true><<<nb, 64, lds, s>>>(gs, g, k, per, g_vol, gr);
     }
     return hipGetLastError();
 }
