@@ -340,7 +340,7 @@ __device__ __forceinline__ void warp_combine_bwd_brick(
                 }
                 const float tot = wave_reduce_scatter16(x, lane);
                 const int ci = g0 + scatter16_index(lane);
-                if (lane < 16 && ci < NC) slot[ci] = tot;
+                if ((lane & 3) == 0 && ci < NC) slot[ci] = tot;
             }
         }
         __syncthreads();
