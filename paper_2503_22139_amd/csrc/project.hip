@@ -690,11 +690,18 @@ __device__ __forceinline__ void bp_scatter(const BwdK &bj, const BrickGeo &q, in
             }
         }
         // flatten the wave's runs: item q in [start, start + len) is
-        // sample q - start + s0 of this lane's ray
+        // sample q - start + s0 of this lane's ray.  Only non-empty runs are
+        // stored (compacted in lane order), so a lane's walk crosses from
+        // one run to the next in one step; the ends past the last run hold
+        // T for the search below.
         const int incl = wave_incl_sum(len);
         const int T = __builtin_amdgcn_readlane(incl, 63);
         if (T == 0) continue;
         {
+            const unsigned long long nz = __ballot(len > 0);
+            const int pos = __builtin_amdgcn_mbcnt_hi((unsigned)(nz >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((unsigned)nz, 0u));
+            const int NR = __popcll(nz);
             RunP rp;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
@@ -703,8 +710,11 @@ __device__ __forceinline__ void bp_scatter(const BwdK &bj, const BrickGeo &q, in
             }
             rp.gp = gp;
             rp.off = s0 - (incl - len);
-            if (len > 0) wr[lane] = rp;
-            we[lane] = incl;
+            if (len > 0) {
+                wr[pos] = rp;
+                we[pos] = incl;
+            }
+            if (lane >= NR) we[lane] = T;
         }
         wave_lds_sync();
         // Lane j takes items [j K, j K + K): every lane does a sample per
@@ -712,7 +722,7 @@ __device__ __forceinline__ void bp_scatter(const BwdK &bj, const BrickGeo &q, in
         const int K = (T + 63) >> 6;
         int it = lane * K;
         const int ite = min(it + K, T);
-        // first ray of the slice: the smallest r with end_r > it (binary
+        // first run of the slice: the smallest r with end_r > it (binary
         // lifting)
         int ri = 0;
 #pragma unroll
@@ -771,10 +781,8 @@ __device__ __forceinline__ void bp_scatter(const BwdK &bj, const BrickGeo &q, in
             // every sample's 8 corners go to LDS at once
             float sf = (float)(it + rp.off);
             for (; it < ite; ++it, sf += 1.0f) {
-                if (it >= rend) {
-                    do {
-                        rend = we[++ri];
-                    } while (it >= rend);
+                if (it >= rend) {           // the next run (none is empty)
+                    rend = we[++ri];
                     rp = wr[ri];
                     lds_wait();
                     sf = (float)(it + rp.off);
@@ -793,10 +801,8 @@ __device__ __forceinline__ void bp_scatter(const BwdK &bj, const BrickGeo &q, in
             sample(sf, cur_off, cw);
             for (++it; it < ite; ++it) {
                 sf += 1.0f;                 // exact: sample indices are small integers
-                if (it >= rend) {
-                    do {
-                        rend = we[++ri];
-                    } while (it >= rend);
+                if (it >= rend) {           // the next run (none is empty)
+                    rend = we[++ri];
                     rp = wr[ri];
                     lds_wait();
                     sf = (float)(it + rp.off);
