@@ -432,6 +432,14 @@ __device__ __forceinline__ void fma_in_place(float &acc, float k, float e) {
     asm("v_fma_f32 %0, %0, %1, %2" : "+v"(acc) : "v"(k), "v"(e));
 }
 
+// 0.0 in the lanes set in mask, 1.0 in the others (one select on the mask's
+// SGPR pair, so a compare feeding both a branch and this needs no twin).
+__device__ __forceinline__ float zero_where(unsigned long long mask) {
+    float r;
+    asm("v_cndmask_b32_e64 %0, 1.0, 0, %1" : "=v"(r) : "s"(mask));
+    return r;
+}
+
 // Waits for this wave's outstanding LDS reads (and, LDS operations retiring
 // in order, everything issued before them).  Placed right after the rare
 // reads of a ray switch so the compiler need not put a conservative wait on
@@ -810,9 +818,10 @@ __device__ __forceinline__ void bp_scatter(const BwdK &bj, const BrickGeo &q, in
                 int off;
                 float e[8];
                 sample(sf, off, e);
-                // a restart is a multiply by 0, so both cases share one fma
+                // a restart is a multiply by 0, so both cases share one fma;
+                // the factor comes from the branch's own lane mask
                 const bool moved = off != cur_off;
-                const float keep = moved ? 0.0f : 1.0f;
+                const float keep = zero_where(__ballot(moved));
                 if (moved) add8(cur_off, cw);
                 cur_off = off;
 #pragma unroll
