@@ -665,6 +665,15 @@ __device__ __forceinline__ void bp_scatter(const BwdK &bj, const BrickGeo &q, in
                     };
                     auto owned = [&](int si) {
                         const float sf = (float)si;
+                        if (interior) {
+                            // floor(x) in [clo, chi] <=> clo <= x < chi + 1,
+                            // and ulo = clo, uhi = chi + 1 in an interior brick
+                            const float x0 = fmaf(sf, r.su[0], r.bu[0]);
+                            const float x1 = fmaf(sf, r.su[1], r.bu[1]);
+                            const float x2 = fmaf(sf, r.su[2], r.bu[2]);
+                            return x0 >= q.ulo[0] && x0 < q.uhi[0] && x1 >= q.ulo[1] &&
+                                   x1 < q.uhi[1] && x2 >= q.ulo[2] && x2 < q.uhi[2];
+                        }
                         float fi = cell(fmaf(sf, r.su[0], r.bu[0]), 0);
                         bool o = fi >= q.clo[0] && fi <= q.chi[0];
                         fi = cell(fmaf(sf, r.su[1], r.bu[1]), 1);
