@@ -153,22 +153,30 @@ struct Shape4 {
 
 // One 1-D transpose pass along axis `ax`, out[c][..p..] = sum_j W(j,p)
 // in[c][..j..] with W(j,p) the forward's linear weight of level index p for
-// fine index j; one thread per line along `ax`: the thread walks the
-// line's nf input values in order, each split between its two level cells
-// (weights 1 - f and f, as the forward reads them), and emits the nc outputs
-// in order (a cell is complete once the walk has passed it).  Every input
-// value is read and weighted once.
+// fine index j.  Each line along `ax` is cut into nseg segments of outputs
+// [p0, p1), one thread each (short or few lines would otherwise leave the
+// pass latency-bound): the thread walks the line's input values from the
+// first one that reaches p0, in order, each split between its two level
+// cells (weights 1 - f and f, as the forward reads them), and emits its
+// outputs in order (a cell is complete once the walk has passed it).  Every
+// output sums its terms in ascending fine order whatever nseg is.
 __global__ __launch_bounds__(256) void k_adj_line(Shape4 in_s, int ax, int nc, float scale,
-                                                  float off, const float *__restrict__ in,
-                                                  AdjSrc src, float *__restrict__ out) {
+                                                  float off, int nseg,
+                                                  const float *__restrict__ in, AdjSrc src,
+                                                  float *__restrict__ out) {
     // lines: all index tuples of (c, d0, d1, d2) with the ax index fixed to 0
     int ld[3] = {in_s.d[0], in_s.d[1], in_s.d[2]};
     ld[ax] = 1;
     const int64_t nlines = (int64_t)in_s.c * ld[0] * ld[1] * ld[2];
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nlines) return;
+    const int64_t tt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tt >= nlines * nseg) return;
+    // segment-major, so neighbouring threads take neighbouring lines
+    const int seg = (int)(tt / nlines);
+    int64_t r = tt - (int64_t)seg * nlines;
+    const int per = (nc + nseg - 1) / nseg;
+    const int p0 = seg * per, p1 = min(nc, p0 + per);
+    if (p0 >= p1) return;
     int idx[3];
-    int64_t r = t;
     idx[2] = (int)(r % ld[2]);
     r /= ld[2];
     idx[1] = (int)(r % ld[1]);
@@ -185,13 +193,20 @@ __global__ __launch_bounds__(256) void k_adj_line(Shape4 in_s, int ax, int nc, f
     od[ax] = nc;
     const int64_t ost = ax == 2 ? 1 : (ax == 1 ? od[2] : (int64_t)od[1] * od[2]);
     const int64_t obase = (((int64_t)c * od[0] + idx[0]) * od[1] + idx[1]) * od[2] + idx[2];
-    int next = 0;           // first output not yet written
+    auto emit = [&](int p, float v) {
+        if (p >= p0 && p < p1) out[obase + (int64_t)p * ost] = v;
+    };
+    // a value at cell i feeds outputs i and i + 1: start a little below the
+    // first fine index whose cell is p0 - 1 (values below it are skipped)
+    const int jlo = p0 == 0 ? 0 : max(0, (int)floorf(((float)(p0 - 1) - off) / scale) - 2);
+    int next = p0;          // first output not yet written
     int cur = -1;           // cell of the pending pair (cur, cur + 1)
     float a0 = 0.0f, a1 = 0.0f;
+    bool done = false;
     // The line's values are fetched ADJ_U at a time ahead of the walk (whose
     // branches would otherwise leave one load in flight per wave).
     constexpr int ADJ_U = 8;
-    for (int j0 = 0; j0 < nf; j0 += ADJ_U) {
+    for (int j0 = jlo; j0 < nf && !done; j0 += ADJ_U) {
         float xs[ADJ_U];
 #pragma unroll
         for (int u = 0; u < ADJ_U; ++u) {
@@ -205,20 +220,25 @@ __global__ __launch_bounds__(256) void k_adj_line(Shape4 in_s, int ax, int nc, f
             int i;
             float f;
             if (!axis_cell(fmaf((float)j, scale, off), nc, i, f)) continue;
+            if (i < p0 - 1) continue;           // reaches no output of this segment
+            if (i >= p1) {                      // nor does anything past it
+                done = true;
+                break;
+            }
             if (i != cur) {
                 // cells below i are complete: write them (zeros for cells no value reached)
                 if (cur >= 0) {
-                    out[obase + (int64_t)cur * ost] = a0;
+                    emit(cur, a0);
                     next = cur + 1;
                     a0 = (cur + 1 == i) ? a1 : 0.0f;
                     if (cur + 1 < i) {
-                        out[obase + (int64_t)(cur + 1) * ost] = a1;
+                        emit(cur + 1, a1);
                         next = cur + 2;
                     }
                 } else {
                     a0 = 0.0f;
                 }
-                for (; next < i; ++next) out[obase + (int64_t)next * ost] = 0.0f;
+                for (; next < i; ++next) emit(next, 0.0f);
                 a1 = 0.0f;
                 cur = i;
             }
@@ -228,11 +248,11 @@ __global__ __launch_bounds__(256) void k_adj_line(Shape4 in_s, int ax, int nc, f
         }
     }
     if (cur >= 0) {
-        out[obase + (int64_t)cur * ost] = a0;
-        out[obase + (int64_t)(cur + 1) * ost] = a1;
-        next = cur + 2;
+        emit(cur, a0);
+        emit(cur + 1, a1);
+        next = max(next, cur + 2);
     }
-    for (; next < nc; ++next) out[obase + (int64_t)next * ost] = 0.0f;
+    for (; next < p1; ++next) emit(next, 0.0f);
 }
 
 // Level grid equals the output grid: the source is the answer.
@@ -306,10 +326,15 @@ hipError_t launch_upsample_adjoint(const LevelsK &lv, int l, const GridK &lvl_gr
         Shape4 os = sh;
         os.d[ax] = m.n[ax];
         const int64_t lines = (int64_t)sh.c * sh.d[0] * sh.d[1] * sh.d[2] / sh.d[ax];
+        // segments per line: enough threads to cover the pass's latency
+        // (about 2^19), at least 8 outputs each
+        int nseg = 1;
+        while (2 * nseg <= m.n[ax] / 8 && lines * nseg < (1 << 19)) nseg *= 2;
+        const int64_t threads = lines * nseg;
         {
             ProfScope prof_("upsample_adjoint", s);
-            k_adj_line<<<(unsigned)((lines + 255) / 256), 256, 0, s>>>(sh, ax, m.n[ax], m.scale[ax],
-                                                                       m.off[ax], in, src, dst);
+            k_adj_line<<<(unsigned)((threads + 255) / 256), 256, 0, s>>>(
+                sh, ax, m.n[ax], m.scale[ax], m.off[ax], nseg, in, src, dst);
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
