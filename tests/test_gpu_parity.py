@@ -525,8 +525,8 @@ def _coeff_within_face_jumps(w, ref, bases, target, got, want, near):
 
 def _mbc_flagged(w, near):
     """Per MBC level, the Gaussians whose gradient can see a near-face voxel
-    (the reading of the survey's FD rule: flag and exclude parameters that a
-    face crossing reaches).  A fine voxel j feeds dL/dE_l at the corners of
+    (a gradient is not pinned where a cell-face crossing reaches it, so such
+    parameters are flagged and excluded).  A fine voxel j feeds dL/dE_l at the corners of
     its upsampling cell on level l; a Gaussian is flagged when its mask
     holds such a corner (the voxelization adjoint of the corner indicator
     with unit values is then positive)."""
