@@ -175,31 +175,52 @@ __global__ __launch_bounds__(256) void k_vox_prep(pmf_gauss_t gs, GridK g, float
 
 // Exclusive scan of n counts (CNT_STRIDE apart) by one workgroup of 1024
 // threads: off[0..n] (dense), and the cursors (CNT_STRIDE apart) = off[] for
-// the fill pass.
+// the fill pass.  Each thread takes a run of up to SCAN_U counts (loaded
+// together and kept in registers for the second pass); the block's scan is
+// a DPP scan per wave plus the wave totals.
+constexpr int SCAN_U = 8;
 __global__ __launch_bounds__(1024) void k_scan(const int32_t *__restrict__ cnt, int64_t n,
                                                int32_t *__restrict__ off,
                                                int32_t *__restrict__ cursor) {
-    __shared__ int32_t part[1024];
+    __shared__ int32_t wsum[16];
     const int64_t per = (n + 1023) / 1024;
     const int64_t b = threadIdx.x * per;
     const int64_t e = b + per < n ? b + per : n;
+    const bool few = per <= SCAN_U;       // uniform
+    int32_t v[SCAN_U];
     int32_t s = 0;
-    for (int64_t i = b; i < e; ++i) s += cnt[i * CNT_STRIDE];
-    part[threadIdx.x] = s;
+    if (few) {
+#pragma unroll
+        for (int k = 0; k < SCAN_U; ++k) v[k] = b + k < e ? cnt[(b + k) * CNT_STRIDE] : 0;
+#pragma unroll
+        for (int k = 0; k < SCAN_U; ++k) s += v[k];
+    } else {
+        for (int64_t i = b; i < e; ++i) s += cnt[i * CNT_STRIDE];
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int32_t incl = wave_incl_sum(s);
+    if (lane == 63) wsum[wave] = incl;
     __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-        int32_t t = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0;
-        __syncthreads();
-        part[threadIdx.x] += t;
-        __syncthreads();
+    int32_t base = 0;
+    for (int w = 0; w < wave; ++w) base += wsum[w];
+    int32_t run = base + incl - s;
+    if (few) {
+#pragma unroll
+        for (int k = 0; k < SCAN_U; ++k) {
+            if (b + k < e) {
+                off[b + k] = run;
+                cursor[(b + k) * CNT_STRIDE] = run;
+                run += v[k];
+            }
+        }
+    } else {
+        for (int64_t i = b; i < e; ++i) {
+            off[i] = run;
+            cursor[i * CNT_STRIDE] = run;
+            run += cnt[i * CNT_STRIDE];
+        }
     }
-    int32_t run = part[threadIdx.x] - s;
-    for (int64_t i = b; i < e; ++i) {
-        off[i] = run;
-        cursor[i * CNT_STRIDE] = run;
-        run += cnt[i * CNT_STRIDE];
-    }
-    if (threadIdx.x == 1023) off[n] = part[1023];
+    if (threadIdx.x == 1023) off[n] = base + incl;
 }
 
 // The large Gaussians in ascending index order (so that every tile adds
