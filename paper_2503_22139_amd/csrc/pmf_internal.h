@@ -225,47 +225,53 @@ __device__ __forceinline__ void swap16(float &a, float &b) {
     b = __uint_as_float(r[1]);
 }
 
-// Reduce-scatter of 32 per-lane values over the 64 lanes of a wave: lane L
-// returns the total over all lanes of value L >> 1 (lanes L and L ^ 1 hold
-// the same total).  Each step pairs lanes that hold the same set of partial
-// sums, keeps half of the set and adds the partner's copy of that half:
-// 16 + 8 + 4 + 2 + 1 + 1 additions instead of 32 six-step reductions.  The
-// halves and rows are paired by the permlane swaps, the lanes of a row by
-// DPP (mirror, half mirror, quad permutes).
+// Reduce-scatter of 32 per-lane values over the 64 lanes of a wave: returns
+// the total over all lanes of value 16*b3 + 8*b2 + 4*b1 + 2*b0 + b4 (b_k =
+// bit k of the lane; the same total in lanes L and L+32).  Each step pairs
+// lanes that hold the same set of partial sums, keeps half of the set and
+// adds the partner's copy of that half: 16 + 8 + 4 + 2 + 1 + 1 additions
+// instead of 32 separate six-step reductions.  (A form that pairs halves and
+// rows with the permlane swaps first, as the 16-value version below does,
+// measured 7% slower in the rasterizer's adjoint, its one user.)
 __device__ __forceinline__ float wave_reduce_scatter32(const float (&x)[32], int lane) {
-    const bool h3 = lane & 8, h2 = lane & 4, h1 = lane & 2;
+    const bool h3 = lane & 8, h2 = lane & 4, h1 = lane & 2, h0 = lane & 1, h4 = lane & 16;
     float a[16], b[8], c[4], d[2];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {     // value j + 16 b5
-        float p = x[j], q = x[16 + j];
-        swap32(p, q);
-        a[j] = p + q;
+    for (int j = 0; j < 16; ++j) {     // partner: row_mirror (lane ^ 15 within 16)
+        const float keep = h3 ? x[16 + j] : x[j], send = h3 ? x[j] : x[16 + j];
+        a[j] = keep + dpp_mov<0x140>(send);
     }
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {      // value j + 8 b4 + 16 b5
-        float p = a[j], q = a[8 + j];
-        swap16(p, q);
-        b[j] = p + q;
+    for (int j = 0; j < 8; ++j) {      // partner: row_half_mirror (lane ^ 7 within 8)
+        const float keep = h2 ? a[8 + j] : a[j], send = h2 ? a[j] : a[8 + j];
+        b[j] = keep + dpp_mov<0x141>(send);
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {      // partner: row_mirror (lane ^ 15 within 16)
-        const float keep = h3 ? b[4 + j] : b[j], send = h3 ? b[j] : b[4 + j];
-        c[j] = keep + dpp_mov<0x140>(send);
+    for (int j = 0; j < 4; ++j) {      // partner: lane ^ 2
+        const float keep = h1 ? b[4 + j] : b[j], send = h1 ? b[j] : b[4 + j];
+        c[j] = keep + dpp_mov<0x4E>(send);
     }
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {      // partner: row_half_mirror (lane ^ 7 within 8)
-        const float keep = h2 ? c[2 + j] : c[j], send = h2 ? c[j] : c[2 + j];
-        d[j] = keep + dpp_mov<0x141>(send);
+    for (int j = 0; j < 2; ++j) {      // partner: lane ^ 1
+        const float keep = h0 ? c[2 + j] : c[j], send = h0 ? c[j] : c[2 + j];
+        d[j] = keep + dpp_mov<0xB1>(send);
     }
-    const float keep = h1 ? d[1] : d[0], send = h1 ? d[0] : d[1];
-    const float e = keep + dpp_mov<0x4E>(send);     // partner: lane ^ 2
-    return e + dpp_mov<0xB1>(e);                    // partner: lane ^ 1
+    const float keep = h4 ? d[1] : d[0], send = h4 ? d[0] : d[1];
+    const float e = keep + __shfl_xor(send, 16, 64);
+    return e + __shfl_xor(e, 32, 64);
 }
 
-__device__ __forceinline__ int scatter32_index(int lane) { return lane >> 1; }
+__device__ __forceinline__ int scatter32_index(int lane) {
+    return 16 * ((lane >> 3) & 1) + 8 * ((lane >> 2) & 1) + 4 * ((lane >> 1) & 1) +
+           2 * (lane & 1) + ((lane >> 4) & 1);
+}
 
-// The same for 16 values: lane L returns the total of value L >> 2 (lanes
-// L .. L ^ 3 hold the same total).
+// Reduce-scatter of 16 per-lane values over the 64 lanes of a wave: lane L
+// returns the total over all lanes of value L >> 2 (lanes L .. L ^ 3 hold the
+// same total).  Each step pairs lanes that hold the same set of partial sums,
+// keeps half of the set and adds the partner's copy of that half; the halves
+// and rows are paired by the permlane swaps (two instructions per pair, no
+// lane select, no LDS permute), the lanes of a row by DPP.
 __device__ __forceinline__ float wave_reduce_scatter16(const float (&x)[16], int lane) {
     const bool h3 = lane & 8, h2 = lane & 4;
     float a[8], b[4], c[2];

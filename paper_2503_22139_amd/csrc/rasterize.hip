@@ -377,7 +377,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_splat_bwd(const SplatP *__restri
             float r = 0.0f;
             if (__ballot(any) != 0) r = wave_reduce_scatter32(xv, lane);   // wave-uniform
             const int jj = idx % 5, q = idx / 5;
-            if ((lane & 1) == 0 && idx < 30 && j0 + jj < n) red[wave][j0 + jj][q] = r;
+            if (lane < 32 && idx < 30 && j0 + jj < n) red[wave][j0 + jj][q] = r;
         }
         __syncthreads();
         for (int i = threadIdx.x; i < n * 6; i += RS_THREADS) {
