@@ -660,6 +660,17 @@ __global__ __launch_bounds__(256) void k_vox_gather(const GaussK *__restrict__ r
     if (ix > e0 || iy > e1) return;
     const int64_t N = grid_size(g);
     float *const vb = vol + ((int64_t)ix * g.n[1] + iy) * g.n[2];
+    if constexpr (SEG == 4) {
+        // a thread's four voxels as one 16-byte store per channel when the
+        // rows and the volume are 16-byte aligned (z0 is a multiple of 4)
+        if ((g.n[2] & 3) == 0 && ((uintptr_t)vol & 15) == 0 && z0 + 3 <= e2) {
+#pragma unroll
+            for (int c = 0; c < CT; ++c)
+                *(float4 *)(vb + (int64_t)c * N + z0) =
+                    make_float4(out[0][c], out[1][c], out[2][c], out[3][c]);
+            return;
+        }
+    }
 #pragma unroll
     for (int c = 0; c < CT; ++c)
 #pragma unroll
