@@ -381,14 +381,15 @@ size_t pmf_profile_names(char *buf, size_t len);
  *                              noted, with
  *                              consecutive samples of a ray in one cell
  *                              summed in registers first unless noted:
- *                              0 = 48x16x8, 1 = 48x16x8 summing each
- *                              sample alone, 2 = 32x16x8, 3, 4 (default), 5
- *                              = 48x16x8 walked in chunks of 2, 8, 4 bricks
- *                              along z by one workgroup, 6 = 32x16x8 in
- *                              chunks of 4, 7 = 64x16x8 and 8 = 80x16x8
- *                              with 12 wavefronts, in chunks of 8 (a launch
- *                              of few views takes shorter chunks, so that
- *                              it still fills the chip);
+ *                              0 = 48x16x8 and 1 = 48x16x8 summing each
+ *                              sample alone, one brick per workgroup; the
+ *                              others walked in chunks of 8 bricks along z
+ *                              by one workgroup: 2 = 32x16x8, 3 = 44x16x8,
+ *                              4 (default) = 44x20x8, 5 = 40x20x8,
+ *                              6 = 48x16x8, 7 = 64x16x8 with 12
+ *                              wavefronts, 8 = 52x16x8 (a launch of few
+ *                              views takes shorter chunks, so that it still
+ *                              fills the chip);
  *   PMF_TUNE_VOXELIZE_BWD      Gaussians per wavefront in pmf_voxelize_bwd:
  *                              0 = chosen from the set's size (default),
  *                              k = 1..7: 2^(k-1).

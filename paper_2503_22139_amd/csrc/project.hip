@@ -1225,8 +1225,8 @@ struct BrickShape {
     int L, W, H, NW;
 };
 static const BrickShape kBricks[] = {{48, 16, 8, 8}, {48, 16, 8, 8}, {32, 16, 8, 8},
-                                     {48, 16, 8, 8}, {48, 16, 8, 8}, {48, 16, 8, 8},
-                                     {32, 16, 8, 8}, {64, 16, 8, 12}, {80, 16, 8, 12}};
+                                     {44, 16, 8, 8}, {44, 20, 8, 8}, {40, 20, 8, 8},
+                                     {48, 16, 8, 8}, {64, 16, 8, 12}, {52, 16, 8, 8}};
 constexpr int NBRICKS = sizeof(kBricks) / sizeof(kBricks[0]);
 
 // Items per view: the brick count of the orientation with more bricks.
@@ -1355,13 +1355,13 @@ hipError_t launch_project_bwd_jobs(const BwdJob *jobs, int n, hipStream_t s) {
     static_assert(NBRICKS == 9, "tune candidates");
     switch (tune_get(KNOB_BACKPROJECT_BRICK)) {
         case 1: return project_bwd_bricks<48, 16, 8, 8, false, 1>(jobs, n, s);
-        case 2: return project_bwd_bricks<32, 16, 8, 8, true, 1>(jobs, n, s);
-        case 3: return project_bwd_chunked<48, 16, 8, 8, true, 2>(jobs, n, s);
-        case 4: return project_bwd_chunked<48, 16, 8, 8, true, 8>(jobs, n, s);
-        case 5: return project_bwd_chunked<48, 16, 8, 8, true, 4>(jobs, n, s);
-        case 6: return project_bwd_chunked<32, 16, 8, 8, true, 4>(jobs, n, s);
+        case 2: return project_bwd_chunked<32, 16, 8, 8, true, 8>(jobs, n, s);
+        case 3: return project_bwd_chunked<44, 16, 8, 8, true, 8>(jobs, n, s);
+        case 4: return project_bwd_chunked<44, 20, 8, 8, true, 8>(jobs, n, s);
+        case 5: return project_bwd_chunked<40, 20, 8, 8, true, 8>(jobs, n, s);
+        case 6: return project_bwd_chunked<48, 16, 8, 8, true, 8>(jobs, n, s);
         case 7: return project_bwd_chunked<64, 16, 8, 12, true, 8>(jobs, n, s);
-        case 8: return project_bwd_chunked<80, 16, 8, 12, true, 8>(jobs, n, s);
+        case 8: return project_bwd_chunked<52, 16, 8, 8, true, 8>(jobs, n, s);
         default: return project_bwd_bricks<48, 16, 8, 8, true, 1>(jobs, n, s);
     }
 }
