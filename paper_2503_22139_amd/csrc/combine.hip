@@ -327,9 +327,9 @@ hipError_t launch_upsample_adjoint(const LevelsK &lv, int l, const GridK &lvl_gr
         os.d[ax] = m.n[ax];
         const int64_t lines = (int64_t)sh.c * sh.d[0] * sh.d[1] * sh.d[2] / sh.d[ax];
         // segments per line: enough threads to cover the pass's latency
-        // (about 2^19), at least 8 outputs each
+        // (about 2^20: measured against 2^18 to 2^22), at least 8 outputs each
         int nseg = 1;
-        while (2 * nseg <= m.n[ax] / 8 && lines * nseg < (1 << 19)) nseg *= 2;
+        while (2 * nseg <= m.n[ax] / 8 && lines * nseg < (1 << 20)) nseg *= 2;
         const int64_t threads = lines * nseg;
         {
             ProfScope prof_("upsample_adjoint", s);
