@@ -139,10 +139,10 @@ constexpr int HALO = 3;
 constexpr int HB = FB + 2 * HALO + 1;
 constexpr int HB3 = HB * HB * HB;
 constexpr int VCH = 64;
-constexpr int FLUSH = 8;   // views per fixed-point accumulation round
+constexpr int FLUSH = 32;  // views per fixed-point accumulation round
 constexpr int WB_THREADS = FB * FB * FB;    // one voxel per thread
 constexpr int WB_WAVES = WB_THREADS / 64;
-constexpr int LO_BITS = 18; // 512 * FLUSH * 2^(LO_BITS-1) < 2^31
+constexpr int LO_BITS = 17; // 512 * FLUSH * 2^(LO_BITS-1) < 2^31
 
 struct GOut {
     float *dst[MAXL];   // per level: [3B][N] destination (g_bases or staging buffer)
@@ -154,7 +154,7 @@ struct GOut {
 // 2^30 / (512 * views * M) with M the largest |dL/dI_v| of those views, which
 // bounds every partial sum; each scaled contribution is split into its
 // nearest integer (high word) and the remainder times 2^LO_BITS (low word),
-// so the two 32-bit sums keep about 48 bits; each round is folded into a
+// so the two 32-bit sums keep about 47 bits; each round is folded into a
 // float box.
 // The float box is staged per brick and summed by k_gather_boxes;
 // displacements that leave the halo add into a 64-bit fixed-point volume
