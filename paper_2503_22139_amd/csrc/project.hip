@@ -1324,9 +1324,10 @@ static hipError_t project_bwd_bricks(const BwdJob *jobs, int n, hipStream_t s) {
     for (int k = 0; k < n; ++k) {
         const int64_t N = grid_size(t.s[k].g);
         ProfScope prof_("project_bwd_fixup", s);
-        // blocks per view: enough to fill the chip across the views
+        // blocks per view: about 16k over the views (measured: 2k, 4k, 8k
+        // and 16k blocks took 0.235, 0.202, 0.185 and 0.178 ms at 32 views)
         const int V = sum_views ? 1 : t.s[k].V;
-        const int per_view = std::max(1, std::min(256, 2048 / V));
+        const int per_view = std::max(1, std::min(2048, 16384 / V));
         (void)N;
         k_project_bwd_fixup<L, W, H><<<dim3((unsigned)per_view, (unsigned)V), 256, 0, s>>>(
             t.s[k], sum_views ? 1 : 0);
