@@ -397,12 +397,14 @@ __global__ __launch_bounds__(256) void k_gather_boxes(const float *__restrict__ 
                                                       const long long *__restrict__ fix,
                                                       const unsigned *__restrict__ vmax_all,
                                                       float *__restrict__ g_ref) {
-    const int64_t N = grid_size(g);
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // N < 2^31 (checked on the host): 32-bit index arithmetic
+    const unsigned N = (unsigned)grid_size(g);
+    const unsigned j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= N) return;
-    const int p2 = (int)(j % g.n[2]);
-    const int p1 = (int)((j / g.n[2]) % g.n[1]);
-    const int p0 = (int)(j / ((int64_t)g.n[2] * g.n[1]));
+    const unsigned q = j / (unsigned)g.n[2];
+    const int p2 = (int)(j - q * (unsigned)g.n[2]);
+    const int p0 = (int)(q / (unsigned)g.n[1]);
+    const int p1 = (int)(q - (unsigned)p0 * (unsigned)g.n[1]);
     // bricks b with b*FB - HALO <= p <= b*FB + FB + HALO
     const int a0 = max(0, (p0 - FB - HALO + FB - 1) / FB), e0 = min(nb0 - 1, (p0 + HALO) / FB);
     const int a1 = max(0, (p1 - FB - HALO + FB - 1) / FB), e1 = min(nb1 - 1, (p1 + HALO) / FB);
@@ -416,8 +418,8 @@ __global__ __launch_bounds__(256) void k_gather_boxes(const float *__restrict__ 
                 s += stage[((int64_t)(b0 * nb1 + b1) * nb2 + b2) * HB3 + (l0 * HB + l1) * HB + l2];
             }
     if (fix) {
-        const double sc = fix_scale(*vmax_all);
-        if (sc > 0.0) s += (float)((double)fix[j] / sc);
+        const long long fv = fix[j];
+        if (fv != 0) s += (float)((double)fv / fix_scale(*vmax_all));  // nonzero: scale > 0
     }
     g_ref[j] += s;
 }

@@ -304,12 +304,10 @@ __global__ __launch_bounds__(TV_THREADS) void k_tv(const float *__restrict__ vol
     if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-__global__ void k_sum_scaled(const float *__restrict__ partial, int n, float scale,
-                             float *__restrict__ out) {
-    if (threadIdx.x != 0) return;
-    float s = 0.0f;
-    for (int i = 0; i < n; ++i) s += partial[i];
-    *out = scale * s;
+__global__ __launch_bounds__(64) void k_sum_scaled(const float *__restrict__ partial, int n,
+                                                   float scale, float *__restrict__ out) {
+    const float s = wave_sum_partials(partial, n);
+    if (threadIdx.x == 63) *out = scale * s;
 }
 
 static int tv_blocks(int D) { return (int)(((int64_t)D * D * D + TV_THREADS - 1) / TV_THREADS); }
@@ -384,15 +382,30 @@ hipError_t launch_tv_noalloc(const float *vol, const GridK &gk, const int corner
 constexpr int NRM_BLOCKS = 256;         // partial sums per channel
 
 // Sum of squares of each channel of one level ([C][N]): NRM_BLOCKS fixed
-// strided partials per channel.
+// strided partials per channel.  VEC: the channels are 16-byte aligned and
+// N % 4 == 0, and the values move as float4.
+template <bool VEC>
 __global__ __launch_bounds__(256) void k_sumsq(const float *__restrict__ e, int64_t N,
                                                float *__restrict__ partial) {
     __shared__ float red[4];
     const int ch = blockIdx.y;
     const float *ec = e + (int64_t)ch * N;
     float acc = 0.0f;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)NRM_BLOCKS * 256)
-        acc = fmaf(ec[i], ec[i], acc);
+    if (VEC) {
+        const float4 *e4 = (const float4 *)ec;
+        for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N / 4;
+             i += (int64_t)NRM_BLOCKS * 256) {
+            const float4 x = e4[i];
+            acc = fmaf(x.x, x.x, acc);
+            acc = fmaf(x.y, x.y, acc);
+            acc = fmaf(x.z, x.z, acc);
+            acc = fmaf(x.w, x.w, acc);
+        }
+    } else {
+        for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N;
+             i += (int64_t)NRM_BLOCKS * 256)
+            acc = fmaf(ec[i], ec[i], acc);
+    }
     acc = wave_sum_lane63(acc);
     if ((threadIdx.x & 63) == 63) red[threadIdx.x >> 6] = acc;
     __syncthreads();
@@ -423,7 +436,9 @@ __global__ __launch_bounds__(256) void k_norm_final(const float *__restrict__ pa
     }
 }
 
-// g[c][j] += fac[c] * e[c][j]; grid (blocks per channel, C), 4 values per thread.
+// g[c][j] += fac[c] * e[c][j]; grid (blocks per channel, C).  VEC as for
+// k_sumsq (g aligned too).
+template <bool VEC>
 __global__ __launch_bounds__(256) void k_norm_grad(const float *__restrict__ e, int64_t N,
                                                    const float *__restrict__ fac,
                                                    float *__restrict__ g) {
@@ -431,8 +446,24 @@ __global__ __launch_bounds__(256) void k_norm_grad(const float *__restrict__ e, 
     const float f = fac[ch];
     const float *ec = e + (int64_t)ch * N;
     float *gc = g + (int64_t)ch * N;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256)
-        gc[i] = fmaf(f, ec[i], gc[i]);
+    if (VEC) {
+        const float4 *e4 = (const float4 *)ec;
+        float4 *g4 = (float4 *)gc;
+        for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N / 4;
+             i += (int64_t)gridDim.x * 256) {
+            const float4 x = e4[i];
+            float4 y = g4[i];
+            y.x = fmaf(f, x.x, y.x);
+            y.y = fmaf(f, x.y, y.y);
+            y.z = fmaf(f, x.z, y.z);
+            y.w = fmaf(f, x.w, y.w);
+            g4[i] = y;
+        }
+    } else {
+        for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N;
+             i += (int64_t)gridDim.x * 256)
+            gc[i] = fmaf(f, ec[i], gc[i]);
+    }
 }
 
 size_t normality_workspace(int L, int C) {
@@ -445,10 +476,15 @@ hipError_t launch_normality(int L, int C, const float *const *bases, const GridK
     float *fac = (float *)((char *)ws + align256(sizeof(float) * (size_t)L * C * NRM_BLOCKS));
     hipError_t e;
     for (int l = 0; l < L; ++l) {
+        const int64_t N = grid_size(lg[l]);
+        const bool vec = (N & 3) == 0 && ((uintptr_t)bases[l] & 15) == 0;
         {
             ProfScope prof_("normality", s);
-            k_sumsq<<<dim3(NRM_BLOCKS, (unsigned)C), 256, 0, s>>>(bases[l], grid_size(lg[l]),
-                                                                  partial + (int64_t)l * C * NRM_BLOCKS);
+            float *pl = partial + (int64_t)l * C * NRM_BLOCKS;
+            if (vec)
+                k_sumsq<true><<<dim3(NRM_BLOCKS, (unsigned)C), 256, 0, s>>>(bases[l], N, pl);
+            else
+                k_sumsq<false><<<dim3(NRM_BLOCKS, (unsigned)C), 256, 0, s>>>(bases[l], N, pl);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
@@ -456,11 +492,17 @@ hipError_t launch_normality(int L, int C, const float *const *bases, const GridK
     if ((e = hipGetLastError()) != hipSuccess || !g) return e;
     for (int l = 0; l < L; ++l) {
         const int64_t N = grid_size(lg[l]);
-        const int64_t blocks = std::min<int64_t>((N + 255) / 256, 1024);
+        const bool vec = (N & 3) == 0 && (((uintptr_t)bases[l] | (uintptr_t)g[l]) & 15) == 0;
+        const int64_t items = vec ? N / 4 : N;
+        const int64_t blocks = std::min<int64_t>((items + 255) / 256, 1024);
         {
             ProfScope prof_("normality", s);
-            k_norm_grad<<<dim3((unsigned)blocks, (unsigned)C), 256, 0, s>>>(
-                bases[l], N, fac + (int64_t)l * C, g[l]);
+            if (vec)
+                k_norm_grad<true><<<dim3((unsigned)blocks, (unsigned)C), 256, 0, s>>>(
+                    bases[l], N, fac + (int64_t)l * C, g[l]);
+            else
+                k_norm_grad<false><<<dim3((unsigned)blocks, (unsigned)C), 256, 0, s>>>(
+                    bases[l], N, fac + (int64_t)l * C, g[l]);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }

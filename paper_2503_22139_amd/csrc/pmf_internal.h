@@ -181,6 +181,15 @@ __device__ __forceinline__ float wave_sum_lane63(float v) {
     return v;
 }
 
+// Sum of n partials by one full wave in a fixed order (lane i adds i, i + 64,
+// ... in turn, then the wave's tree); the total is in lane 63.
+__device__ __forceinline__ float wave_sum_partials(const float *__restrict__ p, int n) {
+    float s = 0.0f;
+#pragma unroll 8
+    for (int i = (int)(threadIdx.x & 63); i < n; i += 64) s += p[i];
+    return wave_sum_lane63(s);
+}
+
 // Orders the LDS accesses of one wavefront (a compiler barrier: the hardware
 // performs a wavefront's LDS operations in order).
 __device__ __forceinline__ void wave_lds_sync() {

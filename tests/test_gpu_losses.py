@@ -108,7 +108,9 @@ def test_tv_block_adds_its_gradient(corner):
 
 
 def test_mbc_normality_adds_its_gradient():
-    levels = [synth.Grid((8, 8, 8), (8.0, 8.0, 8.0)), synth.Grid((16, 12, 10), (4.0, 4.0, 4.0)),
+    # level 0 has 315 voxels (not a multiple of 4: the scalar kernels), the
+    # others take the float4 kernels
+    levels = [synth.Grid((9, 7, 5), (8.0, 8.0, 8.0)), synth.Grid((16, 12, 10), (4.0, 4.0, 4.0)),
               synth.Grid((24, 20, 18), (2.0, 2.0, 2.0))]
     bases = [synth.random_normal(31 + l, (9,) + g.n, 0.05) for l, g in enumerate(levels)]
     g0 = [synth.random_normal(41 + l, b.shape, 0.01) for l, b in enumerate(bases)]

@@ -284,11 +284,21 @@ def test_warp_forward_backward(small):
     assert rel(N(gd), wd) < GRAD_TOL
 
 
-def test_l2_loss():
-    p = synth.random_normal(15, (3, 7, 9))
-    t = synth.random_normal(16, (3, 7, 9))
+@pytest.mark.parametrize("shape,offset", [((3, 7, 9), 0),     # float4 bulk + a 1-value tail
+                                          ((3, 7, 9), 1),     # misaligned: the scalar kernel
+                                          ((2, 384, 513), 0)])  # several hundred blocks
+def test_l2_loss(shape, offset):
+    p = synth.random_normal(15, shape)
+    t = synth.random_normal(16, shape)
     want_l, want_g = oracle.l2_loss(p, t)
-    l, g = ops.pmf_l2_loss(T(p), T(t))
+    n = p.size
+
+    def placed(x):   # the values at a given float offset into a fresh buffer
+        buf = torch.zeros(n + 1, device="cuda")
+        buf[offset:offset + n] = T(x).reshape(-1)
+        return buf[offset:offset + n].view(shape)
+
+    l, g = ops.pmf_l2_loss(placed(p), placed(t))
     assert abs(float(N(l)) - want_l) / want_l < 1e-5
     assert rel(N(g), want_g) < 1e-6
 
