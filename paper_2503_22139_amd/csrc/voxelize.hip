@@ -682,7 +682,11 @@ VoxPlan vox_plan(int64_t m, int c, const GridK &g) {
     VoxPlan p;
     int T[3];
     if (c <= 1) {
-        T[0] = 8; T[1] = 16; T[2] = 16;     // 16^3 measured slower (denser tiles)
+        // 200k Gaussians into 256x256x128, binning + tiles: 8x16x16 0.50 ms
+        // (tiles 0.307), 8x8x32 0.49 ms (tiles 0.275: fewer columns cut at
+        // z faces, a little more binning), 8x16x32 0.66 ms and 8x8x64
+        // 0.63 ms (fewer, longer lists: the fill's cursors contend)
+        T[0] = 8; T[1] = 8; T[2] = 32;
     } else if (c <= 4) {
         T[0] = 8; T[1] = 16; T[2] = 16;
     } else if (c <= 9) {
@@ -805,7 +809,8 @@ hipError_t launch_voxelize(const pmf_gauss_t &gs, const GridK &g, float k, float
         else if (cs == 9) VOX_GATHER(T1_, T2_, 9);                                                \
         else VOX_TILE(T1_, T2_, 0);                                                               \
     } while (0)
-        switch (sel) {
+        if (cs == 1 && p.T[1] == 8 && p.T[2] == 32) VOX_TILE(8, 32, 1);   // one channel
+        else switch (sel) {
             case 3: VOX_TILE_C(16, 16); break;
             case 2: VOX_TILE_C(16, 8); break;
             case 1: VOX_TILE_C(8, 16); break;
