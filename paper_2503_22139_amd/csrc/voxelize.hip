@@ -121,15 +121,17 @@ __device__ __forceinline__ bool far_from_grid(const float *__restrict__ mean,
 }
 
 // ---------------------------------------------------------------- binning
-// Tile counters and cursors sit one per 128-byte line: the binning's atomics
-// are device-scope and contend per line, and a packed array puts every
-// tile's atomics on a few dozen lines.
+// Tile counters sit one per 128-byte line: the count pass's atomics are
+// device-scope and contend per line, and a packed array puts every tile's
+// atomics on a few dozen lines.  Each atomic's old value is the pair's place
+// in its tile's list, so the fill pass writes the lists without atomics.
 constexpr int CNT_STRIDE = 32;
 
 __global__ __launch_bounds__(256) void k_vox_prep(pmf_gauss_t gs, GridK g, float k, int T0,
                                                   int T1, int T2, int nt1, int nt2, int maxtiles,
                                                   GaussK *__restrict__ rec,
                                                   int32_t *__restrict__ tile_count,
+                                                  int32_t *__restrict__ slot,
                                                   int32_t *__restrict__ is_large) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= gs.m) return;
@@ -167,21 +169,23 @@ __global__ __launch_bounds__(256) void k_vox_prep(pmf_gauss_t gs, GridK g, float
         is_large[i] = 1;
         return;
     }
+    // the count's old value is this pair's place in the tile's list: kept
+    // (pair q of Gaussian i at slot[q m + i]) so the fill needs no atomics
+    int q = 0;
     for (int a = t0a; a <= t0b; ++a)
         for (int b = t1a; b <= t1b; ++b)
-            for (int c = t2a; c <= t2b; ++c)
-                atomicAdd(&tile_count[((a * nt1 + b) * nt2 + c) * CNT_STRIDE], 1);
+            for (int c = t2a; c <= t2b; ++c, ++q)
+                slot[(int64_t)q * gs.m + i] =
+                    atomicAdd(&tile_count[((a * nt1 + b) * nt2 + c) * CNT_STRIDE], 1);
 }
 
 // Exclusive scan of n counts (CNT_STRIDE apart) by one workgroup of 1024
-// threads: off[0..n] (dense), and the cursors (CNT_STRIDE apart) = off[] for
-// the fill pass.  Each thread takes a run of up to SCAN_U counts (loaded
+// threads: off[0..n] (dense).  Each thread takes a run of up to SCAN_U counts (loaded
 // together and kept in registers for the second pass); the block's scan is
 // a DPP scan per wave plus the wave totals.
 constexpr int SCAN_U = 8;
 __global__ __launch_bounds__(1024) void k_scan(const int32_t *__restrict__ cnt, int64_t n,
-                                               int32_t *__restrict__ off,
-                                               int32_t *__restrict__ cursor) {
+                                               int32_t *__restrict__ off) {
     __shared__ int32_t wsum[16];
     const int64_t per = (n + 1023) / 1024;
     const int64_t b = threadIdx.x * per;
@@ -209,14 +213,12 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t *__restrict__ cnt, 
         for (int k = 0; k < SCAN_U; ++k) {
             if (b + k < e) {
                 off[b + k] = run;
-                cursor[(b + k) * CNT_STRIDE] = run;
                 run += v[k];
             }
         }
     } else {
         for (int64_t i = b; i < e; ++i) {
             off[i] = run;
-            cursor[i * CNT_STRIDE] = run;
             run += cnt[i * CNT_STRIDE];
         }
     }
@@ -282,7 +284,8 @@ __global__ __launch_bounds__(256) void k_large_fill(const int32_t *__restrict__ 
 
 __global__ __launch_bounds__(256) void k_vox_fill(int64_t m, const GaussK *__restrict__ rec,
                                                   int T0, int T1, int T2, int nt1, int nt2,
-                                                  int maxtiles, int32_t *__restrict__ cursor,
+                                                  int maxtiles, const int32_t *__restrict__ off,
+                                                  const int32_t *__restrict__ slot,
                                                   int32_t *__restrict__ list) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m) return;
@@ -293,10 +296,12 @@ __global__ __launch_bounds__(256) void k_vox_fill(int64_t m, const GaussK *__res
     const int t2a = r.lo2 / T2, t2b = r.hi2 / T2;
     const int64_t cnt = (int64_t)(t0b - t0a + 1) * (t1b - t1a + 1) * (t2b - t2a + 1);
     if (cnt > maxtiles) return;
+    // the pairs in the count pass's order, each to the place that pass drew
+    int q = 0;
     for (int a = t0a; a <= t0b; ++a)
         for (int b = t1a; b <= t1b; ++b)
-            for (int c = t2a; c <= t2b; ++c)
-                list[atomicAdd(&cursor[((a * nt1 + b) * nt2 + c) * CNT_STRIDE], 1)] = (int32_t)i;
+            for (int c = t2a; c <= t2b; ++c, ++q)
+                list[off[(a * nt1 + b) * nt2 + c] + slot[(int64_t)q * m + i]] = (int32_t)i;
 }
 
 // ------------------------------------------------------------ tile splat
@@ -685,7 +690,7 @@ VoxPlan vox_plan(int64_t m, int c, const GridK &g) {
         // 200k Gaussians into 256x256x128, binning + tiles: 8x16x16 0.50 ms
         // (tiles 0.307), 8x8x32 0.49 ms (tiles 0.275: fewer columns cut at
         // z faces, a little more binning), 8x16x32 0.66 ms and 8x8x64
-        // 0.63 ms (fewer, longer lists: the fill's cursors contend)
+        // 0.63 ms (fewer, longer lists: the per-tile atomics contend)
         T[0] = 8; T[1] = 8; T[2] = 32;
     } else if (c <= 4) {
         T[0] = 8; T[1] = 16; T[2] = 16;
@@ -724,12 +729,12 @@ size_t vox_workspace(const VoxPlan &p, int64_t m) {
     s += align256(sizeof(GaussK) * (size_t)(m > 0 ? m : 1));  // records
     s += align256(sizeof(int32_t) * CNT_STRIDE * (size_t)p.ntiles);   // counts
     s += align256(sizeof(int32_t) * (size_t)(p.ntiles + 1));          // offsets
-    s += align256(sizeof(int32_t) * CNT_STRIDE * (size_t)p.ntiles);   // cursors
     s += align256(sizeof(int32_t) * (size_t)(p.cap > 0 ? p.cap : 1));  // list
     s += align256(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));  // large list
     s += align256(sizeof(int32_t));                            // large count
     s += align256(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));  // large flags
     s += align256(sizeof(int32_t) * (size_t)((m + 255) / 256 + 1));   // per-block counts
+    s += align256(sizeof(int32_t) * (size_t)(p.cap > 0 ? p.cap : 1));  // list places
     return s;
 }
 
@@ -743,8 +748,6 @@ hipError_t launch_voxelize(const pmf_gauss_t &gs, const GridK &g, float k, float
     w += align256(sizeof(int32_t) * CNT_STRIDE * (size_t)p.ntiles);
     int32_t *off = (int32_t *)w;
     w += align256(sizeof(int32_t) * (size_t)(p.ntiles + 1));
-    int32_t *cur = (int32_t *)w;
-    w += align256(sizeof(int32_t) * CNT_STRIDE * (size_t)p.ntiles);
     int32_t *list = (int32_t *)w;
     w += align256(sizeof(int32_t) * (size_t)(p.cap > 0 ? p.cap : 1));
     int32_t *large = (int32_t *)w;
@@ -754,6 +757,8 @@ hipError_t launch_voxelize(const pmf_gauss_t &gs, const GridK &g, float k, float
     int32_t *is_large = (int32_t *)w;
     w += align256(sizeof(int32_t) * (size_t)(m > 0 ? m : 1));
     int32_t *blk = (int32_t *)w;
+    w += align256(sizeof(int32_t) * (size_t)((m + 255) / 256 + 1));
+    int32_t *slot = (int32_t *)w;
 
     const float k2 = isinf(k) ? INFINITY : k * k;
     hipError_t e = launch_fill_i32(cnt, CNT_STRIDE * p.ntiles, 0, s);
@@ -764,7 +769,8 @@ hipError_t launch_voxelize(const pmf_gauss_t &gs, const GridK &g, float k, float
         {
             ProfScope prof_("voxelize_prep", s);
             k_vox_prep<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(
-                gs, g, k, p.T[0], p.T[1], p.T[2], p.nt[1], p.nt[2], p.maxtiles, rec, cnt, is_large);
+                gs, g, k, p.T[0], p.T[1], p.T[2], p.nt[1], p.nt[2], p.maxtiles, rec, cnt, slot,
+                is_large);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
         const int nblk = (int)((m + 255) / 256);
@@ -777,15 +783,15 @@ hipError_t launch_voxelize(const pmf_gauss_t &gs, const GridK &g, float k, float
     }
     {
         ProfScope prof_("voxelize_scan", s);
-        k_scan<<<1, 1024, 0, s>>>(cnt, p.ntiles, off, cur);
+        k_scan<<<1, 1024, 0, s>>>(cnt, p.ntiles, off);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (m > 0) {
         {
             ProfScope prof_("voxelize_fill", s);
             k_vox_fill<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(m, rec, p.T[0], p.T[1], p.T[2],
-                                                                  p.nt[1], p.nt[2], p.maxtiles, cur,
-                                                                  list);
+                                                                  p.nt[1], p.nt[2], p.maxtiles, off,
+                                                                  slot, list);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
