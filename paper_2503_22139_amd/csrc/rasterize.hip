@@ -33,8 +33,8 @@ namespace pmf {
 constexpr int RS_T = 16;                // tile edge (pixels)
 constexpr int RS_THREADS = RS_T * RS_T;
 constexpr int RS_TMAX = 16;             // tiles per Gaussian on the tile path
-// Tile counters and cursors one per 128-byte line: the binning's device-scope
-// atomics contend per line.
+// Tile counters one per 128-byte line: the count's device-scope atomics
+// contend per line.
 constexpr int RS_CSTRIDE = 32;
 
 // 2-D splat of one (view, Gaussian): centre, conic (Sigma^-1 = [[a, b], [b, c]]),
@@ -118,7 +118,8 @@ __device__ void splat_setup(const RastGeo &G, double th, const float *p, const f
 
 // ------------------------------------------------------------------ binning
 // Per (view, Gaussian): the splat and its tile rectangle; counts tiles of
-// small rectangles, lists large ones.
+// small rectangles (each count's old value, the pair's place in the tile's
+// list, goes to gslot for the fill), lists large ones.
 __global__ __launch_bounds__(256) void k_splat_prep(const float *__restrict__ mean,
                                                     const float *__restrict__ scale,
                                                     const float *__restrict__ quat,
@@ -127,6 +128,7 @@ __global__ __launch_bounds__(256) void k_splat_prep(const float *__restrict__ me
                                                     const float *__restrict__ angles,
                                                     SplatP *__restrict__ sp,
                                                     int *__restrict__ counts,
+                                                    int *__restrict__ gslot,
                                                     int *__restrict__ large, int *__restrict__ nlarge) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m * V) return;
@@ -169,9 +171,10 @@ __global__ __launch_bounds__(256) void k_splat_prep(const float *__restrict__ me
         return;
     }
     int *cv = counts + (int64_t)v * G.tiles_u * G.tiles_v * RS_CSTRIDE;
+    int k = 0;
     for (int ty = P.tv0; ty <= P.tv1; ++ty)
         for (int tx = P.tu0; tx <= P.tu1; ++tx)
-            atomicAdd(&cv[(ty * G.tiles_u + tx) * RS_CSTRIDE], 1);
+            gslot[i * RS_TMAX + k++] = atomicAdd(&cv[(ty * G.tiles_u + tx) * RS_CSTRIDE], 1);
 }
 
 // Exclusive prefix sum of n counts (RS_CSTRIDE apart; one workgroup, chunks
@@ -201,13 +204,13 @@ __global__ __launch_bounds__(1024) void k_rast_scan(const int *__restrict__ coun
     if (threadIdx.x == 0) offsets[n] = carry;
 }
 
-// Also records, per (view, Gaussian), the list position of each of its tiles
-// in (row, column) order (gslot), so that the adjoint can sum a Gaussian's
-// per-tile partials in a fixed order.
+// Each (view, Gaussian) writes itself at the places the count drew (no
+// atomics) and turns its gslot entries into list positions, in (row,
+// column) order, so that the adjoint can sum a Gaussian's per-tile partials
+// in a fixed order.
 __global__ __launch_bounds__(256) void k_splat_fill(const SplatP *__restrict__ sp, int64_t m,
                                                     int V, RastGeo G,
                                                     const int *__restrict__ offsets,
-                                                    int *__restrict__ cursor,
                                                     int *__restrict__ list,
                                                     int *__restrict__ gslot) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -221,7 +224,7 @@ __global__ __launch_bounds__(256) void k_splat_fill(const SplatP *__restrict__ s
     for (int ty = P.tv0; ty <= P.tv1; ++ty)
         for (int tx = P.tu0; tx <= P.tu1; ++tx) {
             const int64_t tix = (int64_t)v * T + ty * G.tiles_u + tx;
-            const int slot = offsets[tix] + atomicAdd(&cursor[tix * RS_CSTRIDE], 1);
+            const int slot = offsets[tix] + gslot[i * RS_TMAX + k];
             list[slot] = (int)i;
             gslot[i * RS_TMAX + k++] = slot;
         }
@@ -593,7 +596,7 @@ static RastGeo rast_geo(const pmf_cone_t &c, float k) {
 namespace {
 struct RastWs {
     SplatP *sp;
-    int *counts, *cursor, *offsets, *list, *large, *nlarge, *gslot;
+    int *counts, *offsets, *list, *large, *nlarge, *gslot;
     float *acc6, *part;
     size_t total;
 };
@@ -611,7 +614,6 @@ RastWs rast_ws(void *base, int64_t m, const RastGeo &G, int V) {
     };
     w.sp = (SplatP *)take(sizeof(SplatP) * (size_t)mv);
     w.counts = (int *)take(sizeof(int) * RS_CSTRIDE * (size_t)T);
-    w.cursor = (int *)take(sizeof(int) * RS_CSTRIDE * (size_t)T);
     w.offsets = (int *)take(sizeof(int) * (size_t)(T + 1));
     w.list = (int *)take(sizeof(int) * (size_t)mv * RS_TMAX);
     w.large = (int *)take(sizeof(int) * (size_t)mv);
@@ -634,18 +636,18 @@ static hipError_t rast_bin(const pmf_gauss_t &gs, const RastGeo &G, const float 
     const int64_t mv = gs.m * V;
     hipError_t e;
     if ((e = launch_fill_i32(w.counts, RS_CSTRIDE * T, 0, s)) != hipSuccess) return e;
-    if ((e = launch_fill_i32(w.cursor, RS_CSTRIDE * T, 0, s)) != hipSuccess) return e;
     if ((e = launch_fill_i32(w.nlarge, 1, 0, s)) != hipSuccess) return e;
     {
         ProfScope prof_("rasterize_bin", s);
         k_splat_prep<<<(unsigned)((mv + 255) / 256), 256, 0, s>>>(gs.mean, gs.scale, gs.quat,
                                                                   gs.value, gs.m, V, G, angles,
-                                                                  w.sp, w.counts, w.large, w.nlarge);
+                                                                  w.sp, w.counts, w.gslot, w.large,
+                                                                  w.nlarge);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         k_rast_scan<<<1, 1024, 0, s>>>(w.counts, T, w.offsets);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         k_splat_fill<<<(unsigned)((mv + 255) / 256), 256, 0, s>>>(w.sp, gs.m, V, G, w.offsets,
-                                                                  w.cursor, w.list, w.gslot);
+                                                                  w.list, w.gslot);
     }
     return hipGetLastError();
 }
