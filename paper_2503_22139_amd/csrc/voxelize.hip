@@ -763,8 +763,8 @@ hipError_t launch_voxelize(const pmf_gauss_t &gs, const GridK &g, float k, float
     const float k2 = isinf(k) ? INFINITY : k * k;
     hipError_t e = launch_fill_i32(cnt, CNT_STRIDE * p.ntiles, 0, s);
     if (e != hipSuccess) return e;
-    e = launch_fill_i32(nlarge, 1, 0, s);
-    if (e != hipSuccess) return e;
+    // with Gaussians, k_scan_counts writes the large-list length
+    if (m == 0 && (e = launch_fill_i32(nlarge, 1, 0, s)) != hipSuccess) return e;
     if (m > 0) {
         {
             ProfScope prof_("voxelize_prep", s);
